@@ -1,0 +1,240 @@
+"""Oracle: slow, plain FP64 CPU statement of the DMRG operator rotation.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg import this package.  It shares no code with the
+GPU library (``paper_0909_5662_amd``) and never imports it.
+
+Paper: Rincon, Garcia & Hallberg, "Improved parallelization techniques for the
+density matrix renormalization group".  Each function cites the passage it
+follows.  The dense arithmetic lives in ``rot_oracle.c`` (plain C loops,
+OpenMP over operators with the paper's uniform-matrix distribution); the
+block-sparse (quantum-number) variant embeds its blocks into dense matrices
+and calls the dense routine; the bf16 split is a bit-level emulation of
+round-to-nearest-even.
+
+Parity status of each function (what pins it is in tests/test_oracle_*.py):
+  rotate, rotate_entries, adjoint, pair_loss, isometry_deviation,
+  rotate_blocked, bf16_split, umd_range: pinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rot_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile rot_oracle.c into liboracle.so with gcc and OpenMP."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.orc_rotate.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int]
+        lib.orc_rotate.restype = ctypes.c_int
+        lib.orc_rotate_entries.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_int, i32p, i32p, dp]
+        lib.orc_rotate_entries.restype = None
+        lib.orc_adjoint.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
+        lib.orc_adjoint.restype = ctypes.c_int
+        lib.orc_pair_loss.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, dp]
+        lib.orc_pair_loss.restype = ctypes.c_double
+        lib.orc_isometry_deviation.argtypes = [ctypes.c_int64, ctypes.c_int64, dp]
+        lib.orc_isometry_deviation.restype = ctypes.c_double
+        lib.orc_umd_range.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, i64p, i64p]
+        lib.orc_umd_range.restype = None
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def umd_range(n: int, p: int, rank: int) -> tuple[int, int]:
+    """Sec. 3.2, uniform-matrix distribution: worker `rank` of `p` owns a
+    contiguous run of floor(n/p) items, one more for the first mod(n,p)."""
+    lo, hi = ctypes.c_int64(), ctypes.c_int64()
+    _load().orc_umd_range(n, p, rank, ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def rotate(U, O, d: int, nthreads: int = 0) -> np.ndarray:
+    """Sec. 2 step 5 and Sec. 3.2: out_b = U^T kron(O_b, I_d) U, with the
+    blocked operator materialised and the products taken as (Z R^+) first,
+    then R (Z R^+).  U: (m*d, mp); O: (n, m, m) or (m, m)."""
+    U = _f64(U)
+    O = _f64(O)
+    single = O.ndim == 2
+    if single:
+        O = O[None]
+    n, m, _ = O.shape
+    if U.shape[0] != m * d:
+        raise ValueError("U rows must equal m*d")
+    mp = U.shape[1]
+    out = np.empty((n, mp, mp))
+    rc = _load().orc_rotate(m, d, mp, n, _ptr(U), _ptr(O), _ptr(out), nthreads)
+    if rc != 0:
+        raise MemoryError("oracle scratch allocation failed")
+    return out[0] if single else out
+
+
+def rotate_entries(U, O, d: int, alpha, beta) -> np.ndarray:
+    """Selected entries of U^T kron(O, I_d) U for one operator O (m x m), each
+    computed on its own from sum_{i,j,s} U[i d+s, a] O[i,j] U[j d+s, b]."""
+    U = _f64(U)
+    O = _f64(O)
+    m = O.shape[0]
+    mp = U.shape[1]
+    a = np.ascontiguousarray(alpha, dtype=np.int32)
+    b = np.ascontiguousarray(beta, dtype=np.int32)
+    if a.shape != b.shape or (a.size and (a.min() < 0 or a.max() >= mp or b.min() < 0 or b.max() >= mp)):
+        raise ValueError("entry indices out of range")
+    out = np.empty(a.size)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    _load().orc_rotate_entries(m, d, mp, _ptr(U), _ptr(O), a.size, a.ctypes.data_as(i32p),
+                               b.ctypes.data_as(i32p), _ptr(out))
+    return out
+
+
+def adjoint(U, O, dOut, d: int, nthreads: int = 0):
+    """Reverse-mode derivative of out_b = U^T kron(O_b, I_d) U.
+    Returns (dO, dU): dO_b = fold_d(U dOut_b U^T) and
+    dU = sum_b (A_b U dOut_b^T + A_b^T U dOut_b) with A_b = kron(O_b, I_d).
+    dOut may be (mp, mp) (broadcast to every operator) or (n, mp, mp)."""
+    U = _f64(U)
+    O = _f64(O)
+    dOut = _f64(dOut)
+    n, m, _ = O.shape
+    mp = U.shape[1]
+    stride = 0 if dOut.ndim == 2 else mp * mp
+    dO = np.empty((n, m, m))
+    dU = np.empty((m * d, mp))
+    rc = _load().orc_adjoint(m, d, mp, n, _ptr(U), _ptr(O), _ptr(dOut), stride, _ptr(dO), _ptr(dU), nthreads)
+    if rc != 0:
+        raise MemoryError("oracle scratch allocation failed")
+    return dO, dU
+
+
+def pair_loss(X, psi):
+    """Eq. (11) summed over all pairs: L = sum_ij <psi|X_i X_j|psi>.
+    Returns (L, pairs[n,n], dL/dX_k (the same matrix for every k))."""
+    X = _f64(X)
+    psi = _f64(psi)
+    n, mp, _ = X.shape
+    pairs = np.empty((n, n))
+    grad = np.empty((mp, mp))
+    L = _load().orc_pair_loss(mp, n, _ptr(X), _ptr(psi), _ptr(pairs), _ptr(grad))
+    return L, pairs, grad
+
+
+def isometry_deviation(U) -> float:
+    """max |U^T U - I| (orthonormal kept eigenvectors, Sec. 2 step 4)."""
+    U = _f64(U)
+    return _load().orc_isometry_deviation(U.shape[0], U.shape[1], _ptr(U))
+
+
+# ---------------------------------------------------------------------------
+# Quantum-number blocks (Eq. (10)): embed, rotate densely, extract.
+# ---------------------------------------------------------------------------
+
+def blocked_dense_embedding(case):
+    """Dense U (m*d x mp) and dense operators (n x m x m) of a block-sparse
+    case.  Old state (q, i) -> global index off_q + i; row (s, i) of U_Q ->
+    dense row (off_{Q - qn(s)} + i) * d + s; column alpha -> off'_Q + alpha."""
+    d = case.d
+    m, mp = case.m, case.mp
+    by_qn = {s.qn: s for s in case.old}
+    U = np.zeros((m * d, mp))
+    for sec, blk in zip(case.new, case.U_blocks):
+        row = 0
+        for s, sq in enumerate(case.site_qn):
+            q = (sec.qn[0] - sq[0], sec.qn[1] - sq[1])
+            if q not in by_qn:
+                continue
+            osec = by_qn[q]
+            for i in range(osec.dim):
+                U[(osec.offset + i) * d + s, sec.offset:sec.offset + sec.dim] = blk[row + i]
+            row += osec.dim
+        assert row == blk.shape[0]
+    O = np.zeros((len(case.shifts), m, m))
+    for b, (delta, blocks) in enumerate(zip(case.shifts, case.O_blocks)):
+        for k, blk in blocks.items():
+            src = case.old[k]
+            dst = by_qn[(src.qn[0] + delta[0], src.qn[1] + delta[1])]
+            O[b, dst.offset:dst.offset + dst.dim, src.offset:src.offset + src.dim] = blk
+    return U, O
+
+
+def rotate_blocked(case, nthreads: int = 0):
+    """Rotation of a block-sparse batch through its dense embedding.
+    Returns (blocks, dense): blocks[b] maps new-sector index k (source Q) to
+    the (Q+Delta <- Q) block of the rotated operator; dense is the full
+    rotated batch (n x mp x mp), used to check that nothing leaks outside the
+    allowed blocks."""
+    U, O = blocked_dense_embedding(case)
+    dense = rotate(U, O, case.d, nthreads)
+    by_qn = {s.qn: s for s in case.new}
+    blocks = []
+    for b, delta in enumerate(case.shifts):
+        out = {}
+        for k, sec in enumerate(case.new):
+            tq = (sec.qn[0] + delta[0], sec.qn[1] + delta[1])
+            if tq in by_qn:
+                dst = by_qn[tq]
+                out[k] = dense[b, dst.offset:dst.offset + dst.dim, sec.offset:sec.offset + sec.dim].copy()
+        blocks.append(out)
+    return blocks, dense
+
+
+# ---------------------------------------------------------------------------
+# Split of an FP32 value into two bfloat16 parts (not in the paper): the
+# precision variant computes with x = hi + lo, hi = rne_bf16(x),
+# lo = rne_bf16(x - hi).
+# ---------------------------------------------------------------------------
+
+def rne_bf16_bits(x) -> np.ndarray:
+    """Round-to-nearest-even of FP32 values to bfloat16, as uint16 bit
+    patterns (IEEE 754 rounding applied to the top 16 bits)."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    nan = ((b >> 23) & 0xFF) == 0xFF
+    nan &= (b & 0x7FFFFF) != 0
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) & 0xFFFF
+    r = np.where(nan, (b >> 16) | 0x40, r)
+    return r.astype(np.uint16)
+
+
+def bf16_bits_to_f32(h) -> np.ndarray:
+    return (np.asarray(h, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def bf16_split(x):
+    """hi, lo (uint16 bit patterns) with hi = rne(x), lo = rne(x - hi)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    hi = rne_bf16_bits(x)
+    rem = (x - bf16_bits_to_f32(hi)).astype(np.float32)  # exact in FP32
+    lo = rne_bf16_bits(rem)
+    return hi, lo

@@ -1,0 +1,235 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module only draws random numbers and lays them out; it holds none of the
+rotation's arithmetic.  Every stream is ``numpy.random.default_rng([5662, cfg,
+stream])`` with streams 0 = U, 1 = O, 2 = psi, 3 = size draws, 4 = directions.
+
+The shapes follow the workload of the paper's benchmark (Sec. 2.1): the
+one-dimensional Hubbard chain, whose site has d = 4 states
+|0>, |up>, |down>, |up down>, with block dimensions m of a few hundred to
+a thousand kept states (Sec. 3.2).  Stored operators are real symmetric
+(number and S^z operators and their products) or number-shifting (c^+).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED = 5662
+HUBBARD_SITE_QN = ((0, 0), (1, 0), (0, 1), (1, 1))  # (N_up, N_down) of |0>,|up>,|dn>,|up dn>
+
+
+def rng(cfg: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng([SEED, cfg, stream])
+
+
+def isometry(rows: int, cols: int, gen: np.random.Generator) -> np.ndarray:
+    """Q factor of a reduced FP64 QR of a rows x cols N(0,1) matrix, signs
+    fixed so that diag(R) > 0.  Columns are orthonormal (U^T U = I)."""
+    g = gen.standard_normal((rows, cols))
+    q, r = np.linalg.qr(g, mode="reduced")
+    sgn = np.sign(np.diag(r))
+    sgn[sgn == 0] = 1.0
+    return q * sgn[None, :]
+
+
+def symmetric_gaussian(n: int, m: int, gen: np.random.Generator, scale: float) -> np.ndarray:
+    """n symmetric m x m matrices (A + A^T)/2 * scale with A ~ N(0,1)."""
+    a = gen.standard_normal((n, m, m))
+    return (a + a.transpose(0, 2, 1)) * (0.5 * scale)
+
+
+def psi_vector(n: int, gen: np.random.Generator) -> np.ndarray:
+    v = gen.standard_normal(n)
+    return v / np.linalg.norm(v)
+
+
+@dataclasses.dataclass
+class DenseCase:
+    m: int
+    d: int
+    mp: int
+    U: np.ndarray  # (m*d, mp) float64 holding values exactly representable in `dtype`
+    O: np.ndarray  # (n, m, m)
+    dtype: str     # "f64" or "f32": the storage type the GPU receives
+
+
+def dense_case(m: int, d: int, mp: int, n_ops: int, cfg: int, dtype: str = "f32",
+               symmetric: bool = True, scale: float | None = None) -> DenseCase:
+    """Dense shared-U batch.  Values are rounded to `dtype` and returned as
+    float64 arrays, so the oracle sees exactly what the GPU receives."""
+    U = isometry(m * d, mp, rng(cfg, 0))
+    if scale is None:
+        scale = 1.0 / math.sqrt(m)
+    gen = rng(cfg, 1)
+    if symmetric:
+        O = symmetric_gaussian(n_ops, m, gen, scale)
+    else:
+        O = gen.standard_normal((n_ops, m, m)) * scale
+    if dtype == "f32":
+        U = U.astype(np.float32).astype(np.float64)
+        O = O.astype(np.float32).astype(np.float64)
+    elif dtype != "f64":
+        raise ValueError(dtype)
+    return DenseCase(m, d, mp, U, O, dtype)
+
+
+# Named dense workloads (m, d, m', operators, seed stream, storage, O scale).
+# The 64-state FP64 case scales O by 1 (plain symmetrised Gaussians); the
+# others by 1/sqrt(m).
+DENSE_WORKLOADS = {
+    "dense_m64_f64": dict(m=64, d=4, mp=64, n_ops=32, cfg=1, dtype="f64", scale=1.0),
+    "dense_m512_n200": dict(m=512, d=4, mp=512, n_ops=200, cfg=2, dtype="f32", scale=None),
+    "dense_m1024_n64": dict(m=1024, d=4, mp=1024, n_ops=64, cfg=5, dtype="f32", scale=None),
+}
+
+
+def named_dense(name: str) -> DenseCase:
+    return dense_case(**DENSE_WORKLOADS[name])
+
+
+# ---------------------------------------------------------------------------
+# Quantum-number (N_up, N_down) sectors, Eq. (10): block operators and the
+# truncation matrix are block-sparse by particle numbers.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Sector:
+    qn: tuple[int, int]
+    dim: int
+    offset: int
+
+
+@dataclasses.dataclass
+class BlockedCase:
+    """One block-sparse batch.
+
+    old / new: sectors of the old block basis (dims sum to m) and of the kept
+    basis (dims sum to m').  U_blocks[k] is the block of U for new sector
+    new[k]: rows ordered by site state s ascending, then the old state inside
+    old sector (Q - qn(s)); absent old sectors contribute no rows.
+    ops: for each operator its shift Delta and, per old sector index k with
+    target q + Delta present, the block O[q+Delta <- q] (dim_{q+Delta} x dim_q).
+    """
+    d: int
+    site_qn: tuple[tuple[int, int], ...]
+    old: list[Sector]
+    new: list[Sector]
+    U_blocks: list[np.ndarray]
+    shifts: list[tuple[int, int]]
+    O_blocks: list[dict[int, np.ndarray]]
+
+    @property
+    def m(self) -> int:
+        return sum(s.dim for s in self.old)
+
+    @property
+    def mp(self) -> int:
+        return sum(s.dim for s in self.new)
+
+
+def gaussian_sector_sizes(total: int, center=(12, 12), sigma=1.5, min_dim=4, max_dim=128,
+                          radius=8) -> list[tuple[tuple[int, int], int]]:
+    """Sector sizes from a discretised 2-D Gaussian over the (N_up, N_down)
+    grid: size = round(A exp(-r^2 / 2 sigma^2)), sizes below min_dim dropped,
+    capped at max_dim, amplitude A bisected so the sizes sum to `total`, and
+    the remaining residual spread over the largest sectors."""
+    cells = [(center[0] + a, center[1] + b) for a in range(-radius, radius + 1)
+             for b in range(-radius, radius + 1)]
+
+    def sizes(amp):
+        out = []
+        for (u, v) in cells:
+            r2 = (u - center[0]) ** 2 + (v - center[1]) ** 2
+            s = int(round(amp * math.exp(-r2 / (2.0 * sigma * sigma))))
+            if s >= min_dim:
+                out.append(((u, v), min(s, max_dim)))
+        return out
+
+    lo, hi = 1.0, 4.0 * total
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if sum(s for _, s in sizes(mid)) > total:
+            hi = mid
+        else:
+            lo = mid
+    out = sizes(lo)
+    resid = total - sum(s for _, s in out)
+    order = sorted(range(len(out)), key=lambda k: -out[k][1])
+    k = 0
+    while resid != 0:
+        idx = order[k % len(order)]
+        step = 1 if resid > 0 else -1
+        qn, s = out[idx]
+        if min_dim <= s + step <= max_dim:
+            out[idx] = (qn, s + step)
+            resid -= step
+        k += 1
+    out.sort(key=lambda t: t[0])
+    return out
+
+
+def make_sectors(sizes: list[tuple[tuple[int, int], int]]) -> list[Sector]:
+    secs, off = [], 0
+    for qn, dim in sizes:
+        secs.append(Sector(qn, dim, off))
+        off += dim
+    return secs
+
+
+def blocked_case(total: int = 1024, n_conserving: int = 200, n_up_shift: int = 100,
+                 n_dn_shift: int = 100, cfg: int = 3, sigma: float = 1.5,
+                 sizes=None, d_site_qn=HUBBARD_SITE_QN, kept_sizes=None) -> BlockedCase:
+    """Block-sparse batch: old and kept bases share the sector grid (kept
+    sizes default to the old ones); U_Q from QR of an M_Q x m'_Q Gaussian;
+    number-conserving operators are symmetric diagonal blocks, shifting ones
+    (Delta = (1,0) or (0,1), c^+-like) have Gaussian off-diagonal blocks.
+    All values are scaled by 1/sqrt(m) and rounded to FP32."""
+    if sizes is None:
+        sizes = gaussian_sector_sizes(total, sigma=sigma)
+    old = make_sectors(sizes)
+    new = make_sectors(kept_sizes if kept_sizes is not None else sizes)
+    m = sum(s.dim for s in old)
+    by_qn = {s.qn: k for k, s in enumerate(old)}
+    g_u = rng(cfg, 0)
+    U_blocks = []
+    for sec in new:
+        rows = 0
+        for sq in d_site_qn:
+            q = (sec.qn[0] - sq[0], sec.qn[1] - sq[1])
+            if q in by_qn:
+                rows += old[by_qn[q]].dim
+        if rows < sec.dim:
+            raise ValueError(f"kept sector {sec.qn} larger than its block-site space")
+        U_blocks.append(isometry(rows, sec.dim, g_u).astype(np.float32).astype(np.float64))
+    g_o = rng(cfg, 1)
+    scale = 1.0 / math.sqrt(m)
+    shifts, O_blocks = [], []
+    kinds = [(0, 0)] * n_conserving + [(1, 0)] * n_up_shift + [(0, 1)] * n_dn_shift
+    for delta in kinds:
+        blocks = {}
+        for k, sec in enumerate(old):
+            tq = (sec.qn[0] + delta[0], sec.qn[1] + delta[1])
+            if tq not in by_qn:
+                continue
+            rows = old[by_qn[tq]].dim
+            if delta == (0, 0):
+                a = g_o.standard_normal((sec.dim, sec.dim))
+                blk = 0.5 * (a + a.T) * scale
+            else:
+                blk = g_o.standard_normal((rows, sec.dim)) * scale
+            blocks[k] = blk.astype(np.float32).astype(np.float64)
+        shifts.append(delta)
+        O_blocks.append(blocks)
+    return BlockedCase(len(d_site_qn), tuple(d_site_qn), old, new, U_blocks, shifts, O_blocks)
+
+
+# ---------------------------------------------------------------------------
+# Uneven sweep batch: many rotations of different m, a few operators each.
+# ---------------------------------------------------------------------------
+
+def uneven_sizes(n_rot: int, cfg: int = 4, classes=(128, 256, 512, 1024, 2048)) -> list[int]:
+    g = rng(cfg, 3)
+    return [int(classes[k]) for k in g.integers(0, len(classes), size=n_rot)]
