@@ -1,0 +1,240 @@
+/*
+ * librot: batched density-matrix rotation of stored operators on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Operation (Rincon, Garcia & Hallberg, "Improved parallelization techniques
+ * for the density matrix renormalization group", Sec. 2 step 5 and the
+ * paragraph that follows the step list; Sec. 3.2): every operator Z stored
+ * on the block B is blocked onto the enlarged block [B a] (tensored with the
+ * identity of the added site) and then rotated and decimated with the
+ * truncation matrix R built from the kept density-matrix eigenvectors,
+ * Z_new = R Z_[B a] R^+.  In this library, with real arithmetic:
+ *
+ *     out_b = U^T (O_b (x) I_d) U           for every operator b of a group,
+ *
+ * where U = R^T is the (m*d) x mp isometry whose columns are the kept
+ * eigenvectors, with block-site row index r = i*d + s (old block state i
+ * slow, site state s fast).  The Kronecker product is never formed: stage 1
+ * computes T_b = O_b * U_r with U_r the m x (d*mp) view of U (the paper's
+ * "Z R^+" first), stage 2 computes out_b = U^T T_b ("R (Z R^+)").
+ *
+ * Conventions for every entry point:
+ *  - All matrices are dense and row-major.  Data pointers are device
+ *    pointers unless the argument says "host".  FP64 precision takes double
+ *    buffers; FP32 and split-BF16 take float buffers.
+ *  - The caller allocates and owns every buffer, including the workspace;
+ *    the library keeps no pointer after a call returns.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    default stream).  Argument errors are detected on the host before any
+ *    launch and returned synchronously; nothing aborts or throws.
+ *  - A status other than ROT_OK leaves the outputs unspecified;
+ *    rot_last_error() then describes the failure (per calling thread).
+ */
+#ifndef LIBROT_H
+#define LIBROT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ROT_API __attribute__((visibility("default")))
+#else
+#define ROT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ROT_OK = 0,
+    ROT_ERR_INVALID_ARG = -1,   /* null pointer, bad size or stride, bad table */
+    ROT_ERR_UNSUPPORTED = -2,   /* valid request this library does not implement */
+    ROT_ERR_WORKSPACE = -3,     /* workspace smaller than the minimum */
+    ROT_ERR_HIP = -4,           /* HIP runtime error (launch, device query) */
+    ROT_ERR_NOT_ISOMETRY = -5   /* rot_check_isometry: max|U^T U - I| above tolerance */
+} rot_status;
+
+typedef enum {
+    ROT_FP64 = 0,        /* double buffers, FP64 matrix cores */
+    ROT_FP32 = 1,        /* float buffers, FP32 matrix cores, FP32 accumulation */
+    ROT_SPLIT_BF16 = 2   /* float buffers; each operand x = hi + lo with
+                            hi = bf16(x), lo = bf16(x - hi) (round to nearest
+                            even); products hi*hi + hi*lo + lo*hi on BF16
+                            matrix cores, FP32 accumulation */
+} rot_precision;
+
+/*
+ * One group of operators sharing one truncation matrix (Sec. 3.2: R is
+ * common to all stored operators of a step).
+ *   m      old block dimension (> 0)
+ *   d      added-site dimension (> 0; 4 for the Hubbard chain of Eq. (4))
+ *   mp     number of kept states (0 < mp <= m*d)
+ *   n_ops  number of operators (>= 0; 0 is a no-op)
+ *   U      (m*d) x mp, contiguous, row r = i*d + s
+ *   O      operator b is the contiguous m x m matrix at O + b*stride_o
+ *          (stride_o >= m*m, in elements)
+ *   out    result b is the contiguous mp x mp matrix at out + b*stride_out
+ *          (stride_out >= mp*mp); must not overlap U or O
+ */
+typedef struct {
+    int32_t m, d, mp, n_ops;
+    const void* U;
+    const void* O;
+    int64_t stride_o;
+    void* out;
+    int64_t stride_out;
+} rot_problem;
+
+/*
+ * Dense rotation of one or more groups: out_b = U^T (O_b (x) I_d) U.
+ * Sec. 2 step 5; Sec. 3.2 (order of the two products; all stored Z_i and
+ * Z_i Z_j of a step share R).
+ * workspace: device memory of at least rot_workspace_size(..., 1) bytes,
+ * 256-byte aligned; operators are processed in chunks that fit it (larger
+ * workspaces give larger, faster chunks).  Groups may have different m, d,
+ * mp.  Returns ROT_OK, ROT_ERR_INVALID_ARG, ROT_ERR_WORKSPACE, ROT_ERR_HIP.
+ */
+ROT_API rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision prec,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Workspace bytes needed by rot_batch / rot_backward for these groups when
+ * up to `ops_per_chunk` operators are processed at once (<= 0: all
+ * operators of the largest group).  `for_backward` != 0 sizes it for
+ * rot_backward.  Returns 0 for invalid arguments.
+ */
+ROT_API size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_precision prec,
+                          int32_t ops_per_chunk, int32_t for_backward);
+
+/*
+ * Reverse-mode derivative of rot_batch (not in the paper).  For each group,
+ * given dOut_b = dL/dout_b (mp x mp at dOut[g] + b*stride_dout[g]; a stride
+ * of 0 broadcasts one matrix to every operator) it writes
+ *   dO_b = sum_s U_s dOut_b U_s^T     (m x m at dO[g] + b*m*m), U_s the rows
+ *                                      s, s+d, s+2d, ... of U
+ *   dU   = sum_b [ (O_b (x) I) U dOut_b^T + (O_b^T (x) I) U dOut_b ]
+ *                                     ((m*d) x mp at dU[g], summed over b)
+ * Stage 1 is recomputed, never stored between calls.  dO, dU (host arrays of
+ * n_groups device pointers) may be NULL, and so may any element, to skip
+ * that output.  flags: ROT_ASSUME_SYMMETRIC_O lets the library reuse stage 1
+ * for the transposed term (valid only when every O_b is symmetric).
+ * Summation order is fixed: results are deterministic.
+ */
+#define ROT_ASSUME_SYMMETRIC_O 1u
+ROT_API rot_status rot_backward(const rot_problem* groups, int32_t n_groups,
+                        const void* const* dOut, const int64_t* stride_dout,
+                        void* const* dO, void* const* dU, uint32_t flags, rot_precision prec,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Quantum-number (N_up, N_down) block-sparse rotation, Eq. (10) and the
+ * paragraph after it: operators and U are block-sparse by particle numbers;
+ * an operator with shift Delta maps old sector q to q + Delta (Delta = (0,0)
+ * for number-conserving operators such as n and S^z, (1,0) or (0,1) for
+ * c^+_up, c^+_dn).  For every operator and kept sector Q with Q + Delta kept:
+ *   out(Q+Delta <- Q) = sum_s U_{Q+Delta}[s-rows]^T O(q_s+Delta <- q_s) U_Q[s-rows],
+ * q_s = Q - qn(s); terms whose sectors are absent are zero.
+ *
+ * All tables are host arrays; block data are device arrays of floats.
+ *   site_qn      d pairs (n_up, n_dn) of the site states
+ *   old_sec      n_old sectors {n_up, n_dn, dim, offset} of the old block
+ *                (dims sum to m; offsets are their prefix sums)
+ *   new_sec      n_new kept sectors (dims sum to mp)
+ *   U_blk/U_off  U_Q for new sector k is the M_k x new_sec[k].dim matrix at
+ *                U_blk + U_off[k]; its rows run over s ascending and, inside,
+ *                over the old states of sector Q - qn(s) (absent sectors give
+ *                no rows), so M_k = sum_s dim(Q - qn(s))
+ *   shift        n_ops pairs Delta
+ *   O_blk/O_off  block (q+Delta <- q) of operator b for old sector k is the
+ *                dim(q+Delta) x dim(q) matrix at O_blk + O_off[b*n_old + k];
+ *                -1 means the block is absent (zero)
+ *   out_blk/out_off  block (Q+Delta <- Q) of operator b for new sector k is
+ *                written at out_blk + out_off[b*n_new + k] (dim(Q+Delta) x
+ *                dim(Q)); -1 means not requested.  A requested block whose
+ *                target sector is not kept is an error.
+ * Only ROT_FP32 is supported.  workspace: at least
+ * rot_blocked_workspace_size(p) bytes.
+ */
+typedef struct { int32_t n_up, n_dn, dim; int64_t offset; } rot_sector;
+typedef struct {
+    int32_t d;
+    const int32_t* site_qn;
+    int32_t n_old;
+    const rot_sector* old_sec;
+    int32_t n_new;
+    const rot_sector* new_sec;
+    const float* U_blk;
+    const int64_t* U_off;
+    int32_t n_ops;
+    const int32_t* shift;
+    const float* O_blk;
+    const int64_t* O_off;
+    float* out_blk;
+    const int64_t* out_off;
+} rot_blocked_problem;
+
+ROT_API rot_status rot_batch_blocked(const rot_blocked_problem* p, rot_precision prec,
+                             void* workspace, size_t workspace_bytes, void* stream);
+ROT_API size_t rot_blocked_workspace_size(const rot_blocked_problem* p);
+
+/*
+ * Sum of two-point expectation values over all pairs of rotated operators,
+ * Eq. (11): L = sum_i sum_j <psi| X_i X_j |psi> = sum_ij (X_i^T psi).(X_j psi),
+ * reduced in FP64 on the GPU whatever the storage type of X.
+ *   X      n_ops matrices mp x mp at X + b*stride_x (float for ROT_FP32 and
+ *          ROT_SPLIT_BF16, double for ROT_FP64)
+ *   psi    mp doubles (device)
+ *   loss   1 double (device), written
+ *   pairs  optional n_ops x n_ops doubles (device): <psi|X_i X_j|psi>
+ *   grad   optional mp x mp (same type as X, device): dL/dX_k, which is the
+ *          same for every k: psi (S psi)^T + (S^T psi) psi^T, S = sum_j X_j
+ *   workspace: at least rot_pair_loss_workspace_size(mp, n_ops) bytes
+ */
+ROT_API rot_status rot_pair_loss(const void* X, int32_t mp, int32_t n_ops, int64_t stride_x,
+                         rot_precision prec, const double* psi, double* loss, double* pairs,
+                         void* grad, void* workspace, size_t workspace_bytes, void* stream);
+ROT_API size_t rot_pair_loss_workspace_size(int32_t mp, int32_t n_ops);
+
+/*
+ * Isometry check of a truncation matrix (Sec. 2: the kept eigenvectors are
+ * orthonormal; the block basis is complete only up to the truncation):
+ * computes max_{a,b} |(U^T U - I)[a,b]| in FP64 on the GPU for a rows x cols
+ * row-major U (float or double per prec).  Synchronises `stream`, stores the
+ * deviation in *max_dev_host and returns ROT_ERR_NOT_ISOMETRY when it
+ * exceeds `tol` (ROT_OK otherwise).  workspace: at least
+ * rot_isometry_workspace_size(rows, cols, prec) bytes, 256-byte aligned.
+ */
+ROT_API rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, rot_precision prec,
+                              double tol, double* max_dev_host, void* workspace,
+                              size_t workspace_bytes, void* stream);
+ROT_API size_t rot_isometry_workspace_size(int32_t rows, int32_t cols, rot_precision prec);
+
+/* Split of float values into bf16 pairs (the split-BF16 operand format):
+ * hi[k] = bf16(x[k]), lo[k] = bf16(x[k] - hi[k]), round to nearest even,
+ * stored as raw 16-bit patterns.  n elements; device buffers. */
+ROT_API rot_status rot_split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, void* stream);
+
+/*
+ * Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel this library enqueues (measurement support; not in the
+ * paper).  rot_profile_enable(1) clears earlier records and starts
+ * recording; rot_profile_enable(0) stops.  rot_profile_read waits for the
+ * recorded events, writes one line "name launches total_ms\n" per kernel
+ * kind into buf (host, len bytes, NUL-terminated, truncated if short),
+ * clears the records and returns the number of kernel kinds (or -1 on a
+ * HIP error).  Recording is process-wide and mutex-guarded.
+ */
+ROT_API rot_status rot_profile_enable(int32_t on);
+ROT_API int32_t rot_profile_read(char* buf, size_t len);
+
+ROT_API const char* rot_status_string(rot_status s);
+ROT_API const char* rot_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+ROT_API int32_t rot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBROT_H */

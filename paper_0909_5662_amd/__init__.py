@@ -1,0 +1,357 @@
+"""Python binding of librot: batched DMRG operator rotation on MI355X.
+
+Argument marshalling only: every arithmetic step runs in the HIP kernels of
+``librot.so`` (built in-tree by ``paper_0909_5662_amd.build``).  PyTorch
+supplies device memory and the current stream.  There is no CPU fallback:
+if the library is missing, importing the binding's entry points raises.
+
+The entry points mirror the C ABI (include/librot.h):
+  rot_batch, rot_backward, rot_batch_blocked, rot_pair_loss,
+  rot_check_isometry, rot_split_bf16, rot_workspace_size
+plus tensor-level helpers ``rotate``, ``rotate_backward``, ``pair_loss``,
+``check_isometry``, ``rotate_blocked`` and the autograd functions
+``RotateFn`` and ``PairLossFn``.
+
+Operation (Sec. 2 step 5 and Sec. 3.2 of the paper): for every stored
+operator O_b, out_b = U^T (O_b (x) I_d) U, with U the (m*d) x m' truncation
+isometry (row index i*d + s).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "ROT_FP64", "ROT_FP32", "ROT_SPLIT_BF16", "ROT_ASSUME_SYMMETRIC_O", "RotError",
+    "RotProblem", "RotSector", "RotBlockedProblem", "lib", "library_path",
+    "rot_batch", "rot_backward", "rot_batch_blocked", "rot_pair_loss", "rot_check_isometry",
+    "rot_split_bf16", "rot_workspace_size", "rot_blocked_workspace_size",
+    "rotate", "rotate_backward", "pair_loss", "check_isometry", "split_bf16",
+    "RotateFn", "PairLossFn", "precision_code", "profile_enable", "profile_read",
+]
+
+ROT_FP64, ROT_FP32, ROT_SPLIT_BF16 = 0, 1, 2
+ROT_ASSUME_SYMMETRIC_O = 1
+_STATUS = {0: "ROT_OK", -1: "ROT_ERR_INVALID_ARG", -2: "ROT_ERR_UNSUPPORTED", -3: "ROT_ERR_WORKSPACE",
+           -4: "ROT_ERR_HIP", -5: "ROT_ERR_NOT_ISOMETRY"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "librot.so")
+
+
+class RotError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class RotProblem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("d", ctypes.c_int32), ("mp", ctypes.c_int32),
+                ("n_ops", ctypes.c_int32), ("U", ctypes.c_void_p), ("O", ctypes.c_void_p),
+                ("stride_o", ctypes.c_int64), ("out", ctypes.c_void_p), ("stride_out", ctypes.c_int64)]
+
+
+class RotSector(ctypes.Structure):
+    _fields_ = [("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("offset", ctypes.c_int64)]
+
+
+class RotBlockedProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("site_qn", ctypes.POINTER(ctypes.c_int32)),
+                ("n_old", ctypes.c_int32), ("old_sec", ctypes.POINTER(RotSector)),
+                ("n_new", ctypes.c_int32), ("new_sec", ctypes.POINTER(RotSector)),
+                ("U_blk", ctypes.c_void_p), ("U_off", ctypes.POINTER(ctypes.c_int64)),
+                ("n_ops", ctypes.c_int32), ("shift", ctypes.POINTER(ctypes.c_int32)),
+                ("O_blk", ctypes.c_void_p), ("O_off", ctypes.POINTER(ctypes.c_int64)),
+                ("out_blk", ctypes.c_void_p), ("out_off", ctypes.POINTER(ctypes.c_int64))]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded librot.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(f"{library_path} not found: build it with `python -m paper_0909_5662_amd.build`")
+        L = ctypes.CDLL(library_path)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.rot_batch.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, vp, sz, vp]
+        L.rot_workspace_size.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, i32, i32]
+        L.rot_workspace_size.restype = sz
+        L.rot_backward.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                   ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_uint32, ctypes.c_int,
+                                   vp, sz, vp]
+        L.rot_batch_blocked.argtypes = [ctypes.POINTER(RotBlockedProblem), ctypes.c_int, vp, sz, vp]
+        L.rot_blocked_workspace_size.argtypes = [ctypes.POINTER(RotBlockedProblem)]
+        L.rot_blocked_workspace_size.restype = sz
+        L.rot_pair_loss.argtypes = [vp, i32, i32, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz, vp]
+        L.rot_pair_loss_workspace_size.argtypes = [i32, i32]
+        L.rot_pair_loss_workspace_size.restype = sz
+        L.rot_check_isometry.argtypes = [vp, i32, i32, ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+        L.rot_isometry_workspace_size.argtypes = [i32, i32, ctypes.c_int]
+        L.rot_isometry_workspace_size.restype = sz
+        L.rot_split_bf16.argtypes = [vp, i64, vp, vp, vp]
+        L.rot_status_string.restype = ctypes.c_char_p
+        L.rot_status_string.argtypes = [ctypes.c_int]
+        L.rot_last_error.restype = ctypes.c_char_p
+        L.rot_last_error.argtypes = []
+        L.rot_version.restype = ctypes.c_int32
+        L.rot_profile_enable.argtypes = [i32]
+        L.rot_profile_enable.restype = ctypes.c_int
+        L.rot_profile_read.argtypes = [ctypes.c_char_p, sz]
+        L.rot_profile_read.restype = i32
+        for f in ("rot_batch", "rot_backward", "rot_batch_blocked", "rot_pair_loss",
+                  "rot_check_isometry", "rot_split_bf16"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def profile_enable(on: bool) -> None:
+    """Start (clearing earlier records) or stop per-kernel event timing."""
+    _check(lib().rot_profile_enable(int(on)))
+
+
+def profile_read() -> dict[str, tuple[int, float]]:
+    """{kernel kind: (launches, total ms)} since profile_enable(True)."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    n = lib().rot_profile_read(buf, len(buf))
+    if n < 0:
+        raise RotError(-4, "rot_profile_read failed")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise RotError(status, lib().rot_last_error().decode())
+
+
+def precision_code(precision) -> int:
+    if isinstance(precision, int):
+        return precision
+    return {"fp64": ROT_FP64, "fp32": ROT_FP32, "split_bf16": ROT_SPLIT_BF16, "bf16x3": ROT_SPLIT_BF16}[precision]
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace allocation is not 256-byte aligned")
+    return ws
+
+
+# --------------------------------------------------------------- raw C ABI --
+
+def rot_workspace_size(groups, prec: int, ops_per_chunk: int = 0, for_backward: bool = False) -> int:
+    arr = (RotProblem * len(groups))(*groups)
+    return lib().rot_workspace_size(arr, len(groups), prec, ops_per_chunk, int(for_backward))
+
+
+def rot_batch(groups, prec: int, workspace: int, workspace_bytes: int, stream: int) -> None:
+    arr = (RotProblem * len(groups))(*groups)
+    _check(lib().rot_batch(arr, len(groups), prec, workspace, workspace_bytes, stream))
+
+
+def rot_backward(groups, dOut, stride_dout, dO, dU, flags: int, prec: int, workspace: int,
+                 workspace_bytes: int, stream: int) -> None:
+    n = len(groups)
+    arr = (RotProblem * n)(*groups)
+    vp = ctypes.c_void_p
+    dout_arr = (vp * n)(*dOut)
+    sd_arr = (ctypes.c_int64 * n)(*stride_dout)
+    do_arr = None if dO is None else (vp * n)(*dO)
+    du_arr = None if dU is None else (vp * n)(*dU)
+    _check(lib().rot_backward(arr, n, dout_arr, sd_arr, do_arr, du_arr, flags, prec, workspace,
+                              workspace_bytes, stream))
+
+
+def rot_batch_blocked(problem: RotBlockedProblem, prec: int, workspace: int, workspace_bytes: int,
+                      stream: int) -> None:
+    _check(lib().rot_batch_blocked(ctypes.byref(problem), prec, workspace, workspace_bytes, stream))
+
+
+def rot_blocked_workspace_size(problem: RotBlockedProblem) -> int:
+    return lib().rot_blocked_workspace_size(ctypes.byref(problem))
+
+
+def rot_pair_loss(X: int, mp: int, n_ops: int, stride_x: int, prec: int, psi: int, loss: int,
+                  pairs: int | None, grad: int | None, workspace: int, workspace_bytes: int,
+                  stream: int) -> None:
+    _check(lib().rot_pair_loss(X, mp, n_ops, stride_x, prec, psi, loss, pairs, grad, workspace,
+                               workspace_bytes, stream))
+
+
+def rot_check_isometry(U: int, rows: int, cols: int, prec: int, tol: float, workspace: int,
+                       workspace_bytes: int, stream: int) -> tuple[int, float]:
+    dev = ctypes.c_double(float("nan"))
+    st = lib().rot_check_isometry(U, rows, cols, prec, tol, ctypes.byref(dev), workspace,
+                                  workspace_bytes, stream)
+    if st not in (0, -5):
+        _check(st)
+    return st, dev.value
+
+
+def rot_split_bf16(x: int, n: int, hi: int, lo: int, stream: int) -> None:
+    _check(lib().rot_split_bf16(x, n, hi, lo, stream))
+
+
+# ---------------------------------------------------------- tensor helpers --
+
+def _dtype_for(prec: int):
+    return torch.float64 if prec == ROT_FP64 else torch.float32
+
+
+def _problem(U: torch.Tensor, O: torch.Tensor, out: torch.Tensor, d: int) -> RotProblem:
+    n, m, _ = O.shape
+    return RotProblem(m, d, U.shape[1], n, U.data_ptr(), O.data_ptr(), m * m, out.data_ptr(),
+                      out.shape[1] * out.shape[2])
+
+
+def _check_inputs(U: torch.Tensor, O: torch.Tensor, d: int, prec: int) -> None:
+    dt = _dtype_for(prec)
+    if U.dtype != dt or O.dtype != dt:
+        raise TypeError(f"precision {prec} needs {dt} tensors, got {U.dtype}/{O.dtype}")
+    if not (U.is_cuda and O.is_cuda):
+        raise ValueError("U and O must be device tensors")
+    if not (U.is_contiguous() and O.is_contiguous()):
+        raise ValueError("U and O must be contiguous")
+    if O.dim() != 3 or O.shape[1] != O.shape[2] or U.dim() != 2 or U.shape[0] != O.shape[1] * d:
+        raise ValueError("expected O (n, m, m) and U (m*d, mp)")
+
+
+def rotate(U: torch.Tensor, O: torch.Tensor, d: int, precision="fp32", out: torch.Tensor | None = None,
+           workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """out_b = U^T (O_b (x) I_d) U for O of shape (n, m, m), U (m*d, mp)."""
+    prec = precision_code(precision)
+    _check_inputs(U, O, d, prec)
+    n, m, _ = O.shape
+    mp = U.shape[1]
+    if out is None:
+        out = torch.empty((n, mp, mp), dtype=U.dtype, device=U.device)
+    p = _problem(U, O, out, d)
+    if workspace is None:
+        workspace = _workspace(rot_workspace_size([p], prec), U.device)
+    rot_batch([p], prec, workspace.data_ptr(), workspace.numel(), _stream(stream))
+    return out
+
+
+def rotate_backward(U: torch.Tensor, O: torch.Tensor, d: int, dOut: torch.Tensor, precision="fp32",
+                    need_dO: bool = True, need_dU: bool = True, symmetric_O: bool = False,
+                    workspace: torch.Tensor | None = None, stream=None):
+    """(dO, dU) of the rotation for upstream gradient dOut ((mp, mp), broadcast
+    to every operator, or (n, mp, mp))."""
+    prec = precision_code(precision)
+    _check_inputs(U, O, d, prec)
+    n, m, _ = O.shape
+    mp = U.shape[1]
+    if not dOut.is_contiguous() or dOut.dtype != U.dtype:
+        raise ValueError("dOut must be contiguous with the dtype of U")
+    sd = 0 if dOut.dim() == 2 else mp * mp
+    dO = torch.empty_like(O) if need_dO else None
+    dU = torch.empty_like(U) if need_dU else None
+    dummy = torch.empty((1, mp, mp), dtype=U.dtype, device=U.device)
+    p = _problem(U, O, dummy, d)
+    if workspace is None:
+        workspace = _workspace(rot_workspace_size([p], prec, for_backward=True), U.device)
+    rot_backward([p], [dOut.data_ptr()], [sd], None if dO is None else [dO.data_ptr()],
+                 None if dU is None else [dU.data_ptr()], ROT_ASSUME_SYMMETRIC_O if symmetric_O else 0,
+                 prec, workspace.data_ptr(), workspace.numel(), _stream(stream))
+    return dO, dU
+
+
+def pair_loss(X: torch.Tensor, psi: torch.Tensor, want_pairs: bool = False, want_grad: bool = False,
+              precision=None, stream=None):
+    """Eq. (11) summed over pairs, in FP64 on the GPU.  X: (n, mp, mp) float or
+    double; psi: (mp,) double.  Returns (loss (0-d double), pairs, grad)."""
+    prec = precision_code(precision) if precision is not None else (
+        ROT_FP64 if X.dtype == torch.float64 else ROT_FP32)
+    if X.dtype != _dtype_for(prec) or psi.dtype != torch.float64 or not X.is_contiguous():
+        raise TypeError("X must be contiguous float32/float64 matching precision; psi float64")
+    n, mp, _ = X.shape
+    loss = torch.empty((), dtype=torch.float64, device=X.device)
+    pairs = torch.empty((n, n), dtype=torch.float64, device=X.device) if want_pairs else None
+    grad = torch.empty((mp, mp), dtype=X.dtype, device=X.device) if want_grad else None
+    ws = _workspace(lib().rot_pair_loss_workspace_size(mp, n), X.device)
+    rot_pair_loss(X.data_ptr(), mp, n, mp * mp, prec, psi.contiguous().data_ptr(), loss.data_ptr(),
+                  _ptr(pairs), _ptr(grad), ws.data_ptr(), ws.numel(), _stream(stream))
+    return loss, pairs, grad
+
+
+def check_isometry(U: torch.Tensor, tol: float = 1e-6, stream=None) -> tuple[bool, float]:
+    """(ok, max|U^T U - I|) computed in FP64 on the GPU."""
+    prec = ROT_FP64 if U.dtype == torch.float64 else ROT_FP32
+    rows, cols = U.shape
+    ws = _workspace(lib().rot_isometry_workspace_size(rows, cols, prec), U.device)
+    st, dev = rot_check_isometry(U.contiguous().data_ptr(), rows, cols, prec, tol, ws.data_ptr(), ws.numel(),
+                                 _stream(stream))
+    return st == 0, dev
+
+
+def split_bf16(x: torch.Tensor, stream=None):
+    """(hi, lo) int16 tensors holding the bf16 bit patterns of the split."""
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise TypeError("x must be contiguous float32")
+    hi = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    lo = torch.empty_like(hi)
+    rot_split_bf16(x.data_ptr(), x.numel(), hi.data_ptr(), lo.data_ptr(), _stream(stream))
+    return hi, lo
+
+
+class RotateFn(torch.autograd.Function):
+    """Differentiable rotation.  Saves only U and O; stage 1 is recomputed in
+    the backward kernel."""
+
+    @staticmethod
+    def forward(ctx, U, O, d, precision="fp32", symmetric_O=False):
+        ctx.save_for_backward(U, O)
+        ctx.d = d
+        ctx.precision = precision
+        ctx.symmetric_O = symmetric_O
+        return rotate(U, O, d, precision)
+
+    @staticmethod
+    def backward(ctx, dOut):
+        U, O = ctx.saved_tensors
+        prec = precision_code(ctx.precision)
+        bprec = ROT_FP32 if prec == ROT_SPLIT_BF16 else prec
+        if dOut.dim() == 3 and dOut.stride(0) == 0 and dOut[0].is_contiguous():
+            dOut = dOut[0]  # one matrix broadcast to every operator: pass stride 0
+        dO, dU = rotate_backward(U, O, ctx.d, dOut.contiguous(), bprec, ctx.needs_input_grad[1],
+                                 ctx.needs_input_grad[0], ctx.symmetric_O)
+        return dU, dO, None, None, None
+
+
+class PairLossFn(torch.autograd.Function):
+    """L = sum_ij <psi|X_i X_j|psi> (FP64 reduction); backward returns the
+    closed-form gradient psi (S psi)^T + (S^T psi) psi^T for every X_k."""
+
+    @staticmethod
+    def forward(ctx, X, psi):
+        loss, _, grad = pair_loss(X, psi, want_grad=True)
+        ctx.save_for_backward(grad)
+        ctx.n = X.shape[0]
+        return loss
+
+    @staticmethod
+    def backward(ctx, gl):
+        (grad,) = ctx.saved_tensors
+        g = grad if bool(gl == 1) else grad * gl.to(grad.dtype)
+        return g.unsqueeze(0).expand(ctx.n, *grad.shape), None

@@ -1,0 +1,72 @@
+// Split-BF16 operand format: x = hi + lo with hi = bf16(x), lo = bf16(x - hi),
+// both rounded to nearest even (x - hi is exact in FP32).
+#include <hip/hip_runtime.h>
+
+#include "rot_internal.h"
+
+namespace rot {
+namespace {
+
+// IEEE round-to-nearest-even of an FP32 bit pattern to its top 16 bits.
+__device__ inline uint16_t rne_bf16(float x) {
+    const uint32_t b = __float_as_uint(x);
+    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))  // NaN: keep it quiet
+        return (uint16_t)((b >> 16) | 0x40u);
+    return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__global__ void split_kernel(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ hi,
+                             uint16_t* __restrict__ lo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = x[i];
+    const uint16_t h = rne_bf16(v);
+    hi[i] = h;
+    lo[i] = rne_bf16(v - bf16_to_f32(h));
+}
+
+__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void zero_bytes_kernel(unsigned char* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream) {
+    hipLaunchKernelGGL(split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, n, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream) {
+    if (bytes <= 0) return hipSuccess;
+    if ((reinterpret_cast<uintptr_t>(p) & 3) == 0 && bytes % 4 == 0) {
+        const int64_t words = bytes / 4;
+        const int64_t blocks = std::min<int64_t>((words + 255) / 256, 4096);
+        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           static_cast<uint32_t*>(p), words);
+    } else {
+        hipLaunchKernelGGL(zero_bytes_kernel, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, stream,
+                           static_cast<unsigned char*>(p), bytes);
+    }
+    return hipGetLastError();
+}
+
+size_t bf16_group_workspace(int m, int d, int mp, int ops) {
+    (void)m; (void)d; (void)mp; (void)ops;
+    return 0;
+}
+
+hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream_t stream) {
+    (void)p; (void)b0; (void)nb; (void)ws; (void)stream;
+    return hipErrorNotSupported;
+}
+
+}  // namespace rot

@@ -1,0 +1,383 @@
+// Batched GEMM kernels on CDNA4 matrix cores (FP32 and FP64), the two
+// contractions of the operator rotation (stage 1: T_b = O_b U_r; stage 2:
+// out_b = U^T T_b) and of its adjoint.
+//
+// Tiling: a 256-thread workgroup (four 64-wide waves in a 2 x 2 grid) owns a
+// 128 x 128 tile of C and walks K in slices of 16 (FP32) or 16 (FP64)
+// elements, double-buffered in LDS.  Each operand slice is stored in LDS in
+// the same orientation it has in global memory, so the global -> LDS copy
+// is a plain 16-byte vector copy; the assignment of k to matrix-instruction
+// slots is permuted instead: in every slice, lane group h of a wave handles
+// k = h*(slice/groups) + j for step j, for both operands.  A K-contiguous
+// operand is then read with 128-bit LDS loads (all steps of the slice at
+// once) and an M/N-contiguous one with 32/64-bit loads that are contiguous
+// across the 32 (or 16) lanes of a group.
+//
+// Workgroup ids are remapped so that each of the 8 XCDs (hardware assigns
+// consecutive ids round-robin over them) processes a contiguous range of
+// tiles, and tiles sharing an operand panel stay on one XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include "rot_internal.h"
+
+namespace rot {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kTile = 128;   // BM = BN
+constexpr int kSlice = 16;   // K elements per LDS slice
+constexpr int kPadK = 4;     // row padding (elements) of K-contiguous LDS tiles
+constexpr int kPadMN = 4;    // row padding (elements) of M/N-contiguous LDS tiles
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef f32x4 type; };
+template <> struct Vec16<double> { typedef f64x2 type; };
+
+// XCD-aware workgroup order: hardware places workgroup id w on XCD w % 8.
+__device__ inline int xcd_linear_id() {
+    const int nwg = gridDim.x, wg = blockIdx.x;
+    const int per = nwg / 8, rem = nwg % 8;
+    const int xcd = wg % 8, idx = wg / 8;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// One operand slice of R rows (M or N extent) by kSlice k-columns, staged
+// through registers (16-byte chunks) into LDS.
+template <typename T, bool KCONTIG, bool VEC>
+struct Slice {
+    typedef typename Vec16<T>::type V;
+    static constexpr int VW = 16 / sizeof(T);
+    static constexpr int CHUNKS = kTile * kSlice / VW / kThreads;
+    static constexpr int PITCH = KCONTIG ? (kSlice + kPadK) : (kTile + kPadMN);
+    static constexpr int ELEMS = KCONTIG ? kTile * PITCH : kSlice * PITCH;
+    V r[CHUNKS];
+
+    // base points at element (row 0, k 0) of the operand; rows/ks are the
+    // operand's full extents; r0/k0 the slice origin.
+    __device__ inline void load(const T* __restrict__ base, int64_t ld, int r0, int rows, int k0,
+                                int ks, int tid) {
+#pragma unroll
+        for (int c = 0; c < CHUNKS; c++) {
+            const int f = tid + c * kThreads;
+            int row, k;
+            if (KCONTIG) {
+                row = f / (kSlice / VW);
+                k = (f % (kSlice / VW)) * VW;
+            } else {
+                k = f / (kTile / VW);
+                row = (f % (kTile / VW)) * VW;
+            }
+            const int gr = r0 + row, gk = k0 + k;
+            // element (row+e or k+e) of this chunk lies along the contiguous dim
+            const bool full = KCONTIG ? (gr < rows && gk + VW <= ks) : (gk < ks && gr + VW <= rows);
+            const T* p = KCONTIG ? base + (int64_t)gr * ld + gk : base + (int64_t)gk * ld + gr;
+            if (VEC && full) {
+                r[c] = *reinterpret_cast<const V*>(p);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VW; e++) {
+                    const bool ok = KCONTIG ? (gr < rows && gk + e < ks) : (gk < ks && gr + e < rows);
+                    r[c][e] = ok ? p[e] : T(0);
+                }
+            }
+        }
+    }
+    __device__ inline void store(T* lds, int tid) const {
+#pragma unroll
+        for (int c = 0; c < CHUNKS; c++) {
+            const int f = tid + c * kThreads;
+            int off;
+            if (KCONTIG) {
+                off = (f / (kSlice / VW)) * PITCH + (f % (kSlice / VW)) * VW;
+            } else {
+                off = (f / (kTile / VW)) * PITCH + (f % (kTile / VW)) * VW;
+            }
+            *reinterpret_cast<V*>(lds + off) = r[c];
+        }
+    }
+};
+
+struct TileCoord {
+    int g, m0, n0;
+};
+
+__device__ inline TileCoord tile_coord(int lin, int tiles_m, int tiles_n) {
+    TileCoord t;
+    const int per_batch = tiles_m * tiles_n;
+    t.g = lin / per_batch;
+    const int r = lin % per_batch;
+    t.m0 = (r % tiles_m) * kTile;  // M tiles fastest: neighbours share the B panel
+    t.n0 = (r / tiles_m) * kTile;
+    return t;
+}
+
+// ---------------------------------------------------------------- FP32 ----
+// v_mfma_f32_32x32x2f32: lane l supplies A(row l%32, k l/32), B(k l/32, col
+// l%32); accumulator element v of lane l is C(8*(v/4) + 4*(l/32) + v%4, l%32).
+template <bool AK, bool BK, bool VEC, bool ACC>
+__global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tiles_m, int tiles_n) {
+    typedef Slice<float, AK, VEC> SA;
+    typedef Slice<float, BK, VEC> SB;
+    __shared__ __attribute__((aligned(16))) float As[2][SA::ELEMS];
+    __shared__ __attribute__((aligned(16))) float Bs[2][SB::ELEMS];
+
+    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int h = lane >> 5, c = lane & 31;
+
+    const float* Ab = static_cast<const float*>(g.A) + (int64_t)tc.g * g.a_bs;
+    const float* Bb = static_cast<const float*>(g.B) + (int64_t)tc.g * g.b_bs;
+    const int nk = (g.K + kSlice - 1) / kSlice;
+    const int total = nk * g.kbatch;
+
+    SA la;
+    SB lb;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
+
+    auto fetch = [&](int t) {
+        const int kb = t / nk, k0 = (t % nk) * kSlice;
+        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, g.K, tid);
+        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, g.K, tid);
+    };
+
+    fetch(0);
+    la.store(As[0], tid);
+    lb.store(Bs[0], tid);
+    __syncthreads();
+
+    for (int t = 0; t < total; t++) {
+        const int cur = t & 1;
+        if (t + 1 < total) fetch(t + 1);
+        const float* a_s = As[cur];
+        const float* b_s = Bs[cur];
+        // 8 steps of k = 2: lane group h takes k = h*8 + j at step j
+        float av[2][8], bv[2][8];
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const int row = wm * 64 + i * 32 + c;
+            if (AK) {
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + row * SA::PITCH + h * 8);
+                const f32x4 x1 = *reinterpret_cast<const f32x4*>(a_s + row * SA::PITCH + h * 8 + 4);
+#pragma unroll
+                for (int e = 0; e < 4; e++) { av[i][e] = x0[e]; av[i][4 + e] = x1[e]; }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; j++) av[i][j] = a_s[(h * 8 + j) * SA::PITCH + row];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const int col = wn * 64 + i * 32 + c;
+            if (BK) {
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + col * SB::PITCH + h * 8);
+                const f32x4 x1 = *reinterpret_cast<const f32x4*>(b_s + col * SB::PITCH + h * 8 + 4);
+#pragma unroll
+                for (int e = 0; e < 4; e++) { bv[i][e] = x0[e]; bv[i][4 + e] = x1[e]; }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; j++) bv[i][j] = b_s[(h * 8 + j) * SB::PITCH + col];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int k = 0; k < 2; k++)
+                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][j], bv[k][j], acc[i][k], 0, 0, 0);
+        if (t + 1 < total) {
+            la.store(As[cur ^ 1], tid);
+            lb.store(Bs[cur ^ 1], tid);
+        }
+        __syncthreads();
+    }
+
+    float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int col = tc.n0 + wn * 64 + k * 32 + c;
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int row = tc.m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                if (row < g.M) {
+                    float* p = Cb + (int64_t)row * g.ldc + col;
+                    *p = ACC ? *p + acc[i][k][v] : acc[i][k][v];
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------- FP64 ----
+// v_mfma_f64_16x16x4f64: lane l supplies A(row l%16, k l/16), B(k l/16, col
+// l%16); accumulator element v of lane l is C(4*v + l/16, l%16).
+template <bool AK, bool BK, bool VEC, bool ACC>
+__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tiles_m, int tiles_n) {
+    typedef Slice<double, AK, VEC> SA;
+    typedef Slice<double, BK, VEC> SB;
+    __shared__ __attribute__((aligned(16))) double As[2][SA::ELEMS];
+    __shared__ __attribute__((aligned(16))) double Bs[2][SB::ELEMS];
+
+    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int h = lane >> 4, c = lane & 15;
+
+    const double* Ab = static_cast<const double*>(g.A) + (int64_t)tc.g * g.a_bs;
+    const double* Bb = static_cast<const double*>(g.B) + (int64_t)tc.g * g.b_bs;
+    const int nk = (g.K + kSlice - 1) / kSlice;
+    const int total = nk * g.kbatch;
+
+    SA la;
+    SB lb;
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) acc[i][j][v] = 0.0;
+
+    auto fetch = [&](int t) {
+        const int kb = t / nk, k0 = (t % nk) * kSlice;
+        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, g.K, tid);
+        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, g.K, tid);
+    };
+
+    fetch(0);
+    la.store(As[0], tid);
+    lb.store(Bs[0], tid);
+    __syncthreads();
+
+    for (int t = 0; t < total; t++) {
+        const int cur = t & 1;
+        if (t + 1 < total) fetch(t + 1);
+        const double* a_s = As[cur];
+        const double* b_s = Bs[cur];
+        // 4 steps of k = 4: lane group h takes k = h*4 + j at step j
+        double av[4][4], bv[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int row = wm * 64 + i * 16 + c;
+            if (AK) {
+                const f64x2 x0 = *reinterpret_cast<const f64x2*>(a_s + row * SA::PITCH + h * 4);
+                const f64x2 x1 = *reinterpret_cast<const f64x2*>(a_s + row * SA::PITCH + h * 4 + 2);
+                av[i][0] = x0[0]; av[i][1] = x0[1]; av[i][2] = x1[0]; av[i][3] = x1[1];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; j++) av[i][j] = a_s[(h * 4 + j) * SA::PITCH + row];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int col = wn * 64 + i * 16 + c;
+            if (BK) {
+                const f64x2 x0 = *reinterpret_cast<const f64x2*>(b_s + col * SB::PITCH + h * 4);
+                const f64x2 x1 = *reinterpret_cast<const f64x2*>(b_s + col * SB::PITCH + h * 4 + 2);
+                bv[i][0] = x0[0]; bv[i][1] = x0[1]; bv[i][2] = x1[0]; bv[i][3] = x1[1];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; j++) bv[i][j] = b_s[(h * 4 + j) * SB::PITCH + col];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    acc[i][k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][j], bv[k][j], acc[i][k], 0, 0, 0);
+        if (t + 1 < total) {
+            la.store(As[cur ^ 1], tid);
+            lb.store(Bs[cur ^ 1], tid);
+        }
+        __syncthreads();
+    }
+
+    double* Cb = static_cast<double*>(g.C) + (int64_t)tc.g * g.c_bs;
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int col = tc.n0 + wn * 64 + k * 16 + c;
+            if (col >= g.N) continue;
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int row = tc.m0 + wm * 64 + i * 16 + 4 * v + h;
+                if (row < g.M) {
+                    double* p = Cb + (int64_t)row * g.ldc + col;
+                    *p = ACC ? *p + acc[i][k][v] : acc[i][k][v];
+                }
+            }
+        }
+}
+
+template <typename T>
+bool vector_ok(const GemmDesc& g) {
+    const int64_t vw = 16 / sizeof(T);
+    auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    return al(g.A) && al(g.B) && g.lda % vw == 0 && g.ldb % vw == 0 && g.a_bs % vw == 0 &&
+           g.b_bs % vw == 0 && g.a_ks % vw == 0 && g.b_ks % vw == 0;
+}
+
+#define ROT_DISPATCH(KERNEL)                                                                       \
+    template <bool AK, bool BK, bool VEC>                                                          \
+    hipError_t launch_##KERNEL##_acc(const GemmDesc& g, dim3 grid, int tm, int tn, hipStream_t s) { \
+        if (g.accumulate)                                                                          \
+            hipLaunchKernelGGL((KERNEL<AK, BK, VEC, true>), grid, dim3(kThreads), 0, s, g, tm, tn); \
+        else                                                                                       \
+            hipLaunchKernelGGL((KERNEL<AK, BK, VEC, false>), grid, dim3(kThreads), 0, s, g, tm, tn); \
+        return hipGetLastError();                                                                  \
+    }                                                                                              \
+    template <bool AK, bool BK>                                                                    \
+    hipError_t launch_##KERNEL##_vec(const GemmDesc& g, bool vec, dim3 grid, int tm, int tn,       \
+                                     hipStream_t s) {                                              \
+        return vec ? launch_##KERNEL##_acc<AK, BK, true>(g, grid, tm, tn, s)                       \
+                   : launch_##KERNEL##_acc<AK, BK, false>(g, grid, tm, tn, s);                     \
+    }                                                                                              \
+    hipError_t launch_##KERNEL(const GemmDesc& g, bool vec, dim3 grid, int tm, int tn, hipStream_t s) { \
+        if (g.a_kcontig)                                                                           \
+            return g.b_kcontig ? launch_##KERNEL##_vec<true, true>(g, vec, grid, tm, tn, s)        \
+                               : launch_##KERNEL##_vec<true, false>(g, vec, grid, tm, tn, s);      \
+        return g.b_kcontig ? launch_##KERNEL##_vec<false, true>(g, vec, grid, tm, tn, s)           \
+                           : launch_##KERNEL##_vec<false, false>(g, vec, grid, tm, tn, s);         \
+    }
+
+ROT_DISPATCH(gemm_f32_kernel)
+ROT_DISPATCH(gemm_f64_kernel)
+#undef ROT_DISPATCH
+
+template <typename T>
+hipError_t gemm_any(const GemmDesc& g, hipStream_t stream) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+    const int tm = (g.M + kTile - 1) / kTile, tn = (g.N + kTile - 1) / kTile;
+    const int64_t tiles = (int64_t)tm * tn * g.batch;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)tiles);
+    const bool vec = vector_ok<T>(g);
+    if (sizeof(T) == 4) return launch_gemm_f32_kernel(g, vec, grid, tm, tn, stream);
+    return launch_gemm_f64_kernel(g, vec, grid, tm, tn, stream);
+}
+
+}  // namespace
+
+hipError_t gemm_f32(const GemmDesc& g, hipStream_t stream) { return gemm_any<float>(g, stream); }
+hipError_t gemm_f64(const GemmDesc& g, hipStream_t stream) { return gemm_any<double>(g, stream); }
+
+}  // namespace rot

@@ -1,0 +1,470 @@
+// Host side of librot: argument validation, workspace carving, operator
+// chunking and kernel dispatch for the C ABI declared in librot.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rot_internal.h"
+
+namespace rot {
+
+hipError_t split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream);
+size_t bf16_group_workspace(int m, int d, int mp, int ops);
+hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream_t stream);
+size_t blocked_workspace_bytes(const rot_blocked_problem* p);
+rot_status blocked_validate(const rot_blocked_problem* p, std::string* why);
+hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_bytes, hipStream_t stream);
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rot_status fail(rot_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+rot_status hip_fail(hipError_t e, const char* where) {
+    return fail(ROT_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+
+// ---- per-kernel event timing (rot_profile_enable / rot_profile_read) ----
+struct ProfRecord {
+    std::string name;
+    hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;
+
+template <class F>
+hipError_t timed(const char* name, hipStream_t s, F&& launch) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+    }
+    if (!on) return launch();
+    ProfRecord r{name, nullptr, nullptr};
+    hipError_t e = hipEventCreate(&r.start);
+    if (e == hipSuccess) e = hipEventCreate(&r.stop);
+    if (e == hipSuccess) e = hipEventRecord(r.start, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(r.stop, s);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(r);
+    return hipSuccess;
+}
+
+void prof_clear_locked() {
+    for (auto& r : g_prof) {
+        if (r.start) (void)hipEventDestroy(r.start);
+        if (r.stop) (void)hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
+}
+
+inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+size_t elem_size(rot_precision p) { return p == ROT_FP64 ? 8 : 4; }
+
+bool valid_precision(int p) { return p == ROT_FP64 || p == ROT_FP32 || p == ROT_SPLIT_BF16; }
+
+// Bytes of one operator's stage-1 intermediate T_b ((m*d) x mp).
+size_t t_bytes(const rot_problem& p, rot_precision prec) {
+    return align_up((size_t)p.m * p.d * p.mp * elem_size(prec));
+}
+
+rot_status validate_group(const rot_problem& p, int gi) {
+    if (p.m <= 0 || p.d <= 0 || p.mp <= 0)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: m, d, mp must be positive (m=%d d=%d mp=%d)", gi,
+                    p.m, p.d, p.mp);
+    const int64_t md = (int64_t)p.m * p.d, dmp = (int64_t)p.d * p.mp;
+    if (md > INT32_MAX || dmp > INT32_MAX)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: m*d or d*mp exceeds 2^31-1", gi);
+    if (p.mp > md) return fail(ROT_ERR_INVALID_ARG, "group %d: mp=%d exceeds m*d=%lld", gi, p.mp, (long long)md);
+    if (p.n_ops < 0) return fail(ROT_ERR_INVALID_ARG, "group %d: negative n_ops", gi);
+    if (p.n_ops == 0) return ROT_OK;
+    if (!p.U || !p.O || !p.out) return fail(ROT_ERR_INVALID_ARG, "group %d: null U, O or out", gi);
+    if (p.stride_o < (int64_t)p.m * p.m)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: stride_o %lld < m*m", gi, (long long)p.stride_o);
+    if (p.stride_out < (int64_t)p.mp * p.mp)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: stride_out %lld < mp*mp", gi, (long long)p.stride_out);
+    return ROT_OK;
+}
+
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+rot_status validate_outputs_disjoint(const rot_problem& p, rot_precision prec, int gi) {
+    const size_t es = elem_size(prec);
+    const size_t n_out = ((size_t)(p.n_ops - 1) * p.stride_out + (size_t)p.mp * p.mp) * es;
+    const size_t n_o = ((size_t)(p.n_ops - 1) * p.stride_o + (size_t)p.m * p.m) * es;
+    const size_t n_u = (size_t)p.m * p.d * p.mp * es;
+    if (ranges_overlap(p.out, n_out, p.O, n_o) || ranges_overlap(p.out, n_out, p.U, n_u))
+        return fail(ROT_ERR_INVALID_ARG, "group %d: out overlaps U or O", gi);
+    return ROT_OK;
+}
+
+// Stage 1: T_b = O_b * U_r for nb operators from b0 (T batch stride m*d*mp).
+GemmDesc stage1(const rot_problem& p, int b0, int nb, void* T, size_t es) {
+    GemmDesc g{};
+    g.M = p.m;
+    g.N = p.d * p.mp;
+    g.K = p.m;
+    g.batch = nb;
+    g.kbatch = 1;
+    g.A = static_cast<const char*>(p.O) + (size_t)b0 * p.stride_o * es;
+    g.lda = p.m;
+    g.a_bs = p.stride_o;
+    g.a_kcontig = true;  // O_b(i, j) at O_b[i*m + j]
+    g.B = p.U;
+    g.ldb = (int64_t)p.d * p.mp;
+    g.b_bs = 0;
+    g.b_kcontig = false;  // U_r(j, (s,beta)) at U[j*d*mp + s*mp + beta]
+    g.C = T;
+    g.ldc = (int64_t)p.d * p.mp;
+    g.c_bs = (int64_t)p.m * p.d * p.mp;
+    return g;
+}
+
+// Stage 2: out_b = U^T * T_b, T_b viewed as (m*d) x mp.
+GemmDesc stage2(const rot_problem& p, int b0, int nb, const void* T, size_t es) {
+    GemmDesc g{};
+    g.M = p.mp;
+    g.N = p.mp;
+    g.K = p.m * p.d;
+    g.batch = nb;
+    g.kbatch = 1;
+    g.A = p.U;
+    g.lda = p.mp;
+    g.a_bs = 0;
+    g.a_kcontig = false;  // A(alpha, r) = U[r*mp + alpha]
+    g.B = T;
+    g.ldb = p.mp;
+    g.b_bs = (int64_t)p.m * p.d * p.mp;
+    g.b_kcontig = false;  // T_b(r, beta) at T_b[r*mp + beta]
+    g.C = static_cast<char*>(p.out) + (size_t)b0 * p.stride_out * es;
+    g.ldc = p.mp;
+    g.c_bs = p.stride_out;
+    return g;
+}
+
+hipError_t gemm(rot_precision prec, const GemmDesc& g, hipStream_t s, const char* what) {
+    const bool f64 = prec == ROT_FP64;
+    std::string name = std::string(what) + (f64 ? "_fp64" : "_fp32");
+    return timed(name.c_str(), s, [&] { return f64 ? gemm_f64(g, s) : gemm_f32(g, s); });
+}
+
+}  // namespace
+}  // namespace rot
+
+using namespace rot;
+
+extern "C" {
+
+const char* rot_status_string(rot_status s) {
+    switch (s) {
+        case ROT_OK: return "ROT_OK";
+        case ROT_ERR_INVALID_ARG: return "ROT_ERR_INVALID_ARG";
+        case ROT_ERR_UNSUPPORTED: return "ROT_ERR_UNSUPPORTED";
+        case ROT_ERR_WORKSPACE: return "ROT_ERR_WORKSPACE";
+        case ROT_ERR_HIP: return "ROT_ERR_HIP";
+        case ROT_ERR_NOT_ISOMETRY: return "ROT_ERR_NOT_ISOMETRY";
+    }
+    return "unknown rot_status";
+}
+
+const char* rot_last_error(void) { return g_last_error.c_str(); }
+
+rot_status rot_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (on) prof_clear_locked();
+    g_prof_on = on != 0;
+    return ROT_OK;
+}
+
+int32_t rot_profile_read(char* buf, size_t len) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::map<std::string, std::pair<int, double>> agg;
+    int32_t rc = 0;
+    for (auto& r : g_prof) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+            rc = -1;
+            continue;
+        }
+        auto& a = agg[r.name];
+        a.first += 1;
+        a.second += ms;
+    }
+    prof_clear_locked();
+    std::string out;
+    char line[256];
+    for (auto& kv : agg) {
+        snprintf(line, sizeof(line), "%s %d %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+        out += line;
+    }
+    if (buf && len) {
+        const size_t n = std::min(len - 1, out.size());
+        memcpy(buf, out.data(), n);
+        buf[n] = 0;
+    }
+    return rc < 0 ? rc : (int32_t)agg.size();
+}
+
+int32_t rot_version(void) { return 100; }
+
+size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_precision prec,
+                          int32_t ops_per_chunk, int32_t for_backward) {
+    if (n_groups < 0 || (n_groups > 0 && !groups) || !valid_precision(prec)) return 0;
+    size_t need = 0;
+    for (int gi = 0; gi < n_groups; gi++) {
+        const rot_problem& p = groups[gi];
+        if (validate_group(p, gi) != ROT_OK) return 0;
+        if (p.n_ops == 0) continue;
+        const int ops = ops_per_chunk > 0 ? std::min(ops_per_chunk, p.n_ops) : p.n_ops;
+        size_t g;
+        if (prec == ROT_SPLIT_BF16 && !for_backward)
+            g = bf16_group_workspace(p.m, p.d, p.mp, ops);
+        else
+            g = (size_t)ops * t_bytes(p, prec == ROT_FP64 ? ROT_FP64 : ROT_FP32);
+        need = std::max(need, g);
+    }
+    return need;
+}
+
+rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision prec, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+    if (n_groups < 0 || (n_groups > 0 && !groups))
+        return fail(ROT_ERR_INVALID_ARG, "groups is null or n_groups negative");
+    if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    for (int gi = 0; gi < n_groups; gi++) {
+        rot_status s = validate_group(groups[gi], gi);
+        if (s != ROT_OK) return s;
+        if (groups[gi].n_ops > 0) {
+            s = validate_outputs_disjoint(groups[gi], prec, gi);
+            if (s != ROT_OK) return s;
+        }
+    }
+    const size_t min_ws = rot_workspace_size(groups, n_groups, prec, 1, 0);
+    if (min_ws > 0) {
+        if (!workspace) return fail(ROT_ERR_WORKSPACE, "workspace is null (need %zu bytes)", min_ws);
+        if (workspace_bytes < min_ws)
+            return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, min_ws);
+        if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+            return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t es = elem_size(prec);
+    for (int gi = 0; gi < n_groups; gi++) {
+        const rot_problem& p = groups[gi];
+        if (p.n_ops == 0) continue;
+        if (prec == ROT_SPLIT_BF16) {
+            int chunk = 1;
+            while (chunk < p.n_ops && bf16_group_workspace(p.m, p.d, p.mp, chunk + 1) <= workspace_bytes)
+                chunk++;
+            for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
+                const int nb = std::min(chunk, p.n_ops - b0);
+                hipError_t e = rotate_bf16(p, b0, nb, workspace, s);
+                if (e != hipSuccess) return hip_fail(e, "rot_batch split-bf16");
+            }
+            continue;
+        }
+        const size_t per_op = t_bytes(p, prec);
+        const int chunk = (int)std::min<size_t>((size_t)p.n_ops, workspace_bytes / per_op);
+        for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
+            const int nb = std::min(chunk, p.n_ops - b0);
+            hipError_t e = gemm(prec, stage1(p, b0, nb, workspace, es), s, "stage1");
+            if (e == hipSuccess) e = gemm(prec, stage2(p, b0, nb, workspace, es), s, "stage2");
+            if (e != hipSuccess) return hip_fail(e, "rot_batch launch");
+        }
+    }
+    return ROT_OK;
+}
+
+rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void* const* dOut,
+                        const int64_t* stride_dout, void* const* dO, void* const* dU, uint32_t flags,
+                        rot_precision prec, void* workspace, size_t workspace_bytes, void* stream) {
+    if (n_groups < 0 || (n_groups > 0 && (!groups || !dOut || !stride_dout)))
+        return fail(ROT_ERR_INVALID_ARG, "null groups/dOut/stride_dout or negative n_groups");
+    if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (prec == ROT_SPLIT_BF16) return fail(ROT_ERR_UNSUPPORTED, "rot_backward: split-bf16 not implemented; use ROT_FP32");
+    if (flags & ~ROT_ASSUME_SYMMETRIC_O) return fail(ROT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    for (int gi = 0; gi < n_groups; gi++) {
+        const rot_problem& p = groups[gi];
+        rot_status st = validate_group(p, gi);
+        if (st != ROT_OK) return st;
+        if (p.n_ops == 0) continue;
+        if (!dOut[gi]) return fail(ROT_ERR_INVALID_ARG, "group %d: null dOut", gi);
+        if (stride_dout[gi] != 0 && stride_dout[gi] < (int64_t)p.mp * p.mp)
+            return fail(ROT_ERR_INVALID_ARG, "group %d: stride_dout must be 0 or >= mp*mp", gi);
+    }
+    const size_t min_ws = rot_workspace_size(groups, n_groups, prec, 1, 1);
+    if (min_ws > 0) {
+        if (!workspace || workspace_bytes < min_ws)
+            return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, min_ws);
+        if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+            return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t es = elem_size(prec);
+    const bool sym = flags & ROT_ASSUME_SYMMETRIC_O;
+    for (int gi = 0; gi < n_groups; gi++) {
+        const rot_problem& p = groups[gi];
+        void* dOg = dO ? dO[gi] : nullptr;
+        void* dUg = dU ? dU[gi] : nullptr;
+        if (p.n_ops == 0) {
+            if (dUg) {
+                hipError_t e = fill_zero(dUg, (int64_t)p.m * p.d * p.mp * es, s);
+                if (e != hipSuccess) return hip_fail(e, "rot_backward zero dU");
+            }
+            continue;
+        }
+        const int64_t md = (int64_t)p.m * p.d, tsz = md * p.mp;
+        const size_t per_op = t_bytes(p, prec);
+        const int chunk = (int)std::min<size_t>((size_t)p.n_ops, workspace_bytes / per_op);
+        const char* dout_base = static_cast<const char*>(dOut[gi]);
+        const int64_t sd = stride_dout[gi];
+        for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
+            const int nb = std::min(chunk, p.n_ops - b0);
+            const void* g_b0 = dout_base + (size_t)b0 * sd * es;
+            hipError_t e = hipSuccess;
+            if (dOg) {
+                // P_b = U dOut_b   ((m*d) x mp)
+                GemmDesc a{};
+                a.M = (int)md; a.N = p.mp; a.K = p.mp; a.batch = nb; a.kbatch = 1;
+                a.A = p.U; a.lda = p.mp; a.a_bs = 0; a.a_kcontig = true;
+                a.B = g_b0; a.ldb = p.mp; a.b_bs = sd; a.b_kcontig = false;
+                a.C = workspace; a.ldc = p.mp; a.c_bs = tsz;
+                e = gemm(prec, a, s, "adj_P");
+                // dO_b = P_b (m x d*mp) * U_r^T
+                GemmDesc b{};
+                b.M = p.m; b.N = p.m; b.K = p.d * p.mp; b.batch = nb; b.kbatch = 1;
+                b.A = workspace; b.lda = (int64_t)p.d * p.mp; b.a_bs = tsz; b.a_kcontig = true;
+                b.B = p.U; b.ldb = (int64_t)p.d * p.mp; b.b_bs = 0; b.b_kcontig = true;
+                b.C = static_cast<char*>(dOg) + (size_t)b0 * p.m * p.m * es; b.ldc = p.m;
+                b.c_bs = (int64_t)p.m * p.m;
+                if (e == hipSuccess) e = gemm(prec, b, s, "adj_dO");
+            }
+            if (dUg && e == hipSuccess) {
+                // T_b = O_b U_r, then dU (+)= sum_b T_b dOut_b^T
+                e = gemm(prec, stage1(p, b0, nb, workspace, es), s, "adj_T");
+                GemmDesc c{};
+                c.M = (int)md; c.N = p.mp; c.K = p.mp; c.batch = 1; c.kbatch = nb;
+                c.A = workspace; c.lda = p.mp; c.a_ks = tsz; c.a_kcontig = true;
+                c.B = g_b0; c.ldb = p.mp; c.b_ks = sd; c.b_kcontig = true;  // B(beta, alpha) = dOut[alpha][beta]
+                c.C = dUg; c.ldc = p.mp; c.accumulate = b0 > 0;
+                if (e == hipSuccess) e = gemm(prec, c, s, "adj_dU");
+                if (!sym && e == hipSuccess) {
+                    // T~_b = O_b^T U_r
+                    GemmDesc t = stage1(p, b0, nb, workspace, es);
+                    t.a_kcontig = false;  // A(i, j) = O_b[j*m + i]
+                    e = gemm(prec, t, s, "adj_Tt");
+                }
+                // dU += sum_b T~_b dOut_b   (T~ = T when O is symmetric)
+                c.b_kcontig = false;  // B(beta, alpha) = dOut[beta][alpha]
+                c.accumulate = true;
+                if (e == hipSuccess) e = gemm(prec, c, s, "adj_dU");
+            }
+            if (e != hipSuccess) return hip_fail(e, "rot_backward launch");
+        }
+    }
+    return ROT_OK;
+}
+
+size_t rot_pair_loss_workspace_size(int32_t mp, int32_t n_ops) {
+    if (mp <= 0 || n_ops <= 0) return 0;
+    return pair_loss_workspace_bytes(mp, n_ops);
+}
+
+rot_status rot_pair_loss(const void* X, int32_t mp, int32_t n_ops, int64_t stride_x, rot_precision prec,
+                         const double* psi, double* loss, double* pairs, void* grad, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+    if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (mp <= 0 || n_ops <= 0 || n_ops > 65535)
+        return fail(ROT_ERR_INVALID_ARG, "need mp > 0 and 0 < n_ops <= 65535");
+    if (!X || !psi || !loss) return fail(ROT_ERR_INVALID_ARG, "null X, psi or loss");
+    if (stride_x < (int64_t)mp * mp) return fail(ROT_ERR_INVALID_ARG, "stride_x < mp*mp");
+    const size_t need = pair_loss_workspace_bytes(mp, n_ops);
+    if (!workspace || workspace_bytes < need)
+        return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
+    hipError_t e = pair_loss(X, mp, n_ops, stride_x, prec == ROT_FP64, psi, loss, pairs, grad, workspace,
+                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ROT_OK : hip_fail(e, "rot_pair_loss launch");
+}
+
+size_t rot_isometry_workspace_size(int32_t rows, int32_t cols, rot_precision prec) {
+    if (rows <= 0 || cols <= 0 || !valid_precision(prec)) return 0;
+    return isometry_workspace_bytes(rows, cols, prec == ROT_FP64);
+}
+
+rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, rot_precision prec, double tol,
+                              double* max_dev_host, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (!U || !max_dev_host || rows <= 0 || cols <= 0 || cols > rows)
+        return fail(ROT_ERR_INVALID_ARG, "need U, max_dev_host and 0 < cols <= rows");
+    const size_t need = isometry_workspace_bytes(rows, cols, prec == ROT_FP64);
+    if (!workspace || workspace_bytes < need)
+        return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* ws = static_cast<double*>(workspace);
+    hipError_t e = isometry_deviation(U, rows, cols, prec == ROT_FP64, ws, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(max_dev_host, ws, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rot_check_isometry");
+    if (!(*max_dev_host <= tol))
+        return fail(ROT_ERR_NOT_ISOMETRY, "max|U^T U - I| = %.3e exceeds tol %.3e", *max_dev_host, tol);
+    return ROT_OK;
+}
+
+rot_status rot_split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, void* stream) {
+    if (n < 0 || (n > 0 && (!x || !hi || !lo))) return fail(ROT_ERR_INVALID_ARG, "null buffer or n < 0");
+    if (n == 0) return ROT_OK;
+    hipError_t e = split_bf16(x, n, hi, lo, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ROT_OK : hip_fail(e, "rot_split_bf16 launch");
+}
+
+size_t rot_blocked_workspace_size(const rot_blocked_problem* p) {
+    std::string why;
+    if (!p || blocked_validate(p, &why) != ROT_OK) return 0;
+    return blocked_workspace_bytes(p);
+}
+
+rot_status rot_batch_blocked(const rot_blocked_problem* p, rot_precision prec, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+    if (!p) return fail(ROT_ERR_INVALID_ARG, "null problem");
+    if (prec != ROT_FP32) return fail(ROT_ERR_UNSUPPORTED, "rot_batch_blocked supports ROT_FP32 only");
+    std::string why;
+    rot_status st = blocked_validate(p, &why);
+    if (st != ROT_OK) return fail(st, "%s", why.c_str());
+    const size_t need = blocked_workspace_bytes(p);
+    if (need > 0 && (!workspace || workspace_bytes < need))
+        return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
+    hipError_t e = rotate_blocked(p, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ROT_OK : hip_fail(e, "rot_batch_blocked");
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Internal declarations of librot (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "librot.h"
+
+namespace rot {
+
+// Batched, K-batched GEMM on row-major operands:
+//   C[g] (M x N) (+)= alpha_sign * sum_{kb < kbatch} A[g,kb] (M x K) * B[g,kb] (K x N)
+// Operand layouts:
+//   a_kcontig: A(m,k) at A[m*lda + k]   else A(m,k) at A[k*lda + m]
+//   b_kcontig: B(k,n) at B[n*ldb + k]   else B(k,n) at B[k*ldb + n]
+// Element (batch g, k-batch kb) bases: A + g*a_bs + kb*a_ks (same for B).
+// C[g] at C + g*c_bs with leading dimension ldc.  accumulate: C += result.
+struct GemmDesc {
+    int M, N, K;
+    int batch, kbatch;
+    const void* A;
+    int64_t lda, a_bs, a_ks;
+    const void* B;
+    int64_t ldb, b_bs, b_ks;
+    void* C;
+    int64_t ldc, c_bs;
+    bool a_kcontig, b_kcontig, accumulate;
+};
+
+// Enqueue on `stream`; returns hipSuccess or the launch error.
+hipError_t gemm_f32(const GemmDesc& g, hipStream_t stream);
+hipError_t gemm_f64(const GemmDesc& g, hipStream_t stream);
+
+// Zero `bytes` bytes with a fill kernel (safe under stream capture).
+hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream);
+
+// FP64 reductions (reduce_f64.hip).
+size_t pair_loss_workspace_bytes(int mp, int n_ops);
+hipError_t pair_loss(const void* X, int mp, int n_ops, int64_t stride, bool is_double,
+                     const double* psi, double* loss, double* pairs, void* grad, void* ws,
+                     hipStream_t stream);
+size_t isometry_workspace_bytes(int64_t rows, int cols, bool is_double);
+// Result (max |U^T U - I|) lands in ws[0] (device).
+hipError_t isometry_deviation(const void* U, int rows, int cols, bool is_double, double* ws,
+                              hipStream_t stream);
+
+}  // namespace rot

@@ -17,3 +17,23 @@ def oracle_mod():
     import oracle
     oracle.build()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU case on stderr before it runs, so a run that dies on the
+    device still says which case it was."""
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write(f"[gpu-case] {request.node.nodeid}\n")
+        sys.__stderr__.flush()
+    yield
+
+
+@pytest.fixture(scope="session")
+def rot():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0909_5662_amd as rot_mod
+    rot_mod.lib()  # raises if librot.so is missing: no silent fallback
+    return rot_mod

@@ -1,0 +1,112 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects invalid arguments on the host before any device work (these calls
+never reach the GPU, so they run without one)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "librot.h")
+
+
+@pytest.fixture(scope="module")
+def rotlib():
+    import paper_0909_5662_amd as rot
+    if not os.path.exists(rot.library_path):
+        pytest.fail("librot.so is not built (run python -m paper_0909_5662_amd.build)")
+    return rot
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^ROT_API\s+[\w\s\*]+?\b(rot_\w+)\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(rotlib):
+    names = declared_functions()
+    assert len(names) >= 12
+    L = rotlib.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version(rotlib):
+    L = rotlib.lib()
+    assert L.rot_status_string(0) == b"ROT_OK"
+    assert L.rot_status_string(-5) == b"ROT_ERR_NOT_ISOMETRY"
+    assert L.rot_version() >= 100
+
+
+FAKE = 1 << 20  # host-side stand-in addresses: validation compares, never dereferences
+
+
+def prob(rot, m=8, d=4, mp=8, n=2, U=FAKE, O=2 * FAKE, so=None, out=3 * FAKE, sout=None):
+    return rot.RotProblem(m, d, mp, n, U, O, m * m if so is None else so, out, mp * mp if sout is None else sout)
+
+
+@pytest.mark.parametrize("kw,expect", [
+    (dict(m=0), -1), (dict(d=0), -1), (dict(mp=0), -1), (dict(mp=33), -1), (dict(n=-1), -1),
+    (dict(U=0), -1), (dict(O=0), -1), (dict(out=0), -1), (dict(so=63), -1), (dict(sout=10), -1),
+    (dict(out=2 * FAKE + 8), -1),  # out overlaps O
+])
+def test_rot_batch_rejects_bad_groups(rotlib, kw, expect):
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib, **kw))
+    st = L.rot_batch(arr, 1, rotlib.ROT_FP32, 4 * FAKE, 1 << 30, None)
+    assert st == expect
+    assert L.rot_last_error()
+
+
+def test_rot_batch_workspace_and_precision_errors(rotlib):
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib))
+    need = L.rot_workspace_size(arr, 1, rotlib.ROT_FP32, 1, 0)
+    assert need == 8 * 4 * 8 * 4 or need >= 8 * 4 * 8 * 4
+    assert L.rot_batch(arr, 1, rotlib.ROT_FP32, 4 * FAKE, need - 1, None) == -3
+    assert L.rot_batch(arr, 1, rotlib.ROT_FP32, 0, need, None) == -3
+    assert L.rot_batch(arr, 1, rotlib.ROT_FP32, 4 * FAKE + 8, need, None) == -1  # misaligned
+    assert L.rot_batch(arr, 1, 7, 4 * FAKE, need, None) == -1
+    assert L.rot_batch(arr, -1, rotlib.ROT_FP32, 4 * FAKE, need, None) == -1
+    assert L.rot_batch(None, 1, rotlib.ROT_FP32, 4 * FAKE, need, None) == -1
+    # all-empty batches need no workspace and launch nothing
+    empty = (rotlib.RotProblem * 1)(prob(rotlib, n=0, U=0, O=0, out=0))
+    assert L.rot_workspace_size(empty, 1, rotlib.ROT_FP32, 0, 0) == 0
+    assert L.rot_batch(empty, 1, rotlib.ROT_FP32, 0, 0, None) == 0
+    assert L.rot_batch(None, 0, rotlib.ROT_FP32, 0, 0, None) == 0
+
+
+def test_workspace_size_scales_with_chunk(rotlib):
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib, m=100, mp=90, n=7))
+    one = L.rot_workspace_size(arr, 1, rotlib.ROT_FP32, 1, 0)
+    allops = L.rot_workspace_size(arr, 1, rotlib.ROT_FP32, 0, 0)
+    assert one >= 100 * 4 * 90 * 4 and allops == 7 * one
+    assert L.rot_workspace_size(arr, 1, rotlib.ROT_FP64, 1, 0) >= 2 * 100 * 4 * 90 * 4 - 256
+
+
+def test_backward_argument_errors(rotlib):
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib))
+    vp = ctypes.c_void_p
+    dout = (vp * 1)(5 * FAKE)
+    sd = (ctypes.c_int64 * 1)(0)
+    assert L.rot_backward(arr, 1, dout, sd, None, None, 0, rotlib.ROT_SPLIT_BF16, 4 * FAKE, 1 << 30, None) == -2
+    assert L.rot_backward(arr, 1, dout, sd, None, None, 8, rotlib.ROT_FP32, 4 * FAKE, 1 << 30, None) == -1
+    sd_bad = (ctypes.c_int64 * 1)(3)
+    assert L.rot_backward(arr, 1, dout, sd_bad, None, None, 0, rotlib.ROT_FP32, 4 * FAKE, 1 << 30, None) == -1
+    assert L.rot_backward(arr, 1, dout, sd, None, None, 0, rotlib.ROT_FP32, 4 * FAKE, 16, None) == -3
+
+
+def test_reduction_argument_errors(rotlib):
+    L = rotlib.lib()
+    assert L.rot_pair_loss(FAKE, 0, 1, 1, 1, FAKE, FAKE, None, None, FAKE, 1 << 20, None) == -1
+    assert L.rot_pair_loss(FAKE, 8, 70000, 64, 1, FAKE, FAKE, None, None, FAKE, 1 << 30, None) == -1
+    assert L.rot_pair_loss(FAKE, 8, 2, 63, 1, FAKE, FAKE, None, None, FAKE, 1 << 30, None) == -1
+    assert L.rot_pair_loss(FAKE, 8, 2, 64, 1, FAKE, FAKE, None, None, FAKE, 8, None) == -3
+    dev = ctypes.c_double()
+    assert L.rot_check_isometry(FAKE, 4, 8, 1, 1e-6, ctypes.byref(dev), FAKE, 1 << 30, None) == -1
+    assert L.rot_check_isometry(FAKE, 8, 4, 1, 1e-6, ctypes.byref(dev), FAKE, 8, None) == -3
+    assert L.rot_split_bf16(None, 5, None, None, None) == -1
+    assert L.rot_split_bf16(None, 0, None, None, None) == 0

@@ -1,0 +1,262 @@
+"""GPU parity of the dense rotation, its adjoint, the FP64 pair reduction,
+the isometry check and the bf16 split, element by element against the
+oracle on the same seeded inputs (the oracle receives exactly the values the
+GPU receives, widened to FP64).
+
+Tolerances: relative Frobenius error per operator <= 1e-5 for FP32 and
+split-BF16, <= 1e-12 for FP64; bit-exact for the bf16 split."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-12
+
+
+def rel_fro(got, ref):
+    """Per-operator ||got - ref||_F / ||ref||_F over the leading axis."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    axes = tuple(range(1, ref.ndim))
+    return np.sqrt(((got - ref) ** 2).sum(axes)) / np.sqrt((ref ** 2).sum(axes))
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def run_rotate(rot, case, precision):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    U = to_dev(case.U, dt)
+    O = to_dev(case.O, dt)
+    out = rot.rotate(U, O, case.d, precision)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+# (m, d, mp, n): several 128-tiles plus ragged tails, odd leading dimensions
+# (scalar-load path), complete and heavily truncated U, d = 1.
+SHAPES = [
+    (200, 4, 150, 5),
+    (130, 4, 130, 3),
+    (64, 4, 64, 4),
+    (77, 3, 100, 3),
+    (33, 4, 132, 2),   # mp = m*d: nothing truncated
+    (257, 4, 1, 2),    # a single kept state
+    (1, 4, 3, 3),      # one old state
+    (150, 1, 90, 2),   # no added site
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_fp32_parity(rot, oracle_mod, shape, symmetric):
+    m, d, mp, n = shape
+    case = workloads.dense_case(m, d, mp, n, cfg=100 + m, dtype="f32", symmetric=symmetric)
+    got = run_rotate(rot, case, "fp32")
+    ref = oracle_mod.rotate(case.U, case.O, d)
+    err = rel_fro(got, ref)
+    assert err.max() <= TOL32, err
+
+
+@pytest.mark.parametrize("shape", SHAPES[:5])
+def test_fp64_parity(rot, oracle_mod, shape):
+    m, d, mp, n = shape
+    case = workloads.dense_case(m, d, mp, n, cfg=200 + m, dtype="f64", symmetric=False)
+    got = run_rotate(rot, case, "fp64")
+    ref = oracle_mod.rotate(case.U, case.O, d)
+    assert rel_fro(got, ref).max() <= TOL64
+
+
+def test_fp64_config_m64_full(rot, oracle_mod):
+    """The 64-state FP64 workload in full: 32 symmetric 64 x 64 operators."""
+    case = workloads.named_dense("dense_m64_f64")
+    got = run_rotate(rot, case, "fp64")
+    ref = oracle_mod.rotate(case.U, case.O, case.d)
+    assert rel_fro(got, ref).max() <= TOL64
+
+
+def sampled_parity(rot, oracle_mod, case, precision, per_op, tol, seed):
+    got = run_rotate(rot, case, precision)
+    rng = np.random.default_rng(seed)
+    n = case.O.shape[0]
+    worst = 0.0
+    for b in range(n):
+        al = rng.integers(0, case.mp, per_op)
+        be = rng.integers(0, case.mp, per_op)
+        ref = oracle_mod.rotate_entries(case.U, case.O[b], case.d, al, be)
+        # entries are compared against the operator's own scale: the
+        # Frobenius norm per entry, ||O'||_F / mp
+        scale = np.linalg.norm(got[b]) / case.mp
+        worst = max(worst, np.abs(got[b][al, be] - ref).max() / scale)
+    return got, worst
+
+
+def test_fp32_headline_m1024_sampled(rot, oracle_mod):
+    """m = m' = 1024, d = 4, 64 operators, in the configuration the benchmark
+    times; sampled entries against the oracle's entry-by-entry definition."""
+    case = workloads.named_dense("dense_m1024_n64")
+    got, worst = sampled_parity(rot, oracle_mod, case, "fp32", 24, TOL32, 1)
+    assert worst <= 20 * TOL32  # per-entry bound: loose vs the Frobenius bound
+    # symmetric operators rotate to symmetric operators (any size)
+    asym = np.abs(got - got.transpose(0, 2, 1)).max() / np.abs(got).max()
+    assert asym <= 1e-5
+
+
+def test_fp32_m512_n200_sampled(rot, oracle_mod):
+    case = workloads.named_dense("dense_m512_n200")
+    _, worst = sampled_parity(rot, oracle_mod, case, "fp32", 8, TOL32, 2)
+    assert worst <= 20 * TOL32
+
+
+def test_identity_operator_full_size(rot):
+    """O = I_m rotates to I_mp for an isometry U, at the headline size."""
+    m, d, mp = 1024, 4, 1024
+    U = workloads.isometry(m * d, mp, workloads.rng(5, 0))
+    Ut = to_dev(U, torch.float32)
+    O = torch.eye(m, device="cuda").unsqueeze(0).repeat(2, 1, 1)
+    out = rot.rotate(Ut, O, d, "fp32")
+    err = (out - torch.eye(mp, device="cuda")).abs().max().item()
+    assert err < 2e-5
+
+
+def test_padded_operator_stride(rot, oracle_mod):
+    """Operators spaced wider than m*m in memory (stride_o > m*m)."""
+    m, d, mp, n = 96, 4, 80, 3
+    case = workloads.dense_case(m, d, mp, n, cfg=300, symmetric=False)
+    U = to_dev(case.U, torch.float32)
+    big = torch.zeros((n, m * m + 37), dtype=torch.float32, device="cuda")
+    big[:, : m * m] = to_dev(case.O.reshape(n, -1), torch.float32)
+    out = torch.empty((n, mp * mp + 5), dtype=torch.float32, device="cuda")
+    p = rot.RotProblem(m, d, mp, n, U.data_ptr(), big.data_ptr(), m * m + 37, out.data_ptr(), mp * mp + 5)
+    need = rot.rot_workspace_size([p], rot.ROT_FP32)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rot.rot_batch([p], rot.ROT_FP32, ws.data_ptr(), need, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = out[:, : mp * mp].reshape(n, mp, mp).double().cpu().numpy()
+    assert rel_fro(got, oracle_mod.rotate(case.U, case.O, d)).max() <= TOL32
+
+
+def test_small_workspace_chunks(rot, oracle_mod):
+    """A workspace for one operator at a time gives the same result."""
+    m, d, mp, n = 130, 4, 120, 5
+    case = workloads.dense_case(m, d, mp, n, cfg=301)
+    U = to_dev(case.U, torch.float32)
+    O = to_dev(case.O, torch.float32)
+    out = torch.empty((n, mp, mp), device="cuda")
+    p = rot._problem(U, O, out, d)
+    one = rot.rot_workspace_size([p], rot.ROT_FP32, ops_per_chunk=1)
+    ws = torch.empty(one + 1000, dtype=torch.uint8, device="cuda")
+    rot.rot_batch([p], rot.ROT_FP32, ws.data_ptr(), one + 1000, torch.cuda.current_stream().cuda_stream)
+    full = rot.rotate(U, O, d, "fp32")
+    torch.cuda.synchronize()
+    assert torch.equal(out, full)
+    assert rel_fro(out.double().cpu().numpy(), oracle_mod.rotate(case.U, case.O, d)).max() <= TOL32
+
+
+def test_multiple_groups_one_call(rot, oracle_mod):
+    cases = [workloads.dense_case(m, 4, mp, n, cfg=400 + m) for (m, mp, n) in ((64, 60, 3), (140, 200, 2))]
+    tens = []
+    probs = []
+    for c in cases:
+        U = to_dev(c.U, torch.float32)
+        O = to_dev(c.O, torch.float32)
+        out = torch.empty((c.O.shape[0], c.mp, c.mp), device="cuda")
+        tens.append((U, O, out))
+        probs.append(rot._problem(U, O, out, c.d))
+    need = rot.rot_workspace_size(probs, rot.ROT_FP32)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rot.rot_batch(probs, rot.ROT_FP32, ws.data_ptr(), need, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    for c, (_, _, out) in zip(cases, tens):
+        assert rel_fro(out.double().cpu().numpy(), oracle_mod.rotate(c.U, c.O, c.d)).max() <= TOL32
+
+
+def test_zero_operators_is_noop(rot):
+    U = torch.zeros((8, 2), device="cuda")
+    p = rot.RotProblem(2, 4, 2, 0, U.data_ptr(), 0, 4, 0, 4)
+    rot.rot_batch([p], rot.ROT_FP32, 0, 0, torch.cuda.current_stream().cuda_stream)
+
+
+def test_deterministic(rot):
+    case = workloads.dense_case(256, 4, 200, 4, cfg=500)
+    U = to_dev(case.U, torch.float32)
+    O = to_dev(case.O, torch.float32)
+    a = rot.rotate(U, O, 4, "fp32")
+    for _ in range(3):
+        assert torch.equal(a, rot.rotate(U, O, 4, "fp32"))
+
+
+# ----------------------------------------------------------------- adjoint --
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("symmetric", [True, False])
+@pytest.mark.parametrize("shape", [(96, 4, 80, 3), (130, 3, 140, 2)])
+def test_adjoint_parity(rot, oracle_mod, precision, symmetric, shape):
+    m, d, mp, n = shape
+    case = workloads.dense_case(m, d, mp, n, cfg=600 + m, dtype="f32" if precision == "fp32" else "f64",
+                                symmetric=symmetric)
+    G = np.random.default_rng(7).standard_normal((n, mp, mp))
+    if precision == "fp32":
+        G = G.astype(np.float32).astype(np.float64)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    U, O, Gd = to_dev(case.U, dt), to_dev(case.O, dt), to_dev(G, dt)
+    dO, dU = rot.rotate_backward(U, O, d, Gd, precision, symmetric_O=symmetric)
+    torch.cuda.synchronize()
+    rdO, rdU = oracle_mod.adjoint(case.U, case.O, G, d)
+    tol = TOL32 if precision == "fp32" else TOL64
+    assert rel_fro(dO.double().cpu().numpy(), rdO).max() <= tol
+    assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= tol
+
+
+def test_adjoint_broadcast_gradient(rot, oracle_mod):
+    m, d, mp, n = 64, 4, 70, 4
+    case = workloads.dense_case(m, d, mp, n, cfg=650, symmetric=True)
+    G = np.random.default_rng(8).standard_normal((mp, mp)).astype(np.float32).astype(np.float64)
+    U, O, Gd = to_dev(case.U, torch.float32), to_dev(case.O, torch.float32), to_dev(G, torch.float32)
+    dO, dU = rot.rotate_backward(U, O, d, Gd, "fp32", symmetric_O=True)
+    torch.cuda.synchronize()
+    rdO, rdU = oracle_mod.adjoint(case.U, case.O, G, d)
+    assert rel_fro(dO.double().cpu().numpy(), rdO).max() <= TOL32
+    assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= TOL32
+
+
+# ------------------------------------------------------- FP64 reductions --
+
+@pytest.mark.parametrize("mp,n", [(130, 5), (1024, 8), (33, 1)])
+def test_pair_loss_parity(rot, oracle_mod, mp, n):
+    rng = np.random.default_rng(mp + n)
+    X = rng.standard_normal((n, mp, mp)).astype(np.float32).astype(np.float64)
+    psi = workloads.psi_vector(mp, rng)
+    L, pairs, grad = rot.pair_loss(to_dev(X, torch.float32), to_dev(psi, torch.float64), True, True)
+    torch.cuda.synchronize()
+    rL, rpairs, rgrad = oracle_mod.pair_loss(X, psi)
+    assert abs(L.item() - rL) <= 1e-12 * max(1.0, abs(rL)) * n
+    np.testing.assert_allclose(pairs.cpu().numpy(), rpairs, rtol=1e-11, atol=1e-12)
+    assert rel_fro(grad.double().cpu().numpy()[None], rgrad[None]).max() <= 1e-7  # grad stored as FP32
+
+
+def test_isometry_check(rot):
+    U = workloads.isometry(4096, 1024, workloads.rng(5, 0))
+    ok, dev = rot.check_isometry(to_dev(U, torch.float32))
+    assert ok and dev < 1e-6
+    ok64, dev64 = rot.check_isometry(to_dev(U, torch.float64), tol=1e-12)
+    assert ok64 and dev64 < 1e-13
+    bad = U.copy()
+    bad[:, 7] *= 1.001
+    ok_bad, dev_bad = rot.check_isometry(to_dev(bad, torch.float32))
+    assert not ok_bad and abs(dev_bad - (1.001 ** 2 - 1)) < 1e-5
+
+
+def test_bf16_split_bit_exact(rot, oracle_mod):
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(100003) * 10.0 ** rng.integers(-20, 20, 100003)).astype(np.float32)
+    hi, lo = rot.split_bf16(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    rhi, rlo = oracle_mod.bf16_split(x)
+    np.testing.assert_array_equal(hi.cpu().numpy().view(np.uint16), rhi)
+    np.testing.assert_array_equal(lo.cpu().numpy().view(np.uint16), rlo)
