@@ -177,6 +177,11 @@ hipError_t gemm(rot_precision prec, const GemmDesc& g, hipStream_t s, const char
 }
 
 }  // namespace
+
+hipError_t prof_timed(const char* name, hipStream_t stream, const std::function<hipError_t()>& launch) {
+    return timed(name, stream, launch);
+}
+
 }  // namespace rot
 
 using namespace rot;

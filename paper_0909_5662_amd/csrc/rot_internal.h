@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "librot.h"
 
 namespace rot {
@@ -26,6 +28,11 @@ struct GemmDesc {
     int64_t ldc, c_bs;
     bool a_kcontig, b_kcontig, accumulate;
 };
+
+// Runs `launch` (which enqueues kernels on `stream`); when per-kernel timing
+// is enabled (rot_profile_enable) it is bracketed by HIP events recorded on
+// `stream` and filed under `name`.
+hipError_t prof_timed(const char* name, hipStream_t stream, const std::function<hipError_t()>& launch);
 
 // Enqueue on `stream`; returns hipSuccess or the launch error.
 hipError_t gemm_f32(const GemmDesc& g, hipStream_t stream);

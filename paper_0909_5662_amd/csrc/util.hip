@@ -1,6 +1,9 @@
-// Split-BF16 operand format: x = hi + lo with hi = bf16(x), lo = bf16(x - hi),
-// both rounded to nearest even (x - hi is exact in FP32).
+// Element-wise utilities: the split-BF16 operand format (x = hi + lo with
+// hi = bf16(x), lo = bf16(x - hi), both rounded to nearest even; x - hi is
+// exact in FP32) and a zero-fill kernel that is safe under stream capture.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "rot_internal.h"
 
@@ -57,16 +60,6 @@ hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream) {
                            static_cast<unsigned char*>(p), bytes);
     }
     return hipGetLastError();
-}
-
-size_t bf16_group_workspace(int m, int d, int mp, int ops) {
-    (void)m; (void)d; (void)mp; (void)ops;
-    return 0;
-}
-
-hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream_t stream) {
-    (void)p; (void)b0; (void)nb; (void)ws; (void)stream;
-    return hipErrorNotSupported;
 }
 
 }  // namespace rot

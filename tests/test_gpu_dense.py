@@ -260,3 +260,50 @@ def test_bf16_split_bit_exact(rot, oracle_mod):
     rhi, rlo = oracle_mod.bf16_split(x)
     np.testing.assert_array_equal(hi.cpu().numpy().view(np.uint16), rhi)
     np.testing.assert_array_equal(lo.cpu().numpy().view(np.uint16), rlo)
+
+
+# -------------------------------------------------------------- split-BF16 --
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_split_bf16_parity(rot, oracle_mod, shape, symmetric):
+    m, d, mp, n = shape
+    case = workloads.dense_case(m, d, mp, n, cfg=700 + m, dtype="f32", symmetric=symmetric)
+    got = run_rotate(rot, case, "split_bf16")
+    ref = oracle_mod.rotate(case.U, case.O, d)
+    err = rel_fro(got, ref)
+    assert err.max() <= TOL32, err
+
+
+def test_split_bf16_headline_m1024_sampled(rot, oracle_mod):
+    case = workloads.named_dense("dense_m1024_n64")
+    got, worst = sampled_parity(rot, oracle_mod, case, "split_bf16", 24, TOL32, 3)
+    assert worst <= 20 * TOL32
+    asym = np.abs(got - got.transpose(0, 2, 1)).max() / np.abs(got).max()
+    assert asym <= 1e-5
+
+
+def test_split_bf16_full_frobenius_m512_subset(rot, oracle_mod):
+    """Full relative-Frobenius check on 8 operators of the 512-state
+    workload (the oracle's full cost is 5.4 GFLOP per operator)."""
+    case = workloads.named_dense("dense_m512_n200")
+    case.O = case.O[:8]
+    got = run_rotate(rot, case, "split_bf16")
+    ref = oracle_mod.rotate(case.U, case.O, case.d)
+    err = rel_fro(got, ref)
+    assert err.max() <= TOL32, err
+
+
+def test_split_bf16_chunked_equals_single_chunk(rot):
+    m, d, mp, n = 130, 4, 120, 5
+    case = workloads.dense_case(m, d, mp, n, cfg=701)
+    U = to_dev(case.U, torch.float32)
+    O = to_dev(case.O, torch.float32)
+    out = torch.empty((n, mp, mp), device="cuda")
+    p = rot._problem(U, O, out, d)
+    one = rot.rot_workspace_size([p], rot.ROT_SPLIT_BF16, ops_per_chunk=2)
+    ws = torch.empty(one, dtype=torch.uint8, device="cuda")
+    rot.rot_batch([p], rot.ROT_SPLIT_BF16, ws.data_ptr(), one, torch.cuda.current_stream().cuda_stream)
+    full = rot.rotate(U, O, d, "split_bf16")
+    torch.cuda.synchronize()
+    assert torch.equal(out, full)
