@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split-bf16", action="store_true",
+                    help="with --precision fp32, skip the split-BF16 measurement")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 GPU rotation (speedup denominator)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -60,6 +62,55 @@ def time_steps(rot, U, O, out, ws, d, precision, steps, warmup, profile):
     if profile:
         rot.profile_enable(False)
     return start.elapsed_time(stop), kernels
+
+
+def recorded_traffic(kernel_kind):
+    """HBM bytes per launch from the rocprofv3 counter runs recorded in
+    profiles/hbm_traffic.txt, or None when the kernel source has changed since
+    (its sha256 no longer matches) or no record exists."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        kind, src, sha, rd, wr = line.split()
+        if kind != kernel_kind:
+            continue
+        cur = hashlib.sha256(open(os.path.join(root, src), "rb").read()).hexdigest()[:16]
+        return int(rd) + int(wr) if cur == sha else None
+    return None
+
+
+def measure(rot, U, O, out, d, precision, steps, warmup):
+    """Time `steps` rotations of the batch; returns the figures for one precision."""
+    import torch
+    n, m, _ = O.shape
+    mp = U.shape[1]
+    p = rot._problem(U, O, out, d)
+    prec = rot.precision_code(precision)
+    ws = torch.empty(rot.rot_workspace_size([p], prec), dtype=torch.uint8, device=U.device)
+    ms, kernels = time_steps(rot, U, O, out, ws, d, precision, steps, warmup, True)
+    del ws
+    ops_per_s = n * steps / (ms / 1e3)
+    F = flops_per_op(m, d, mp)
+    tflops = F * ops_per_s / 1e12
+    peak = PEAK_TFLOPS[precision]
+    exec_factor = 3.0 if precision == "split_bf16" else 1.0
+    per_launch_flops = {"stage1": n * 2.0 * m * m * d * mp, "stage2": n * 2.0 * m * d * mp * mp}
+    stage_kernels = {k: v for k, v in kernels.items() if k.split("_")[0] in per_launch_flops}
+    dom_name, (dom_count, dom_ms) = max(stage_kernels.items(), key=lambda kv: kv[1][1])
+    dom_avg_ms = dom_ms / dom_count
+    achieved = per_launch_flops[dom_name.split("_")[0]] * exec_factor / (dom_avg_ms / 1e3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": recorded_traffic(dom_name),
+                "kernel": dom_name, "avg_ms": round(dom_avg_ms, 4)}
+    return {"ops_per_s": ops_per_s, "ms_per_step": ms / steps, "tflops": tflops,
+            "pct_mfma_peak": 100 * tflops * exec_factor / peak,
+            "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
+            "roofline": roofline}
 
 
 def cpu_baseline(case, n_total):
@@ -105,39 +156,16 @@ def main():
     U = torch.from_numpy(case.U).to(dt).to(dev)
     O = torch.from_numpy(case.O).to(dt).to(dev)
     out = torch.empty((n, mp, mp), dtype=dt, device=dev)
-    p = rot._problem(U, O, out, d)
-    prec = rot.precision_code(args.precision)
-    ws = torch.empty(rot.rot_workspace_size([p], prec), dtype=torch.uint8, device=dev)
-
-    ms, kernels = time_steps(rot, U, O, out, ws, d, args.precision, args.steps, args.warmup, True)
-    ms_per_step = ms / args.steps
-    ops_per_s = n * args.steps / (ms / 1e3)
-    F = flops_per_op(m, d, mp)
-    tflops = F * ops_per_s / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    exec_factor = 3.0 if args.precision == "split_bf16" else 1.0
-
-    # dominant kernel: the kind with the most total time in the timed region
-    per_launch_flops = {
-        "stage1": n * 2.0 * m * m * d * mp,
-        "stage2": n * 2.0 * m * d * mp * mp,
-    }
-    dom_name, (dom_count, dom_ms) = max(kernels.items(), key=lambda kv: kv[1][1])
-    base = dom_name.split("_")[0]
-    dom_avg_ms = dom_ms / dom_count
-    achieved = per_launch_flops.get(base, F * n / 2) * exec_factor / (dom_avg_ms / 1e3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom_name,
-                "avg_ms": round(dom_avg_ms, 4)}
+    main_run = measure(rot, U, O, out, d, args.precision, args.steps, args.warmup)
 
     result = {
         "metric": METRIC,
-        "value": round(ops_per_s, 2),
+        "value": round(main_run["ops_per_s"], 2),
         "unit": "operator rotations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(main_run["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -146,22 +174,28 @@ def main():
         "config": {"workload": WORKLOAD, "m": m, "d": d, "mp": mp, "n_ops": n,
                    "precision": args.precision, "operators": "symmetric Gaussian / sqrt(m)",
                    "U": "QR of seeded 4096x1024 Gaussian"},
-        "tflops": round(tflops, 2),
-        "pct_mfma_peak": round(100 * tflops * exec_factor / peak, 2),
-        "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
-        "roofline": roofline,
+        "tflops": round(main_run["tflops"], 2),
+        "pct_mfma_peak": round(main_run["pct_mfma_peak"], 2),
+        "kernels_ms_avg": main_run["kernels_ms_avg"],
+        "roofline": main_run["roofline"],
     }
+
+    if args.precision == "fp32" and not args.no_split_bf16:
+        b = measure(rot, U, O, out, d, "split_bf16", args.steps, args.warmup)
+        result["split_bf16"] = {"value": round(b["ops_per_s"], 2), "unit": "operator rotations/s",
+                                "ms_per_step": round(b["ms_per_step"], 4),
+                                "tflops_fp32_equivalent": round(b["tflops"], 2),
+                                "pct_bf16_mfma_peak": round(b["pct_mfma_peak"], 2),
+                                "speedup_vs_fp32": round(b["ops_per_s"] / main_run["ops_per_s"], 3),
+                                "kernels_ms_avg": b["kernels_ms_avg"], "roofline": b["roofline"]}
 
     if not args.no_fp64_reference and args.precision != "fp64":
         U64, O64 = U.double(), O.double()
         out64 = torch.empty((n, mp, mp), dtype=torch.float64, device=dev)
-        p64 = rot._problem(U64, O64, out64, d)
-        ws64 = torch.empty(rot.rot_workspace_size([p64], rot.ROT_FP64), dtype=torch.uint8, device=dev)
-        ms64, _ = time_steps(rot, U64, O64, out64, ws64, d, "fp64", max(2, args.steps // 5), 1, False)
-        fp64_ops = n * max(2, args.steps // 5) / (ms64 / 1e3)
-        result["fp64_gpu_ops_per_s"] = round(fp64_ops, 2)
-        result["speedup_vs_fp64_gpu"] = round(ops_per_s / fp64_ops, 3)
-        del U64, O64, out64, ws64
+        r64 = measure(rot, U64, O64, out64, d, "fp64", max(2, args.steps // 5), 1)
+        result["fp64_gpu_ops_per_s"] = round(r64["ops_per_s"], 2)
+        result["speedup_vs_fp64_gpu"] = round(main_run["ops_per_s"] / r64["ops_per_s"], 3)
+        del U64, O64, out64
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(case, n)
