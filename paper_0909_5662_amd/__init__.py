@@ -30,6 +30,7 @@ __all__ = [
     "rot_split_bf16", "rot_workspace_size", "rot_blocked_workspace_size",
     "rotate", "rotate_backward", "pair_loss", "check_isometry", "split_bf16",
     "RotateFn", "PairLossFn", "precision_code", "profile_enable", "profile_read",
+    "blocked_problem", "rotate_blocked",
 ]
 
 ROT_FP64, ROT_FP32, ROT_SPLIT_BF16 = 0, 1, 2
@@ -313,6 +314,58 @@ def split_bf16(x: torch.Tensor, stream=None):
     lo = torch.empty_like(hi)
     rot_split_bf16(x.data_ptr(), x.numel(), hi.data_ptr(), lo.data_ptr(), _stream(stream))
     return hi, lo
+
+
+def _sectors(table) -> ctypes.Array:
+    """(n, 3) rows (n_up, n_dn, dim) -> rot_sector array with prefix-sum offsets."""
+    arr = (RotSector * len(table))()
+    off = 0
+    for k, (u, d_, dim) in enumerate(table):
+        arr[k] = RotSector(int(u), int(d_), int(dim), off)
+        off += int(dim)
+    return arr
+
+
+def blocked_problem(site_qn, old, new, shift, U_blk: torch.Tensor, U_off, O_blk: torch.Tensor, O_off,
+                    out_off, out_blk: torch.Tensor):
+    """Build the rot_blocked_problem descriptor.  Tables are host sequences
+    (kept alive by the returned holder); block data are float32 device tensors."""
+    import numpy as np
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    keep = {
+        "site_qn": np.ascontiguousarray(site_qn, dtype=np.int32).ravel(),
+        "old": _sectors(old), "new": _sectors(new),
+        "U_off": np.ascontiguousarray(U_off, dtype=np.int64),
+        "shift": np.ascontiguousarray(shift, dtype=np.int32).ravel(),
+        "O_off": np.ascontiguousarray(O_off, dtype=np.int64),
+        "out_off": np.ascontiguousarray(out_off, dtype=np.int64),
+    }
+    for t in (U_blk, O_blk, out_blk):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("block data must be contiguous float32 device tensors")
+    p = RotBlockedProblem(
+        len(keep["site_qn"]) // 2, keep["site_qn"].ctypes.data_as(i32p),
+        len(old), keep["old"], len(new), keep["new"],
+        U_blk.data_ptr(), keep["U_off"].ctypes.data_as(i64p),
+        len(keep["shift"]) // 2, keep["shift"].ctypes.data_as(i32p),
+        O_blk.data_ptr(), keep["O_off"].ctypes.data_as(i64p),
+        out_blk.data_ptr(), keep["out_off"].ctypes.data_as(i64p))
+    return p, keep
+
+
+def rotate_blocked(site_qn, old, new, shift, U_blk, U_off, O_blk, O_off, out_off, out_blk,
+                   workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Quantum-number block-sparse rotation (FP32); writes and returns out_blk."""
+    p, keep = blocked_problem(site_qn, old, new, shift, U_blk, U_off, O_blk, O_off, out_off, out_blk)
+    need = rot_blocked_workspace_size(p)
+    if need == 0 and len(shift) > 0:
+        # invalid descriptor: let the call report why
+        need = 256
+    if workspace is None:
+        workspace = _workspace(need, U_blk.device)
+    rot_batch_blocked(p, ROT_FP32, workspace.data_ptr(), workspace.numel(), _stream(stream))
+    del keep
+    return out_blk
 
 
 class RotateFn(torch.autograd.Function):

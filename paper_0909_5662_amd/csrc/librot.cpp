@@ -468,6 +468,8 @@ rot_status rot_batch_blocked(const rot_blocked_problem* p, rot_precision prec, v
     const size_t need = blocked_workspace_bytes(p);
     if (need > 0 && (!workspace || workspace_bytes < need))
         return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     hipError_t e = rotate_blocked(p, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? ROT_OK : hip_fail(e, "rot_batch_blocked");
 }

@@ -29,6 +29,35 @@ struct GemmDesc {
     bool a_kcontig, b_kcontig, accumulate;
 };
 
+// ---- grouped GEMM over a work-list (grouped.hip) ----
+enum class GroupedShape : int { k128 = 0, k64 = 1, k32 = 2 };
+constexpr int kGroupedVec = 1;         // 16-byte vector loads allowed for this problem
+constexpr int kGroupedAccumulate = 2;  // C += result
+// One GEMM C (M x N) (+)= A (M x K) B (K x N); operand/result positions are
+// element offsets from the launch's base pointers.  Layouts are per launch.
+struct GroupedProblem {
+    int M, N, K, flags;
+    int64_t a_off, lda, b_off, ldb, c_off, ldc;
+};
+struct GroupedTile {
+    int prob, m0, n0, pad;
+};
+struct GroupedLaunch {
+    const float* a_base;
+    const float* b_base;
+    float* c_base;
+    const GroupedProblem* probs;  // device
+    const GroupedTile* tiles;     // device
+    int n_tiles;
+    bool a_kcontig, b_kcontig;    // as in GemmDesc
+    bool dynamic;                 // atomic tile queue (needs counter) vs static stride
+    GroupedShape shape;
+    int grid;                     // persistent workgroups (<= 0: one per tile)
+    int* counter;                 // device int for the dynamic queue
+};
+int grouped_tile_edge(GroupedShape shape);
+hipError_t grouped_gemm_f32(const GroupedLaunch& L, hipStream_t stream);
+
 // Runs `launch` (which enqueues kernels on `stream`); when per-kernel timing
 // is enabled (rot_profile_enable) it is bracketed by HIP events recorded on
 // `stream` and filed under `name`.

@@ -110,3 +110,60 @@ def test_reduction_argument_errors(rotlib):
     assert L.rot_check_isometry(FAKE, 8, 4, 1, 1e-6, ctypes.byref(dev), FAKE, 8, None) == -3
     assert L.rot_split_bf16(None, 5, None, None, None) == -1
     assert L.rot_split_bf16(None, 0, None, None, None) == 0
+
+
+def test_blocked_descriptor_validation(rotlib):
+    """Bad sector tables are rejected on the host (no device work)."""
+    import numpy as np
+    import workloads
+    L = rotlib.lib()
+    sizes = [((0, 0), 2), ((1, 0), 3), ((0, 1), 2), ((1, 1), 4)]
+    case = workloads.blocked_case(sizes=sizes, n_conserving=1, n_up_shift=1, n_dn_shift=0, cfg=60)
+    pk = workloads.pack_blocked(case)
+
+    class FakeT:  # stands in for a device tensor: only data_ptr is read
+        def __init__(self, p):
+            self.p = p
+            self.dtype = __import__("torch").float32
+            self.is_cuda = True
+
+        def data_ptr(self):
+            return self.p
+
+        def is_contiguous(self):
+            return True
+
+    def status(**over):
+        args = dict(site_qn=pk.site_qn, old=pk.old, new=pk.new, shift=pk.shift, U_off=pk.U_off,
+                    O_off=pk.O_off, out_off=pk.out_off)
+        args.update(over)
+        p, keep = rotlib.blocked_problem(args["site_qn"], args["old"], args["new"], args["shift"],
+                                         FakeT(FAKE), args["U_off"], FakeT(2 * FAKE), args["O_off"],
+                                         args["out_off"], FakeT(3 * FAKE))
+        st = L.rot_batch_blocked(ctypes.byref(p), rotlib.ROT_FP32, None, 0, None)
+        return st, L.rot_last_error().decode()
+
+    assert rotlib.rot_blocked_workspace_size(rotlib.blocked_problem(
+        pk.site_qn, pk.old, pk.new, pk.shift, FakeT(FAKE), pk.U_off, FakeT(2 * FAKE), pk.O_off, pk.out_off,
+        FakeT(3 * FAKE))[0]) > 0
+    assert status()[0] == -3                        # valid tables, no workspace
+    bad_old = pk.old.copy()
+    bad_old[1, 2] = 0
+    assert status(old=bad_old)[0] == -1             # empty sector
+    dup = pk.old.copy()
+    dup[1, :2] = dup[0, :2]
+    assert status(old=dup)[0] == -1                 # duplicate quantum numbers
+    big_new = pk.new.copy()
+    big_new[0, 2] = 50
+    assert status(new=big_new)[0] == -1             # kept sector larger than its block-site space
+    bad_out = pk.out_off.copy()
+    n_new = len(pk.new)
+    # request an output whose target sector (Q + Delta) is not kept: sector (1,1) shifted by (1,0)
+    k11 = [k for k, r in enumerate(pk.new) if (r[0], r[1]) == (1, 1)][0]
+    bad_out[1 * n_new + k11] = 0
+    st, msg = status(out_off=bad_out)
+    assert st == -1 and "not kept" in msg
+    assert L.rot_batch_blocked(None, rotlib.ROT_FP32, None, 0, None) == -1
+    p, keep = rotlib.blocked_problem(pk.site_qn, pk.old, pk.new, pk.shift, FakeT(FAKE), pk.U_off,
+                                     FakeT(2 * FAKE), pk.O_off, pk.out_off, FakeT(3 * FAKE))
+    assert L.rot_batch_blocked(ctypes.byref(p), rotlib.ROT_FP64, None, 0, None) == -2

@@ -233,3 +233,60 @@ def blocked_case(total: int = 1024, n_conserving: int = 200, n_up_shift: int = 1
 def uneven_sizes(n_rot: int, cfg: int = 4, classes=(128, 256, 512, 1024, 2048)) -> list[int]:
     g = rng(cfg, 3)
     return [int(classes[k]) for k in g.integers(0, len(classes), size=n_rot)]
+
+
+@dataclasses.dataclass
+class PackedBlocked:
+    """Flat arrays of a BlockedCase in the layout of the blocked C entry point:
+    U blocks concatenated (U_off per kept sector), operator blocks
+    concatenated (O_off per operator and old sector, -1 when absent), and the
+    output offsets (out_off per operator and kept sector, -1 when the target
+    sector is not kept).  Offsets are in elements and multiples of 4."""
+    site_qn: np.ndarray   # (d, 2) int32
+    old: np.ndarray       # (n_old, 3) int64: n_up, n_dn, dim
+    new: np.ndarray       # (n_new, 3) int64
+    shift: np.ndarray     # (n_ops, 2) int32
+    U_blk: np.ndarray     # float64 values exactly representable in FP32
+    U_off: np.ndarray     # int64
+    O_blk: np.ndarray
+    O_off: np.ndarray     # (n_ops * n_old,) int64
+    out_off: np.ndarray   # (n_ops * n_new,) int64
+    out_size: int
+
+
+def _pad4(n: int) -> int:
+    return (n + 3) // 4 * 4
+
+
+def pack_blocked(case: BlockedCase) -> PackedBlocked:
+    U_parts, U_off, pos = [], [], 0
+    for blk in case.U_blocks:
+        U_off.append(pos)
+        flat = blk.ravel()
+        U_parts.append(np.concatenate([flat, np.zeros(_pad4(flat.size) - flat.size)]))
+        pos += _pad4(flat.size)
+    n_old, n_new = len(case.old), len(case.new)
+    O_parts, O_off, pos = [], np.full(len(case.shifts) * n_old, -1, dtype=np.int64), 0
+    for b, blocks in enumerate(case.O_blocks):
+        for k, blk in sorted(blocks.items()):
+            O_off[b * n_old + k] = pos
+            flat = blk.ravel()
+            O_parts.append(np.concatenate([flat, np.zeros(_pad4(flat.size) - flat.size)]))
+            pos += _pad4(flat.size)
+    by_qn = {s.qn: s for s in case.new}
+    out_off, pos = np.full(len(case.shifts) * n_new, -1, dtype=np.int64), 0
+    for b, delta in enumerate(case.shifts):
+        for k, sec in enumerate(case.new):
+            t = (sec.qn[0] + delta[0], sec.qn[1] + delta[1])
+            if t in by_qn:
+                out_off[b * n_new + k] = pos
+                pos += _pad4(by_qn[t].dim * sec.dim)
+    return PackedBlocked(
+        site_qn=np.array(case.site_qn, dtype=np.int32),
+        old=np.array([(s.qn[0], s.qn[1], s.dim) for s in case.old], dtype=np.int64),
+        new=np.array([(s.qn[0], s.qn[1], s.dim) for s in case.new], dtype=np.int64),
+        shift=np.array(case.shifts, dtype=np.int32).reshape(-1, 2),
+        U_blk=np.concatenate(U_parts) if U_parts else np.zeros(0),
+        U_off=np.array(U_off, dtype=np.int64),
+        O_blk=np.concatenate(O_parts) if O_parts else np.zeros(4),
+        O_off=O_off, out_off=out_off, out_size=max(pos, 4))
