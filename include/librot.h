@@ -128,6 +128,44 @@ ROT_API rot_status rot_backward(const rot_problem* groups, int32_t n_groups,
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Plans: repeated rotation of a fixed set of groups with different sizes (a
+ * sweep step rotates the stored operators of many blocks; Sec. 3.2 counts
+ * l(l+3)/2 of them per block).  rot_plan_create buckets the groups into size
+ * classes (ceil log2 of m*d and of mp), packs their operators into chunks
+ * whose stage-1 intermediates fit `workspace`, builds per-chunk work-lists for
+ * a grouped persistent kernel, picks per class the tile shape and the
+ * schedule (static contiguous runs, like the paper's uniform-matrix
+ * distribution, or an atomic tile queue, like its pool of tasks) from the
+ * tuning cache or by timing candidates on the class's first chunk, and
+ * captures all launches in a hipGraph.  Only ROT_FP32.
+ *   groups, workspace: as for rot_batch; every buffer (U, O, out, workspace)
+ *       is bound to the plan by address and must stay valid, unmoved and
+ *       unoverlapped until rot_plan_destroy.
+ *   stream: pending work on it is waited for before tuning writes to out and
+ *       the workspace; create returns after its own device work has finished.
+ *   flags: ROT_PLAN_NO_GRAPH (issue launches directly on execute),
+ *       ROT_PLAN_NO_TUNE (use cache entries or the default, never time),
+ *       ROT_PLAN_RETUNE (time candidates even when the cache has an entry).
+ *   The tuning cache lives in memory and, when the environment variable
+ *   ROT_TUNE_CACHE names a file, in that text file (unreadable lines are
+ *   ignored).  Plans own device memory for their work-lists, a stream and the
+ *   graph; they are not thread-safe (one caller at a time per plan).
+ * rot_plan_execute enqueues one full rotation of every group on `stream`.
+ * rot_plan_describe writes a JSON summary (classes, choices) into buf and
+ * returns its full length (-1 for a null plan).
+ */
+typedef struct rot_plan_s* rot_plan;
+#define ROT_PLAN_NO_GRAPH 1u
+#define ROT_PLAN_NO_TUNE 2u
+#define ROT_PLAN_RETUNE 4u
+ROT_API rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_precision prec,
+                                   void* workspace, size_t workspace_bytes, uint32_t flags,
+                                   void* stream, rot_plan* plan);
+ROT_API rot_status rot_plan_execute(rot_plan plan, void* stream);
+ROT_API int32_t rot_plan_describe(rot_plan plan, char* buf, size_t len);
+ROT_API rot_status rot_plan_destroy(rot_plan plan);
+
+/*
  * Quantum-number (N_up, N_down) block-sparse rotation, Eq. (10) and the
  * paragraph after it: operators and U are block-sparse by particle numbers;
  * an operator with shift Delta maps old sector q to q + Delta (Delta = (0,0)

@@ -30,7 +30,7 @@ __all__ = [
     "rot_split_bf16", "rot_workspace_size", "rot_blocked_workspace_size",
     "rotate", "rotate_backward", "pair_loss", "check_isometry", "split_bf16",
     "RotateFn", "PairLossFn", "precision_code", "profile_enable", "profile_read",
-    "blocked_problem", "rotate_blocked",
+    "blocked_problem", "rotate_blocked", "Plan", "ROT_PLAN_NO_GRAPH", "ROT_PLAN_NO_TUNE", "ROT_PLAN_RETUNE",
 ]
 
 ROT_FP64, ROT_FP32, ROT_SPLIT_BF16 = 0, 1, 2
@@ -102,6 +102,15 @@ def lib() -> ctypes.CDLL:
         L.rot_last_error.restype = ctypes.c_char_p
         L.rot_last_error.argtypes = []
         L.rot_version.restype = ctypes.c_int32
+        L.rot_plan_create.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, vp, sz, ctypes.c_uint32, vp,
+                                      ctypes.POINTER(vp)]
+        L.rot_plan_create.restype = ctypes.c_int
+        L.rot_plan_execute.argtypes = [vp, vp]
+        L.rot_plan_execute.restype = ctypes.c_int
+        L.rot_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+        L.rot_plan_describe.restype = i32
+        L.rot_plan_destroy.argtypes = [vp]
+        L.rot_plan_destroy.restype = ctypes.c_int
         L.rot_profile_enable.argtypes = [i32]
         L.rot_profile_enable.restype = ctypes.c_int
         L.rot_profile_read.argtypes = [ctypes.c_char_p, sz]
@@ -366,6 +375,58 @@ def rotate_blocked(site_qn, old, new, shift, U_blk, U_off, O_blk, O_off, out_off
     rot_batch_blocked(p, ROT_FP32, workspace.data_ptr(), workspace.numel(), _stream(stream))
     del keep
     return out_blk
+
+
+ROT_PLAN_NO_GRAPH, ROT_PLAN_NO_TUNE, ROT_PLAN_RETUNE = 1, 2, 4
+
+
+class Plan:
+    """A fixed set of rotation groups of different sizes, executed as grouped
+    persistent launches replayed from a hipGraph (C ABI: rot_plan_*).
+
+    groups: list of (U, O, out, d) device tensors (FP32).  The tensors and the
+    workspace are bound by address: keep them alive and in place while the plan
+    exists (the plan holds references)."""
+
+    def __init__(self, groups, workspace_bytes: int | None = None, graph: bool = True, tune: bool = True,
+                 retune: bool = False, stream=None):
+        self._groups = list(groups)
+        probs = []
+        for U, O, out, d in self._groups:
+            _check_inputs(U, O, d, ROT_FP32)
+            probs.append(_problem(U, O, out, d))
+        self._probs = (RotProblem * len(probs))(*probs)
+        if workspace_bytes is None:
+            workspace_bytes = rot_workspace_size(probs, ROT_FP32)  # everything in one chunk per class
+        dev = self._groups[0][0].device if self._groups else torch.device("cuda")
+        self.workspace = _workspace(workspace_bytes, dev)
+        flags = (0 if graph else ROT_PLAN_NO_GRAPH) | (0 if tune else ROT_PLAN_NO_TUNE) | (
+            ROT_PLAN_RETUNE if retune else 0)
+        h = ctypes.c_void_p()
+        _check(lib().rot_plan_create(self._probs, len(probs), ROT_FP32, self.workspace.data_ptr(),
+                                     self.workspace.numel(), flags, _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def execute(self, stream=None) -> None:
+        _check(lib().rot_plan_execute(self._h, _stream(stream)))
+
+    def describe(self) -> dict:
+        import json
+        n = lib().rot_plan_describe(self._h, None, 0)
+        buf = ctypes.create_string_buffer(n + 1)
+        lib().rot_plan_describe(self._h, buf, n + 1)
+        return json.loads(buf.value.decode())
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rot_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class RotateFn(torch.autograd.Function):

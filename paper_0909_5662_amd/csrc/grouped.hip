@@ -10,7 +10,7 @@
 //
 // Problem pointers are given as element offsets from per-launch base
 // pointers, so a tile list built once for a block structure can be reused
-// with new buffers.
+// with new buffers; with a null base the offset is an absolute address.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -107,8 +107,9 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
     while (t < L.n_tiles) {
         const GroupedTile tile = L.tiles[t];
         const GroupedProblem p = L.probs[tile.prob];
-        const float* Ab = L.a_base + p.a_off;
-        const float* Bb = L.b_base + p.b_off;
+        // null base: the offset is an absolute address
+        const float* Ab = L.a_base ? L.a_base + p.a_off : reinterpret_cast<const float*>(p.a_off);
+        const float* Bb = L.b_base ? L.b_base + p.b_off : reinterpret_cast<const float*>(p.b_off);
         const bool vec = p.flags & kGroupedVec;
         const int nk = (p.K + kSlice - 1) / kSlice;
 
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
             __syncthreads();
         }
 
-        float* Cb = L.c_base + p.c_off;
+        float* Cb = L.c_base ? L.c_base + p.c_off : reinterpret_cast<float*>(p.c_off);
         const bool accum = p.flags & kGroupedAccumulate;
 #pragma unroll
         for (int i = 0; i < BI; i++)

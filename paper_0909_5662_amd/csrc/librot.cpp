@@ -178,6 +178,11 @@ hipError_t gemm(rot_precision prec, const GemmDesc& g, hipStream_t s, const char
 
 }  // namespace
 
+rot_status set_error(rot_status s, const char* msg) {
+    g_last_error = msg;
+    return s;
+}
+
 hipError_t prof_timed(const char* name, hipStream_t stream, const std::function<hipError_t()>& launch) {
     return timed(name, stream, launch);
 }

@@ -34,7 +34,8 @@ enum class GroupedShape : int { k128 = 0, k64 = 1, k32 = 2 };
 constexpr int kGroupedVec = 1;         // 16-byte vector loads allowed for this problem
 constexpr int kGroupedAccumulate = 2;  // C += result
 // One GEMM C (M x N) (+)= A (M x K) B (K x N); operand/result positions are
-// element offsets from the launch's base pointers.  Layouts are per launch.
+// element offsets from the launch's base pointers (absolute byte addresses
+// when the base is null).  Layouts are per launch.
 struct GroupedProblem {
     int M, N, K, flags;
     int64_t a_off, lda, b_off, ldb, c_off, ldc;
@@ -57,6 +58,10 @@ struct GroupedLaunch {
 };
 int grouped_tile_edge(GroupedShape shape);
 hipError_t grouped_gemm_f32(const GroupedLaunch& L, hipStream_t stream);
+
+// Records `msg` as the calling thread's last error (rot_last_error) and
+// returns `s`.
+rot_status set_error(rot_status s, const char* msg);
 
 // Runs `launch` (which enqueues kernels on `stream`); when per-kernel timing
 // is enabled (rot_profile_enable) it is bracketed by HIP events recorded on

@@ -290,3 +290,33 @@ def pack_blocked(case: BlockedCase) -> PackedBlocked:
         U_off=np.array(U_off, dtype=np.int64),
         O_blk=np.concatenate(O_parts) if O_parts else np.zeros(4),
         O_off=O_off, out_off=out_off, out_size=max(pos, 4))
+
+
+def uneven_case_gpu(sizes, d: int = 4, ops_per_rot: int = 8, cfg: int = 4, device="cuda", mp_of=None,
+                    symmetric: bool = True):
+    """Many rotations of different m generated on the GPU (seeded torch
+    generator, deterministic for a given device and torch build).  U_r is the
+    orthonormal factor of a (m*d) x m' Gaussian from Cholesky QR in FP64
+    (R = chol(A^T A), Q = A R^-1; diag(R) > 0, so Q is the positive-diagonal
+    QR factor; Gaussian panels of aspect d are well conditioned), then FP32.
+    O: ops_per_rot symmetric Gaussians scaled by 1/sqrt(m), FP32.
+    Returns a list of (U, O) device tensors."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED * 1000 + cfg)
+    out = []
+    for m in sizes:
+        mp = m if mp_of is None else mp_of(m)
+        A = torch.randn((m * d, mp), generator=gen, device=device, dtype=torch.float64)
+        R = torch.linalg.cholesky(A.T @ A, upper=True)
+        Q = torch.linalg.solve_triangular(R, A, upper=True, left=False)
+        U = Q.float().contiguous()
+        del A, R, Q
+        G = torch.randn((ops_per_rot, m, m), generator=gen, device=device, dtype=torch.float32)
+        if symmetric:
+            O = (G + G.transpose(1, 2)) * (0.5 / math.sqrt(m))
+        else:
+            O = G * (1.0 / math.sqrt(m))
+        out.append((U, O.contiguous()))
+        del G
+    return out
