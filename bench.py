@@ -35,6 +35,10 @@ def parse():
                     help="with --precision fp32, skip the split-BF16 measurement")
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 GPU rotation (speedup denominator)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=[WORKLOAD, "blocked_1024_n400", "uneven_1000", "differentiated_m1024_n64"],
+                    help="default: the headline dense workload; the others time the quantum-number "
+                         "blocked batch or the uneven sweep plan")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -113,6 +117,153 @@ def measure(rot, U, O, out, d, precision, steps, warmup):
             "roofline": roofline}
 
 
+def base_record(args, value, unit, ms_per_step, config, dtype="f32"):
+    return {"metric": METRIC, "value": round(value, 2), "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def bench_blocked(args, rot, torch, workloads):
+    """Quantum-number blocked batch: m = m' = 1024 in (N_up, N_dn) sectors, 400
+    operators (200 conserving, 100 + 100 shifting)."""
+    case = workloads.blocked_case()
+    pk = workloads.pack_blocked(case)
+    dev = torch.device("cuda:0")
+    U_blk = torch.from_numpy(pk.U_blk).float().to(dev)
+    O_blk = torch.from_numpy(pk.O_blk).float().to(dev)
+    out_blk = torch.empty(pk.out_size, device=dev)
+    p, keep = rot.blocked_problem(pk.site_qn, pk.old, pk.new, pk.shift, U_blk, pk.U_off, O_blk, pk.O_off,
+                                  pk.out_off, out_blk)
+    ws = torch.empty(max(256, rot.rot_blocked_workspace_size(p)), dtype=torch.uint8, device=dev)
+    run = lambda: rot.rot_batch_blocked(p, rot.ROT_FP32, ws.data_ptr(), ws.numel(),
+                                        torch.cuda.current_stream().cuda_stream)
+    # algorithmic work: the block GEMMs that the sector structure requires
+    old = {s.qn: s for s in case.old}
+    new = {s.qn: s for s in case.new}
+    flops = 0.0
+    bytes_alg = sum(v.size for b in case.O_blocks for v in b.values()) * 4 + pk.U_blk.size * 4
+    for delta, blocks in zip(case.shifts, case.O_blocks):
+        for sec in case.new:
+            t = (sec.qn[0] + delta[0], sec.qn[1] + delta[1])
+            if t not in new:
+                continue
+            MT = sum(old[(t[0] - a, t[1] - b)].dim for a, b in case.site_qn if (t[0] - a, t[1] - b) in old)
+            for a, b in case.site_qn:
+                qs, qt = (sec.qn[0] - a, sec.qn[1] - b), (t[0] - a, t[1] - b)
+                if qs in old and qt in old:
+                    flops += 2.0 * old[qt].dim * old[qs].dim * sec.dim
+            flops += 2.0 * new[t].dim * MT * sec.dim
+            bytes_alg += new[t].dim * sec.dim * 4
+    for _ in range(max(1, args.warmup)):
+        run()
+    torch.cuda.synchronize()
+    rot.profile_enable(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        run()
+    t1.record()
+    torch.cuda.synchronize()
+    kernels = rot.profile_read()
+    rot.profile_enable(False)
+    ms = t0.elapsed_time(t1) / args.steps
+    n = len(case.shifts)
+    tflops = flops / (ms / 1e3) / 1e12
+    rec = base_record(args, n / (ms / 1e3), "operator rotations/s", ms,
+                      {"workload": "blocked_1024_n400", "m": case.m, "mp": case.mp, "d": case.d,
+                       "sectors": len(case.old), "sector_dims": [min(s.dim for s in case.old),
+                                                                 max(s.dim for s in case.old)],
+                       "n_ops": n, "precision": "fp32"})
+    dom, (cnt, tot) = max(kernels.items(), key=lambda kv: kv[1][1])
+    rec.update({"gflop_per_step": round(flops / 1e9, 3), "tflops": round(tflops, 2),
+                "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2),
+                "algorithmic_gb_per_s": round(bytes_alg / (ms / 1e3) / 1e9, 1),
+                "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
+                "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": round(tflops / 157.3, 4), "traffic": None, "kernel": "blocked (both stages)",
+                             "note": "small sector GEMMs (4..76): latency/occupancy bound"}})
+    del keep
+    return rec
+
+
+def bench_uneven(args, rot, torch, workloads):
+    """1000 rotations, m uniform in {128,...,2048}, d = 4, m' = m, 8 operators
+    each, one plan (grouped persistent launches, tuned, hipGraph replay)."""
+    sizes = workloads.uneven_sizes(1000)
+    data = workloads.uneven_case_gpu(sizes, d=4, ops_per_rot=8, cfg=4)
+    groups = [(U, O, torch.empty((8, U.shape[1], U.shape[1]), device=U.device), 4) for U, O in data]
+    plan = rot.Plan(groups, workspace_bytes=32 << 30)
+    flops = sum(8 * flops_per_op(m, 4, m) for m in sizes)
+    for _ in range(max(1, args.warmup)):
+        plan.execute()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        plan.execute()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    tflops = flops / (ms / 1e3) / 1e12
+    rec = base_record(args, 8000 / (ms / 1e3), "operator rotations/s", ms,
+                      {"workload": "uneven_1000", "rotations": 1000, "ops_per_rotation": 8, "d": 4,
+                       "m_classes": [128, 256, 512, 1024, 2048], "precision": "fp32"})
+    rec.update({"tflop_per_step": round(flops / 1e12, 2), "tflops": round(tflops, 2),
+                "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2), "plan": plan.describe(),
+                "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": round(tflops / 157.3, 4), "traffic": None, "kernel": "plan graph (all launches)"}})
+    plan.close()
+    return rec
+
+
+def bench_differentiated(args, rot, torch, workloads):
+    """Forward (FP32) + FP64 pair loss + adjoint (FP32, stage 1 recomputed)
+    through torch.autograd, m = m' = 1024, d = 4, 64 symmetric operators."""
+    case = workloads.named_dense(WORKLOAD)
+    psi = torch.from_numpy(workloads.psi_vector(case.mp, workloads.rng(5, 2))).cuda()
+    U = torch.from_numpy(case.U).float().cuda().requires_grad_(True)
+    O = torch.from_numpy(case.O).float().cuda().requires_grad_(True)
+
+    def step():
+        U.grad = None
+        O.grad = None
+        X = rot.RotateFn.apply(U, O, 4, "fp32", True)
+        L = rot.PairLossFn.apply(X, psi)
+        L.backward()
+        return L
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    rot.profile_enable(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    kernels = rot.profile_read()
+    rot.profile_enable(False)
+    ms = t0.elapsed_time(t1) / args.steps
+    n, m, mp, d = 64, 1024, 1024, 4
+    f_fwd = n * flops_per_op(m, d, mp)
+    # backward: P = U dOut (2 md mp^2), dO = P U_r^T (2 m^2 d mp), T (2 m^2 d mp),
+    # dU terms 2 x (2 md mp^2) per operator
+    f_bwd = n * (2.0 * m * d * mp * mp + 2.0 * m * m * d * mp + 2.0 * m * m * d * mp + 4.0 * m * d * mp * mp)
+    tflops = (f_fwd + f_bwd) / (ms / 1e3) / 1e12
+    rec = base_record(args, n / (ms / 1e3), "operator rotations/s (forward + loss + adjoint)", ms,
+                      {"workload": "differentiated_m1024_n64", "m": m, "d": d, "mp": mp, "n_ops": n,
+                       "precision": "fp32 forward/adjoint, fp64 loss"})
+    rec.update({"tflop_per_step": round((f_fwd + f_bwd) / 1e12, 3), "tflops": round(tflops, 2),
+                "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2),
+                "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
+                "kernels_ms_total_per_step": {k: round(v[1] / args.steps, 4) for k, v in kernels.items()}})
+    return rec
+
+
 def cpu_baseline(case, n_total):
     """The oracle, as it stands, on a bounded sample: one operator per host
     thread (at most the whole batch), all threads of this process."""
@@ -148,6 +299,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}))
+        return
+
+    if args.workload != WORKLOAD:
+        fn = {"blocked_1024_n400": bench_blocked, "uneven_1000": bench_uneven,
+              "differentiated_m1024_n64": bench_differentiated}[args.workload]
+        print(json.dumps(fn(args, rot, torch, workloads)), flush=True)
         return
 
     case = workloads.named_dense(WORKLOAD)
