@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <list>
 #include <map>
@@ -115,6 +116,155 @@ bool build_structure(const rot_blocked_problem* p, Structure* st, std::string* w
 
 bool aligned16(const float* base, int64_t off) { return ((reinterpret_cast<uintptr_t>(base + off)) & 15) == 0; }
 
+// ------------------------------------------------------------ fused path --
+// One 64-wide wave per output block (operator b, kept sector Q), computing
+//   Out^T(Q <- T) = sum_s X_s^T U_T[s rows],   X_s = O(q_s+Delta <- q_s) U_Q[s rows]
+// on v_mfma_f32_16x16x4f32 (lane l supplies A(l%16, l/16), B(l/16, l%16);
+// accumulator element v of lane l is D(4*(l/16)+v, l%16)).  A 16 x 16 block
+// of X_s in accumulator layout is, read with the k order 4*(l/16)+j at step
+// j, exactly the A operand of X_s^T: X never leaves registers.
+struct BlkTask {
+    int mT, mQ;          // output block rows (kept dim of T) and columns (kept dim of Q)
+    int term0, n_terms;  // terms (site states with a non-zero operator block)
+    int64_t uT_off;      // U_T in U_blk, leading dimension mT
+    int64_t uQ_off;      // U_Q in U_blk, leading dimension mQ
+    int64_t out_off;     // output block in out_blk, leading dimension mQ
+};
+struct BlkTerm {
+    int a, k;        // rows of X_s (old states of q_s + Delta), stage-1 K (old states of q_s)
+    int rt, rq;      // first row of site state s inside U_T and inside U_Q
+    int64_t o_off;   // operator block (a x k, leading dimension k) in O_blk
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int MAXA>
+__global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __restrict__ tasks, int n_tasks,
+                                                            const BlkTerm* __restrict__ terms,
+                                                            const float* __restrict__ U, const float* __restrict__ O,
+                                                            float* __restrict__ out, int* __restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lh = lane >> 4;
+    int t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1);
+    t = __shfl(t, 0, 64);
+    while (t < n_tasks) {
+        const BlkTask T = tasks[t];
+        const float* uT = U + T.uT_off;
+        const float* uQ = U + T.uQ_off;
+        const int nbc = (T.mQ + 15) >> 4, nba = (T.mT + 15) >> 4;
+        for (int cb = 0; cb < nbc; cb++) {
+            const int beta = cb * 16 + li;  // this lane's column of X / U_Q
+            f32x4 acc[MAXA];
+#pragma unroll
+            for (int ca = 0; ca < MAXA; ca++) acc[ca] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int e = 0; e < T.n_terms; e++) {
+                const BlkTerm tm = terms[T.term0 + e];
+                const float* o = O + tm.o_off;
+                for (int rb = 0; rb * 16 < tm.a; rb++) {
+                    // stage 1: 16 x 16 block of X_s
+                    f32x4 x = {0.f, 0.f, 0.f, 0.f};
+                    const int row = rb * 16 + li;
+#pragma unroll 4
+                    for (int k0 = 0; k0 < tm.k; k0 += 4) {
+                        const int k = k0 + lh;
+                        const float av = (row < tm.a && k < tm.k) ? o[(int64_t)row * tm.k + k] : 0.f;
+                        const float bv = (k < tm.k && beta < T.mQ) ? uQ[(int64_t)(tm.rq + k) * T.mQ + beta] : 0.f;
+                        x = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, x, 0, 0, 0);
+                    }
+                    // stage 2: acc(beta, alpha) += sum_r X_s[r][beta] U_T[rt + r][alpha]
+#pragma unroll 1
+                    for (int j = 0; j < 4; j++) {
+                        const int r = rb * 16 + 4 * lh + j;
+                        const bool rok = r < tm.a;
+                        const float* urow = uT + (int64_t)(tm.rt + r) * T.mT;
+#pragma unroll
+                        for (int ca = 0; ca < MAXA; ca++) {
+                            if (ca < nba) {
+                                const int alpha = ca * 16 + li;
+                                const float bv = (rok && alpha < T.mT) ? urow[alpha] : 0.f;
+                                acc[ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j], bv, acc[ca], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+            }
+            // acc[ca] element v of lane l = Out^T(beta = 16 cb + 4*(l/16) + v, alpha = 16 ca + l%16)
+#pragma unroll
+            for (int ca = 0; ca < MAXA; ca++) {
+                const int alpha = ca * 16 + li;
+                if (ca < nba && alpha < T.mT) {
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int b = cb * 16 + 4 * lh + v;
+                        if (b < T.mQ) out[T.out_off + (int64_t)alpha * T.mQ + b] = acc[ca][v];
+                    }
+                }
+            }
+        }
+        if (lane == 0) t = atomicAdd(counter, 1);
+        t = __shfl(t, 0, 64);
+    }
+}
+
+__global__ void reset_fused_counter(int* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+struct FusedLists {
+    std::vector<BlkTask> tasks;
+    std::vector<BlkTerm> terms;
+    int max_mT = 0;
+};
+
+void build_fused(const rot_blocked_problem* p, const Structure& st, FusedLists* F) {
+    std::vector<std::pair<double, BlkTask>> work;
+    std::vector<BlkTerm> terms;
+    for (int b = 0; b < p->n_ops; b++) {
+        const int du = p->shift[2 * b], dd = p->shift[2 * b + 1];
+        for (int k = 0; k < p->n_new; k++) {
+            const int64_t out_off = p->out_off[(int64_t)b * p->n_new + k];
+            if (out_off < 0) continue;
+            const rot_sector& Q = p->new_sec[k];
+            const int kt = st.new_idx.at(QN{Q.n_up + du, Q.n_dn + dd});
+            const rot_sector& Tsec = p->new_sec[kt];
+            BlkTask task{};
+            task.mT = Tsec.dim;
+            task.mQ = Q.dim;
+            task.term0 = (int)terms.size();
+            task.uT_off = p->U_off[kt];
+            task.uQ_off = p->U_off[k];
+            task.out_off = out_off;
+            double cost = 1.0;
+            for (int s = 0; s < p->d; s++) {
+                const int64_t rt = st.rowstart[kt][s], rq = st.rowstart[k][s];
+                if (rt < 0 || rq < 0) continue;
+                const QN qt{Tsec.n_up - p->site_qn[2 * s], Tsec.n_dn - p->site_qn[2 * s + 1]};
+                const QN qs{qt.u - du, qt.d - dd};
+                auto it = st.old_idx.find(qs);
+                if (it == st.old_idx.end()) continue;
+                const int64_t oo = p->O_off[(int64_t)b * p->n_old + it->second];
+                if (oo < 0) continue;
+                BlkTerm tm{};
+                tm.a = p->old_sec[st.old_idx.at(qt)].dim;
+                tm.k = p->old_sec[it->second].dim;
+                tm.rt = (int)rt;
+                tm.rq = (int)rq;
+                tm.o_off = oo;
+                terms.push_back(tm);
+                cost += (double)tm.a * tm.k * Q.dim + (double)Tsec.dim * tm.a * Q.dim;
+            }
+            task.n_terms = (int)terms.size() - task.term0;
+            F->max_mT = std::max(F->max_mT, task.mT);
+            work.emplace_back(cost, task);
+        }
+    }
+    // longest processing time first
+    std::stable_sort(work.begin(), work.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (auto& w : work) F->tasks.push_back(w.second);
+    F->terms = std::move(terms);
+}
+
 struct Lists {
     std::vector<GroupedProblem> p1, p2;
     int64_t x_elems = 0;
@@ -202,12 +352,19 @@ struct Plan {
     DeviceLists s1, s2;
     int* counter = nullptr;
     int64_t x_elems = 0;
+    BlkTask* f_tasks = nullptr;
+    BlkTerm* f_terms = nullptr;
+    int f_n_tasks = 0;
+    int f_max_mT = 0;
+    int path = -1;  // 0 grouped two-stage, 1 fused; -1 not chosen yet
     ~Plan() {
         (void)hipFree(s1.probs);
         (void)hipFree(s1.tiles);
         (void)hipFree(s2.probs);
         (void)hipFree(s2.tiles);
         (void)hipFree(counter);
+        (void)hipFree(f_tasks);
+        (void)hipFree(f_terms);
     }
 };
 
@@ -221,7 +378,8 @@ void put(std::vector<unsigned char>& v, const T* p, size_t n) {
 }
 
 // Everything the work-lists depend on: the tables' contents, the shape, and
-// the 16-byte alignment of the buffers (which decides vector loads).
+// the 16-byte alignment of the buffers (which decides vector loads).  The
+// chosen path (fused or two grouped launches) is cached with the lists.
 std::vector<unsigned char> signature(const rot_blocked_problem* p, const void* ws, GroupedShape shape) {
     std::vector<unsigned char> v;
     const int32_t head[4] = {p->d, p->n_old, p->n_new, p->n_ops};
@@ -289,38 +447,9 @@ rot_status blocked_validate(const rot_blocked_problem* p, std::string* why) {
     return build_structure(p, &st, why) ? ROT_OK : ROT_ERR_INVALID_ARG;
 }
 
-hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_bytes, hipStream_t stream) {
-    (void)ws_bytes;
-    if (p->n_ops == 0) return hipSuccess;
-    const GroupedShape shape = blocked_shape();
-    std::vector<unsigned char> sig = signature(p, ws, shape);
-    Plan* plan = nullptr;
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
-        if ((*it)->sig == sig) {
-            g_plans.splice(g_plans.begin(), g_plans, it);
-            plan = g_plans.front().get();
-            break;
-        }
-    }
-    if (!plan) {
-        Structure st;
-        std::string why;
-        if (!build_structure(p, &st, &why)) return hipErrorInvalidValue;  // validated by the caller
-        Lists L;
-        build_lists(p, st, static_cast<const float*>(ws), &L);
-        auto np = std::make_unique<Plan>();
-        np->sig = std::move(sig);
-        np->x_elems = L.x_elems;
-        const int edge = grouped_tile_edge(shape);
-        hipError_t e = upload(L.p1, make_tiles(L.p1, edge), &np->s1);
-        if (e == hipSuccess) e = upload(L.p2, make_tiles(L.p2, edge), &np->s2);
-        if (e == hipSuccess) e = hipMalloc(&np->counter, sizeof(int));
-        if (e != hipSuccess) return e;
-        g_plans.push_front(std::move(np));
-        if (g_plans.size() > kPlanCacheSize) g_plans.pop_back();
-        plan = g_plans.front().get();
-    }
+namespace {
+
+hipError_t run_grouped(const rot_blocked_problem* p, Plan* plan, void* ws, GroupedShape shape, hipStream_t stream) {
     GroupedLaunch a{};
     a.a_base = p->O_blk;
     a.b_base = p->U_blk;
@@ -346,6 +475,109 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
     b.a_kcontig = false;  // A(alpha, r) = U_T[r][alpha]
     b.b_kcontig = false;  // X[r][beta]
     return prof_timed("blocked_stage2_fp32", stream, [&] { return grouped_gemm_f32(b, stream); });
+}
+
+hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, hipStream_t stream) {
+    if (plan->f_n_tasks == 0) return hipSuccess;
+    return prof_timed("blocked_fused_fp32", stream, [&] {
+        hipLaunchKernelGGL(reset_fused_counter, dim3(1), dim3(64), 0, stream, plan->counter);
+        const int grid = 256 * 4;  // 4 workgroups of 4 waves per CU, each wave a task queue consumer
+        if (plan->f_max_mT <= 64)
+            hipLaunchKernelGGL((blocked_fused_kernel<4>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
+                               plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
+        else if (plan->f_max_mT <= 80)
+            hipLaunchKernelGGL((blocked_fused_kernel<5>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
+                               plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
+        else
+            hipLaunchKernelGGL((blocked_fused_kernel<8>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
+                               plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
+        return hipGetLastError();
+    });
+}
+
+// ROT_BLOCKED_PATH = fused | grouped forces a path; otherwise both are timed
+// once per block structure and the faster is kept.
+int forced_path() {
+    const char* e = getenv("ROT_BLOCKED_PATH");
+    if (!e) return -1;
+    if (!strcmp(e, "fused")) return 1;
+    if (!strcmp(e, "grouped")) return 0;
+    return -1;
+}
+
+}  // namespace
+
+hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_bytes, hipStream_t stream) {
+    (void)ws_bytes;
+    if (p->n_ops == 0) return hipSuccess;
+    const GroupedShape shape = blocked_shape();
+    const int forced = forced_path();
+    std::vector<unsigned char> sig = signature(p, ws, shape);
+    Plan* plan = nullptr;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
+        if ((*it)->sig == sig) {
+            g_plans.splice(g_plans.begin(), g_plans, it);
+            plan = g_plans.front().get();
+            break;
+        }
+    }
+    if (!plan) {
+        Structure st;
+        std::string why;
+        if (!build_structure(p, &st, &why)) return hipErrorInvalidValue;  // validated by the caller
+        Lists L;
+        build_lists(p, st, static_cast<const float*>(ws), &L);
+        FusedLists F;
+        build_fused(p, st, &F);
+        auto np = std::make_unique<Plan>();
+        np->sig = std::move(sig);
+        np->x_elems = L.x_elems;
+        const int edge = grouped_tile_edge(shape);
+        hipError_t e = upload(L.p1, make_tiles(L.p1, edge), &np->s1);
+        if (e == hipSuccess) e = upload(L.p2, make_tiles(L.p2, edge), &np->s2);
+        if (e == hipSuccess) e = hipMalloc(&np->counter, sizeof(int));
+        np->f_n_tasks = (int)F.tasks.size();
+        np->f_max_mT = F.max_mT;
+        if (e == hipSuccess && !F.tasks.empty()) e = hipMalloc(&np->f_tasks, sizeof(BlkTask) * F.tasks.size());
+        if (e == hipSuccess && !F.terms.empty()) e = hipMalloc(&np->f_terms, sizeof(BlkTerm) * F.terms.size());
+        if (e == hipSuccess && !F.tasks.empty())
+            e = hipMemcpy(np->f_tasks, F.tasks.data(), sizeof(BlkTask) * F.tasks.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !F.terms.empty())
+            e = hipMemcpy(np->f_terms, F.terms.data(), sizeof(BlkTerm) * F.terms.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+        if (F.max_mT > 128) np->path = 0;  // the fused kernel keeps at most 8 x 16 output rows per lane set
+        g_plans.push_front(std::move(np));
+        if (g_plans.size() > kPlanCacheSize) g_plans.pop_back();
+        plan = g_plans.front().get();
+    }
+    int path = forced >= 0 ? forced : plan->path;
+    if (path == 1 && plan->f_max_mT > 128) path = 0;
+    if (path < 0) {
+        // time both (second run of each, after a warm-up run)
+        hipEvent_t a, b, c;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e == hipSuccess) e = hipEventCreate(&c);
+        for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
+            e = hipEventRecord(a, stream);
+            if (e == hipSuccess) e = run_grouped(p, plan, ws, shape, stream);
+            if (e == hipSuccess) e = hipEventRecord(b, stream);
+            if (e == hipSuccess) e = run_fused(p, plan, stream);
+            if (e == hipSuccess) e = hipEventRecord(c, stream);
+        }
+        float t_grouped = 0.f, t_fused = 0.f;
+        if (e == hipSuccess) e = hipEventSynchronize(c);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t_grouped, a, b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t_fused, b, c);
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        (void)hipEventDestroy(c);
+        if (e != hipSuccess) return e;
+        plan->path = t_fused <= t_grouped ? 1 : 0;
+        return hipSuccess;  // the last timed run (fused) or both left the full result in out_blk
+    }
+    return path == 1 ? run_fused(p, plan, stream) : run_grouped(p, plan, ws, shape, stream);
 }
 
 }  // namespace rot

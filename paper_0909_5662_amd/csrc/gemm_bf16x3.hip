@@ -13,6 +13,8 @@
 //            B = Tt_b; FP32 output.
 // Stage 1's N index is ordered n = beta*d + s (site state fastest), so that
 // one lane's d neighbours hold the d consecutive entries r = i*d + s of Tt.
+// Tiles are 256 x 256 (four waves of 128 x 128) so that each 128-bit LDS
+// fragment read feeds 3 x 4 matrix instructions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,10 +31,8 @@ typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 256;
-constexpr int kTile = 128;
-constexpr int kSlice = 32;              // K elements per LDS slice (two matrix steps of 16)
-constexpr int kPitch = kSlice + 8;      // LDS row pitch in bf16 elements (80 bytes)
-constexpr int kArr = kTile * kPitch;    // one LDS array (hi or lo) of one operand
+constexpr int kSlice = 16;   // K elements per LDS slice: one matrix step
+constexpr int kPitch = 24;   // LDS row pitch in bf16 elements (48 bytes): conflict-free 128-bit reads
 
 __device__ inline uint16_t rne_bf16(float x) {
     const uint32_t b = __float_as_uint(x);
@@ -69,17 +69,19 @@ struct Bf16Desc {
     int64_t t_ld, t_bs;
 };
 
-// Stage a 128 x 32 slice of a pre-split K-contiguous operand into LDS.
-// 2 arrays x 128 rows x 4 chunks of 8 = 1024 chunks, 4 per thread.
+// Stage an R x 16 slice of a pre-split K-contiguous operand into LDS:
+// 2 arrays x R rows x 2 chunks of 8 = 4R chunks of 16 bytes.
+template <int R>
 struct SplitSlice {
-    u16x8 r[4];
+    static constexpr int CH = 4 * R / kThreads;
+    u16x8 r[CH];
     __device__ inline void load(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t ld,
                                 int r0, int rows, int k0, int ks, int tid) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
-            const int f = tid + c * kThreads;  // [0, 1024)
-            const int arr = f >> 9, q = f & 511;
-            const int row = q >> 2, k = (q & 3) * 8;
+        for (int c = 0; c < CH; c++) {
+            const int f = tid + c * kThreads;  // [0, 4R)
+            const int arr = f / (2 * R), q = f % (2 * R);
+            const int row = q >> 1, k = (q & 1) * 8;
             const int gr = r0 + row, gk = k0 + k;
             const uint16_t* p = (arr ? lo : hi) + (int64_t)gr * ld + gk;
             if (gr < rows && gk + 8 <= ks) {
@@ -92,26 +94,27 @@ struct SplitSlice {
     }
     __device__ inline void store(uint16_t* s_hi, uint16_t* s_lo, int tid) const {
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
+        for (int c = 0; c < CH; c++) {
             const int f = tid + c * kThreads;
-            const int arr = f >> 9, q = f & 511;
-            const int row = q >> 2, k = (q & 3) * 8;
+            const int arr = f / (2 * R), q = f % (2 * R);
+            const int row = q >> 1, k = (q & 1) * 8;
             *reinterpret_cast<u16x8*>((arr ? s_lo : s_hi) + row * kPitch + k) = r[c];
         }
     }
 };
 
-// Stage a 128 x 32 slice of an FP32 K-contiguous operand, splitting it.
-// 128 rows x 8 chunks of 4 floats = 1024 chunks, 4 per thread.
-template <bool VEC>
+// Stage an R x 16 slice of an FP32 K-contiguous operand, splitting it:
+// R rows x 4 chunks of 4 floats.
+template <int R, bool VEC>
 struct F32Slice {
-    f32x4 r[4];
+    static constexpr int CH = 4 * R / kThreads;
+    f32x4 r[CH];
     __device__ inline void load(const float* __restrict__ a, int64_t ld, int r0, int rows, int k0, int ks,
                                 int tid) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
+        for (int c = 0; c < CH; c++) {
             const int f = tid + c * kThreads;
-            const int row = f >> 3, k = (f & 7) * 4;
+            const int row = f >> 2, k = (f & 3) * 4;
             const int gr = r0 + row, gk = k0 + k;
             const float* p = a + (int64_t)gr * ld + gk;
             if (VEC && gr < rows && gk + 4 <= ks) {
@@ -124,9 +127,9 @@ struct F32Slice {
     }
     __device__ inline void store(uint16_t* s_hi, uint16_t* s_lo, int tid) const {
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
+        for (int c = 0; c < CH; c++) {
             const int f = tid + c * kThreads;
-            const int row = f >> 3, k = (f & 7) * 4;
+            const int row = f >> 2, k = (f & 3) * 4;
             u16x4 h, l;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
@@ -140,58 +143,68 @@ struct F32Slice {
     }
 };
 
-template <bool A_F32, bool VEC_A>
+template <int R, bool A_F32, bool VEC_A>
 struct ASlice;
-template <bool VEC_A>
-struct ASlice<true, VEC_A> : F32Slice<VEC_A> {
+template <int R, bool VEC_A>
+struct ASlice<R, true, VEC_A> : F32Slice<R, VEC_A> {
     __device__ inline void fetch(const Bf16Desc& g, int bidx, int r0, int k0, int tid) {
         this->load(g.a32 + (int64_t)bidx * g.a_bs, g.lda, r0, g.M, k0, g.K, tid);
     }
 };
-template <bool VEC_A>
-struct ASlice<false, VEC_A> : SplitSlice {
+template <int R, bool VEC_A>
+struct ASlice<R, false, VEC_A> : SplitSlice<R> {
     __device__ inline void fetch(const Bf16Desc& g, int bidx, int r0, int k0, int tid) {
         this->load(g.a_hi + (int64_t)bidx * g.a_bs, g.a_lo + (int64_t)bidx * g.a_bs, g.lda, r0, g.M, k0, g.K, tid);
     }
 };
 
-// v_mfma_f32_32x32x16_bf16: lane l supplies A(row l%32, k 8*(l/32)+e) and
-// B(k 8*(l/32)+e, col l%32), e < 8; accumulator element v of lane l is
-// C(8*(v/4) + 4*(l/32) + v%4, l%32).  In slice step j, lane group h covers
-// k = 16*j + 8*h + e for both operands.
-template <bool A_F32, bool VEC_A, bool EPI_T>
-__global__ __launch_bounds__(kThreads) void gemm_bf16x3_kernel(Bf16Desc g, int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2][4][kArr];  // [buf][A_hi, A_lo, B_hi, B_lo]
+// Tile BM x BN = (2*BI*32) x (2*BJ*32): four waves in a 2 x 2 grid, each
+// BI x BJ blocks of v_mfma_f32_32x32x16_bf16.  That instruction takes from
+// lane l A(row l%32, k 8*(l/32)+e) and B(k 8*(l/32)+e, col l%32), e < 8, and
+// leaves C(8*(v/4) + 4*(l/32) + v%4, l%32) in accumulator element v.  One
+// LDS slice is one k step of 16; its 128-bit fragment reads are
+// conflict-free with the 48-byte row pitch.
+template <int BI, int BJ, bool A_F32, bool VEC_A, bool EPI_T>
+__global__ __launch_bounds__(kThreads, 1) void gemm_bf16x3_kernel(Bf16Desc g, int tiles_m, int tiles_n) {
+    constexpr int BM = 64 * BI, BN = 64 * BJ;
+    constexpr int A_ARR = BM * kPitch, B_ARR = BN * kPitch;
+    constexpr int BUF = 2 * A_ARR + 2 * B_ARR;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * BUF];  // per buffer: A_hi, A_lo, B_hi, B_lo
 
     const int lin = xcd_linear_id();
     const int per_batch = tiles_m * tiles_n;
     const int bidx = lin / per_batch;
     const int rr = lin % per_batch;
-    const int m0 = (rr % tiles_m) * kTile, n0 = (rr / tiles_m) * kTile;
+    const int m0 = (rr % tiles_m) * BM, n0 = (rr / tiles_m) * BN;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int h = lane >> 5, c = lane & 31;
 
-    ASlice<A_F32, VEC_A> la;
-    SplitSlice lb;
+    ASlice<BM, A_F32, VEC_A> la;
+    SplitSlice<BN> lb;
     const uint16_t* bh = g.b_hi + (int64_t)bidx * g.b_bs;
     const uint16_t* bl = g.b_lo + (int64_t)bidx * g.b_bs;
     const int nk = (g.K + kSlice - 1) / kSlice;
 
-    f32x16 acc[2][2];
+    f32x16 acc[BI][BJ];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < BI; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int j = 0; j < BJ; j++)
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
 
+    auto A_hi = [&](int b) { return lds + b * BUF; };
+    auto A_lo = [&](int b) { return lds + b * BUF + A_ARR; };
+    auto B_hi = [&](int b) { return lds + b * BUF + 2 * A_ARR; };
+    auto B_lo = [&](int b) { return lds + b * BUF + 2 * A_ARR + B_ARR; };
+
     la.fetch(g, bidx, m0, 0, tid);
     lb.load(bh, bl, g.ldb, n0, g.N, 0, g.K, tid);
-    la.store(lds[0][0], lds[0][1], tid);
-    lb.store(lds[0][2], lds[0][3], tid);
+    la.store(A_hi(0), A_lo(0), tid);
+    lb.store(B_hi(0), B_lo(0), tid);
     __syncthreads();
 
     for (int t = 0; t < nk; t++) {
@@ -200,39 +213,39 @@ __global__ __launch_bounds__(kThreads) void gemm_bf16x3_kernel(Bf16Desc g, int t
             la.fetch(g, bidx, m0, (t + 1) * kSlice, tid);
             lb.load(bh, bl, g.ldb, n0, g.N, (t + 1) * kSlice, g.K, tid);
         }
+        bf16x8 ah[BI], al[BI], bhv[BJ], blv[BJ];
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-            bf16x8 ah[2], al[2], bhv[2], blv[2];
-#pragma unroll
-            for (int i = 0; i < 2; i++) {
-                const int ra = (wm * 64 + i * 32 + c) * kPitch + j * 16 + h * 8;
-                const int rb = (wn * 64 + i * 32 + c) * kPitch + j * 16 + h * 8;
-                ah[i] = *reinterpret_cast<const bf16x8*>(&lds[cur][0][ra]);
-                al[i] = *reinterpret_cast<const bf16x8*>(&lds[cur][1][ra]);
-                bhv[i] = *reinterpret_cast<const bf16x8*>(&lds[cur][2][rb]);
-                blv[i] = *reinterpret_cast<const bf16x8*>(&lds[cur][3][rb]);
-            }
-#pragma unroll
-            for (int i = 0; i < 2; i++)
-#pragma unroll
-                for (int k = 0; k < 2; k++) {
-                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhv[k], acc[i][k], 0, 0, 0);
-                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], blv[k], acc[i][k], 0, 0, 0);
-                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhv[k], acc[i][k], 0, 0, 0);
-                }
+        for (int i = 0; i < BI; i++) {
+            const int ra = (wm * 32 * BI + i * 32 + c) * kPitch + h * 8;
+            ah[i] = *reinterpret_cast<const bf16x8*>(A_hi(cur) + ra);
+            al[i] = *reinterpret_cast<const bf16x8*>(A_lo(cur) + ra);
         }
+#pragma unroll
+        for (int j = 0; j < BJ; j++) {
+            const int rb = (wn * 32 * BJ + j * 32 + c) * kPitch + h * 8;
+            bhv[j] = *reinterpret_cast<const bf16x8*>(B_hi(cur) + rb);
+            blv[j] = *reinterpret_cast<const bf16x8*>(B_lo(cur) + rb);
+        }
+#pragma unroll
+        for (int i = 0; i < BI; i++)
+#pragma unroll
+            for (int k = 0; k < BJ; k++) {
+                acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhv[k], acc[i][k], 0, 0, 0);
+                acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], blv[k], acc[i][k], 0, 0, 0);
+                acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhv[k], acc[i][k], 0, 0, 0);
+            }
         if (t + 1 < nk) {
-            la.store(lds[cur ^ 1][0], lds[cur ^ 1][1], tid);
-            lb.store(lds[cur ^ 1][2], lds[cur ^ 1][3], tid);
+            la.store(A_hi(cur ^ 1), A_lo(cur ^ 1), tid);
+            lb.store(B_hi(cur ^ 1), B_lo(cur ^ 1), tid);
         }
         __syncthreads();
     }
 
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < BI; i++)
 #pragma unroll
-        for (int k = 0; k < 2; k++) {
-            const int col = n0 + wn * 64 + k * 32 + c;
+        for (int k = 0; k < BJ; k++) {
+            const int col = n0 + wn * 32 * BJ + k * 32 + c;
             if (col >= g.N) continue;
             if (EPI_T) {
                 const int beta = col / g.d, s = col % g.d;
@@ -240,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void gemm_bf16x3_kernel(Bf16Desc g, int t
                 uint16_t* tl = g.t_lo + (int64_t)bidx * g.t_bs + (int64_t)beta * g.t_ld + s;
 #pragma unroll
                 for (int v = 0; v < 16; v++) {
-                    const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                    const int row = m0 + wm * 32 * BI + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
                     if (row < g.M) {
                         const float x = acc[i][k][v];
                         const uint16_t hh = rne_bf16(x);
@@ -252,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void gemm_bf16x3_kernel(Bf16Desc g, int t
                 float* cb = g.c + (int64_t)bidx * g.c_bs;
 #pragma unroll
                 for (int v = 0; v < 16; v++) {
-                    const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                    const int row = m0 + wm * 32 * BI + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
                     if (row < g.M) cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
                 }
             }
@@ -296,14 +309,22 @@ __global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ 
 inline int64_t pad8(int64_t k) { return (k + 7) / 8 * 8; }
 inline size_t al256(size_t n) { return (n + 255) / 256 * 256; }
 
-template <bool A_F32, bool VEC_A, bool EPI_T>
-hipError_t launch_bf16(const Bf16Desc& g, hipStream_t s) {
-    const int tm = (g.M + kTile - 1) / kTile, tn = (g.N + kTile - 1) / kTile;
+template <int BI, bool A_F32, bool VEC_A, bool EPI_T>
+hipError_t launch_tile(const Bf16Desc& g, hipStream_t s) {
+    const int edge = 64 * BI;
+    const int tm = (g.M + edge - 1) / edge, tn = (g.N + edge - 1) / edge;
     const int64_t tiles = (int64_t)tm * tn * g.batch;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<A_F32, VEC_A, EPI_T>), dim3((unsigned)tiles), dim3(kThreads), 0, s,
-                       g, tm, tn);
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<BI, BI, A_F32, VEC_A, EPI_T>), dim3((unsigned)tiles), dim3(kThreads),
+                       0, s, g, tm, tn);
     return hipGetLastError();
+}
+
+// 256 x 256 tiles when both output extents reach 256, else 128 x 128.
+template <bool A_F32, bool VEC_A, bool EPI_T>
+hipError_t launch_bf16(const Bf16Desc& g, hipStream_t s) {
+    if (g.M >= 256 && g.N >= 256) return launch_tile<4, A_F32, VEC_A, EPI_T>(g, s);
+    return launch_tile<2, A_F32, VEC_A, EPI_T>(g, s);
 }
 
 struct Bf16Layout {

@@ -49,19 +49,26 @@ __global__ __launch_bounds__(256) void psi_products(const T* __restrict__ X, int
     }
 }
 
-// v[b][c] = sum over stripes (fixed order); also S_w = sum_b w_b, S_v = sum_b v_b.
-__global__ void finish_vectors(const double* __restrict__ w, const double* __restrict__ vpart,
-                               double* __restrict__ v, double* __restrict__ sw,
-                               double* __restrict__ sv, int mp, int n_ops, int stripes) {
+// v[b][c] = sum over stripes (fixed order), one thread per (b, c)
+__global__ void reduce_stripes(const double* __restrict__ vpart, double* __restrict__ v, int mp, int n_ops,
+                               int stripes) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)mp * n_ops) return;
+    const int64_t b = idx / mp, c = idx % mp;
+    double acc = 0.0;
+    for (int s = 0; s < stripes; s++) acc += vpart[(b * stripes + s) * mp + c];
+    v[idx] = acc;
+}
+
+// S_w = sum_b w_b, S_v = sum_b v_b (fixed order over b)
+__global__ void sum_over_ops(const double* __restrict__ w, const double* __restrict__ v, double* __restrict__ sw,
+                             double* __restrict__ sv, int mp, int n_ops) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= mp) return;
     double tw = 0.0, tv = 0.0;
     for (int b = 0; b < n_ops; b++) {
-        double acc = 0.0;
-        for (int s = 0; s < stripes; s++) acc += vpart[((int64_t)b * stripes + s) * mp + c];
-        v[(int64_t)b * mp + c] = acc;
-        tv += acc;
         tw += w[(int64_t)b * mp + c];
+        tv += v[(int64_t)b * mp + c];
     }
     sw[c] = tw;
     sv[c] = tv;
@@ -162,8 +169,10 @@ hipError_t pair_loss(const void* X, int mp, int n_ops, int64_t stride, bool is_d
     else
         hipLaunchKernelGGL(psi_products<float>, g1, dim3(256), 0, stream,
                            static_cast<const float*>(X), mp, stride, psi, w, vpart, stripes);
-    hipLaunchKernelGGL(finish_vectors, dim3((mp + 255) / 256), dim3(256), 0, stream, w, vpart, v, sw,
-                       sv, mp, n_ops, stripes);
+    const int64_t nv = (int64_t)mp * n_ops;
+    hipLaunchKernelGGL(reduce_stripes, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, stream, vpart, v, mp,
+                       n_ops, stripes);
+    hipLaunchKernelGGL(sum_over_ops, dim3((mp + 255) / 256), dim3(256), 0, stream, w, v, sw, sv, mp, n_ops);
     if (pairs)
         hipLaunchKernelGGL(pair_dots, dim3(n_ops, n_ops), dim3(256), 0, stream, v, w, pairs, mp, n_ops);
     hipLaunchKernelGGL(loss_dot, dim3(1), dim3(256), 0, stream, sv, sw, loss, mp);

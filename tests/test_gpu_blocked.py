@@ -121,3 +121,28 @@ def test_blocked_repeat_uses_cached_plan_and_is_deterministic(rot):
     _, a = run_blocked(rot, case)
     _, b = run_blocked(rot, case)
     np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("path", ["fused", "grouped"])
+def test_blocked_each_path_vs_oracle(rot, oracle_mod, monkeypatch, path):
+    """Both execution paths (one fused wave per output block; two grouped
+    launches through an intermediate) against the oracle, on sectors up to
+    90 states (beyond one 80-row register set of the fused kernel)."""
+    monkeypatch.setenv("ROT_BLOCKED_PATH", path)
+    sizes = workloads.gaussian_sector_sizes(500, sigma=1.3, min_dim=5, max_dim=90)
+    kept = [(qn, max(1, s - 3)) for qn, s in sizes]
+    case = workloads.blocked_case(sizes=sizes, kept_sizes=kept, n_conserving=3, n_up_shift=3, n_dn_shift=3,
+                                  cfg=54)
+    pk, flat = run_blocked(rot, case)
+    ref, _ = oracle_mod.rotate_blocked(case)
+    check(case, pk, flat, ref, range(len(case.shifts)))
+
+
+@pytest.mark.parametrize("path", ["fused", "grouped"])
+def test_blocked_1024_each_path_sampled(rot, oracle_mod, monkeypatch, path):
+    monkeypatch.setenv("ROT_BLOCKED_PATH", path)
+    case = workloads.blocked_case()
+    pk, flat = run_blocked(rot, case)
+    ops = [3, 201, 377]
+    ref, _ = oracle_mod.rotate_blocked(subset(case, ops))
+    check(case, pk, flat, ref, ops)
