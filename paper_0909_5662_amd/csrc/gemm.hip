@@ -58,9 +58,24 @@ struct Slice {
     V r[CHUNKS];
 
     // base points at element (row 0, k 0) of the operand; rows/ks are the
-    // operand's full extents; r0/k0 the slice origin.
+    // operand's full extents; r0/k0 the slice origin.  A slice wholly inside
+    // the operand (uniform over the workgroup) takes unconditional vector
+    // loads, so they are all in flight together; edge slices load element by
+    // element with bounds checks.
     __device__ inline void load(const T* __restrict__ base, int64_t ld, int r0, int rows, int k0,
                                 int ks, int tid) {
+        const bool interior = VEC && r0 + kTile <= rows && k0 + kSlice <= ks;
+        if (interior) {
+#pragma unroll
+            for (int c = 0; c < CHUNKS; c++) {
+                const int f = tid + c * kThreads;
+                const int row = KCONTIG ? f / (kSlice / VW) : (f % (kTile / VW)) * VW;
+                const int k = KCONTIG ? (f % (kSlice / VW)) * VW : f / (kTile / VW);
+                const T* p = KCONTIG ? base + (int64_t)(r0 + row) * ld + k0 + k : base + (int64_t)(k0 + k) * ld + r0 + row;
+                r[c] = *reinterpret_cast<const V*>(p);
+            }
+            return;
+        }
 #pragma unroll
         for (int c = 0; c < CHUNKS; c++) {
             const int f = tid + c * kThreads;
@@ -73,17 +88,11 @@ struct Slice {
                 row = (f % (kTile / VW)) * VW;
             }
             const int gr = r0 + row, gk = k0 + k;
-            // element (row+e or k+e) of this chunk lies along the contiguous dim
-            const bool full = KCONTIG ? (gr < rows && gk + VW <= ks) : (gk < ks && gr + VW <= rows);
             const T* p = KCONTIG ? base + (int64_t)gr * ld + gk : base + (int64_t)gk * ld + gr;
-            if (VEC && full) {
-                r[c] = *reinterpret_cast<const V*>(p);
-            } else {
 #pragma unroll
-                for (int e = 0; e < VW; e++) {
-                    const bool ok = KCONTIG ? (gr < rows && gk + e < ks) : (gk < ks && gr + e < rows);
-                    r[c][e] = ok ? p[e] : T(0);
-                }
+            for (int e = 0; e < VW; e++) {
+                const bool ok = KCONTIG ? (gr < rows && gk + e < ks) : (gk < ks && gr + e < rows);
+                r[c][e] = ok ? p[e] : T(0);
             }
         }
     }

@@ -36,8 +36,22 @@ struct GSlice {
     static_assert(CHUNKS >= 1 && CHUNKS * NT * 4 == R * kSlice, "slice must split evenly over threads");
     f32x4 r[CHUNKS];
 
+    // A slice wholly inside the operand (uniform over the workgroup) takes
+    // unconditional vector loads; edge slices load element by element.
     __device__ inline void load(const float* __restrict__ base, int64_t ld, int r0, int rows, int k0, int ks,
                                 bool vec, int tid) {
+        if (vec && r0 + R <= rows && k0 + kSlice <= ks) {
+#pragma unroll
+            for (int c = 0; c < CHUNKS; c++) {
+                const int f = tid + c * NT;
+                const int row = KCONTIG ? f / (kSlice / 4) : (f % (R / 4)) * 4;
+                const int k = KCONTIG ? (f % (kSlice / 4)) * 4 : f / (R / 4);
+                const float* p = KCONTIG ? base + (int64_t)(r0 + row) * ld + k0 + k
+                                         : base + (int64_t)(k0 + k) * ld + r0 + row;
+                r[c] = *reinterpret_cast<const f32x4*>(p);
+            }
+            return;
+        }
 #pragma unroll
         for (int c = 0; c < CHUNKS; c++) {
             const int f = tid + c * NT;
@@ -50,16 +64,11 @@ struct GSlice {
                 row = (f % (R / 4)) * 4;
             }
             const int gr = r0 + row, gk = k0 + k;
-            const bool full = KCONTIG ? (gr < rows && gk + 4 <= ks) : (gk < ks && gr + 4 <= rows);
             const float* p = KCONTIG ? base + (int64_t)gr * ld + gk : base + (int64_t)gk * ld + gr;
-            if (vec && full) {
-                r[c] = *reinterpret_cast<const f32x4*>(p);
-            } else {
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const bool ok = KCONTIG ? (gr < rows && gk + e < ks) : (gk < ks && gr + e < rows);
-                    r[c][e] = ok ? p[e] : 0.f;
-                }
+            for (int e = 0; e < 4; e++) {
+                const bool ok = KCONTIG ? (gr < rows && gk + e < ks) : (gk < ks && gr + e < rows);
+                r[c][e] = ok ? p[e] : 0.f;
             }
         }
     }
