@@ -138,7 +138,11 @@ struct BlkTerm {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int MAXA>
+// MAXA: most 16-wide blocks of output rows (kept dim of T) a task can have;
+// CG: output column blocks (kept dim of Q) handled together, so each value of
+// the operator block fetched in stage 1 feeds CG instructions and each value
+// of U_T fetched in stage 2 feeds CG instructions.
+template <int MAXA, int CG>
 __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __restrict__ tasks, int n_tasks,
                                                             const BlkTerm* __restrict__ terms,
                                                             const float* __restrict__ U, const float* __restrict__ O,
@@ -153,27 +157,37 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
         const float* uT = U + T.uT_off;
         const float* uQ = U + T.uQ_off;
         const int nbc = (T.mQ + 15) >> 4, nba = (T.mT + 15) >> 4;
-        for (int cb = 0; cb < nbc; cb++) {
-            const int beta = cb * 16 + li;  // this lane's column of X / U_Q
-            f32x4 acc[MAXA];
+        for (int cg0 = 0; cg0 < nbc; cg0 += CG) {
+            f32x4 acc[CG][MAXA];
 #pragma unroll
-            for (int ca = 0; ca < MAXA; ca++) acc[ca] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < CG; c++)
+#pragma unroll
+                for (int ca = 0; ca < MAXA; ca++) acc[c][ca] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int e = 0; e < T.n_terms; e++) {
                 const BlkTerm tm = terms[T.term0 + e];
                 const float* o = O + tm.o_off;
                 for (int rb = 0; rb * 16 < tm.a; rb++) {
-                    // stage 1: 16 x 16 block of X_s
-                    f32x4 x = {0.f, 0.f, 0.f, 0.f};
+                    // stage 1: X_s rows 16 rb.., column blocks cg0 .. cg0+CG-1
+                    f32x4 x[CG];
+#pragma unroll
+                    for (int c = 0; c < CG; c++) x[c] = f32x4{0.f, 0.f, 0.f, 0.f};
                     const int row = rb * 16 + li;
-#pragma unroll 4
+#pragma unroll 2
                     for (int k0 = 0; k0 < tm.k; k0 += 4) {
                         const int k = k0 + lh;
-                        const float av = (row < tm.a && k < tm.k) ? o[(int64_t)row * tm.k + k] : 0.f;
-                        const float bv = (k < tm.k && beta < T.mQ) ? uQ[(int64_t)(tm.rq + k) * T.mQ + beta] : 0.f;
-                        x = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, x, 0, 0, 0);
+                        const bool kok = k < tm.k;
+                        const float av = (row < tm.a && kok) ? o[(int64_t)row * tm.k + k] : 0.f;
+                        const float* uqrow = uQ + (int64_t)(tm.rq + k) * T.mQ;
+#pragma unroll
+                        for (int c = 0; c < CG; c++) {
+                            const int beta = (cg0 + c) * 16 + li;
+                            const float bv = (kok && beta < T.mQ) ? uqrow[beta] : 0.f;
+                            x[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, x[c], 0, 0, 0);
+                        }
                     }
-                    // stage 2: acc(beta, alpha) += sum_r X_s[r][beta] U_T[rt + r][alpha]
-#pragma unroll 1
+                    // stage 2: acc(beta, alpha) += sum_r X_s[r][beta] U_T[rt + r][alpha], the X block
+                    // in accumulator layout read with k order 4*(l/16) + j at step j
+#pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const int r = rb * 16 + 4 * lh + j;
                         const bool rok = r < tm.a;
@@ -183,24 +197,28 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
                             if (ca < nba) {
                                 const int alpha = ca * 16 + li;
                                 const float bv = (rok && alpha < T.mT) ? urow[alpha] : 0.f;
-                                acc[ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j], bv, acc[ca], 0, 0, 0);
+#pragma unroll
+                                for (int c = 0; c < CG; c++)
+                                    acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], bv, acc[c][ca], 0, 0, 0);
                             }
                         }
                     }
                 }
             }
-            // acc[ca] element v of lane l = Out^T(beta = 16 cb + 4*(l/16) + v, alpha = 16 ca + l%16)
+            // acc[c][ca] element v of lane l = Out^T(beta = 16 (cg0+c) + 4*(l/16) + v, alpha = 16 ca + l%16)
 #pragma unroll
-            for (int ca = 0; ca < MAXA; ca++) {
-                const int alpha = ca * 16 + li;
-                if (ca < nba && alpha < T.mT) {
+            for (int c = 0; c < CG; c++)
 #pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int b = cb * 16 + 4 * lh + v;
-                        if (b < T.mQ) out[T.out_off + (int64_t)alpha * T.mQ + b] = acc[ca][v];
+                for (int ca = 0; ca < MAXA; ca++) {
+                    const int alpha = ca * 16 + li;
+                    if (ca < nba && alpha < T.mT) {
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const int b = (cg0 + c) * 16 + 4 * lh + v;
+                            if (b < T.mQ) out[T.out_off + (int64_t)alpha * T.mQ + b] = acc[c][ca][v];
+                        }
                     }
                 }
-            }
         }
         if (lane == 0) t = atomicAdd(counter, 1);
         t = __shfl(t, 0, 64);
@@ -356,7 +374,7 @@ struct Plan {
     BlkTerm* f_terms = nullptr;
     int f_n_tasks = 0;
     int f_max_mT = 0;
-    int path = -1;  // 0 grouped two-stage, 1 fused; -1 not chosen yet
+    int path = -1;  // 0 grouped two-stage, 1 fused, 2 fused wide; -1 not chosen yet
     ~Plan() {
         (void)hipFree(s1.probs);
         (void)hipFree(s1.tiles);
@@ -477,32 +495,47 @@ hipError_t run_grouped(const rot_blocked_problem* p, Plan* plan, void* ws, Group
     return prof_timed("blocked_stage2_fp32", stream, [&] { return grouped_gemm_f32(b, stream); });
 }
 
-hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, hipStream_t stream) {
+// Fused variants: (register set of output row blocks, column blocks per
+// pass); `wide` keeps every column block of a task in one pass (fewest
+// operand fetches), otherwise fewer per pass (more resident waves).
+template <int MAXA, int CG>
+void launch_fused(const rot_blocked_problem* p, Plan* plan, hipStream_t stream) {
+    const int grid = 256 * 4;  // 4 workgroups of 4 waves per CU, each wave a task queue consumer
+    hipLaunchKernelGGL((blocked_fused_kernel<MAXA, CG>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
+                       plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
+}
+
+hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, hipStream_t stream) {
     if (plan->f_n_tasks == 0) return hipSuccess;
     return prof_timed("blocked_fused_fp32", stream, [&] {
         hipLaunchKernelGGL(reset_fused_counter, dim3(1), dim3(64), 0, stream, plan->counter);
-        const int grid = 256 * 4;  // 4 workgroups of 4 waves per CU, each wave a task queue consumer
-        if (plan->f_max_mT <= 64)
-            hipLaunchKernelGGL((blocked_fused_kernel<4>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
-                               plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
-        else if (plan->f_max_mT <= 80)
-            hipLaunchKernelGGL((blocked_fused_kernel<5>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
-                               plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
-        else
-            hipLaunchKernelGGL((blocked_fused_kernel<8>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
-                               plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
+        if (plan->f_max_mT <= 64) {
+            if (wide) launch_fused<4, 4>(p, plan, stream); else launch_fused<4, 2>(p, plan, stream);
+        } else if (plan->f_max_mT <= 80) {
+            if (wide) launch_fused<5, 5>(p, plan, stream); else launch_fused<5, 3>(p, plan, stream);
+        } else {
+            if (wide) launch_fused<8, 3>(p, plan, stream); else launch_fused<8, 2>(p, plan, stream);
+        }
         return hipGetLastError();
     });
 }
 
-// ROT_BLOCKED_PATH = fused | grouped forces a path; otherwise both are timed
-// once per block structure and the faster is kept.
+// Paths: 0 two grouped launches, 1 fused (narrow passes), 2 fused (wide).
+// ROT_BLOCKED_PATH = grouped | fused | fused_wide forces one; otherwise all
+// are timed once per block structure and the fastest is kept.
 int forced_path() {
     const char* e = getenv("ROT_BLOCKED_PATH");
     if (!e) return -1;
-    if (!strcmp(e, "fused")) return 1;
     if (!strcmp(e, "grouped")) return 0;
+    if (!strcmp(e, "fused")) return 1;
+    if (!strcmp(e, "fused_wide")) return 2;
     return -1;
+}
+
+hipError_t run_path(const rot_blocked_problem* p, Plan* plan, void* ws, GroupedShape shape, int path,
+                    hipStream_t stream) {
+    if (path == 0) return run_grouped(p, plan, ws, shape, stream);
+    return run_fused(p, plan, path == 2, stream);
 }
 
 }  // namespace
@@ -552,32 +585,37 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         plan = g_plans.front().get();
     }
     int path = forced >= 0 ? forced : plan->path;
-    if (path == 1 && plan->f_max_mT > 128) path = 0;
+    if (path >= 1 && plan->f_max_mT > 128) path = 0;
     if (path < 0) {
-        // time both (second run of each, after a warm-up run)
-        hipEvent_t a, b, c;
-        hipError_t e = hipEventCreate(&a);
-        if (e == hipSuccess) e = hipEventCreate(&b);
-        if (e == hipSuccess) e = hipEventCreate(&c);
+        // time each path (second run, after a warm-up run)
+        const int n_paths = plan->f_max_mT > 128 ? 1 : 3;
+        hipEvent_t ev[4];
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
         for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
-            e = hipEventRecord(a, stream);
-            if (e == hipSuccess) e = run_grouped(p, plan, ws, shape, stream);
-            if (e == hipSuccess) e = hipEventRecord(b, stream);
-            if (e == hipSuccess) e = run_fused(p, plan, stream);
-            if (e == hipSuccess) e = hipEventRecord(c, stream);
+            for (int q = 0; q < n_paths && e == hipSuccess; q++) {
+                e = hipEventRecord(ev[q], stream);
+                if (e == hipSuccess) e = run_path(p, plan, ws, shape, q, stream);
+            }
+            if (e == hipSuccess) e = hipEventRecord(ev[n_paths], stream);
         }
-        float t_grouped = 0.f, t_fused = 0.f;
-        if (e == hipSuccess) e = hipEventSynchronize(c);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t_grouped, a, b);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t_fused, b, c);
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        (void)hipEventDestroy(c);
+        float best = 1e30f;
+        int best_q = 0;
+        if (e == hipSuccess) e = hipEventSynchronize(ev[n_paths]);
+        for (int q = 0; q < n_paths && e == hipSuccess; q++) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            if (ms < best) {
+                best = ms;
+                best_q = q;
+            }
+        }
+        for (int i = 0; i < 4; i++) (void)hipEventDestroy(ev[i]);
         if (e != hipSuccess) return e;
-        plan->path = t_fused <= t_grouped ? 1 : 0;
-        return hipSuccess;  // the last timed run (fused) or both left the full result in out_blk
+        plan->path = best_q;
+        return hipSuccess;  // every timed run left the full result in out_blk
     }
-    return path == 1 ? run_fused(p, plan, stream) : run_grouped(p, plan, ws, shape, stream);
+    return run_path(p, plan, ws, shape, path, stream);
 }
 
 }  // namespace rot

@@ -123,7 +123,7 @@ def test_blocked_repeat_uses_cached_plan_and_is_deterministic(rot):
     np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("path", ["fused", "grouped"])
+@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped"])
 def test_blocked_each_path_vs_oracle(rot, oracle_mod, monkeypatch, path):
     """Both execution paths (one fused wave per output block; two grouped
     launches through an intermediate) against the oracle, on sectors up to
@@ -138,7 +138,7 @@ def test_blocked_each_path_vs_oracle(rot, oracle_mod, monkeypatch, path):
     check(case, pk, flat, ref, range(len(case.shifts)))
 
 
-@pytest.mark.parametrize("path", ["fused", "grouped"])
+@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped"])
 def test_blocked_1024_each_path_sampled(rot, oracle_mod, monkeypatch, path):
     monkeypatch.setenv("ROT_BLOCKED_PATH", path)
     case = workloads.blocked_case()
