@@ -219,7 +219,7 @@ def bench_uneven(args, rot, torch, workloads):
 
 
 def bench_differentiated(args, rot, torch, workloads):
-    """Forward (FP32) + FP64 pair loss + adjoint (FP32, stage 1 recomputed)
+    """Forward (FP32) + FP64 pair loss + adjoint (FP32, nothing stored)
     through torch.autograd, m = m' = 1024, d = 4, 64 symmetric operators."""
     case = workloads.named_dense(WORKLOAD)
     psi = torch.from_numpy(workloads.psi_vector(case.mp, workloads.rng(5, 2))).cuda()
@@ -250,9 +250,9 @@ def bench_differentiated(args, rot, torch, workloads):
     ms = t0.elapsed_time(t1) / args.steps
     n, m, mp, d = 64, 1024, 1024, 4
     f_fwd = n * flops_per_op(m, d, mp)
-    # backward: P = U dOut (2 md mp^2), dO = P U_r^T (2 m^2 d mp), T (2 m^2 d mp),
-    # dU terms 2 x (2 md mp^2) per operator
-    f_bwd = n * (2.0 * m * d * mp * mp + 2.0 * m * m * d * mp + 2.0 * m * m * d * mp + 4.0 * m * d * mp * mp)
+    # backward per symmetric operator: P = U dOut and P += U dOut^T (2 md mp^2
+    # each), dO = P_r U_r^T and dU_r += O P_r (2 m^2 d mp each)
+    f_bwd = n * (4.0 * m * d * mp * mp + 4.0 * m * m * d * mp)
     tflops = (f_fwd + f_bwd) / (ms / 1e3) / 1e12
     rec = base_record(args, n / (ms / 1e3), "operator rotations/s (forward + loss + adjoint)", ms,
                       {"workload": "differentiated_m1024_n64", "m": m, "d": d, "mp": mp, "n_ops": n,

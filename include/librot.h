@@ -102,7 +102,12 @@ ROT_API rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_pr
  * Workspace bytes needed by rot_batch / rot_backward for these groups when
  * up to `ops_per_chunk` operators are processed at once (<= 0: all
  * operators of the largest group).  `for_backward` != 0 sizes it for
- * rot_backward.  Returns 0 for invalid arguments.
+ * rot_backward: the chunk's intermediates plus, when dU has fewer than
+ * 1024 output tiles of 128x128, up to 8 partial sums of dU (the operator sum
+ * is split into parts that run concurrently and are added in fixed order).
+ * rot_backward accepts any workspace of at least the ops_per_chunk = 1 size
+ * and uses fewer parts, or none, when it is smaller.  Returns 0 for invalid
+ * arguments.
  */
 ROT_API size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_precision prec,
                           int32_t ops_per_chunk, int32_t for_backward);
@@ -115,10 +120,14 @@ ROT_API size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, r
  *                                      s, s+d, s+2d, ... of U
  *   dU   = sum_b [ (O_b (x) I) U dOut_b^T + (O_b^T (x) I) U dOut_b ]
  *                                     ((m*d) x mp at dU[g], summed over b)
- * Stage 1 is recomputed, never stored between calls.  dO, dU (host arrays of
- * n_groups device pointers) may be NULL, and so may any element, to skip
- * that output.  flags: ROT_ASSUME_SYMMETRIC_O lets the library reuse stage 1
- * for the transposed term (valid only when every O_b is symmetric).
+ * Nothing is kept from the forward call: with P_b = U dOut_b and
+ * Q_b = U dOut_b^T (viewed as m x d*mp), dO_b = P_b U_r^T and
+ * dU = sum_b O_b^T P_b + O_b Q_b, so the stage-1 intermediate is never
+ * formed.  dO, dU (host arrays of n_groups device pointers) may be NULL, and
+ * so may any element, to skip that output.  flags: ROT_ASSUME_SYMMETRIC_O
+ * merges the two dU terms into sum_b O_b (P_b + Q_b) (valid only when every
+ * O_b is symmetric): four products of 2 m^2 d mp flops per operator instead
+ * of five.
  * Summation order is fixed: results are deterministic.
  */
 #define ROT_ASSUME_SYMMETRIC_O 1u

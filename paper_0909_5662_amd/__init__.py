@@ -430,8 +430,9 @@ class Plan:
 
 
 class RotateFn(torch.autograd.Function):
-    """Differentiable rotation.  Saves only U and O; stage 1 is recomputed in
-    the backward kernel."""
+    """Differentiable rotation.  Saves only U and O; the backward forms
+    U dOut_b (and U dOut_b^T) and contracts them with O_b, so no stage-1
+    intermediate is stored."""
 
     @staticmethod
     def forward(ctx, U, O, d, precision="fp32", symmetric_O=False):

@@ -29,7 +29,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kTile = 128;   // BM = BN
+constexpr int kTile = kGemmTile;   // BM = BN
 constexpr int kSlice = 16;   // K elements per LDS slice
 constexpr int kPadK = 4;     // row padding (elements) of K-contiguous LDS tiles
 constexpr int kPadMN = 4;    // row padding (elements) of M/N-contiguous LDS tiles

@@ -92,6 +92,20 @@ size_t t_bytes(const rot_problem& p, rot_precision prec) {
     return align_up((size_t)p.m * p.d * p.mp * elem_size(prec));
 }
 
+// The dU reduction of rot_backward is one GEMM with M = m, N = d*mp and a K
+// range over every operator of a chunk; when its 128x128 output tiles are too
+// few to fill the chip the operator range is split into parts, each reduced
+// into its own partial dU (one workspace slot of t_bytes), and the parts are
+// summed in fixed order.  Returns the number of parts (0: no split) for a
+// chunk of `ops` operators.
+int du_split_parts(const rot_problem& p, int ops) {
+    const int64_t tiles = (((int64_t)p.m + kGemmTile - 1) / kGemmTile) *
+                          (((int64_t)p.d * p.mp + kGemmTile - 1) / kGemmTile);
+    int parts = (int)std::min<int64_t>(8, (4 * 256 + tiles - 1) / tiles);
+    parts = std::min(parts, ops);
+    return parts > 1 ? parts : 0;
+}
+
 rot_status validate_group(const rot_problem& p, int gi) {
     if (p.m <= 0 || p.d <= 0 || p.mp <= 0)
         return fail(ROT_ERR_INVALID_ARG, "group %d: m, d, mp must be positive (m=%d d=%d mp=%d)", gi,
@@ -257,6 +271,8 @@ size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_preci
         size_t g;
         if (prec == ROT_SPLIT_BF16 && !for_backward)
             g = bf16_group_workspace(p.m, p.d, p.mp, ops);
+        else if (for_backward)
+            g = (size_t)(ops + du_split_parts(p, ops)) * t_bytes(p, prec == ROT_FP64 ? ROT_FP64 : ROT_FP32);
         else
             g = (size_t)ops * t_bytes(p, prec == ROT_FP64 ? ROT_FP64 : ROT_FP32);
         need = std::max(need, g);
@@ -351,51 +367,91 @@ rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void*
             }
             continue;
         }
+        if (!dOg && !dUg) continue;
         const int64_t md = (int64_t)p.m * p.d, tsz = md * p.mp;
         const size_t per_op = t_bytes(p, prec);
-        const int chunk = (int)std::min<size_t>((size_t)p.n_ops, workspace_bytes / per_op);
+        const size_t slots = workspace_bytes / per_op;
+        // Chunk size, leaving `parts` slots for the partial dU sums when dU is
+        // wanted and the workspace holds at least one operator per part.
+        int parts = 0;
+        if (dUg) {
+            parts = du_split_parts(p, p.n_ops);
+            while (parts > 1 && slots < (size_t)2 * parts) parts /= 2;
+            if (parts < 2) parts = 0;
+        }
+        const int chunk = (int)std::min<size_t>((size_t)p.n_ops, slots - parts);
         const char* dout_base = static_cast<const char*>(dOut[gi]);
         const int64_t sd = stride_dout[gi];
+        char* partial = static_cast<char*>(workspace) + (size_t)chunk * per_op;
+        const int64_t part_stride = (int64_t)(per_op / es);
         for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
             const int nb = std::min(chunk, p.n_ops - b0);
             const void* g_b0 = dout_base + (size_t)b0 * sd * es;
             hipError_t e = hipSuccess;
-            if (dOg) {
-                // P_b = U dOut_b   ((m*d) x mp)
+            // P_b = U dOut_b ((m*d) x mp), the only intermediate: the adjoint of
+            // stage 2 applied to dOut_b.  Viewed as P_b,r (m x d*mp) it gives
+            // dO_b = P_b,r U_r^T, and dU_r = sum_b (O_b^T P_b,r + O_b Q_b,r)
+            // with Q_b = U dOut_b^T, so stage 1 (O_b U_r) is never formed.
+            auto form_P = [&](bool transposed, bool accumulate, const char* what) {
                 GemmDesc a{};
                 a.M = (int)md; a.N = p.mp; a.K = p.mp; a.batch = nb; a.kbatch = 1;
                 a.A = p.U; a.lda = p.mp; a.a_bs = 0; a.a_kcontig = true;
-                a.B = g_b0; a.ldb = p.mp; a.b_bs = sd; a.b_kcontig = false;
-                a.C = workspace; a.ldc = p.mp; a.c_bs = tsz;
-                e = gemm(prec, a, s, "adj_P");
-                // dO_b = P_b (m x d*mp) * U_r^T
+                // B(alpha, beta) = dOut_b[alpha][beta], or dOut_b[beta][alpha] for Q_b
+                a.B = g_b0; a.ldb = p.mp; a.b_bs = sd; a.b_kcontig = transposed;
+                a.C = workspace; a.ldc = p.mp; a.c_bs = tsz; a.accumulate = accumulate;
+                return gemm(prec, a, s, what);
+            };
+            e = form_P(false, false, "adj_P");
+            if (dOg && e == hipSuccess) {
                 GemmDesc b{};
                 b.M = p.m; b.N = p.m; b.K = p.d * p.mp; b.batch = nb; b.kbatch = 1;
                 b.A = workspace; b.lda = (int64_t)p.d * p.mp; b.a_bs = tsz; b.a_kcontig = true;
                 b.B = p.U; b.ldb = (int64_t)p.d * p.mp; b.b_bs = 0; b.b_kcontig = true;
                 b.C = static_cast<char*>(dOg) + (size_t)b0 * p.m * p.m * es; b.ldc = p.m;
                 b.c_bs = (int64_t)p.m * p.m;
-                if (e == hipSuccess) e = gemm(prec, b, s, "adj_dO");
+                e = gemm(prec, b, s, "adj_dO");
             }
             if (dUg && e == hipSuccess) {
-                // T_b = O_b U_r, then dU (+)= sum_b T_b dOut_b^T
-                e = gemm(prec, stage1(p, b0, nb, workspace, es), s, "adj_T");
-                GemmDesc c{};
-                c.M = (int)md; c.N = p.mp; c.K = p.mp; c.batch = 1; c.kbatch = nb;
-                c.A = workspace; c.lda = p.mp; c.a_ks = tsz; c.a_kcontig = true;
-                c.B = g_b0; c.ldb = p.mp; c.b_ks = sd; c.b_kcontig = true;  // B(beta, alpha) = dOut[alpha][beta]
-                c.C = dUg; c.ldc = p.mp; c.accumulate = b0 > 0;
-                if (e == hipSuccess) e = gemm(prec, c, s, "adj_dU");
-                if (!sym && e == hipSuccess) {
-                    // T~_b = O_b^T U_r
-                    GemmDesc t = stage1(p, b0, nb, workspace, es);
-                    t.a_kcontig = false;  // A(i, j) = O_b[j*m + i]
-                    e = gemm(prec, t, s, "adj_Tt");
+                // The chunk's operators go to np parts of q operators each; the
+                // remaining r operators are added to part 0.
+                const int np = parts ? std::min(parts, nb) : 1;
+                const int q = nb / np, r = nb % np;
+                // dU_r (or its part) (+)= sum over the part's operators of A_b P_b,r,
+                // A_b = O_b or O_b^T.
+                auto reduce = [&](bool o_transposed, bool acc_first) -> hipError_t {
+                    GemmDesc c{};
+                    c.M = p.m; c.N = p.d * p.mp; c.K = p.m; c.batch = np; c.kbatch = q;
+                    c.A = static_cast<const char*>(p.O) + (size_t)b0 * p.stride_o * es; c.lda = p.m;
+                    c.a_ks = p.stride_o; c.a_bs = q * p.stride_o;
+                    c.a_kcontig = !o_transposed;  // A(i, j) = O_b[i][j], or O_b[j][i]
+                    c.B = workspace; c.ldb = (int64_t)p.d * p.mp; c.b_ks = tsz; c.b_bs = q * tsz;
+                    c.b_kcontig = false;
+                    c.C = np > 1 ? static_cast<void*>(partial) : dUg; c.ldc = (int64_t)p.d * p.mp;
+                    c.c_bs = part_stride; c.accumulate = acc_first;
+                    hipError_t err = gemm(prec, c, s, "adj_dU");
+                    if (err == hipSuccess && r > 0) {
+                        GemmDesc t = c;
+                        t.batch = 1; t.kbatch = r; t.accumulate = true;
+                        t.A = static_cast<const char*>(c.A) + (size_t)np * q * p.stride_o * es;
+                        t.B = static_cast<const char*>(workspace) + (size_t)np * q * tsz * es;
+                        err = gemm(prec, t, s, "adj_dU");
+                    }
+                    return err;
+                };
+                const bool first_acc = np == 1 && b0 > 0;
+                if (sym) {
+                    // O_b = O_b^T: dU_r = sum_b O_b (P_b + Q_b)_r
+                    e = form_P(true, true, "adj_Q");
+                    if (e == hipSuccess) e = reduce(false, first_acc);
+                } else {
+                    e = reduce(true, first_acc);
+                    if (e == hipSuccess) e = form_P(true, false, "adj_Q");
+                    if (e == hipSuccess) e = reduce(false, true);
                 }
-                // dU += sum_b T~_b dOut_b   (T~ = T when O is symmetric)
-                c.b_kcontig = false;  // B(beta, alpha) = dOut[beta][alpha]
-                c.accumulate = true;
-                if (e == hipSuccess) e = gemm(prec, c, s, "adj_dU");
+                if (e == hipSuccess && np > 1)
+                    e = prof_timed("adj_dU_sum", s, [&] {
+                        return sum_parts(dUg, partial, md * p.mp, np, part_stride, b0 > 0, prec == ROT_FP64, s);
+                    });
             }
             if (e != hipSuccess) return hip_fail(e, "rot_backward launch");
         }

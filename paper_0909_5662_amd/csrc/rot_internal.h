@@ -69,11 +69,16 @@ rot_status set_error(rot_status s, const char* msg);
 hipError_t prof_timed(const char* name, hipStream_t stream, const std::function<hipError_t()>& launch);
 
 // Enqueue on `stream`; returns hipSuccess or the launch error.
+constexpr int kGemmTile = 128;  // output tile edge of gemm_f32 / gemm_f64
 hipError_t gemm_f32(const GemmDesc& g, hipStream_t stream);
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t stream);
 
 // Zero `bytes` bytes with a fill kernel (safe under stream capture).
 hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream);
+// dst (+)= sum of `parts` arrays of n elements at src + p*stride, summed in
+// ascending p (deterministic).
+hipError_t sum_parts(void* dst, const void* src, int64_t n, int parts, int64_t stride, bool accumulate,
+                     bool is_double, hipStream_t stream);
 
 // FP64 reductions (reduce_f64.hip).
 size_t pair_loss_workspace_bytes(int mp, int n_ops);

@@ -41,7 +41,34 @@ __global__ void zero_bytes_kernel(unsigned char* __restrict__ p, int64_t n) {
     if (i < n) p[i] = 0;
 }
 
+// dst[i] = (accumulate ? dst[i] : 0) + part_0[i] + part_1[i] + ... in that
+// fixed order (parts `stride` elements apart), so split-K results do not
+// depend on scheduling.
+template <typename T>
+__global__ void sum_parts_kernel(T* __restrict__ dst, const T* __restrict__ src, int64_t n, int parts,
+                                 int64_t stride, bool accumulate) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        T acc = accumulate ? dst[i] : T(0);
+        for (int p = 0; p < parts; p++) acc += src[i + p * stride];
+        dst[i] = acc;
+    }
+}
+
 }  // namespace
+
+hipError_t sum_parts(void* dst, const void* src, int64_t n, int parts, int64_t stride, bool accumulate,
+                     bool is_double, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 8192));
+    if (is_double)
+        hipLaunchKernelGGL(sum_parts_kernel<double>, grid, dim3(256), 0, stream, static_cast<double*>(dst),
+                           static_cast<const double*>(src), n, parts, stride, accumulate);
+    else
+        hipLaunchKernelGGL(sum_parts_kernel<float>, grid, dim3(256), 0, stream, static_cast<float*>(dst),
+                           static_cast<const float*>(src), n, parts, stride, accumulate);
+    return hipGetLastError();
+}
 
 hipError_t split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream) {
     hipLaunchKernelGGL(split_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, n, hi, lo);

@@ -86,6 +86,25 @@ def test_workspace_size_scales_with_chunk(rotlib):
     assert L.rot_workspace_size(arr, 1, rotlib.ROT_FP64, 1, 0) >= 2 * 100 * 4 * 90 * 4 - 256
 
 
+def test_backward_workspace_reserves_dU_parts(rotlib):
+    """With few 128x128 output tiles of dU (M = m*d, N = mp) the backward
+    workspace holds the chunk's intermediates plus up to 8 partial dU sums;
+    one operator per chunk needs no partial sums."""
+    L = rotlib.lib()
+    small = (rotlib.RotProblem * 1)(prob(rotlib, m=96, d=4, mp=80, n=11))
+    slot = L.rot_workspace_size(small, 1, rotlib.ROT_FP32, 1, 0)
+    assert L.rot_workspace_size(small, 1, rotlib.ROT_FP32, 1, 1) == slot
+    assert L.rot_workspace_size(small, 1, rotlib.ROT_FP32, 0, 1) == (11 + 8) * slot
+    assert L.rot_workspace_size(small, 1, rotlib.ROT_FP32, 3, 1) == (3 + 3) * slot
+    # 32 x 8 = 256 tiles: 4 parts; 2048 tiles: no split
+    mid = (rotlib.RotProblem * 1)(prob(rotlib, m=1024, d=4, mp=1024, n=64))
+    slot = L.rot_workspace_size(mid, 1, rotlib.ROT_FP32, 1, 0)
+    assert L.rot_workspace_size(mid, 1, rotlib.ROT_FP32, 0, 1) == (64 + 4) * slot
+    big = (rotlib.RotProblem * 1)(prob(rotlib, m=4096, d=4, mp=2048, n=4))
+    slot = L.rot_workspace_size(big, 1, rotlib.ROT_FP32, 1, 0)
+    assert L.rot_workspace_size(big, 1, rotlib.ROT_FP32, 0, 1) == 4 * slot
+
+
 def test_backward_argument_errors(rotlib):
     L = rotlib.lib()
     arr = (rotlib.RotProblem * 1)(prob(rotlib))

@@ -225,6 +225,32 @@ def test_adjoint_broadcast_gradient(rot, oracle_mod):
     assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= TOL32
 
 
+@pytest.mark.parametrize("slots", [None, 13, 3, 1])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_adjoint_dU_split_and_chunks(rot, oracle_mod, slots, symmetric):
+    """11 operators with few output tiles: the dU operator sum is split into
+    parts (8 parts of one operator plus a remainder of 3 with the full
+    workspace; 4 parts over two chunks with 13 slots) or not split at all (3
+    slots, 1 slot: chunks of 3 and of 1 accumulate into dU).  Every layout
+    must match the oracle, and repeated calls give identical bits."""
+    m, d, mp, n = 96, 4, 80, 11
+    case = workloads.dense_case(m, d, mp, n, cfg=660, symmetric=symmetric)
+    G = np.random.default_rng(9).standard_normal((n, mp, mp)).astype(np.float32).astype(np.float64)
+    U, O, Gd = to_dev(case.U, torch.float32), to_dev(case.O, torch.float32), to_dev(G, torch.float32)
+    ws = None
+    if slots is not None:
+        p = rot._problem(U, O, torch.empty((1, mp, mp), device=U.device), d)
+        one = rot.rot_workspace_size([p], rot.ROT_FP32, ops_per_chunk=1, for_backward=True)
+        ws = torch.empty(slots * one, dtype=torch.uint8, device=U.device)
+    dO, dU = rot.rotate_backward(U, O, d, Gd, "fp32", symmetric_O=symmetric, workspace=ws)
+    dO2, dU2 = rot.rotate_backward(U, O, d, Gd, "fp32", symmetric_O=symmetric, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(dU, dU2) and torch.equal(dO, dO2)
+    rdO, rdU = oracle_mod.adjoint(case.U, case.O, G, d)
+    assert rel_fro(dO.double().cpu().numpy(), rdO).max() <= TOL32
+    assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= TOL32
+
+
 # ------------------------------------------------------- FP64 reductions --
 
 @pytest.mark.parametrize("mp,n", [(130, 5), (1024, 8), (33, 1)])
