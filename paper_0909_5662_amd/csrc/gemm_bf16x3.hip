@@ -16,8 +16,15 @@
 // Stage 1's M index is ordered beta*d + s (site state fastest): the four
 // consecutive rows of a lane's accumulator group are, for d = 4, the entries
 // r = i*d + s, s < 4 of Tt[beta], one 8-byte store.
-// Tiles are 256 x 256 (four waves of 128 x 128) so that each 128-bit LDS
-// fragment read feeds 3 x 4 matrix instructions.
+//
+// Slab layout.  Every split operand (rows x K) is stored as K/16 slabs; slab
+// q holds k = 16q..16q+15 of all rows, 32 bytes per row, row after row, and
+// the two 16-byte halves of row r are swapped when bit 3 of r is set.  The
+// 16-wide K slice of a tile is then one contiguous block per array, copied
+// verbatim into LDS by buffer loads with LDS destination (1 KB per wave
+// instruction, whole cache lines), and the swap spreads the 128-bit fragment
+// reads of 16 lanes (rows c..c+15, one k half) over all 64 LDS banks.  The
+// last slab of an operand whose K is not a multiple of 16 is zero beyond K.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,10 +42,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kThreads = 256;
-constexpr int kSlice = 16;   // K elements per LDS slice: one matrix step
-constexpr int kPitch = 24;   // LDS row pitch in bf16 elements (48 bytes): conflict-free 128-bit reads
-
 __device__ inline uint16_t rne_bf16(float x) {
     const uint32_t b = __float_as_uint(x);
     if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (uint16_t)((b >> 16) | 0x40u);
@@ -53,185 +56,75 @@ __device__ inline int xcd_linear_id() {
     return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+constexpr int kSlabK = 16;  // k per slab
+
+inline __host__ __device__ int64_t n_slabs(int64_t K) { return (K + kSlabK - 1) / kSlabK; }
+
+// Element (r, k) of a slab-layout operand with `rows` rows.
+inline __host__ __device__ int64_t slab_off(int64_t r, int64_t k, int64_t rows) {
+    return (k >> 4) * rows * kSlabK + r * kSlabK + ((((k >> 3) & 1) ^ ((r >> 3) & 1)) << 3) + (k & 7);
+}
+
 struct Bf16Desc {
     int M, N, K, batch;
-    // A (M x K, K-contiguous), pre-split
+    // A: M rows, B: N rows, both K-contiguous slab layout, pre-split
     const uint16_t* a_hi;
     const uint16_t* a_lo;
-    int64_t lda, a_bs;
-    // B (N x K, K-contiguous), pre-split
+    int64_t a_bs;
     const uint16_t* b_hi;
     const uint16_t* b_lo;
-    int64_t ldb, b_bs;
+    int64_t b_bs;
     // plain epilogue: C[row*ldc + col] (FP32)
     float* c;
     int64_t ldc, c_bs;
-    // split-transposed epilogue: C(n = beta*d + s, i) -> T[beta*t_ld + i*d + s]
+    // split-transposed epilogue: C(n = beta*d + s, i) -> T (t_rows rows,
+    // slab layout), element (beta, i*d + s)
     uint16_t* t_hi;
     uint16_t* t_lo;
     int d;
-    int64_t t_ld, t_bs;
+    int64_t t_rows, t_bs;
 };
 
-// Stage an R x KS slice of a pre-split K-contiguous operand into LDS with
-// row pitch KS + 8: 2 arrays x R rows x KS/8 chunks of 16 bytes.
-template <int R, int KS = kSlice>
-struct SplitSlice {
-    static constexpr int CPR = KS / 8;                 // chunks per row
-    static constexpr int CH = 2 * R * CPR / kThreads;  // chunks per thread
-    static constexpr int PITCH = KS + 8;
-    u16x8 r[CH];
-    __device__ inline void load(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t ld,
-                                int r0, int rows, int k0, int ks, int tid) {
-        if (r0 + R <= rows && k0 + KS <= ks) {  // interior slice: unconditional vector loads
-#pragma unroll
-            for (int c = 0; c < CH; c++) {
-                const int f = tid + c * kThreads;
-                const int arr = f / (CPR * R), q = f % (CPR * R);
-                r[c] = *reinterpret_cast<const u16x8*>((arr ? lo : hi) + (int64_t)(r0 + q / CPR) * ld + k0 +
-                                                       (q % CPR) * 8);
-            }
-            return;
-        }
-#pragma unroll
-        for (int c = 0; c < CH; c++) {
-            const int f = tid + c * kThreads;
-            const int arr = f / (CPR * R), q = f % (CPR * R);
-            const int row = q / CPR, k = (q % CPR) * 8;
-            const int gr = r0 + row, gk = k0 + k;
-            const uint16_t* p = (arr ? lo : hi) + (int64_t)gr * ld + gk;
-#pragma unroll
-            for (int e = 0; e < 8; e++) r[c][e] = (gr < rows && gk + e < ks) ? p[e] : (uint16_t)0;
-        }
-    }
-    __device__ inline void store(uint16_t* s_hi, uint16_t* s_lo, int tid) const {
-#pragma unroll
-        for (int c = 0; c < CH; c++) {
-            const int f = tid + c * kThreads;
-            const int arr = f / (CPR * R), q = f % (CPR * R);
-            *reinterpret_cast<u16x8*>((arr ? s_lo : s_hi) + (q / CPR) * PITCH + (q % CPR) * 8) = r[c];
-        }
-    }
-};
+// Buffer descriptor over one slab-layout operand (raw addressing; loads past
+// its last slab return zero).
+constexpr int kBufferFlags = 0x00020000;
+__device__ inline __amdgpu_buffer_rsrc_t operand_rsrc(const uint16_t* p, int rows, int K) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(p), (short)0,
+                                             (int)(n_slabs(K) * rows * kSlabK * 2), kBufferFlags);
+}
 
-// Tile BM x BN = (2*BI*32) x (2*BJ*32): four waves in a 2 x 2 grid, each
-// BI x BJ blocks of v_mfma_f32_32x32x16_bf16.  That instruction takes from
-// lane l A(row l%32, k 8*(l/32)+e) and B(k 8*(l/32)+e, col l%32), e < 8, and
-// leaves C(8*(v/4) + 4*(l/32) + v%4, l%32) in accumulator element v.  An LDS
-// slice holds KS values of k (KS/16 matrix steps); with the row pitch KS + 8
-// (48 or 80 bytes) the 128-bit fragment reads of 16 lanes hit 16 distinct
-// 4-bank groups.  Slice t+1 is fetched from HBM while slice t is multiplied.
-template <int BI, int BJ, int KS, bool EPI_T, bool D4>
-__global__ __launch_bounds__(kThreads, 1) void gemm_bf16x3_kernel(Bf16Desc g, int tiles_m, int tiles_n,
-                                                                  int n_fastest) {
-    constexpr int BM = 64 * BI, BN = 64 * BJ;
-    constexpr int PITCH = KS + 8;
-    constexpr int A_ARR = BM * PITCH, B_ARR = BN * PITCH;
-    constexpr int BUF = 2 * A_ARR + 2 * B_ARR;
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * BUF];  // per buffer: A_hi, A_lo, B_hi, B_lo
+// s_waitcnt immediate that waits until at most n vector-memory operations
+// of this wave are outstanding (other counters unconstrained).
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
+// s_waitcnt immediate that waits for every LDS access of this wave.
+constexpr int kLgkmcnt0 = 0xF | (3 << 14) | 0x70;
 
-    const int lin = xcd_linear_id();
-    const int per_batch = tiles_m * tiles_n;
-    const int bidx = lin / per_batch;
-    const int rr = lin % per_batch;
-    // neighbouring workgroups share the B panel (M tiles fastest) or the A
-    // panel (N tiles fastest)
-    const int m0 = (n_fastest ? rr / tiles_n : rr % tiles_m) * BM;
-    const int n0 = (n_fastest ? rr % tiles_n : rr / tiles_m) * BN;
+// Ordering point for the compiler only: memory accesses are not moved across
+// it (s_barrier alone does not order them for the optimiser).
+__device__ inline void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int h = lane >> 5, c = lane & 31;
-
-    SplitSlice<BM, KS> la;
-    SplitSlice<BN, KS> lb;
-    const uint16_t* ah_g = g.a_hi + (int64_t)bidx * g.a_bs;
-    const uint16_t* al_g = g.a_lo + (int64_t)bidx * g.a_bs;
-    const uint16_t* bh_g = g.b_hi + (int64_t)bidx * g.b_bs;
-    const uint16_t* bl_g = g.b_lo + (int64_t)bidx * g.b_bs;
-    const int nk = (g.K + KS - 1) / KS;
-
-    f32x16 acc[BI][BJ];
-#pragma unroll
-    for (int i = 0; i < BI; i++)
-#pragma unroll
-        for (int j = 0; j < BJ; j++)
-#pragma unroll
-            for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
-
-    auto A_hi = [&](int b) { return lds + b * BUF; };
-    auto A_lo = [&](int b) { return lds + b * BUF + A_ARR; };
-    auto B_hi = [&](int b) { return lds + b * BUF + 2 * A_ARR; };
-    auto B_lo = [&](int b) { return lds + b * BUF + 2 * A_ARR + B_ARR; };
-
-    la.load(ah_g, al_g, g.lda, m0, g.M, 0, g.K, tid);
-    lb.load(bh_g, bl_g, g.ldb, n0, g.N, 0, g.K, tid);
-    la.store(A_hi(0), A_lo(0), tid);
-    lb.store(B_hi(0), B_lo(0), tid);
-    __syncthreads();
-
-    for (int t = 0; t < nk; t++) {
-        const int cur = t & 1;
-        if (t + 1 < nk) {
-            la.load(ah_g, al_g, g.lda, m0, g.M, (t + 1) * KS, g.K, tid);
-            lb.load(bh_g, bl_g, g.ldb, n0, g.N, (t + 1) * KS, g.K, tid);
-        }
-#pragma unroll
-        for (int ks = 0; ks < KS / 16; ks++) {
-            bf16x8 ah[BI], al[BI], bhv[BJ], blv[BJ];
-#pragma unroll
-            for (int i = 0; i < BI; i++) {
-                const int ra = (wm * 32 * BI + i * 32 + c) * PITCH + ks * 16 + h * 8;
-                ah[i] = *reinterpret_cast<const bf16x8*>(A_hi(cur) + ra);
-                al[i] = *reinterpret_cast<const bf16x8*>(A_lo(cur) + ra);
-            }
-#pragma unroll
-            for (int j = 0; j < BJ; j++) {
-                const int rb = (wn * 32 * BJ + j * 32 + c) * PITCH + ks * 16 + h * 8;
-                bhv[j] = *reinterpret_cast<const bf16x8*>(B_hi(cur) + rb);
-                blv[j] = *reinterpret_cast<const bf16x8*>(B_lo(cur) + rb);
-            }
-            // small terms first; consecutive instructions use different accumulators
-#pragma unroll
-            for (int i = 0; i < BI; i++)
-#pragma unroll
-                for (int k = 0; k < BJ; k++)
-                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhv[k], acc[i][k], 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < BI; i++)
-#pragma unroll
-                for (int k = 0; k < BJ; k++)
-                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], blv[k], acc[i][k], 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < BI; i++)
-#pragma unroll
-                for (int k = 0; k < BJ; k++)
-                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhv[k], acc[i][k], 0, 0, 0);
-        }
-        if (t + 1 < nk) {
-            la.store(A_hi(cur ^ 1), A_lo(cur ^ 1), tid);
-            lb.store(B_hi(cur ^ 1), B_lo(cur ^ 1), tid);
-        }
-        __syncthreads();
-    }
-
+// Write a wave's BI x BJ accumulator blocks (origin row0w, col0 of C):
+// split-transposed into T (EPI_T) or plain FP32.  Accumulator element v of
+// lane (h, c) of a 32 x 32 block is C(8*(v/4) + 4*h + v%4, c).
+template <int BI, int BJ, bool EPI_T, bool D4>
+__device__ inline void store_tile(const Bf16Desc& g, const f32x16 (&acc)[BI][BJ], int bidx, int row0w, int col0, int h,
+                                  int c) {
     if (EPI_T) {
-        // C(n = beta*d + s, i) -> T[beta][i*d + s].  The four rows 4q..4q+3 a
+        // C(n = beta*d + s, i) -> T(beta, i*d + s).  The four rows 4q..4q+3 a
         // lane holds in accumulator elements 4q..4q+3 are, for d = 4, the four
-        // site states of one beta: one 8-byte store per array.
+        // site states of one beta: k = 4i..4i+3, one 8-byte store per array.
         uint16_t* th = g.t_hi + (int64_t)bidx * g.t_bs;
         uint16_t* tl = g.t_lo + (int64_t)bidx * g.t_bs;
 #pragma unroll
         for (int i = 0; i < BI; i++)
 #pragma unroll
             for (int k = 0; k < BJ; k++) {
-                const int col = n0 + wn * 32 * BJ + k * 32 + c;  // old block state i
+                const int col = col0 + k * 32 + c;  // old block state i
                 if (col >= g.N) continue;
                 const f32x16 a = acc[i][k];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const int row0 = m0 + wm * 32 * BI + i * 32 + 8 * q + 4 * h;
+                    const int row0 = row0w + i * 32 + 8 * q + 4 * h;
                     u16x4 hv, lv;
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
@@ -240,7 +133,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_bf16x3_kernel(Bf16Desc g, in
                         lv[e] = rne_bf16(x - bf16_f32(hv[e]));
                     }
                     if (D4 && row0 + 4 <= g.M) {
-                        const int64_t off = (int64_t)(row0 >> 2) * g.t_ld + (int64_t)col * 4;
+                        const int64_t off = slab_off(row0 >> 2, (int64_t)col * 4, g.t_rows);
                         *reinterpret_cast<u16x4*>(th + off) = hv;
                         *reinterpret_cast<u16x4*>(tl + off) = lv;
                     } else if (!D4) {
@@ -248,7 +141,7 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_bf16x3_kernel(Bf16Desc g, in
                         for (int e = 0; e < 4; e++) {
                             const int row = row0 + e;
                             if (row < g.M) {
-                                const int64_t off = (int64_t)(row / g.d) * g.t_ld + (int64_t)col * g.d + row % g.d;
+                                const int64_t off = slab_off(row / g.d, (int64_t)col * g.d + row % g.d, g.t_rows);
                                 th[off] = hv[e];
                                 tl[off] = lv[e];
                             }
@@ -262,24 +155,166 @@ __global__ __launch_bounds__(kThreads, 1) void gemm_bf16x3_kernel(Bf16Desc g, in
         for (int i = 0; i < BI; i++)
 #pragma unroll
             for (int k = 0; k < BJ; k++) {
-                const int col = n0 + wn * 32 * BJ + k * 32 + c;
+                const int col = col0 + k * 32 + c;
                 if (col >= g.N) continue;
 #pragma unroll
                 for (int v = 0; v < 16; v++) {
-                    const int row = m0 + wm * 32 * BI + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                    const int row = row0w + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
                     if (row < g.M) cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
                 }
             }
     }
 }
 
-// U (rows = m*d, cols = mp) -> U1[(beta*d+s)*ld1 + j] = U[j*d+s][beta]  (ld1 >= m)
-//                            U2[alpha*ld2 + r]     = U[r][alpha]        (ld2 >= m*d)
-// both split into hi/lo.  64 x 64 tiles through LDS.
+// Square tile T x T, T = 32 * (number of waves), as WGM x WGN waves of
+// (32 BI) x (32 BJ), each BI x BJ blocks of v_mfma_f32_32x32x16_bf16.  That
+// instruction takes from lane l A(row l%32, k 8*(l/32)+e) and B(k 8*(l/32)+e,
+// col l%32), e < 8.  The K loop runs over slabs through a ring of S LDS
+// stages, each holding one slab of A_hi, A_lo, B_hi, B_lo for the tile
+// (T rows x 32 bytes per array, as in memory).  Vector memory fills the
+// stages directly: wave w copies block w (32 rows, 1 KB) of each array with
+// one buffer load with LDS destination, 16 bytes per lane.  S - 1 slabs are
+// in flight while one is multiplied.  Before step t each wave waits for its
+// own loads of slab t + 1, and the barrier makes every wave's loads visible
+// and frees slab t - 1's stage (every wave consumed its fragments in step
+// t - 1) for slab t + S - 1.  The fragments of slab t + 1 are read into a
+// second register set while slab t is multiplied.
+template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T, bool D4>
+__global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc g, int tiles_m, int tiles_n,
+                                                                         int n_fastest) {
+    constexpr int NW = WGM * WGN;
+    constexpr int T = 32 * NW;
+    static_assert(32 * WGM * BI == T && 32 * WGN * BJ == T, "square tile of 32 rows per wave");
+    constexpr int ARR = T * kSlabK;  // elements of one array in a stage
+    constexpr int STAGE = 4 * ARR;   // A_hi, A_lo, B_hi, B_lo
+    constexpr int LOADS = 4;         // direct loads per wave per stage
+    __shared__ __attribute__((aligned(1024))) uint16_t lds[S * STAGE];
+
+    const int lin = xcd_linear_id();
+    const int per_batch = tiles_m * tiles_n;
+    const int bidx = lin / per_batch;
+    const int rr = lin % per_batch;
+    // neighbouring workgroups share the B panel (M tiles fastest) or the A
+    // panel (N tiles fastest)
+    const int m0 = (n_fastest ? rr / tiles_n : rr % tiles_m) * T;
+    const int n0 = (n_fastest ? rr % tiles_n : rr / tiles_m) * T;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int h = lane >> 5, c = lane & 31;
+
+    const __amdgpu_buffer_rsrc_t rs[4] = {operand_rsrc(g.a_hi + (int64_t)bidx * g.a_bs, g.M, g.K),
+                                          operand_rsrc(g.a_lo + (int64_t)bidx * g.a_bs, g.M, g.K),
+                                          operand_rsrc(g.b_hi + (int64_t)bidx * g.b_bs, g.N, g.K),
+                                          operand_rsrc(g.b_lo + (int64_t)bidx * g.b_bs, g.N, g.K)};
+    // byte offsets of this lane's 16 bytes in slab 0, and the slab strides
+    const uint32_t a_off = (uint32_t)((m0 + wave * 32) * kSlabK * 2 + lane * 16);
+    const uint32_t b_off = (uint32_t)((n0 + wave * 32) * kSlabK * 2 + lane * 16);
+    const uint32_t a_slab = (uint32_t)g.M * kSlabK * 2, b_slab = (uint32_t)g.N * kSlabK * 2;
+    const int nk = (int)n_slabs(g.K);
+
+    auto issue = [&](int st) {
+        uint16_t* base = lds + (st % S) * STAGE + wave * 512;
+#pragma unroll
+        for (int j = 0; j < LOADS; j++)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rs[j], (__attribute__((address_space(3))) void*)(base + j * ARR), 16,
+                j < 2 ? a_off + (uint32_t)st * a_slab : b_off + (uint32_t)st * b_slab, 0, 0, 0);
+    };
+
+    f32x16 acc[BI][BJ];
+#pragma unroll
+    for (int i = 0; i < BI; i++)
+#pragma unroll
+        for (int j = 0; j < BJ; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
+
+    // fragment slot of this lane: rows c (+ multiples of 32) and k half h
+    const int fslot = (h ^ ((c >> 3) & 1)) * 8;
+    struct Frags {
+        bf16x8 ah[BI], al[BI], bh[BJ], bl[BJ];
+    };
+    auto read = [&](Frags& f, int st) {
+        const uint16_t* sb = lds + (st % S) * STAGE;
+#pragma unroll
+        for (int i = 0; i < BI; i++) {
+            const int ra = (wm * 32 * BI + i * 32 + c) * kSlabK + fslot;
+            f.ah[i] = *reinterpret_cast<const bf16x8*>(sb + ra);
+            f.al[i] = *reinterpret_cast<const bf16x8*>(sb + ARR + ra);
+        }
+#pragma unroll
+        for (int j = 0; j < BJ; j++) {
+            const int rb = (wn * 32 * BJ + j * 32 + c) * kSlabK + fslot;
+            f.bh[j] = *reinterpret_cast<const bf16x8*>(sb + 2 * ARR + rb);
+            f.bl[j] = *reinterpret_cast<const bf16x8*>(sb + 3 * ARR + rb);
+        }
+    };
+    auto multiply = [&](const Frags& f) {
+        // small terms first; consecutive instructions use different accumulators
+#pragma unroll
+        for (int i = 0; i < BI; i++)
+#pragma unroll
+            for (int k = 0; k < BJ; k++)
+                acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[i], f.bh[k], acc[i][k], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < BI; i++)
+#pragma unroll
+            for (int k = 0; k < BJ; k++)
+                acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[i], f.bl[k], acc[i][k], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < BI; i++)
+#pragma unroll
+            for (int k = 0; k < BJ; k++)
+                acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[i], f.bh[k], acc[i][k], 0, 0, 0);
+    };
+    // wait until this wave's loads of slab `st` are done, given that slabs up
+    // to min(st + later, nk - 1) have been issued; then the barrier
+    auto wait_stage = [&](int st, int later) {
+        if (st + later < nk) {
+            if (later == S - 2)
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(LOADS * (S - 2)));
+            else
+                __builtin_amdgcn_s_waitcnt(vmcnt_imm(LOADS * (S - 3)));
+        } else {
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        }
+        compiler_fence();
+        __builtin_amdgcn_s_barrier();
+        compiler_fence();
+    };
+
+    for (int st = 0; st < S - 1 && st < nk; st++) issue(st);
+    Frags f0, f1;
+    wait_stage(0, S - 2);
+    read(f0, 0);
+    auto step = [&](int t, Frags& cur, Frags& nxt) {
+        // the reads of `cur` (issued a step ago) complete before the reads of
+        // `nxt` start, so the matrix instructions below wait for nothing
+        __builtin_amdgcn_s_waitcnt(kLgkmcnt0);
+        if (t + 1 < nk) {
+            wait_stage(t + 1, S - 3);
+            if (t + S - 1 < nk) issue(t + S - 1);
+            read(nxt, t + 1);
+        }
+        multiply(cur);
+        compiler_fence();
+    };
+    for (int t = 0; t < nk; t += 2) {
+        step(t, f0, f1);
+        if (t + 1 < nk) step(t + 1, f1, f0);
+    }
+    store_tile<BI, BJ, EPI_T, D4>(g, acc, bidx, m0 + wm * 32 * BI, n0 + wn * 32 * BJ, h, c);
+}
+
+// U (rows = m*d, cols = mp), row r = j*d + s, both split into hi/lo (slab layout):
+//   U1 (d*mp rows, K = m):   element (beta*d + s, j) = U[j*d+s][beta]
+//   U2 (mp rows, K = m*d):   element (alpha, r)      = U[r][alpha]
+// 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ U, int rows, int cols, int d,
                                                       uint16_t* __restrict__ u1h, uint16_t* __restrict__ u1l,
-                                                      int64_t ld1, uint16_t* __restrict__ u2h,
-                                                      uint16_t* __restrict__ u2l, int64_t ld2) {
+                                                      uint16_t* __restrict__ u2h, uint16_t* __restrict__ u2l) {
     __shared__ float tile[64][65];
     const int r0 = blockIdx.y * 64, a0 = blockIdx.x * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -292,6 +327,7 @@ __global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ 
     const int r = r0 + tx;
     if (r >= rows) return;
     const int j = r / d, s = r % d;
+    const int64_t rows1 = (int64_t)d * cols;
 #pragma unroll 4
     for (int k = 0; k < 16; k++) {
         const int a = a0 + ty + 4 * k;
@@ -299,53 +335,84 @@ __global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ 
         const float x = tile[tx][ty + 4 * k];
         const uint16_t hh = rne_bf16(x);
         const uint16_t ll = rne_bf16(x - bf16_f32(hh));
-        u2h[(int64_t)a * ld2 + r] = hh;
-        u2l[(int64_t)a * ld2 + r] = ll;
-        const int64_t o1 = ((int64_t)a * d + s) * ld1 + j;
+        const int64_t o2 = slab_off(a, r, cols);
+        u2h[o2] = hh;
+        u2l[o2] = ll;
+        const int64_t o1 = slab_off((int64_t)a * d + s, j, rows1);
         u1h[o1] = hh;
         u1l[o1] = ll;
     }
 }
 
-// O_b (m x m at O + b*stride_o) -> hi/lo at b*ob + i*ld + j (ld >= m).
-// Four consecutive j per thread (8-byte stores) when m and stride_o allow
-// 16-byte loads; element by element otherwise.
+// O_b (m x m at O + b*stride_o) -> hi/lo at b*ob in slab layout (m rows,
+// K = m), one 64 x 64 block per workgroup: rows are read contiguously into
+// LDS, then the block's 4 slabs x 64 rows x 2 halves are written as 16-byte
+// chunks in memory order (each slab's part of the block is 2 KB contiguous
+// per array).  Columns past m in the last slab are written as zero.
 __global__ __launch_bounds__(256) void split_o_kernel(const float* __restrict__ O, int m, int64_t stride_o,
                                                       uint16_t* __restrict__ oh, uint16_t* __restrict__ ol,
-                                                      int64_t ld, int64_t ob, int vec) {
-    const int b = blockIdx.z, i = blockIdx.y;
-    const float* src = O + (int64_t)b * stride_o + (int64_t)i * m;
-    uint16_t* dh = oh + (int64_t)b * ob + (int64_t)i * ld;
-    uint16_t* dl = ol + (int64_t)b * ob + (int64_t)i * ld;
-    if (vec) {
-        for (int j = (blockIdx.x * 256 + threadIdx.x) * 4; j < m; j += gridDim.x * 256 * 4) {
-            const f32x4 x = *reinterpret_cast<const f32x4*>(src + j);
-            u16x4 hv, lv;
+                                                      int64_t ob) {
+    __shared__ float tile[64][64 + 1];
+    const int b = blockIdx.z, i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const float* src = O + (int64_t)b * stride_o;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                hv[e] = rne_bf16(x[e]);
-                lv[e] = rne_bf16(x[e] - bf16_f32(hv[e]));
-            }
-            *reinterpret_cast<u16x4*>(dh + j) = hv;
-            *reinterpret_cast<u16x4*>(dl + j) = lv;
-        }
-        return;
+    for (int k = 0; k < 16; k++) {
+        const int i = i0 + ty + 4 * k, j = j0 + tx;
+        tile[ty + 4 * k][tx] = (i < m && j < m) ? src[(int64_t)i * m + j] : 0.f;
     }
-    for (int j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
-        const float x = src[j];
-        const uint16_t hh = rne_bf16(x);
-        dh[j] = hh;
-        dl[j] = rne_bf16(x - bf16_f32(hh));
+    __syncthreads();
+    uint16_t* dh = oh + (int64_t)b * ob;
+    uint16_t* dl = ol + (int64_t)b * ob;
+    const int64_t nslab = n_slabs(m);
+#pragma unroll
+    for (int x = 0; x < 2; x++) {
+        const int ch = threadIdx.x + 256 * x;        // chunk: slab q, row, slot
+        const int q = ch >> 7, row = (ch & 127) >> 1, slot = ch & 1;
+        const int i = i0 + row;
+        const int64_t sq = j0 / kSlabK + q;          // global slab index
+        if (i >= m || sq >= nslab) continue;
+        const int half = slot ^ ((i >> 3) & 1);
+        u16x8 hv, lv;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const float v = tile[row][q * kSlabK + half * 8 + e];
+            hv[e] = rne_bf16(v);
+            lv[e] = rne_bf16(v - bf16_f32(hv[e]));
+        }
+        const int64_t off = sq * (int64_t)m * kSlabK + (int64_t)i * kSlabK + slot * 8;
+        *reinterpret_cast<u16x8*>(dh + off) = hv;
+        *reinterpret_cast<u16x8*>(dl + off) = lv;
     }
 }
 
-inline int64_t pad8(int64_t k) { return (k + 7) / 8 * 8; }
-inline size_t al256(size_t n) { return (n + 255) / 256 * 256; }
+// `len` elements at a + b*bstride and at l + b*bstride, b < gridDim.y, set
+// to zero.
+__global__ __launch_bounds__(256) void zero_pair_kernel(uint16_t* __restrict__ a, uint16_t* __restrict__ l,
+                                                        int64_t len, int64_t bstride) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= len) return;
+    const int64_t off = (int64_t)blockIdx.y * bstride + i;
+    a[off] = 0;
+    l[off] = 0;
+}
 
-template <int BI, int KS, bool EPI_T>
+// Zero the K padding of `batch` slab-layout operands (rows x K, bstride
+// elements apart): their whole last slab when K is not a multiple of 16,
+// before the producer writes its valid part.
+hipError_t zero_last_slab(uint16_t* a, uint16_t* l, int64_t rows, int64_t K, int64_t bstride, int batch,
+                          hipStream_t s) {
+    if (K % kSlabK == 0 || rows <= 0 || batch <= 0) return hipSuccess;
+    const int64_t len = rows * kSlabK, off = (n_slabs(K) - 1) * len;
+    hipLaunchKernelGGL(zero_pair_kernel, dim3((unsigned)((len + 255) / 256), (unsigned)batch), dim3(256), 0, s,
+                       a + off, l + off, len, bstride);
+    return hipGetLastError();
+}
+
+template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T>
 hipError_t launch_tile(const Bf16Desc& g, hipStream_t s) {
-    const int edge = 64 * BI;
-    const int tm = (g.M + edge - 1) / edge, tn = (g.N + edge - 1) / edge;
+    constexpr int T = 32 * WGM * WGN;
+    const int tm = (g.M + T - 1) / T, tn = (g.N + T - 1) / T;
     const int64_t tiles = (int64_t)tm * tn * g.batch;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     const char* order = getenv("ROT_BF16_ORDER");
@@ -353,53 +420,59 @@ hipError_t launch_tile(const Bf16Desc& g, hipStream_t s) {
     // with d = 4 the row extent d*mp is a multiple of 4, so every group of
     // four rows is complete and the vector store path covers all of them
     if (EPI_T && g.d == 4)
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<BI, BI, KS, EPI_T, true>), dim3((unsigned)tiles), dim3(kThreads), 0, s,
-                           g, tm, tn, nf);
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<WGM, WGN, BI, BJ, S, EPI_T, true>), dim3((unsigned)tiles),
+                           dim3(64 * WGM * WGN), 0, s, g, tm, tn, nf);
     else
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<BI, BI, KS, EPI_T, false>), dim3((unsigned)tiles), dim3(kThreads), 0,
-                           s, g, tm, tn, nf);
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<WGM, WGN, BI, BJ, S, EPI_T, false>), dim3((unsigned)tiles),
+                           dim3(64 * WGM * WGN), 0, s, g, tm, tn, nf);
     return hipGetLastError();
 }
 
-// 256 x 256 tiles with 32-wide K slices when both output extents reach 256
-// (fewer LDS reads per matrix instruction, and a longer multiply phase per
-// slice to hide the next slice's HBM latency); else 128 x 128 with 16-wide
-// slices.  Environment ROT_BF16_TILE=128 forces the small tile and
-// ROT_BF16_KS=16 the narrow slice (measurement knobs).
+// 256 x 256 tiles (eight waves of 128 x 64, two per SIMD; a ring of 4 stages
+// of 32 KB) when both output extents reach 256, else 128 x 128 (four waves
+// of 64 x 64; 4 stages of 16 KB).  Environment ROT_BF16_CFG=128 forces the
+// small tile and ROT_BF16_CFG=ring5 a ring of 5 stages (measurement knobs).
 template <bool EPI_T>
 hipError_t launch_bf16(const Bf16Desc& g, hipStream_t s) {
-    const char* env = getenv("ROT_BF16_TILE");
-    const char* ks = getenv("ROT_BF16_KS");
+    const char* env = getenv("ROT_BF16_CFG");
     const bool small = env && !strcmp(env, "128");
-    const bool narrow = ks && !strcmp(ks, "16");
-    // the split-transposed epilogue fits the 256 x 256 register budget only in
-    // its d = 4 vector-store form
-    const bool big_ok = !EPI_T || g.d == 4;
-    if (!small && big_ok && g.M >= 256 && g.N >= 256)
-        return narrow ? launch_tile<4, 16, EPI_T>(g, s) : launch_tile<4, 32, EPI_T>(g, s);
-    return launch_tile<2, 16, EPI_T>(g, s);
+    if (!small && g.M >= 256 && g.N >= 256) {
+        if (env && !strcmp(env, "ring5")) return launch_tile<2, 4, 4, 2, 5, EPI_T>(g, s);
+        return launch_tile<2, 4, 4, 2, 4, EPI_T>(g, s);
+    }
+    return launch_tile<2, 2, 2, 2, 4, EPI_T>(g, s);
 }
 
 struct Bf16Layout {
-    int64_t ld1, ld2;     // padded K of U1 and O (m) and of U2 / Tt (m*d)
-    size_t u1, u2, t_op;  // bytes of one hi (or lo) array
-    size_t o_op;          // bytes of one operator's split O (hi or lo)
-    size_t shared;        // bytes of the pre-split U (4 arrays)
+    int64_t u1_rows, u2_rows;  // rows of U1 (d*mp) and U2 (mp)
+    size_t u1, u2, t_op;       // bytes of one hi (or lo) array
+    size_t o_op;               // bytes of one operator's split O (hi or lo)
+    size_t shared;             // bytes of the pre-split U (4 arrays)
 };
+
+inline size_t al256(size_t n) { return (n + 255) / 256 * 256; }
 
 Bf16Layout layout(int m, int d, int mp) {
     Bf16Layout L;
-    L.ld1 = pad8(m);
-    L.ld2 = pad8((int64_t)m * d);
-    L.u1 = al256((size_t)d * mp * L.ld1 * 2);
-    L.u2 = al256((size_t)mp * L.ld2 * 2);
-    L.t_op = al256((size_t)mp * L.ld2 * 2);
-    L.o_op = al256((size_t)m * L.ld1 * 2);
+    L.u1_rows = (int64_t)d * mp;
+    L.u2_rows = mp;
+    L.u1 = al256((size_t)(n_slabs(m) * L.u1_rows * kSlabK * 2));
+    L.u2 = al256((size_t)(n_slabs((int64_t)m * d) * mp * kSlabK * 2));
+    L.t_op = L.u2;  // Tt_b: mp rows, K = m*d
+    L.o_op = al256((size_t)(n_slabs(m) * m * kSlabK * 2));
     L.shared = 2 * L.u1 + 2 * L.u2;
     return L;
 }
 
 }  // namespace
+
+// Every split operand array, with one tile (256 rows) of overhang, must stay
+// below 2 GiB: loads address it with 32-bit byte offsets.
+bool bf16_shape_supported(int m, int d, int mp) {
+    const Bf16Layout L = layout(m, d, mp);
+    const size_t lim = (size_t)1 << 31, over = 256 * kSlabK * 2;
+    return L.u1 + over < lim && L.u2 + over < lim && L.o_op + over < lim;
+}
 
 size_t bf16_group_workspace(int m, int d, int mp, int ops) {
     const Bf16Layout L = layout(m, d, mp);
@@ -421,13 +494,16 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream
     if (b0 == 0) {
         const dim3 grid((p.mp + 63) / 64, (rows + 63) / 64);
         hipError_t e = prof_timed("split_u_bf16x3", stream, [&] {
+            hipError_t err = zero_last_slab(u1h, u1l, L.u1_rows, p.m, 0, 1, stream);
+            if (err == hipSuccess) err = zero_last_slab(u2h, u2l, L.u2_rows, rows, 0, 1, stream);
+            if (err != hipSuccess) return err;
             hipLaunchKernelGGL(split_u_kernel, grid, dim3(256), 0, stream, static_cast<const float*>(p.U), rows,
-                               p.mp, p.d, u1h, u1l, L.ld1, u2h, u2l, L.ld2);
+                               p.mp, p.d, u1h, u1l, u2h, u2l);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
     }
-    // stage 1, transposed: C(beta*d+s, i) = sum_j U1[beta*d+s][j] O_b[i][j] = T_b(i, beta*d+s)
+    // stage 1, transposed: C(beta*d+s, i) = sum_j U1(beta*d+s, j) O_b(i, j) = T_b(i, beta*d+s)
     Bf16Desc a{};
     a.M = p.d * p.mp;
     a.N = p.m;
@@ -435,29 +511,29 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream
     a.batch = nb;
     a.a_hi = u1h;
     a.a_lo = u1l;
-    a.lda = L.ld1;
     a.a_bs = 0;
     a.b_hi = oh;
     a.b_lo = ol;
-    a.ldb = L.ld1;
     a.b_bs = (int64_t)(L.o_op / 2);
     a.t_hi = th;
     a.t_lo = tl;
     a.d = p.d;
-    a.t_ld = L.ld2;
+    a.t_rows = p.mp;
     a.t_bs = (int64_t)(L.t_op / 2);
     hipError_t e = prof_timed("split_o_bf16x3", stream, [&] {
+        // Tt's K padding (stage 1 writes only k < m*d); O's is written by the split
+        hipError_t err = zero_last_slab(th, tl, p.mp, rows, (int64_t)(L.t_op / 2), nb, stream);
+        if (err != hipSuccess) return err;
         const float* Ob = static_cast<const float*>(p.O) + (int64_t)b0 * p.stride_o;
-        const int vec = (reinterpret_cast<uintptr_t>(Ob) & 15) == 0 && p.m % 4 == 0 && p.stride_o % 4 == 0;
-        const dim3 grid((p.m + (vec ? 1023 : 255)) / (vec ? 1024 : 256), p.m, nb);
-        hipLaunchKernelGGL(split_o_kernel, grid, dim3(256), 0, stream, Ob, p.m, p.stride_o, oh, ol, L.ld1,
-                           (int64_t)(L.o_op / 2), vec);
+        const dim3 grid((p.m + 63) / 64, (p.m + 63) / 64, nb);
+        hipLaunchKernelGGL(split_o_kernel, grid, dim3(256), 0, stream, Ob, p.m, p.stride_o, oh, ol,
+                           (int64_t)(L.o_op / 2));
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
     e = prof_timed("stage1_bf16x3", stream, [&] { return launch_bf16<true>(a, stream); });
     if (e != hipSuccess) return e;
-    // stage 2: out_b[alpha][beta] = sum_r U2[alpha][r] Tt_b[beta][r]
+    // stage 2: out_b(alpha, beta) = sum_r U2(alpha, r) Tt_b(beta, r)
     Bf16Desc b{};
     b.M = p.mp;
     b.N = p.mp;
@@ -465,11 +541,9 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream
     b.batch = nb;
     b.a_hi = u2h;
     b.a_lo = u2l;
-    b.lda = L.ld2;
     b.a_bs = 0;
     b.b_hi = th;
     b.b_lo = tl;
-    b.ldb = L.ld2;
     b.b_bs = (int64_t)(L.t_op / 2);
     b.c = static_cast<float*>(p.out) + (int64_t)b0 * p.stride_out;
     b.ldc = p.mp;

@@ -17,6 +17,7 @@ namespace rot {
 
 hipError_t split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream);
 size_t bf16_group_workspace(int m, int d, int mp, int ops);
+bool bf16_shape_supported(int m, int d, int mp);
 hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream_t stream);
 size_t blocked_workspace_bytes(const rot_blocked_problem* p);
 rot_status blocked_validate(const rot_blocked_problem* p, std::string* why);
@@ -291,6 +292,10 @@ rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision 
         if (groups[gi].n_ops > 0) {
             s = validate_outputs_disjoint(groups[gi], prec, gi);
             if (s != ROT_OK) return s;
+            if (prec == ROT_SPLIT_BF16 && !bf16_shape_supported(groups[gi].m, groups[gi].d, groups[gi].mp))
+                return fail(ROT_ERR_UNSUPPORTED,
+                            "group %d: split-bf16 operand arrays must stay below 2 GiB (m=%d d=%d mp=%d); use ROT_FP32",
+                            gi, groups[gi].m, groups[gi].d, groups[gi].mp);
         }
     }
     const size_t min_ws = rot_workspace_size(groups, n_groups, prec, 1, 0);

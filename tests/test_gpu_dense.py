@@ -315,6 +315,44 @@ def test_split_bf16_parity(rot, oracle_mod, shape, symmetric):
     assert err.max() <= TOL32, err
 
 
+@pytest.mark.parametrize("cfg", ["ring4", "ring5", "128"])
+@pytest.mark.parametrize("shape", [(300, 4, 270, 2), (290, 3, 300, 2)])
+def test_split_bf16_tile_configs_ragged(rot, oracle_mod, monkeypatch, cfg, shape):
+    """Each tile configuration (256 x 256 with a ring of 4 or 5 stages;
+    128 x 128) on extents that leave ragged tiles in both stages and K not a
+    multiple of the 16-wide slab (zero padding); d = 3 takes the element-wise
+    split-transposed store."""
+    if cfg == "ring4":
+        monkeypatch.delenv("ROT_BF16_CFG", raising=False)  # the default
+    else:
+        monkeypatch.setenv("ROT_BF16_CFG", cfg)
+    m, d, mp, n = shape
+    case = workloads.dense_case(m, d, mp, n, cfg=710 + m, dtype="f32", symmetric=True)
+    got = run_rotate(rot, case, "split_bf16")
+    ref = oracle_mod.rotate(case.U, case.O, d)
+    assert np.all(np.abs(got - ref) <= elementwise_bound(oracle_mod, case, 2.0 ** -16))
+    assert rel_fro(got, ref).max() <= TOL32
+
+
+def test_split_bf16_ignores_stale_workspace(rot, oracle_mod):
+    """The K padding of every split operand is written by the library: a
+    workspace full of NaN bit patterns from an earlier use changes nothing."""
+    m, d, mp, n = 130, 3, 120, 3
+    case = workloads.dense_case(m, d, mp, n, cfg=702)
+    U = to_dev(case.U, torch.float32)
+    O = to_dev(case.O, torch.float32)
+    out = torch.empty((n, mp, mp), device="cuda")
+    p = rot._problem(U, O, out, d)
+    need = rot.rot_workspace_size([p], rot.ROT_SPLIT_BF16)
+    ws = torch.full((need,), 0xFF, dtype=torch.uint8, device="cuda")
+    rot.rot_batch([p], rot.ROT_SPLIT_BF16, ws.data_ptr(), need, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    ref = oracle_mod.rotate(case.U, case.O, d)
+    assert np.all(np.isfinite(got))
+    assert rel_fro(got, ref).max() <= TOL32
+
+
 def test_split_bf16_headline_m1024_sampled(rot, oracle_mod):
     case = workloads.named_dense("dense_m1024_n64")
     got, worst = sampled_parity(rot, oracle_mod, case, "split_bf16", 24, TOL32, 3)
