@@ -122,21 +122,51 @@ bool aligned16(const float* base, int64_t off) { return ((reinterpret_cast<uintp
 // on v_mfma_f32_16x16x4f32 (lane l supplies A(l%16, l/16), B(l/16, l%16);
 // accumulator element v of lane l is D(4*(l/16)+v, l%16)).  A 16 x 16 block
 // of X_s in accumulator layout is, read with the k order 4*(l/16)+j at step
-// j, exactly the A operand of X_s^T: X never leaves registers.
+// j, exactly the A operand of X_s^T: X never leaves registers.  Stage 1 uses
+// the same k order (16-wide k groups, lane group h taking k = 4h + j at step
+// j), so every lane fetches four consecutive k with one 16-byte load in both
+// stages.  For that the U blocks are read transposed from the workspace
+// (U^T_Q[beta][padded row], filled per call by transpose_u_kernel): each
+// site state's rows start at a multiple of 4 and the padding is zero.
 struct BlkTask {
     int mT, mQ;          // output block rows (kept dim of T) and columns (kept dim of Q)
     int term0, n_terms;  // terms (site states with a non-zero operator block)
-    int64_t uT_off;      // U_T in U_blk, leading dimension mT
-    int64_t uQ_off;      // U_Q in U_blk, leading dimension mQ
+    int ldT, ldQ;        // padded row counts of U^T_T and U^T_Q (leading dimensions)
+    int64_t uT_off;      // U^T_T in the transposed-U area
+    int64_t uQ_off;      // U^T_Q in the transposed-U area
     int64_t out_off;     // output block in out_blk, leading dimension mQ
 };
 struct BlkTerm {
     int a, k;        // rows of X_s (old states of q_s + Delta), stage-1 K (old states of q_s)
-    int rt, rq;      // first row of site state s inside U_T and inside U_Q
+    int rt, rq;      // first padded row of site state s in U^T_T and in U^T_Q (multiples of 4)
     int64_t o_off;   // operator block (a x k, leading dimension k) in O_blk
+};
+// One site state's rows of one kept sector in the transposed-U area.
+struct UtSeg {
+    int64_t u_off;   // first row of the segment in U_blk (leading dimension mp)
+    int64_t ut_off;  // U^T area offset of column 0 of this segment (leading dimension ld)
+    int rows, rows4, mp, ld;
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
+// Slack after the transposed-U area: stage 1 reads up to CG - 1 column
+// blocks (and a partial one) past a sector, i.e. fewer than 96 rows of the
+// widest block, and padded k runs past a row by fewer than 16 values.  The
+// whole area, slack and alignment gaps included, is zero before the
+// transpose fills it, so such reads only ever meet finite values.
+inline int64_t ut_slack(int max_ld) { return 96 * (int64_t)max_ld + 64; }
+
+__global__ __launch_bounds__(256) void transpose_u_kernel(const UtSeg* __restrict__ segs, const float* __restrict__ U,
+                                                          float* __restrict__ Ut) {
+    const UtSeg g = segs[blockIdx.y];
+    const int64_t n = (int64_t)g.rows4 * g.mp;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e / g.mp), beta = (int)(e % g.mp);
+        Ut[g.ut_off + (int64_t)beta * g.ld + i] = i < g.rows ? U[g.u_off + (int64_t)i * g.mp + beta] : 0.f;
+    }
+}
 
 // MAXA: most 16-wide blocks of output rows (kept dim of T) a task can have;
 // CG: output column blocks (kept dim of Q) handled together, so each value of
@@ -145,7 +175,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int MAXA, int CG>
 __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __restrict__ tasks, int n_tasks,
                                                             const BlkTerm* __restrict__ terms,
-                                                            const float* __restrict__ U, const float* __restrict__ O,
+                                                            const float* __restrict__ Ut, const float* __restrict__ O,
                                                             float* __restrict__ out, int* __restrict__ counter) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lh = lane >> 4;
@@ -154,8 +184,8 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
     t = __shfl(t, 0, 64);
     while (t < n_tasks) {
         const BlkTask T = tasks[t];
-        const float* uT = U + T.uT_off;
-        const float* uQ = U + T.uQ_off;
+        const float* uT = Ut + T.uT_off;
+        const float* uQ = Ut + T.uQ_off;
         const int nbc = (T.mQ + 15) >> 4, nba = (T.mT + 15) >> 4;
         for (int cg0 = 0; cg0 < nbc; cg0 += CG) {
             f32x4 acc[CG][MAXA];
@@ -172,35 +202,41 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
 #pragma unroll
                     for (int c = 0; c < CG; c++) x[c] = f32x4{0.f, 0.f, 0.f, 0.f};
                     const int row = rb * 16 + li;
-#pragma unroll 2
-                    for (int k0 = 0; k0 < tm.k; k0 += 4) {
-                        const int k = k0 + lh;
-                        const bool kok = k < tm.k;
-                        const float av = (row < tm.a && kok) ? o[(int64_t)row * tm.k + k] : 0.f;
-                        const float* uqrow = uQ + (int64_t)(tm.rq + k) * T.mQ;
+                    const bool rok = row < tm.a;
+                    const float* orow = o + (int64_t)row * tm.k;
+                    for (int k0 = 0; k0 < tm.k; k0 += 16) {
+                        const int kk = k0 + 4 * lh;  // this lane's k = kk + j at step j
+                        f32x4 av;
+                        if (rok && kk + 4 <= tm.k) {
+                            av = *reinterpret_cast<const f32x4u*>(orow + kk);
+                        } else {
 #pragma unroll
-                        for (int c = 0; c < CG; c++) {
-                            const int beta = (cg0 + c) * 16 + li;
-                            const float bv = (kok && beta < T.mQ) ? uqrow[beta] : 0.f;
-                            x[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, x[c], 0, 0, 0);
+                            for (int j = 0; j < 4; j++) av[j] = (rok && kk + j < tm.k) ? orow[kk + j] : 0.f;
                         }
+                        f32x4 bv[CG];
+#pragma unroll
+                        for (int c = 0; c < CG; c++)
+                            bv[c] = *reinterpret_cast<const f32x4*>(uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ +
+                                                                    tm.rq + kk);
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+#pragma unroll
+                            for (int c = 0; c < CG; c++)
+                                x[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[c][j], x[c], 0, 0, 0);
                     }
                     // stage 2: acc(beta, alpha) += sum_r X_s[r][beta] U_T[rt + r][alpha], the X block
                     // in accumulator layout read with k order 4*(l/16) + j at step j
 #pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        const int r = rb * 16 + 4 * lh + j;
-                        const bool rok = r < tm.a;
-                        const float* urow = uT + (int64_t)(tm.rt + r) * T.mT;
+                    for (int ca = 0; ca < MAXA; ca++) {
+                        if (ca < nba) {
+                            const f32x4 bv = *reinterpret_cast<const f32x4*>(
+                                uT + (int64_t)(ca * 16 + li) * T.ldT + tm.rt + rb * 16 + 4 * lh);
 #pragma unroll
-                        for (int ca = 0; ca < MAXA; ca++) {
-                            if (ca < nba) {
-                                const int alpha = ca * 16 + li;
-                                const float bv = (rok && alpha < T.mT) ? urow[alpha] : 0.f;
+                            for (int j = 0; j < 4; j++)
 #pragma unroll
                                 for (int c = 0; c < CG; c++)
-                                    acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], bv, acc[c][ca], 0, 0, 0);
-                            }
+                                    acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], bv[j], acc[c][ca], 0,
+                                                                                       0, 0);
                         }
                     }
                 }
@@ -229,13 +265,78 @@ __global__ void reset_fused_counter(int* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
+// Layout of the transposed U blocks: kept sector k occupies mp_k rows of
+// ld[k] values (its site states' row ranges, each padded to a multiple of 4,
+// start at pstart[k][s]), from off[k].
+struct UtLayout {
+    std::vector<int> ld;
+    std::vector<std::vector<int>> pstart;  // -1 where the site state has no rows
+    std::vector<int64_t> off;
+    std::vector<UtSeg> segs;
+    int64_t elems = 0;  // including the slack
+    int max_ld = 0;
+};
+
+UtLayout ut_layout(const rot_blocked_problem* p, const Structure& st) {
+    UtLayout L;
+    L.ld.assign(p->n_new, 0);
+    L.pstart.assign(p->n_new, std::vector<int>(p->d, -1));
+    L.off.assign(p->n_new, 0);
+    int64_t off = 0;
+    for (int k = 0; k < p->n_new; k++) {
+        const rot_sector& Q = p->new_sec[k];
+        std::vector<std::pair<int, int>> rows;  // (s, rows of s)
+        int ld = 0;
+        for (int s = 0; s < p->d; s++) {
+            if (st.rowstart[k][s] < 0) continue;
+            const QN q{Q.n_up - p->site_qn[2 * s], Q.n_dn - p->site_qn[2 * s + 1]};
+            const int len = p->old_sec[st.old_idx.at(q)].dim;
+            L.pstart[k][s] = ld;
+            rows.emplace_back(s, len);
+            ld += (len + 3) / 4 * 4;
+        }
+        L.ld[k] = ld;
+        L.max_ld = std::max(L.max_ld, ld);
+        L.off[k] = off;
+        for (auto [s, len] : rows) {
+            UtSeg g{};
+            g.u_off = p->U_off[k] + st.rowstart[k][s] * Q.dim;
+            g.ut_off = off + L.pstart[k][s];
+            g.rows = len;
+            g.rows4 = (len + 3) / 4 * 4;
+            g.mp = Q.dim;
+            g.ld = ld;
+            L.segs.push_back(g);
+        }
+        off += (int64_t)Q.dim * ld;
+        off = (off + 3) / 4 * 4;
+    }
+    L.elems = off + ut_slack(L.max_ld);
+    return L;
+}
+
+// Workspace of the grouped path's intermediate X (elements).
+int64_t x_elements(const rot_blocked_problem* p, const Structure& st) {
+    int64_t x = 0;
+    for (int b = 0; b < p->n_ops; b++) {
+        const int du = p->shift[2 * b], dd = p->shift[2 * b + 1];
+        for (int k = 0; k < p->n_new; k++) {
+            if (p->out_off[(int64_t)b * p->n_new + k] < 0) continue;
+            const rot_sector& Q = p->new_sec[k];
+            const int kt = st.new_idx.at(QN{Q.n_up + du, Q.n_dn + dd});
+            x += (st.M[kt] * Q.dim + 63) / 64 * 64;
+        }
+    }
+    return x;
+}
+
 struct FusedLists {
     std::vector<BlkTask> tasks;
     std::vector<BlkTerm> terms;
     int max_mT = 0;
 };
 
-void build_fused(const rot_blocked_problem* p, const Structure& st, FusedLists* F) {
+void build_fused(const rot_blocked_problem* p, const Structure& st, const UtLayout& ut, FusedLists* F) {
     std::vector<std::pair<double, BlkTask>> work;
     std::vector<BlkTerm> terms;
     for (int b = 0; b < p->n_ops; b++) {
@@ -250,8 +351,10 @@ void build_fused(const rot_blocked_problem* p, const Structure& st, FusedLists* 
             task.mT = Tsec.dim;
             task.mQ = Q.dim;
             task.term0 = (int)terms.size();
-            task.uT_off = p->U_off[kt];
-            task.uQ_off = p->U_off[k];
+            task.ldT = ut.ld[kt];
+            task.ldQ = ut.ld[k];
+            task.uT_off = ut.off[kt];
+            task.uQ_off = ut.off[k];
             task.out_off = out_off;
             double cost = 1.0;
             for (int s = 0; s < p->d; s++) {
@@ -266,8 +369,8 @@ void build_fused(const rot_blocked_problem* p, const Structure& st, FusedLists* 
                 BlkTerm tm{};
                 tm.a = p->old_sec[st.old_idx.at(qt)].dim;
                 tm.k = p->old_sec[it->second].dim;
-                tm.rt = (int)rt;
-                tm.rq = (int)rq;
+                tm.rt = ut.pstart[kt][s];
+                tm.rq = ut.pstart[k][s];
                 tm.o_off = oo;
                 terms.push_back(tm);
                 cost += (double)tm.a * tm.k * Q.dim + (double)Tsec.dim * tm.a * Q.dim;
@@ -372,8 +475,12 @@ struct Plan {
     int64_t x_elems = 0;
     BlkTask* f_tasks = nullptr;
     BlkTerm* f_terms = nullptr;
+    UtSeg* f_segs = nullptr;
     int f_n_tasks = 0;
+    int f_n_segs = 0;
     int f_max_mT = 0;
+    int64_t ut_base = 0;   // transposed U area in the workspace (elements)
+    int64_t ut_elems = 0;  // its size, slack included
     int path = -1;  // 0 grouped two-stage, 1 fused, 2 fused wide; -1 not chosen yet
     ~Plan() {
         (void)hipFree(s1.probs);
@@ -383,6 +490,7 @@ struct Plan {
         (void)hipFree(counter);
         (void)hipFree(f_tasks);
         (void)hipFree(f_terms);
+        (void)hipFree(f_segs);
     }
 };
 
@@ -443,21 +551,13 @@ GroupedShape blocked_shape() { return GroupedShape::k32; }
 
 }  // namespace
 
+// X of the grouped path, then the transposed U blocks of the fused path.
 size_t blocked_workspace_bytes(const rot_blocked_problem* p) {
     Structure st;
     std::string why;
     if (!build_structure(p, &st, &why)) return 0;
-    int64_t x = 0;
-    for (int b = 0; b < p->n_ops; b++) {
-        const int du = p->shift[2 * b], dd = p->shift[2 * b + 1];
-        for (int k = 0; k < p->n_new; k++) {
-            if (p->out_off[(int64_t)b * p->n_new + k] < 0) continue;
-            const rot_sector& Q = p->new_sec[k];
-            const int kt = st.new_idx.at(QN{Q.n_up + du, Q.n_dn + dd});
-            x += (st.M[kt] * Q.dim + 63) / 64 * 64;
-        }
-    }
-    return (size_t)x * sizeof(float);
+    const int64_t x = (x_elements(p, st) + 63) / 64 * 64;
+    return (size_t)(x + ut_layout(p, st).elems) * sizeof(float);
 }
 
 rot_status blocked_validate(const rot_blocked_problem* p, std::string* why) {
@@ -499,22 +599,31 @@ hipError_t run_grouped(const rot_blocked_problem* p, Plan* plan, void* ws, Group
 // pass); `wide` keeps every column block of a task in one pass (fewest
 // operand fetches), otherwise fewer per pass (more resident waves).
 template <int MAXA, int CG>
-void launch_fused(const rot_blocked_problem* p, Plan* plan, hipStream_t stream) {
+void launch_fused(Plan* plan, const float* ut, const rot_blocked_problem* p, hipStream_t stream) {
     const int grid = 256 * 4;  // 4 workgroups of 4 waves per CU, each wave a task queue consumer
     hipLaunchKernelGGL((blocked_fused_kernel<MAXA, CG>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
-                       plan->f_n_tasks, plan->f_terms, p->U_blk, p->O_blk, p->out_blk, plan->counter);
+                       plan->f_n_tasks, plan->f_terms, ut, p->O_blk, p->out_blk, plan->counter);
 }
 
-hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, hipStream_t stream) {
+hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, void* ws, hipStream_t stream) {
     if (plan->f_n_tasks == 0) return hipSuccess;
+    float* ut = static_cast<float*>(ws) + plan->ut_base;
+    hipError_t e = prof_timed("blocked_transpose_u", stream, [&] {
+        hipError_t err = fill_zero(ut, plan->ut_elems * (int64_t)sizeof(float), stream);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(transpose_u_kernel, dim3(16, (unsigned)plan->f_n_segs), dim3(256), 0, stream,
+                           plan->f_segs, p->U_blk, ut);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
     return prof_timed("blocked_fused_fp32", stream, [&] {
         hipLaunchKernelGGL(reset_fused_counter, dim3(1), dim3(64), 0, stream, plan->counter);
         if (plan->f_max_mT <= 64) {
-            if (wide) launch_fused<4, 4>(p, plan, stream); else launch_fused<4, 2>(p, plan, stream);
+            if (wide) launch_fused<4, 4>(plan, ut, p, stream); else launch_fused<4, 2>(plan, ut, p, stream);
         } else if (plan->f_max_mT <= 80) {
-            if (wide) launch_fused<5, 5>(p, plan, stream); else launch_fused<5, 3>(p, plan, stream);
+            if (wide) launch_fused<5, 3>(plan, ut, p, stream); else launch_fused<5, 2>(plan, ut, p, stream);
         } else {
-            if (wide) launch_fused<8, 3>(p, plan, stream); else launch_fused<8, 2>(p, plan, stream);
+            if (wide) launch_fused<8, 3>(plan, ut, p, stream); else launch_fused<8, 2>(plan, ut, p, stream);
         }
         return hipGetLastError();
     });
@@ -535,7 +644,7 @@ int forced_path() {
 hipError_t run_path(const rot_blocked_problem* p, Plan* plan, void* ws, GroupedShape shape, int path,
                     hipStream_t stream) {
     if (path == 0) return run_grouped(p, plan, ws, shape, stream);
-    return run_fused(p, plan, path == 2, stream);
+    return run_fused(p, plan, path == 2, ws, stream);
 }
 
 }  // namespace
@@ -561,8 +670,9 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         if (!build_structure(p, &st, &why)) return hipErrorInvalidValue;  // validated by the caller
         Lists L;
         build_lists(p, st, static_cast<const float*>(ws), &L);
+        const UtLayout ut = ut_layout(p, st);
         FusedLists F;
-        build_fused(p, st, &F);
+        build_fused(p, st, ut, &F);
         auto np = std::make_unique<Plan>();
         np->sig = std::move(sig);
         np->x_elems = L.x_elems;
@@ -572,6 +682,12 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         if (e == hipSuccess) e = hipMalloc(&np->counter, sizeof(int));
         np->f_n_tasks = (int)F.tasks.size();
         np->f_max_mT = F.max_mT;
+        np->f_n_segs = (int)ut.segs.size();
+        np->ut_base = (L.x_elems + 63) / 64 * 64;
+        np->ut_elems = ut.elems;
+        if (e == hipSuccess && !ut.segs.empty()) e = hipMalloc(&np->f_segs, sizeof(UtSeg) * ut.segs.size());
+        if (e == hipSuccess && !ut.segs.empty())
+            e = hipMemcpy(np->f_segs, ut.segs.data(), sizeof(UtSeg) * ut.segs.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess && !F.tasks.empty()) e = hipMalloc(&np->f_tasks, sizeof(BlkTask) * F.tasks.size());
         if (e == hipSuccess && !F.terms.empty()) e = hipMalloc(&np->f_terms, sizeof(BlkTerm) * F.terms.size());
         if (e == hipSuccess && !F.tasks.empty())

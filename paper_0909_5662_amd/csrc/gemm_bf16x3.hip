@@ -166,14 +166,15 @@ __device__ inline void store_tile(const Bf16Desc& g, const f32x16 (&acc)[BI][BJ]
     }
 }
 
-// Square tile T x T, T = 32 * (number of waves), as WGM x WGN waves of
-// (32 BI) x (32 BJ), each BI x BJ blocks of v_mfma_f32_32x32x16_bf16.  That
+// Square tile T x T as WGM x WGN waves of (32 BI) x (32 BJ), each BI x BJ
+// blocks of v_mfma_f32_32x32x16_bf16.  That
 // instruction takes from lane l A(row l%32, k 8*(l/32)+e) and B(k 8*(l/32)+e,
 // col l%32), e < 8.  The K loop runs over slabs through a ring of S LDS
 // stages, each holding one slab of A_hi, A_lo, B_hi, B_lo for the tile
 // (T rows x 32 bytes per array, as in memory).  Vector memory fills the
-// stages directly: wave w copies block w (32 rows, 1 KB) of each array with
-// one buffer load with LDS destination, 16 bytes per lane.  S - 1 slabs are
+// stages directly: wave w copies blocks w, w + waves, ... (32 rows, 1 KB
+// each) of each array, one buffer load with LDS destination per block, 16
+// bytes per lane.  S - 1 slabs are
 // in flight while one is multiplied.  Before step t each wave waits for its
 // own loads of slab t + 1, and the barrier makes every wave's loads visible
 // and frees slab t - 1's stage (every wave consumed its fragments in step
@@ -183,11 +184,14 @@ template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T, bool D4>
 __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc g, int tiles_m, int tiles_n,
                                                                          int n_fastest) {
     constexpr int NW = WGM * WGN;
-    constexpr int T = 32 * NW;
-    static_assert(32 * WGM * BI == T && 32 * WGN * BJ == T, "square tile of 32 rows per wave");
+    constexpr int T = 32 * WGM * BI;
+    static_assert(32 * WGN * BJ == T, "square tile");
+    constexpr int NBLK = T / 32;     // 1 KB blocks per array in a stage
+    static_assert(NBLK % NW == 0, "whole blocks per wave");
+    constexpr int BPW = NBLK / NW;   // blocks per wave per array
     constexpr int ARR = T * kSlabK;  // elements of one array in a stage
     constexpr int STAGE = 4 * ARR;   // A_hi, A_lo, B_hi, B_lo
-    constexpr int LOADS = 4;         // direct loads per wave per stage
+    constexpr int LOADS = 4 * BPW;   // direct loads per wave per stage
     __shared__ __attribute__((aligned(1024))) uint16_t lds[S * STAGE];
 
     const int lin = xcd_linear_id();
@@ -214,13 +218,18 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc
     const uint32_t a_slab = (uint32_t)g.M * kSlabK * 2, b_slab = (uint32_t)g.N * kSlabK * 2;
     const int nk = (int)n_slabs(g.K);
 
+    // wave w copies blocks w, w + NW, ... (32 rows each) of every array
     auto issue = [&](int st) {
         uint16_t* base = lds + (st % S) * STAGE + wave * 512;
 #pragma unroll
-        for (int j = 0; j < LOADS; j++)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rs[j], (__attribute__((address_space(3))) void*)(base + j * ARR), 16,
-                j < 2 ? a_off + (uint32_t)st * a_slab : b_off + (uint32_t)st * b_slab, 0, 0, 0);
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int x = 0; x < BPW; x++)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs[j], (__attribute__((address_space(3))) void*)(base + j * ARR + x * NW * 512), 16,
+                    (j < 2 ? a_off + (uint32_t)st * a_slab : b_off + (uint32_t)st * b_slab) +
+                        (uint32_t)(x * NW * 1024),
+                    0, 0, 0);
     };
 
     f32x16 acc[BI][BJ];
