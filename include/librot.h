@@ -201,7 +201,12 @@ ROT_API rot_status rot_plan_destroy(rot_plan plan);
  *                dim(Q)); -1 means not requested.  A requested block whose
  *                target sector is not kept is an error.
  * Only ROT_FP32 is supported.  workspace: at least
- * rot_blocked_workspace_size(p) bytes.
+ * rot_blocked_workspace_size(p) bytes.  The first call for a block structure
+ * (sector tables, offsets and buffers) times the available execution paths
+ * (one fused kernel in two register layouts, or two grouped launches) and
+ * keeps the fastest for later calls with the same structure; every call's
+ * result comes from the kept path, so repeated calls agree bit for bit.
+ * ROT_BLOCKED_PATH=fused|fused_wide|grouped in the environment forces one.
  */
 typedef struct { int32_t n_up, n_dn, dim; int64_t offset; } rot_sector;
 typedef struct {

@@ -729,7 +729,9 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         for (int i = 0; i < 4; i++) (void)hipEventDestroy(ev[i]);
         if (e != hipSuccess) return e;
         plan->path = best_q;
-        return hipSuccess;  // every timed run left the full result in out_blk
+        // the chosen path writes the result, so this call matches every later
+        // one bit for bit (the paths sum in different orders)
+        path = best_q;
     }
     return run_path(p, plan, ws, shape, path, stream);
 }
