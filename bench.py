@@ -49,23 +49,26 @@ def flops_per_op(m, d, mp):
 
 
 def time_steps(rot, U, O, out, ws, d, precision, steps, warmup, profile):
+    """Total ms of `steps` rotations (events on the launch stream around the
+    whole loop), the per-step times (one event per step boundary) and the
+    kernel timings of librot's profiler."""
     import torch
     for _ in range(warmup):
         rot.rotate(U, O, d, precision, out=out, workspace=ws)
     torch.cuda.synchronize()
     if profile:
         rot.profile_enable(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
         rot.rotate(U, O, d, precision, out=out, workspace=ws)
-    stop.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     kernels = rot.profile_read() if profile else {}
     if profile:
         rot.profile_enable(False)
-    return start.elapsed_time(stop), kernels
+    per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]), kernels, per_step
 
 
 def recorded_traffic(kernel_kind):
@@ -96,7 +99,7 @@ def measure(rot, U, O, out, d, precision, steps, warmup):
     p = rot._problem(U, O, out, d)
     prec = rot.precision_code(precision)
     ws = torch.empty(rot.rot_workspace_size([p], prec), dtype=torch.uint8, device=U.device)
-    ms, kernels = time_steps(rot, U, O, out, ws, d, precision, steps, warmup, True)
+    ms, kernels, per_step = time_steps(rot, U, O, out, ws, d, precision, steps, warmup, True)
     del ws
     ops_per_s = n * steps / (ms / 1e3)
     F = flops_per_op(m, d, mp)
@@ -111,7 +114,9 @@ def measure(rot, U, O, out, d, precision, steps, warmup):
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": recorded_traffic(dom_name),
                 "kernel": dom_name, "avg_ms": round(dom_avg_ms, 4)}
+    per_step.sort()
     return {"ops_per_s": ops_per_s, "ms_per_step": ms / steps, "tflops": tflops,
+            "ms_per_step_median": per_step[len(per_step) // 2], "ms_per_step_min": per_step[0],
             "pct_mfma_peak": 100 * tflops * exec_factor / peak,
             "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
             "roofline": roofline}
@@ -154,9 +159,16 @@ def bench_blocked(args, rot, torch, workloads):
                     flops += 2.0 * old[qt].dim * old[qs].dim * sec.dim
             flops += 2.0 * new[t].dim * MT * sec.dim
             bytes_alg += new[t].dim * sec.dim * 4
+    # cold first call: builds the work-lists and times the execution paths
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - c0) * 1e3
     for _ in range(max(1, args.warmup)):
         run()
     torch.cuda.synchronize()
+    # direct calls, with librot's per-kernel profiler
     rot.profile_enable(True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -167,7 +179,23 @@ def bench_blocked(args, rot, torch, workloads):
     torch.cuda.synchronize()
     kernels = rot.profile_read()
     rot.profile_enable(False)
-    ms = t0.elapsed_time(t1) / args.steps
+    direct_ms = t0.elapsed_time(t1) / args.steps
+    # the timed figure: replays of the call captured in a hipGraph
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run()
+    for _ in range(max(1, args.warmup)):
+        graph.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for i in range(args.steps):
+        graph.replay()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
+    ms = ev[0].elapsed_time(ev[args.steps]) / args.steps
+    del graph
     n = len(case.shifts)
     tflops = flops / (ms / 1e3) / 1e12
     rec = base_record(args, n / (ms / 1e3), "operator rotations/s", ms,
@@ -176,7 +204,10 @@ def bench_blocked(args, rot, torch, workloads):
                                                                  max(s.dim for s in case.old)],
                        "n_ops": n, "precision": "fp32"})
     dom, (cnt, tot) = max(kernels.items(), key=lambda kv: kv[1][1])
-    rec.update({"gflop_per_step": round(flops / 1e9, 3), "tflops": round(tflops, 2),
+    rec.update({"timing": "hipGraph replays of one call", "ms_per_step_median": round(per_step[len(per_step) // 2], 4),
+                "ms_per_step_min": round(per_step[0], 4), "direct_call_ms_per_step": round(direct_ms, 4),
+                "cold_first_call_ms": round(cold_ms, 2),
+                "gflop_per_step": round(flops / 1e9, 3), "tflops": round(tflops, 2),
                 "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2),
                 "algorithmic_gb_per_s": round(bytes_alg / (ms / 1e3) / 1e9, 1),
                 "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
@@ -193,8 +224,16 @@ def bench_uneven(args, rot, torch, workloads):
     sizes = workloads.uneven_sizes(1000)
     data = workloads.uneven_case_gpu(sizes, d=4, ops_per_rot=8, cfg=4)
     groups = [(U, O, torch.empty((8, U.shape[1], U.shape[1]), device=U.device), 4) for U, O in data]
-    plan = rot.Plan(groups, workspace_bytes=32 << 30)
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    plan = rot.Plan(groups, workspace_bytes=32 << 30)  # size classes, tuning, graph capture
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - c0
     flops = sum(8 * flops_per_op(m, 4, m) for m in sizes)
+    c0 = time.perf_counter()
+    plan.execute()
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - c0) * 1e3
     for _ in range(max(1, args.warmup)):
         plan.execute()
     torch.cuda.synchronize()
@@ -210,7 +249,9 @@ def bench_uneven(args, rot, torch, workloads):
     rec = base_record(args, 8000 / (ms / 1e3), "operator rotations/s", ms,
                       {"workload": "uneven_1000", "rotations": 1000, "ops_per_rotation": 8, "d": 4,
                        "m_classes": [128, 256, 512, 1024, 2048], "precision": "fp32"})
-    rec.update({"tflop_per_step": round(flops / 1e12, 2), "tflops": round(tflops, 2),
+    rec.update({"timing": "hipGraph replays of the plan", "plan_create_s": round(plan_s, 2),
+                "cold_first_execute_ms": round(cold_ms, 1),
+                "tflop_per_step": round(flops / 1e12, 2), "tflops": round(tflops, 2),
                 "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2), "plan": plan.describe(),
                 "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 157.3, "unit": "TFLOP/s",
                              "frac": round(tflops / 157.3, 4), "traffic": None, "kernel": "plan graph (all launches)"}})
@@ -264,19 +305,60 @@ def bench_differentiated(args, rot, torch, workloads):
     return rec
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(case, n_total):
     """The oracle, as it stands, on a bounded sample: one operator per host
-    thread (at most the whole batch), all threads of this process."""
+    thread (at most the whole batch), all threads of this process; then one
+    operator on one thread."""
     import oracle
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     n_s = max(1, min(n_total, nthreads))
     t0 = time.perf_counter()
     oracle.rotate(case.U, case.O[:n_s], case.d, nthreads=nthreads)
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.rotate(case.U, case.O[:1], case.d, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n_s / dt, "unit": "operator rotations/s", "cores": min(nthreads, n_s),
             "kind": "oracle",
             "sample": f"{n_s} of {n_total} operators (m=1024, d=4, m'=1024), FP64, explicit kron, "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall; then 1 operator on 1 thread, {dt1:.1f} s",
+            "value_1thread": 1.0 / dt1, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def torch_fp64_naive(torch, U, O, d, sample=8, reps=3):
+    """Operators/s of the naive PyTorch FP64 rotation (explicit kron(O_b, I_d),
+    then two batched matmuls) on the GPU, for a sample of the batch: a
+    reported reference point, not part of the library."""
+    U64 = U.double()
+    Ut64 = U64.t().contiguous()
+    O64 = O[:sample].double()
+    eye = torch.eye(d, dtype=torch.float64, device=U.device)
+    n, m, _ = O64.shape
+
+    def step():
+        A = (O64[:, :, None, :, None] * eye[None, None, :, None, :]).reshape(n, m * d, m * d)
+        return torch.matmul(Ut64, torch.matmul(A, U64))
+
+    step()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    return n * reps / (t0.elapsed_time(t1) / 1e3)
 
 
 def main():
@@ -331,6 +413,8 @@ def main():
         "config": {"workload": WORKLOAD, "m": m, "d": d, "mp": mp, "n_ops": n,
                    "precision": args.precision, "operators": "symmetric Gaussian / sqrt(m)",
                    "U": "QR of seeded 4096x1024 Gaussian"},
+        "ms_per_step_median": round(main_run["ms_per_step_median"], 4),
+        "ms_per_step_min": round(main_run["ms_per_step_min"], 4),
         "tflops": round(main_run["tflops"], 2),
         "pct_mfma_peak": round(main_run["pct_mfma_peak"], 2),
         "kernels_ms_avg": main_run["kernels_ms_avg"],
@@ -341,6 +425,8 @@ def main():
         b = measure(rot, U, O, out, d, "split_bf16", args.steps, args.warmup)
         result["split_bf16"] = {"value": round(b["ops_per_s"], 2), "unit": "operator rotations/s",
                                 "ms_per_step": round(b["ms_per_step"], 4),
+                                "ms_per_step_median": round(b["ms_per_step_median"], 4),
+                                "ms_per_step_min": round(b["ms_per_step_min"], 4),
                                 "tflops_fp32_equivalent": round(b["tflops"], 2),
                                 "pct_bf16_mfma_peak": round(b["pct_mfma_peak"], 2),
                                 "speedup_vs_fp32": round(b["ops_per_s"] / main_run["ops_per_s"], 3),
@@ -353,6 +439,9 @@ def main():
         result["fp64_gpu_ops_per_s"] = round(r64["ops_per_s"], 2)
         result["speedup_vs_fp64_gpu"] = round(main_run["ops_per_s"] / r64["ops_per_s"], 3)
         del U64, O64, out64
+        naive = torch_fp64_naive(torch, U, O, d)
+        result["torch_fp64_kron_ops_per_s"] = round(naive, 2)
+        result["speedup_vs_torch_fp64_kron"] = round(main_run["ops_per_s"] / naive, 2)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(case, n)
