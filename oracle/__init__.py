@@ -51,6 +51,8 @@ def _load():
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.orc_rotate.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int]
         lib.orc_rotate.restype = ctypes.c_int
+        lib.orc_rotate_site.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, dp, ctypes.c_int]
+        lib.orc_rotate_site.restype = ctypes.c_int
         lib.orc_rotate_entries.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_int, i32p, i32p, dp]
         lib.orc_rotate_entries.restype = None
         lib.orc_adjoint.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
@@ -96,6 +98,28 @@ def rotate(U, O, d: int, nthreads: int = 0) -> np.ndarray:
     mp = U.shape[1]
     out = np.empty((n, mp, mp))
     rc = _load().orc_rotate(m, d, mp, n, _ptr(U), _ptr(O), _ptr(out), nthreads)
+    if rc != 0:
+        raise MemoryError("oracle scratch allocation failed")
+    return out[0] if single else out
+
+
+def rotate_site(U, X, S, nthreads: int = 0) -> np.ndarray:
+    """Sec. 2 step 3 (blocking of operators that act on the added site) then
+    step 5: out_b = U^T kron(X_b, S) U with the blocked operator materialised.
+    U: (m*d, mp); X: (n, m, m) or (m, m); S: (d, d)."""
+    U = _f64(U)
+    X = _f64(X)
+    S = _f64(S)
+    single = X.ndim == 2
+    if single:
+        X = X[None]
+    n, m, _ = X.shape
+    d = S.shape[0]
+    if S.shape != (d, d) or U.shape[0] != m * d:
+        raise ValueError("S must be d x d and U must have m*d rows")
+    mp = U.shape[1]
+    out = np.empty((n, mp, mp))
+    rc = _load().orc_rotate_site(m, d, mp, n, _ptr(U), _ptr(X), _ptr(S), _ptr(out), nthreads)
     if rc != 0:
         raise MemoryError("oracle scratch allocation failed")
     return out[0] if single else out

@@ -140,6 +140,62 @@ int orc_rotate(int m, int d, int mp, int n_ops, const double* U, const double* O
     return failed ? -1 : 0;
 }
 
+/* Blocking of an operator together with the added site (Sec. 2 step 3, the
+ * blocking Z_[B a] <- Z_[B (+) a] for operators that act on the new site):
+ * A = kron(X, S), A[i*d+s, j*d+t] = X[i,j] * S[s,t].  X = I_m gives the new
+ * site's own operator I_B (x) Z_a; X = P_B (block fermion parity) gives a
+ * fermionic site operator with its Jordan-Wigner string over the block; a
+ * block operator X gives the block-site product X (x) Z_a. */
+static void orc_block_site(int m, int d, const double* X, const double* S, double* A) {
+    int64_t md = (int64_t)m * d;
+    for (int i = 0; i < m; i++)
+        for (int s = 0; s < d; s++)
+            for (int j = 0; j < m; j++)
+                for (int t = 0; t < d; t++)
+                    A[((int64_t)i * d + s) * md + (int64_t)j * d + t] = X[(int64_t)i * m + j] * S[s * d + t];
+}
+
+/*
+ * Rotation of operators blocked with a site operator:
+ *   out_b = U^T kron(X_b, S) U
+ *   U   : (m*d) x mp;  X : n_ops x m x m;  S : d x d (shared by the batch)
+ *   out : n_ops x mp x mp
+ * Same order as orc_rotate: blocked operator times U first, then U^T times
+ * that.  Returns 0, or -1 if a scratch allocation failed.
+ */
+int orc_rotate_site(int m, int d, int mp, int n_ops, const double* U, const double* X, const double* S,
+                    double* out, int nthreads) {
+    int p = orc_threads(nthreads);
+    int64_t md = (int64_t)m * d;
+    int failed = 0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(p) reduction(| : failed)
+#endif
+    {
+        int rank = 0;
+#ifdef _OPENMP
+        rank = omp_get_thread_num();
+#endif
+        int64_t lo, hi;
+        orc_umd_range(n_ops, p, rank, &lo, &hi);
+        double* A = NULL;
+        double* T = NULL;
+        if (hi > lo) {
+            A = (double*)malloc(sizeof(double) * md * md);
+            T = (double*)malloc(sizeof(double) * md * mp);
+            if (!A || !T) failed = 1;
+        }
+        for (int64_t b = lo; b < hi && !failed; b++) {
+            orc_block_site(m, d, X + b * (int64_t)m * m, S, A);
+            orc_matmul(md, md, mp, A, U, T);
+            orc_matmul_tn(mp, md, mp, U, T, out + b * (int64_t)mp * mp);
+        }
+        free(A);
+        free(T);
+    }
+    return failed ? -1 : 0;
+}
+
 /*
  * Selected entries of one rotated operator, each computed on its own straight
  * from the definition:  out[alpha,beta] = sum_{i,j,s} U[i*d+s,alpha] O[i,j] U[j*d+s,beta].
