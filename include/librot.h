@@ -137,6 +137,47 @@ ROT_API rot_status rot_backward(const rot_problem* groups, int32_t n_groups,
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Operators blocked together with the added site (Sec. 2 step 3: the blocking
+ * Z_[B a] <- Z_[B (+) a] for operators that act on the new site a; Sec. 3.2
+ * task ii), rotated as in step 5:
+ *     out_b = U^T (X_b (x) S) U          (mp x mp at out + b*stride_out)
+ * S is one d x d site operator for the group (host memory, d*d doubles,
+ * row-major, d <= 16); X_b acts on the old block, by block_kind:
+ *   ROT_BLOCK_IDENTITY  X = I_m, the site's own operator I_B (x) Z_a
+ *                       (n_ops = 1, X = NULL);
+ *   ROT_BLOCK_DIAGONAL  X = diag(x), x = m values at X: with x the block's
+ *                       fermion parity P_B = (-1)^N_B this is a fermionic site
+ *                       operator with its Jordan-Wigner string (n_ops = 1);
+ *   ROT_BLOCK_DENSE     X_b = m x m at X + b*stride_x (stride_x >= m*m): the
+ *                       block-site products Z_B (x) Z_a, including the
+ *                       hopping-type c+_B P_B (x) c_a (n_ops >= 0).
+ * U and out follow rot_problem (U (m*d) x mp, row r = i*d + s).  X (x) S is
+ * never formed: with U' = (diag(x) (x) S^T) U, out = U'^T U for the identity
+ * and diagonal kinds and out = U'^T (X_b U_r) for the dense kind.
+ * Precisions ROT_FP64 and ROT_FP32 (buffers of that type; S is always
+ * double).  workspace: at least rot_site_workspace_size(..., 1) bytes,
+ * 256-byte aligned; larger workspaces give larger operator chunks.
+ */
+#define ROT_BLOCK_IDENTITY 0
+#define ROT_BLOCK_DIAGONAL 1
+#define ROT_BLOCK_DENSE 2
+typedef struct {
+    int32_t m, d, mp, n_ops;
+    int32_t block_kind;
+    const void* U;
+    const double* site;
+    const void* X;
+    int64_t stride_x;
+    void* out;
+    int64_t stride_out;
+} rot_site_problem;
+
+ROT_API size_t rot_site_workspace_size(const rot_site_problem* groups, int32_t n_groups, rot_precision prec,
+                               int32_t ops_per_chunk);
+ROT_API rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_groups, rot_precision prec,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Plans: repeated rotation of a fixed set of groups with different sizes (a
  * sweep step rotates the stored operators of many blocks; Sec. 3.2 counts
  * l(l+3)/2 of them per block).  rot_plan_create buckets the groups into size

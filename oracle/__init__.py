@@ -53,6 +53,8 @@ def _load():
         lib.orc_rotate.restype = ctypes.c_int
         lib.orc_rotate_site.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, dp, ctypes.c_int]
         lib.orc_rotate_site.restype = ctypes.c_int
+        lib.orc_rotate_site_entries.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_int, i32p, i32p, dp]
+        lib.orc_rotate_site_entries.restype = None
         lib.orc_rotate_entries.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_int, i32p, i32p, dp]
         lib.orc_rotate_entries.restype = None
         lib.orc_adjoint.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
@@ -123,6 +125,22 @@ def rotate_site(U, X, S, nthreads: int = 0) -> np.ndarray:
     if rc != 0:
         raise MemoryError("oracle scratch allocation failed")
     return out[0] if single else out
+
+
+def rotate_site_entries(U, X, S, alpha, beta) -> np.ndarray:
+    """Selected entries of U^T kron(X, S) U for one block operator X (m x m),
+    each computed on its own from the quadruple sum of the definition."""
+    U = _f64(U)
+    X = _f64(X)
+    S = _f64(S)
+    m, d = X.shape[0], S.shape[0]
+    alpha = np.ascontiguousarray(alpha, dtype=np.int32)
+    beta = np.ascontiguousarray(beta, dtype=np.int32)
+    vals = np.empty(len(alpha))
+    _load().orc_rotate_site_entries(m, d, U.shape[1], _ptr(U), _ptr(X), _ptr(S), len(alpha),
+                                    alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    beta.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(vals))
+    return vals
 
 
 def rotate_entries(U, O, d: int, alpha, beta) -> np.ndarray:

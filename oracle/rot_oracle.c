@@ -197,6 +197,32 @@ int orc_rotate_site(int m, int d, int mp, int n_ops, const double* U, const doub
 }
 
 /*
+ * Selected entries of one operator blocked with a site operator, each on its
+ * own from the definition:
+ *   out[alpha,beta] = sum_{i,s,j,t} U[i*d+s,alpha] X[i,j] S[s,t] U[j*d+t,beta].
+ * Cost m*m*d*d per entry; used to check full-size results at sampled positions.
+ */
+void orc_rotate_site_entries(int m, int d, int mp, const double* U, const double* X, const double* S,
+                             int n_entries, const int32_t* alpha, const int32_t* beta, double* values) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int e = 0; e < n_entries; e++) {
+        const int a = alpha[e], b = beta[e];
+        double acc = 0.0;
+        for (int i = 0; i < m; i++)
+            for (int s = 0; s < d; s++) {
+                const double ua = U[((int64_t)i * d + s) * mp + a];
+                for (int j = 0; j < m; j++) {
+                    const double x = X[(int64_t)i * m + j];
+                    for (int t = 0; t < d; t++) acc += ua * x * S[s * d + t] * U[((int64_t)j * d + t) * mp + b];
+                }
+            }
+        values[e] = acc;
+    }
+}
+
+/*
  * Selected entries of one rotated operator, each computed on its own straight
  * from the definition:  out[alpha,beta] = sum_{i,j,s} U[i*d+s,alpha] O[i,j] U[j*d+s,beta].
  * Cost m*m*d per entry; used to check full-size results at sampled positions.

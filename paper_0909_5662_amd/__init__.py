@@ -31,6 +31,8 @@ __all__ = [
     "rotate", "rotate_backward", "pair_loss", "check_isometry", "split_bf16",
     "RotateFn", "PairLossFn", "precision_code", "profile_enable", "profile_read",
     "blocked_problem", "rotate_blocked", "Plan", "ROT_PLAN_NO_GRAPH", "ROT_PLAN_NO_TUNE", "ROT_PLAN_RETUNE",
+    "RotSiteProblem", "ROT_BLOCK_IDENTITY", "ROT_BLOCK_DIAGONAL", "ROT_BLOCK_DENSE", "rot_batch_site",
+    "rot_site_workspace_size", "rotate_site",
 ]
 
 ROT_FP64, ROT_FP32, ROT_SPLIT_BF16 = 0, 1, 2
@@ -52,6 +54,16 @@ class RotProblem(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("d", ctypes.c_int32), ("mp", ctypes.c_int32),
                 ("n_ops", ctypes.c_int32), ("U", ctypes.c_void_p), ("O", ctypes.c_void_p),
                 ("stride_o", ctypes.c_int64), ("out", ctypes.c_void_p), ("stride_out", ctypes.c_int64)]
+
+
+ROT_BLOCK_IDENTITY, ROT_BLOCK_DIAGONAL, ROT_BLOCK_DENSE = 0, 1, 2
+
+
+class RotSiteProblem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("d", ctypes.c_int32), ("mp", ctypes.c_int32),
+                ("n_ops", ctypes.c_int32), ("block_kind", ctypes.c_int32), ("U", ctypes.c_void_p),
+                ("site", ctypes.POINTER(ctypes.c_double)), ("X", ctypes.c_void_p), ("stride_x", ctypes.c_int64),
+                ("out", ctypes.c_void_p), ("stride_out", ctypes.c_int64)]
 
 
 class RotSector(ctypes.Structure):
@@ -86,6 +98,9 @@ def lib() -> ctypes.CDLL:
         L.rot_backward.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                    ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_uint32, ctypes.c_int,
                                    vp, sz, vp]
+        L.rot_batch_site.argtypes = [ctypes.POINTER(RotSiteProblem), i32, ctypes.c_int, vp, sz, vp]
+        L.rot_site_workspace_size.argtypes = [ctypes.POINTER(RotSiteProblem), i32, ctypes.c_int, i32]
+        L.rot_site_workspace_size.restype = sz
         L.rot_batch_blocked.argtypes = [ctypes.POINTER(RotBlockedProblem), ctypes.c_int, vp, sz, vp]
         L.rot_blocked_workspace_size.argtypes = [ctypes.POINTER(RotBlockedProblem)]
         L.rot_blocked_workspace_size.restype = sz
@@ -261,6 +276,55 @@ def rotate(U: torch.Tensor, O: torch.Tensor, d: int, precision="fp32", out: torc
         workspace = _workspace(rot_workspace_size([p], prec), U.device)
     rot_batch([p], prec, workspace.data_ptr(), workspace.numel(), _stream(stream))
     return out
+
+
+def rot_site_workspace_size(groups, prec: int, ops_per_chunk: int = 0) -> int:
+    arr = (RotSiteProblem * len(groups))(*groups)
+    return lib().rot_site_workspace_size(arr, len(groups), prec, ops_per_chunk)
+
+
+def rot_batch_site(groups, prec: int, workspace: int, workspace_bytes: int, stream: int) -> None:
+    arr = (RotSiteProblem * len(groups))(*groups)
+    _check(lib().rot_batch_site(arr, len(groups), prec, workspace, workspace_bytes, stream))
+
+
+def rotate_site(U: torch.Tensor, X, S, precision="fp32", workspace: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """out_b = U^T (X_b (x) S) U for a site operator S (d x d, host array) and
+    X = None (identity of the old block: returns (mp, mp)), a vector of m
+    values (diagonal, e.g. the block's fermion parity: returns (mp, mp)), or
+    block operators of shape (n, m, m) (returns (n, mp, mp))."""
+    import numpy as np
+    prec = precision_code(precision)
+    if prec == ROT_SPLIT_BF16:
+        raise ValueError("rotate_site supports fp32 and fp64")
+    S_host = np.ascontiguousarray(np.asarray(S, dtype=np.float64))
+    d = S_host.shape[0]
+    if S_host.shape != (d, d) or U.shape[0] % d:
+        raise ValueError("S must be d x d and U must have m*d rows")
+    if U.dtype != _dtype_for(prec) or not U.is_contiguous() or not U.is_cuda:
+        raise TypeError("U must be a contiguous CUDA tensor of the precision's dtype")
+    m, mp = U.shape[0] // d, U.shape[1]
+    if X is None:
+        kind, n, xp, sx = ROT_BLOCK_IDENTITY, 1, None, 0
+    else:
+        if X.dtype != U.dtype or not X.is_contiguous() or not X.is_cuda:
+            raise TypeError("X must be a contiguous CUDA tensor with the dtype of U")
+        if X.dim() == 1:
+            if X.shape[0] != m:
+                raise ValueError("diagonal X must have m entries")
+            kind, n, xp, sx = ROT_BLOCK_DIAGONAL, 1, X.data_ptr(), 0
+        else:
+            if X.dim() != 3 or X.shape[1:] != (m, m):
+                raise ValueError("block operators must have shape (n, m, m)")
+            kind, n, xp, sx = ROT_BLOCK_DENSE, X.shape[0], X.data_ptr(), m * m
+    out = torch.empty((n, mp, mp), dtype=U.dtype, device=U.device)
+    p = RotSiteProblem(m, d, mp, n, kind, U.data_ptr(), S_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       xp, sx, out.data_ptr(), mp * mp)
+    if workspace is None:
+        workspace = _workspace(rot_site_workspace_size([p], prec), U.device)
+    rot_batch_site([p], prec, workspace.data_ptr(), workspace.numel(), _stream(stream))
+    return out if kind == ROT_BLOCK_DENSE else out[0]
 
 
 def rotate_backward(U: torch.Tensor, O: torch.Tensor, d: int, dOut: torch.Tensor, precision="fp32",

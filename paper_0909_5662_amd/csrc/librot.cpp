@@ -334,6 +334,129 @@ rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision 
     return ROT_OK;
 }
 
+namespace {
+
+rot_status validate_site(const rot_site_problem& p, rot_precision prec, int gi) {
+    if (p.m <= 0 || p.d <= 0 || p.mp <= 0 || p.n_ops < 0)
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: m, d, mp must be positive and n_ops >= 0", gi);
+    if (p.d > kMaxSite) return fail(ROT_ERR_UNSUPPORTED, "site group %d: d = %d exceeds %d", gi, p.d, kMaxSite);
+    const int64_t md = (int64_t)p.m * p.d;
+    if (md > INT32_MAX || (int64_t)p.d * p.mp > INT32_MAX || p.mp > md)
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: need mp <= m*d and extents below 2^31", gi);
+    if (p.block_kind != ROT_BLOCK_IDENTITY && p.block_kind != ROT_BLOCK_DIAGONAL && p.block_kind != ROT_BLOCK_DENSE)
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: unknown block_kind %d", gi, p.block_kind);
+    if (p.n_ops == 0) return ROT_OK;
+    if (!p.U || !p.site || !p.out) return fail(ROT_ERR_INVALID_ARG, "site group %d: null U, site or out", gi);
+    if (p.block_kind == ROT_BLOCK_IDENTITY && p.X)
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: X must be NULL for ROT_BLOCK_IDENTITY", gi);
+    if (p.block_kind != ROT_BLOCK_IDENTITY && !p.X) return fail(ROT_ERR_INVALID_ARG, "site group %d: null X", gi);
+    if (p.block_kind != ROT_BLOCK_DENSE && p.n_ops != 1)
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: identity and diagonal kinds take n_ops = 1", gi);
+    if (p.block_kind == ROT_BLOCK_DENSE && p.stride_x < (int64_t)p.m * p.m)
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: stride_x must be >= m*m", gi);
+    if (p.stride_out < (int64_t)p.mp * p.mp)
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: stride_out must be >= mp*mp", gi);
+    const size_t es = elem_size(prec);
+    const size_t n_out = ((size_t)(p.n_ops - 1) * p.stride_out + (size_t)p.mp * p.mp) * es;
+    const size_t n_u = (size_t)md * p.mp * es;
+    size_t n_x = 0;
+    if (p.block_kind == ROT_BLOCK_DENSE) n_x = ((size_t)(p.n_ops - 1) * p.stride_x + (size_t)p.m * p.m) * es;
+    if (p.block_kind == ROT_BLOCK_DIAGONAL) n_x = (size_t)p.m * es;
+    if (ranges_overlap(p.out, n_out, p.U, n_u) || (n_x && ranges_overlap(p.out, n_out, p.X, n_x)))
+        return fail(ROT_ERR_INVALID_ARG, "site group %d: out overlaps U or X", gi);
+    return ROT_OK;
+}
+
+// Bytes of the mixed operand U' of one group, and of one operator's T.
+size_t site_up_bytes(const rot_site_problem& p, rot_precision prec) {
+    return align_up((size_t)p.m * p.d * p.mp * elem_size(prec));
+}
+
+}  // namespace
+
+size_t rot_site_workspace_size(const rot_site_problem* groups, int32_t n_groups, rot_precision prec,
+                               int32_t ops_per_chunk) {
+    if (n_groups < 0 || (n_groups > 0 && !groups) || (prec != ROT_FP32 && prec != ROT_FP64)) return 0;
+    size_t need = 0;
+    for (int gi = 0; gi < n_groups; gi++) {
+        const rot_site_problem& p = groups[gi];
+        if (validate_site(p, prec, gi) != ROT_OK) return 0;
+        if (p.n_ops == 0) continue;
+        const size_t slot = site_up_bytes(p, prec);
+        const int ops = p.block_kind != ROT_BLOCK_DENSE ? 0
+                        : (ops_per_chunk > 0 ? std::min(ops_per_chunk, p.n_ops) : p.n_ops);
+        need = std::max(need, slot * (size_t)(1 + ops));
+    }
+    return need;
+}
+
+rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_groups, rot_precision prec, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+    if (n_groups < 0 || (n_groups > 0 && !groups))
+        return fail(ROT_ERR_INVALID_ARG, "null groups or negative n_groups");
+    if (prec != ROT_FP32 && prec != ROT_FP64)
+        return fail(prec == ROT_SPLIT_BF16 ? ROT_ERR_UNSUPPORTED : ROT_ERR_INVALID_ARG,
+                    "rot_batch_site supports ROT_FP64 and ROT_FP32");
+    for (int gi = 0; gi < n_groups; gi++) {
+        rot_status st = validate_site(groups[gi], prec, gi);
+        if (st != ROT_OK) return st;
+    }
+    const size_t min_ws = rot_site_workspace_size(groups, n_groups, prec, 1);
+    if (min_ws > 0) {
+        if (!workspace || workspace_bytes < min_ws)
+            return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, min_ws);
+        if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+            return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t es = elem_size(prec);
+    for (int gi = 0; gi < n_groups; gi++) {
+        const rot_site_problem& sp = groups[gi];
+        if (sp.n_ops == 0) continue;
+        SiteMatrix S{};
+        for (int k = 0; k < sp.d * sp.d; k++) S.v[k] = sp.site[k];
+        char* up = static_cast<char*>(workspace);
+        const void* x = sp.block_kind == ROT_BLOCK_DIAGONAL ? sp.X : nullptr;
+        hipError_t e = prof_timed("site_mix", s, [&] {
+            return site_mix(sp.U, sp.m, sp.d, sp.mp, S, x, up, prec == ROT_FP64, s);
+        });
+        if (e != hipSuccess) return hip_fail(e, "rot_batch_site mix");
+        // the same shapes as a dense group: X_b in place of O_b
+        rot_problem p{};
+        p.m = sp.m;
+        p.d = sp.d;
+        p.mp = sp.mp;
+        p.n_ops = sp.n_ops;
+        p.U = sp.U;
+        p.O = sp.X;
+        p.stride_o = sp.stride_x;
+        p.out = sp.out;
+        p.stride_out = sp.stride_out;
+        if (sp.block_kind != ROT_BLOCK_DENSE) {
+            // out = U'^T U: stage 2 with U' as A and U itself as B
+            GemmDesc g = stage2(p, 0, 1, sp.U, es);
+            g.A = up;
+            e = gemm(prec, g, s, "site_stage2");
+            if (e != hipSuccess) return hip_fail(e, "rot_batch_site launch");
+            continue;
+        }
+        const size_t slot = site_up_bytes(sp, prec);
+        char* T = up + slot;
+        const int chunk = (int)std::min<size_t>((size_t)sp.n_ops, workspace_bytes / slot - 1);
+        for (int b0 = 0; b0 < sp.n_ops; b0 += chunk) {
+            const int nb = std::min(chunk, sp.n_ops - b0);
+            e = gemm(prec, stage1(p, b0, nb, T, es), s, "site_stage1");
+            if (e == hipSuccess) {
+                GemmDesc g = stage2(p, b0, nb, T, es);
+                g.A = up;
+                e = gemm(prec, g, s, "site_stage2");
+            }
+            if (e != hipSuccess) return hip_fail(e, "rot_batch_site launch");
+        }
+    }
+    return ROT_OK;
+}
+
 rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void* const* dOut,
                         const int64_t* stride_dout, void* const* dO, void* const* dU, uint32_t flags,
                         rot_precision prec, void* workspace, size_t workspace_bytes, void* stream) {

@@ -75,6 +75,15 @@ hipError_t gemm_f64(const GemmDesc& g, hipStream_t stream);
 
 // Zero `bytes` bytes with a fill kernel (safe under stream capture).
 hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream);
+
+// A d x d site operator passed by value to kernels (d <= kMaxSite).
+constexpr int kMaxSite = 16;
+struct SiteMatrix {
+    double v[kMaxSite * kMaxSite];  // row-major S[s][t] at v[s*d + t]
+};
+// Up = (diag(x) (x) S^T) U for U with m*d rows of mp (x may be null: identity).
+hipError_t site_mix(const void* U, int m, int d, int mp, const SiteMatrix& S, const void* x, void* Up,
+                    bool is_double, hipStream_t stream);
 // dst (+)= sum of `parts` arrays of n elements at src + p*stride, summed in
 // ascending p (deterministic).
 hipError_t sum_parts(void* dst, const void* src, int64_t n, int parts, int64_t stride, bool accumulate,

@@ -186,3 +186,38 @@ def test_blocked_descriptor_validation(rotlib):
     p, keep = rotlib.blocked_problem(pk.site_qn, pk.old, pk.new, pk.shift, FakeT(FAKE), pk.U_off,
                                      FakeT(2 * FAKE), pk.O_off, pk.out_off, FakeT(3 * FAKE))
     assert L.rot_batch_blocked(ctypes.byref(p), rotlib.ROT_FP64, None, 0, None) == -2
+
+
+def test_site_problem_validation(rotlib):
+    """rot_batch_site rejects bad site groups on the host."""
+    import numpy as np
+    L = rotlib.lib()
+    S = np.eye(4)
+    Sp = S.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def status(m=8, d=4, mp=8, n=2, kind=rotlib.ROT_BLOCK_DENSE, U=FAKE, site=Sp, X=2 * FAKE, sx=None,
+               out=3 * FAKE, so=None, prec=rotlib.ROT_FP32, ws=4 * FAKE, wsb=1 << 30):
+        p = rotlib.RotSiteProblem(m, d, mp, n, kind, U, site, X, m * m if sx is None else sx, out,
+                                  mp * mp if so is None else so)
+        arr = (rotlib.RotSiteProblem * 1)(p)
+        return L.rot_batch_site(arr, 1, prec, ws, wsb, None)
+
+    assert status(kind=7) == -1
+    assert status(d=17, mp=8) == -2
+    assert status(mp=33) == -1                                    # mp > m*d
+    assert status(kind=rotlib.ROT_BLOCK_IDENTITY) == -1           # X must be NULL
+    assert status(kind=rotlib.ROT_BLOCK_IDENTITY, X=0) == -1      # n_ops must be 1
+    assert status(kind=rotlib.ROT_BLOCK_DIAGONAL, X=0, n=1) == -1
+    assert status(sx=63) == -1
+    assert status(so=10) == -1
+    assert status(out=2 * FAKE + 8) == -1                         # out overlaps X
+    assert status(site=None) == -1
+    assert status(prec=rotlib.ROT_SPLIT_BF16) == -2
+    assert status(wsb=16) == -3
+    assert status(ws=4 * FAKE + 8) == -1                          # misaligned workspace
+    p = rotlib.RotSiteProblem(8, 4, 8, 3, rotlib.ROT_BLOCK_DENSE, FAKE, Sp, 2 * FAKE, 64, 3 * FAKE, 64)
+    one = rotlib.rot_site_workspace_size([p], rotlib.ROT_FP32, 1)
+    assert rotlib.rot_site_workspace_size([p], rotlib.ROT_FP32, 0) == 2 * one  # U' + 3 slots vs U' + 1
+    assert one >= 2 * 8 * 4 * 8 * 4
+    q = rotlib.RotSiteProblem(8, 4, 8, 1, rotlib.ROT_BLOCK_IDENTITY, FAKE, Sp, None, 0, 3 * FAKE, 64)
+    assert rotlib.rot_site_workspace_size([q], rotlib.ROT_FP32, 1) == one // 2

@@ -9,7 +9,6 @@ explicit kron, and by physics: a block-growth chain that builds every
 annihilator and hopping product this way reproduces <c+_{i s} c_{j s}> of
 free fermions (Wick's theorem) and of the interacting chain (exact
 diagonalisation), which fails without the parity string."""
-import math
 
 import numpy as np
 import pytest
@@ -145,3 +144,15 @@ def test_without_parity_string_the_hopping_is_wrong(oracle_mod):
     worst = max(abs(phi @ hops[(i, j, s)] @ phi - G[s][i, j]) for s in (0, 1) for i in range(L)
                 for j in range(i + 1, L))
     assert worst > 1e-3
+
+
+def test_sampled_entries_match_full_site_rotation(oracle_mod):
+    rng = np.random.default_rng(36)
+    m, d, mp = 9, 4, 13
+    U = rng.standard_normal((m * d, mp))
+    X = rng.standard_normal((m, m))
+    S = rng.standard_normal((d, d))
+    full = oracle_mod.rotate_site(U, X, S)
+    a = rng.integers(0, mp, 30)
+    b = rng.integers(0, mp, 30)
+    np.testing.assert_allclose(oracle_mod.rotate_site_entries(U, X, S, a, b), full[a, b], rtol=1e-12, atol=1e-12)
