@@ -55,6 +55,10 @@ def _load():
         lib.orc_rotate_site.restype = ctypes.c_int
         lib.orc_rotate_site_entries.argtypes = [ctypes.c_int] * 3 + [dp, dp, dp, ctypes.c_int, i32p, i32p, dp]
         lib.orc_rotate_site_entries.restype = None
+        lib.orc_expect_block.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, ctypes.c_int, dp, dp]
+        lib.orc_expect_block.restype = None
+        lib.orc_expect_cross.argtypes = [ctypes.c_int] * 4 + [dp, ctypes.c_int, dp, ctypes.c_int, dp, dp]
+        lib.orc_expect_cross.restype = ctypes.c_int
         lib.orc_rotate_entries.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_int, i32p, i32p, dp]
         lib.orc_rotate_entries.restype = None
         lib.orc_adjoint.argtypes = [ctypes.c_int] * 4 + [dp, dp, dp, ctypes.c_int64, dp, dp, ctypes.c_int]
@@ -141,6 +145,38 @@ def rotate_site_entries(U, X, S, alpha, beta) -> np.ndarray:
                                     alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                     beta.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(vals))
     return vals
+
+
+def expect_block(psi, Z, d: int) -> np.ndarray:
+    """Sec. 3.2 one-point values <psi|Z_b (x) I|psi> of block operators Z
+    (n, m, m) in the superblock state psi ((m*d) x ncols), summed literally."""
+    psi = _f64(psi)
+    Z = _f64(Z)
+    if Z.ndim == 2:
+        Z = Z[None]
+    n, m, _ = Z.shape
+    if psi.shape[0] != m * d:
+        raise ValueError("psi must have m*d rows")
+    e = np.empty(n)
+    _load().orc_expect_block(m, d, psi.shape[1], _ptr(psi), n, _ptr(Z), _ptr(e))
+    return e
+
+
+def expect_cross(psi, Z, W, d: int, dR: int) -> np.ndarray:
+    """Sec. 3.2 products of operators of the two blocks:
+    c[b,k] = <psi| kron(Z_b, I_d) (x) kron(I_dR, W_k) |psi> for psi
+    ((m*d) x (dR*mR)), Z (nL, m, m), W (nR, mR, mR)."""
+    psi = _f64(psi)
+    Z = _f64(Z)
+    W = _f64(W)
+    nL, m, _ = Z.shape
+    nR, mR, _ = W.shape
+    if psi.shape != (m * d, dR * mR):
+        raise ValueError("psi must be (m*d) x (dR*mR)")
+    c = np.empty((nL, nR))
+    if _load().orc_expect_cross(m, d, mR, dR, _ptr(psi), nL, _ptr(Z), nR, _ptr(W), _ptr(c)) != 0:
+        raise MemoryError("oracle scratch allocation failed")
+    return c
 
 
 def rotate_entries(U, O, d: int, alpha, beta) -> np.ndarray:

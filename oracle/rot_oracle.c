@@ -223,6 +223,70 @@ void orc_rotate_site_entries(int m, int d, int mp, const double* U, const double
 }
 
 /*
+ * Measurements in the superblock state (Sec. 3.2: <Z_i> = <psi0|Z_i|psi0> and
+ * <Z_i Z_j>, with correlations between the two blocks taken as products of
+ * operators of each block).  The state of [B a a~ B~] is the matrix psi with
+ * rows i*d + s (block B state i, site a state s) and columns s'*mR + j (site
+ * a~ state s', block B~ state j); dR is the dimension of a~.
+ *   orc_expect_block: e_b = sum psi[i*d+s, y] Z_b[i,i'] psi[i'*d+s, y]
+ *                     (Z_b on B, identity elsewhere), summed literally.
+ *   orc_expect_cross: c[b,k] = <psi| kron(Z_b, I_d) psi kron(I_dR, W_k)^T>,
+ *                     with both Kronecker products materialised.
+ */
+void orc_expect_block(int m, int d, int64_t ncols, const double* psi, int n_ops, const double* Z, double* e) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int b = 0; b < n_ops; b++) {
+        const double* z = Z + (int64_t)b * m * m;
+        double acc = 0.0;
+        for (int i = 0; i < m; i++)
+            for (int s = 0; s < d; s++)
+                for (int ip = 0; ip < m; ip++) {
+                    const double zv = z[(int64_t)i * m + ip];
+                    const double* r1 = psi + ((int64_t)i * d + s) * ncols;
+                    const double* r2 = psi + ((int64_t)ip * d + s) * ncols;
+                    for (int64_t y = 0; y < ncols; y++) acc += r1[y] * zv * r2[y];
+                }
+        e[b] = acc;
+    }
+}
+
+int orc_expect_cross(int m, int d, int mR, int dR, const double* psi, int nL, const double* Z, int nR,
+                     const double* W, double* c) {
+    const int64_t ml = (int64_t)m * d, mr = (int64_t)dR * mR;
+    double* A = (double*)malloc(sizeof(double) * ml * ml);   /* kron(Z_b, I_d) */
+    double* B = (double*)malloc(sizeof(double) * mr * mr);   /* kron(I_dR, W_k) */
+    double* AP = (double*)malloc(sizeof(double) * ml * mr);  /* A psi */
+    double* APB = (double*)malloc(sizeof(double) * ml * mr); /* A psi B^T */
+    if (!A || !B || !AP || !APB) {
+        free(A); free(B); free(AP); free(APB);
+        return -1;
+    }
+    for (int b = 0; b < nL; b++) {
+        const double* z = Z + (int64_t)b * m * m;
+        memset(A, 0, sizeof(double) * ml * ml);
+        for (int i = 0; i < m; i++)
+            for (int j = 0; j < m; j++)
+                for (int s = 0; s < d; s++) A[((int64_t)i * d + s) * ml + (int64_t)j * d + s] = z[(int64_t)i * m + j];
+        orc_matmul(ml, ml, mr, A, psi, AP);
+        for (int k = 0; k < nR; k++) {
+            const double* w = W + (int64_t)k * mR * mR;
+            memset(B, 0, sizeof(double) * mr * mr);
+            for (int s = 0; s < dR; s++)
+                for (int i = 0; i < mR; i++)
+                    for (int j = 0; j < mR; j++) B[((int64_t)s * mR + i) * mr + (int64_t)s * mR + j] = w[(int64_t)i * mR + j];
+            orc_matmul_nt(ml, mr, mr, AP, B, APB);
+            double acc = 0.0;
+            for (int64_t e = 0; e < ml * mr; e++) acc += psi[e] * APB[e];
+            c[(int64_t)b * nR + k] = acc;
+        }
+    }
+    free(A); free(B); free(AP); free(APB);
+    return 0;
+}
+
+/*
  * Selected entries of one rotated operator, each computed on its own straight
  * from the definition:  out[alpha,beta] = sum_{i,j,s} U[i*d+s,alpha] O[i,j] U[j*d+s,beta].
  * Cost m*m*d per entry; used to check full-size results at sampled positions.
