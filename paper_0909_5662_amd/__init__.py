@@ -32,7 +32,7 @@ __all__ = [
     "RotateFn", "PairLossFn", "precision_code", "profile_enable", "profile_read",
     "blocked_problem", "rotate_blocked", "Plan", "ROT_PLAN_NO_GRAPH", "ROT_PLAN_NO_TUNE", "ROT_PLAN_RETUNE",
     "RotSiteProblem", "ROT_BLOCK_IDENTITY", "ROT_BLOCK_DIAGONAL", "ROT_BLOCK_DENSE", "rot_batch_site",
-    "rot_site_workspace_size", "rotate_site",
+    "rot_site_workspace_size", "rotate_site", "expect_block", "expect_cross",
 ]
 
 ROT_FP64, ROT_FP32, ROT_SPLIT_BF16 = 0, 1, 2
@@ -101,6 +101,12 @@ def lib() -> ctypes.CDLL:
         L.rot_batch_site.argtypes = [ctypes.POINTER(RotSiteProblem), i32, ctypes.c_int, vp, sz, vp]
         L.rot_site_workspace_size.argtypes = [ctypes.POINTER(RotSiteProblem), i32, ctypes.c_int, i32]
         L.rot_site_workspace_size.restype = sz
+        L.rot_expect_block_workspace_size.argtypes = [i32, i32]
+        L.rot_expect_block_workspace_size.restype = sz
+        L.rot_expect_block.argtypes = [vp, i32, i32, i64, vp, i32, i64, ctypes.c_int, vp, vp, sz, vp]
+        L.rot_expect_cross_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.rot_expect_cross_workspace_size.restype = sz
+        L.rot_expect_cross.argtypes = [vp, i32, i32, i32, i32, vp, i32, i64, vp, i32, i64, vp, vp, sz, vp]
         L.rot_batch_blocked.argtypes = [ctypes.POINTER(RotBlockedProblem), ctypes.c_int, vp, sz, vp]
         L.rot_blocked_workspace_size.argtypes = [ctypes.POINTER(RotBlockedProblem)]
         L.rot_blocked_workspace_size.restype = sz
@@ -325,6 +331,43 @@ def rotate_site(U: torch.Tensor, X, S, precision="fp32", workspace: torch.Tensor
         workspace = _workspace(rot_site_workspace_size([p], prec), U.device)
     rot_batch_site([p], prec, workspace.data_ptr(), workspace.numel(), _stream(stream))
     return out if kind == ROT_BLOCK_DENSE else out[0]
+
+
+def expect_block(psi: torch.Tensor, Z: torch.Tensor, d: int, stream=None) -> torch.Tensor:
+    """<psi| Z_b (x) I |psi> (FP64) for block operators Z (n, m, m), float32 or
+    float64, in the superblock state psi ((m*d) x ncols, float64)."""
+    if psi.dtype != torch.float64 or not psi.is_contiguous() or not psi.is_cuda:
+        raise TypeError("psi must be a contiguous float64 CUDA tensor")
+    if Z.dtype not in (torch.float32, torch.float64) or not Z.is_contiguous() or Z.dim() != 3:
+        raise TypeError("Z must be a contiguous (n, m, m) float32/float64 tensor")
+    n, m, _ = Z.shape
+    if psi.shape[0] != m * d:
+        raise ValueError("psi must have m*d rows")
+    e = torch.empty(n, dtype=torch.float64, device=psi.device)
+    ws = _workspace(lib().rot_expect_block_workspace_size(m, n), psi.device)
+    prec = ROT_FP64 if Z.dtype == torch.float64 else ROT_FP32
+    _check(lib().rot_expect_block(psi.data_ptr(), m, d, psi.shape[1], Z.data_ptr(), n, m * m, prec, e.data_ptr(),
+                                  ws.data_ptr(), ws.numel(), _stream(stream)))
+    return e
+
+
+def expect_cross(psi: torch.Tensor, Z: torch.Tensor, W: torch.Tensor, d: int, dR: int,
+                 ops_per_chunk: int = 0, stream=None) -> torch.Tensor:
+    """<psi| (Z_b (x) I_a) (x) (I_a~ (x) W_k) |psi> (FP64, shape (nL, nR)) for
+    Z (nL, m, m) on the left block and W (nR, mR, mR) on the right block, all
+    float64; psi is (m*d) x (dR*mR)."""
+    for t in (psi, Z, W):
+        if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise TypeError("psi, Z and W must be contiguous float64 CUDA tensors")
+    nL, m, _ = Z.shape
+    nR, mR, _ = W.shape
+    if psi.shape != (m * d, dR * mR):
+        raise ValueError("psi must be (m*d) x (dR*mR)")
+    c = torch.empty((nL, nR), dtype=torch.float64, device=psi.device)
+    ws = _workspace(lib().rot_expect_cross_workspace_size(m, d, mR, dR, nL, ops_per_chunk), psi.device)
+    _check(lib().rot_expect_cross(psi.data_ptr(), m, d, mR, dR, Z.data_ptr(), nL, m * m, W.data_ptr(), nR, mR * mR,
+                                  c.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return c
 
 
 def rotate_backward(U: torch.Tensor, O: torch.Tensor, d: int, dOut: torch.Tensor, precision="fp32",

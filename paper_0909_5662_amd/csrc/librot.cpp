@@ -457,6 +457,114 @@ rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_groups, rot_
     return ROT_OK;
 }
 
+size_t rot_expect_block_workspace_size(int32_t m, int32_t n_ops) {
+    if (m <= 0 || n_ops < 0) return 0;
+    return align_up((size_t)m * m * sizeof(double)) + align_up(expect_dot_scratch(n_ops));
+}
+
+rot_status rot_expect_block(const double* psi, int32_t m, int32_t d, int64_t ncols, const void* Z, int32_t n_ops,
+                            int64_t stride_z, rot_precision prec, double* e, void* workspace, size_t workspace_bytes,
+                            void* stream) {
+    if (m <= 0 || d <= 0 || ncols <= 0 || n_ops < 0)
+        return fail(ROT_ERR_INVALID_ARG, "m, d, ncols must be positive and n_ops >= 0");
+    if (prec != ROT_FP64 && prec != ROT_FP32) return fail(ROT_ERR_INVALID_ARG, "Z must be FP64 or FP32");
+    if ((int64_t)d * ncols > INT32_MAX || (int64_t)m * m > INT32_MAX)
+        return fail(ROT_ERR_INVALID_ARG, "extents too large");
+    if (n_ops == 0) return ROT_OK;
+    if (!psi || !Z || !e) return fail(ROT_ERR_INVALID_ARG, "null psi, Z or e");
+    if (stride_z < (int64_t)m * m) return fail(ROT_ERR_INVALID_ARG, "stride_z must be >= m*m");
+    const size_t need = rot_expect_block_workspace_size(m, n_ops);
+    if (!workspace || workspace_bytes < need)
+        return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < %zu", workspace_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* rho = static_cast<double*>(workspace);
+    double* partial = reinterpret_cast<double*>(static_cast<char*>(workspace) + align_up((size_t)m * m * 8));
+    // rho_B[i][i'] = sum over (s, column) of psi[i*d+s][.] psi[i'*d+s][.]: psi viewed as m x (d*ncols)
+    GemmDesc g{};
+    g.M = m; g.N = m; g.K = (int)(d * ncols); g.batch = 1; g.kbatch = 1;
+    g.A = psi; g.lda = d * ncols; g.a_kcontig = true;
+    g.B = psi; g.ldb = d * ncols; g.b_kcontig = true;
+    g.C = rho; g.ldc = m;
+    hipError_t err = gemm(ROT_FP64, g, s, "expect_rho");
+    if (err == hipSuccess)
+        err = prof_timed("expect_dots", s, [&] {
+            return expect_dots(Z, prec == ROT_FP64, stride_z, (int64_t)m * m, n_ops, rho, partial, e, s);
+        });
+    return err == hipSuccess ? ROT_OK : hip_fail(err, "rot_expect_block");
+}
+
+size_t rot_expect_cross_workspace_size(int32_t m, int32_t d, int32_t mR, int32_t dR, int32_t n_left,
+                                       int32_t ops_per_chunk) {
+    if (m <= 0 || d <= 0 || mR <= 0 || dR <= 0 || n_left < 0) return 0;
+    const size_t md = (size_t)m * d, mp = (size_t)dR * mR;
+    const int ops = ops_per_chunk > 0 ? std::min(ops_per_chunk, std::max(n_left, 1)) : std::max(n_left, 1);
+    const size_t per_op = align_up(md * mp * 8) + align_up(mp * mp * 8);
+    return align_up((size_t)n_left * mR * mR * 8) + (size_t)ops * per_op;
+}
+
+rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR, int32_t dR, const double* Z,
+                            int32_t n_left, int64_t stride_z, const double* W, int32_t n_right, int64_t stride_w,
+                            double* c, void* workspace, size_t workspace_bytes, void* stream) {
+    if (m <= 0 || d <= 0 || mR <= 0 || dR <= 0 || n_left < 0 || n_right < 0)
+        return fail(ROT_ERR_INVALID_ARG, "m, d, mR, dR must be positive, operator counts >= 0");
+    const int64_t md = (int64_t)m * d, mp = (int64_t)dR * mR;
+    if (md > INT32_MAX || (int64_t)m * mp > INT32_MAX || (int64_t)mR * mR > INT32_MAX)
+        return fail(ROT_ERR_INVALID_ARG, "extents too large");
+    if (n_left == 0 || n_right == 0) return ROT_OK;
+    if (!psi || !Z || !W || !c) return fail(ROT_ERR_INVALID_ARG, "null psi, Z, W or c");
+    if (stride_z < (int64_t)m * m || stride_w < (int64_t)mR * mR)
+        return fail(ROT_ERR_INVALID_ARG, "stride_z must be >= m*m and stride_w >= mR*mR");
+    const size_t need = rot_expect_cross_workspace_size(m, d, mR, dR, n_left, 1);
+    if (!workspace || workspace_bytes < need)
+        return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(workspace);
+    double* q = reinterpret_cast<double*>(base);
+    const size_t q_bytes = align_up((size_t)n_left * mR * mR * 8);
+    const size_t t_bytes_op = align_up((size_t)md * mp * 8), qq_bytes_op = align_up((size_t)mp * mp * 8);
+    const int chunk = (int)std::min<size_t>((size_t)n_left, (workspace_bytes - q_bytes) / (t_bytes_op + qq_bytes_op));
+    char* T = base + q_bytes;
+    char* Q = T + (size_t)chunk * t_bytes_op;
+    hipError_t err = hipSuccess;
+    for (int b0 = 0; b0 < n_left && err == hipSuccess; b0 += chunk) {
+        const int nb = std::min(chunk, n_left - b0);
+        // Q_b = psi^T (Z_b (x) I_d) psi: the rotation with psi in place of U (m' = dR*mR)
+        rot_problem p{};
+        p.m = m; p.d = d; p.mp = (int32_t)mp; p.n_ops = nb;
+        p.U = psi; p.O = Z + (size_t)b0 * stride_z; p.stride_o = stride_z;
+        p.out = Q; p.stride_out = mp * mp;
+        GemmDesc g1 = stage1(p, 0, nb, T, 8);
+        g1.c_bs = (int64_t)(t_bytes_op / 8);
+        err = gemm(ROT_FP64, g1, s, "expect_stage1");
+        if (err == hipSuccess) {
+            GemmDesc g2 = stage2(p, 0, nb, T, 8);
+            g2.b_bs = (int64_t)(t_bytes_op / 8);
+            g2.c_bs = (int64_t)(qq_bytes_op / 8);
+            err = gemm(ROT_FP64, g2, s, "expect_stage2");
+        }
+        if (err == hipSuccess) {
+            err = prof_timed("expect_trace", s, [&] {
+                return partial_trace(reinterpret_cast<const double*>(Q), (int64_t)(qq_bytes_op / 8), mR, dR, nb,
+                                     q + (size_t)b0 * mR * mR, s);
+            });
+        }
+    }
+    if (err == hipSuccess) {
+        // c[b][k] = sum_e q_b[e] W_k[e]
+        GemmDesc g{};
+        g.M = n_left; g.N = n_right; g.K = mR * mR; g.batch = 1; g.kbatch = 1;
+        g.A = q; g.lda = (int64_t)mR * mR; g.a_kcontig = true;
+        g.B = W; g.ldb = stride_w; g.b_kcontig = true;
+        g.C = c; g.ldc = n_right;
+        err = gemm(ROT_FP64, g, s, "expect_pairs");
+    }
+    return err == hipSuccess ? ROT_OK : hip_fail(err, "rot_expect_cross");
+}
+
 rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void* const* dOut,
                         const int64_t* stride_dout, void* const* dO, void* const* dU, uint32_t flags,
                         rot_precision prec, void* workspace, size_t workspace_bytes, void* stream) {

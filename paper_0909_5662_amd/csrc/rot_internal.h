@@ -76,6 +76,15 @@ hipError_t gemm_f64(const GemmDesc& g, hipStream_t stream);
 // Zero `bytes` bytes with a fill kernel (safe under stream capture).
 hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream);
 
+// Superblock measurements (measure.hip): e_b = sum_e Z_b[e] rho[e] in FP64
+// (n elements per operator, fixed summation order; partial needs
+// expect_dot_scratch(n_ops) bytes), and q_b = partial trace of Q_b over the
+// right site (Q_b of side dR*mR at Q + b*q_stride, q_b of side mR).
+size_t expect_dot_scratch(int n_ops);
+hipError_t expect_dots(const void* Z, bool z_double, int64_t stride_z, int64_t n, int n_ops, const double* rho,
+                       double* partial, double* e, hipStream_t s);
+hipError_t partial_trace(const double* Q, int64_t q_stride, int mR, int dR, int n_ops, double* q, hipStream_t s);
+
 // A d x d site operator passed by value to kernels (d <= kMaxSite).
 constexpr int kMaxSite = 16;
 struct SiteMatrix {

@@ -221,3 +221,32 @@ def test_site_problem_validation(rotlib):
     assert one >= 2 * 8 * 4 * 8 * 4
     q = rotlib.RotSiteProblem(8, 4, 8, 1, rotlib.ROT_BLOCK_IDENTITY, FAKE, Sp, None, 0, 3 * FAKE, 64)
     assert rotlib.rot_site_workspace_size([q], rotlib.ROT_FP32, 1) == one // 2
+
+
+def test_measurement_argument_errors(rotlib):
+    L = rotlib.lib()
+    ws = 4 * FAKE
+    assert L.rot_expect_block(FAKE, 0, 4, 8, 2 * FAKE, 1, 0, rotlib.ROT_FP64, 3 * FAKE, ws, 1 << 30, None) == -1
+    assert L.rot_expect_block(FAKE, 8, 4, 8, 2 * FAKE, 1, 63, rotlib.ROT_FP64, 3 * FAKE, ws, 1 << 30, None) == -1
+    assert L.rot_expect_block(FAKE, 8, 4, 8, 2 * FAKE, 1, 64, rotlib.ROT_SPLIT_BF16, 3 * FAKE, ws, 1 << 30,
+                              None) == -1
+    assert L.rot_expect_block(FAKE, 8, 4, 8, 2 * FAKE, 1, 64, rotlib.ROT_FP64, 3 * FAKE, ws, 8, None) == -3
+    assert L.rot_expect_block(None, 8, 4, 8, 2 * FAKE, 1, 64, rotlib.ROT_FP64, 3 * FAKE, ws, 1 << 30, None) == -1
+    assert L.rot_expect_block(None, 8, 4, 8, None, 0, 64, rotlib.ROT_FP64, None, None, 0, None) == 0
+    assert L.rot_expect_block_workspace_size(8, 3) >= 8 * 8 * 8
+    args = dict(m=8, d=4, mR=6, dR=2, nL=3, sz=64, nR=2, sw=36)
+
+    def cross(**kw):
+        a = dict(args)
+        a.update(kw)
+        return L.rot_expect_cross(FAKE, a["m"], a["d"], a["mR"], a["dR"], 2 * FAKE, a["nL"], a["sz"], 3 * FAKE,
+                                  a["nR"], a["sw"], 5 * FAKE, ws, a.get("wsb", 1 << 30), None)
+
+    assert cross(mR=0) == -1
+    assert cross(sz=10) == -1
+    assert cross(sw=35) == -1
+    assert cross(wsb=64) == -3
+    assert cross(nR=0) == 0
+    one = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 1)
+    allops = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 0)
+    assert allops > one > 0
