@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 GPU rotation (speedup denominator)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "blocked_1024_n400", "uneven_1000", "differentiated_m1024_n64"],
+                    choices=[WORKLOAD, "blocked_1024_n400", "uneven_1000", "differentiated_m1024_n64",
+                             "site_m1024_n64", "measure_m1024"],
                     help="default: the headline dense workload; the others time the quantum-number "
                          "blocked batch or the uneven sweep plan")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -305,6 +306,111 @@ def bench_differentiated(args, rot, torch, workloads):
     return rec
 
 
+def timed_loop(torch, fn, steps, warmup):
+    """ms per call of fn over `steps` calls (events on the current stream)."""
+    for _ in range(max(1, warmup)):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+C_UP = ((0.0, 1.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 1.0), (0.0, 0.0, 0.0, 0.0))
+C_DN = ((0.0, 0.0, 1.0, 0.0), (0.0, 0.0, 0.0, -1.0), (0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0))
+N_SITE = ((0.0, 0.0, 0.0, 0.0), (0.0, 1.0, 0.0, 0.0), (0.0, 0.0, 1.0, 0.0), (0.0, 0.0, 0.0, 2.0))
+SZ_SITE = ((0.0, 0.0, 0.0, 0.0), (0.0, 0.5, 0.0, 0.0), (0.0, 0.0, -0.5, 0.0), (0.0, 0.0, 0.0, 0.0))
+
+
+def bench_site(args, rot, torch, workloads):
+    """Blocking with the added site (m = m' = 1024, d = 4, FP32): the 64
+    block-site products X_b (x) c_up of one step, and the new site's own
+    operators I_B (x) n_a, I_B (x) S^z_a, P_B (x) c_up, P_B (x) c_dn."""
+    import numpy as np
+    case = workloads.named_dense(WORKLOAD)
+    U = torch.from_numpy(case.U).float().cuda()
+    X = torch.from_numpy(case.O).float().cuda()
+    parity = torch.from_numpy(np.where(np.arange(case.m) % 2 == 0, 1.0, -1.0)).float().cuda()
+    n = X.shape[0]
+    import ctypes
+    S = np.ascontiguousarray(C_UP, dtype=np.float64)
+    p = rot.RotSiteProblem(case.m, 4, case.mp, n, rot.ROT_BLOCK_DENSE, U.data_ptr(),
+                           S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), X.data_ptr(), case.m * case.m,
+                           1 << 40, case.mp * case.mp)
+    ws = torch.empty(rot.rot_site_workspace_size([p], rot.ROT_FP32), dtype=torch.uint8, device=U.device)
+    rot.profile_enable(True)
+    ms_dense = timed_loop(torch, lambda: rot.rotate_site(U, X, C_UP, "fp32", workspace=ws), args.steps, args.warmup)
+    kernels = rot.profile_read()
+    rot.profile_enable(False)
+
+    def new_site():
+        rot.rotate_site(U, None, N_SITE, "fp32", workspace=ws)
+        rot.rotate_site(U, None, SZ_SITE, "fp32", workspace=ws)
+        rot.rotate_site(U, parity, C_UP, "fp32", workspace=ws)
+        rot.rotate_site(U, parity, C_DN, "fp32", workspace=ws)
+
+    ms_new = timed_loop(torch, new_site, args.steps, args.warmup)
+    F = flops_per_op(case.m, 4, case.mp)
+    tflops = n * F / (ms_dense / 1e3) / 1e12
+    stage = {k: v for k, v in kernels.items() if k.startswith("site_stage")}
+    dom, (cnt, tot) = max(stage.items(), key=lambda kv: kv[1][1])
+    achieved = n * F / 2 / (tot / cnt / 1e3) / 1e12
+    rec = base_record(args, n / (ms_dense / 1e3), "operator rotations/s (block-site products)", ms_dense,
+                      {"workload": "site_m1024_n64", "m": case.m, "d": 4, "mp": case.mp, "n_ops": n,
+                       "site_operator": "c_up", "precision": "fp32"})
+    rec.update({"tflops": round(tflops, 2), "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2),
+                "new_site_operators_ms": round(ms_new, 4), "new_site_operators": 4,
+                "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
+                "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": 157.3, "unit": "TFLOP/s",
+                             "frac": round(achieved / 157.3, 4), "traffic": None, "kernel": dom,
+                             "avg_ms": round(tot / cnt, 4)}})
+    return rec
+
+
+def bench_measure(args, rot, torch, workloads):
+    """Superblock measurements in FP64: block B of m = 1024 states with site
+    a (d = 4), site a~ and block B~ (dR = 4, mR = 1024), a seeded unit state
+    psi (4096 x 4096); one-point values of the 64 stored operators of the
+    headline batch (FP32), and the 8 x 8 products of operators of the two
+    blocks (FP64)."""
+    import numpy as np
+    case = workloads.named_dense(WORKLOAD)
+    m, d, mR, dR = case.m, 4, 1024, 4
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5662 * 100 + 7)
+    psi = torch.randn((m * d, dR * mR), generator=g, dtype=torch.float64, device="cuda")
+    psi /= psi.norm()
+    Z32 = torch.from_numpy(case.O).float().cuda()
+    ZL = Z32[:8].double().contiguous()
+    WR = Z32[8:16].double().contiguous()
+    n = Z32.shape[0]
+    ms_one = timed_loop(torch, lambda: rot.expect_block(psi, Z32, d), args.steps, args.warmup)
+    rot.profile_enable(True)
+    ms_cross = timed_loop(torch, lambda: rot.expect_cross(psi, ZL, WR, d, dR), max(2, args.steps // 4), 1)
+    kernels = rot.profile_read()
+    rot.profile_enable(False)
+    mp = dR * mR
+    f_one = 2.0 * m * m * d * dR * mR + 2.0 * n * m * m
+    f_cross = 8 * (2.0 * m * m * d * mp + 2.0 * m * d * mp * mp) + 2.0 * 8 * 8 * mR * mR
+    t_one = f_one / (ms_one / 1e3) / 1e12
+    t_cross = f_cross / (ms_cross / 1e3) / 1e12
+    rec = base_record(args, n / (ms_one / 1e3), "stored operators measured/s (one-point, FP64)", ms_one,
+                      {"workload": "measure_m1024", "m": m, "d": d, "mR": mR, "dR": dR, "n_stored": n,
+                       "cross_pairs": "8 x 8", "precision": "fp64 state and reductions"}, dtype="f64")
+    rec.update({"one_point_tflops_fp64": round(t_one, 2), "cross_block_ms": round(ms_cross, 3),
+                "cross_block_tflops_fp64": round(t_cross, 2),
+                "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
+                "roofline": {"bound": "mfma", "achieved": round(t_cross, 2), "peak": 78.6, "unit": "TFLOP/s",
+                             "frac": round(t_cross / 78.6, 4), "traffic": None,
+                             "kernel": "cross-block products (FP64 rotation by psi, pair product)"}})
+    return rec
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -385,7 +491,8 @@ def main():
 
     if args.workload != WORKLOAD:
         fn = {"blocked_1024_n400": bench_blocked, "uneven_1000": bench_uneven,
-              "differentiated_m1024_n64": bench_differentiated}[args.workload]
+              "differentiated_m1024_n64": bench_differentiated, "site_m1024_n64": bench_site,
+              "measure_m1024": bench_measure}[args.workload]
         print(json.dumps(fn(args, rot, torch, workloads)), flush=True)
         return
 

@@ -190,23 +190,27 @@ ROT_API rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_grou
  *   psi has m*d rows of ncols columns.  Computed as <Z_b, rho_B> with rho_B
  *   the reduced density matrix of B (one FP64 product of psi with itself),
  *   then FP64 dot products summed in a fixed order.  workspace:
- *   rot_expect_block_workspace_size(m, n_ops) bytes, 256-byte aligned.
+ *   rot_expect_block_workspace_size(m, d, ncols, n_ops) bytes, 256-byte
+ *   aligned.
  * rot_expect_cross: c[b*n_right + k] = <psi| (Z_b (x) I_a) (x) (I_a~ (x) W_k) |psi>
  *   for Z_b on B (m x m, FP64, stride_z >= m*m) and W_k on B~ (mR x mR, FP64,
  *   stride_w >= mR*mR); psi is (m*d) x (dR*mR); c (n_left*n_right doubles)
  *   on the device.  Computed as <q_b, W_k> with q_b the partial trace over
  *   a~ of psi^T (Z_b (x) I_d) psi (the rotation of Z_b with psi in place of U,
  *   FP64), then one FP64 product over all pairs.  workspace:
- *   rot_expect_cross_workspace_size(m, d, mR, dR, n_left, ops_per_chunk)
- *   bytes (ops_per_chunk left operators per chunk, <= 0: all; at least 1).
+ *   rot_expect_cross_workspace_size(m, d, mR, dR, n_left, n_right,
+ *   ops_per_chunk) bytes (ops_per_chunk left operators per chunk, <= 0: all;
+ *   at least 1).  Products whose outputs have few tiles are split over K
+ *   into partial sums added in a fixed order, so results do not depend on
+ *   the chunking.
  * Both return ROT_OK, ROT_ERR_INVALID_ARG, ROT_ERR_WORKSPACE or ROT_ERR_HIP.
  */
-ROT_API size_t rot_expect_block_workspace_size(int32_t m, int32_t n_ops);
+ROT_API size_t rot_expect_block_workspace_size(int32_t m, int32_t d, int64_t ncols, int32_t n_ops);
 ROT_API rot_status rot_expect_block(const double* psi, int32_t m, int32_t d, int64_t ncols, const void* Z,
                             int32_t n_ops, int64_t stride_z, rot_precision prec, double* e, void* workspace,
                             size_t workspace_bytes, void* stream);
 ROT_API size_t rot_expect_cross_workspace_size(int32_t m, int32_t d, int32_t mR, int32_t dR, int32_t n_left,
-                                       int32_t ops_per_chunk);
+                                       int32_t n_right, int32_t ops_per_chunk);
 ROT_API rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR, int32_t dR,
                             const double* Z, int32_t n_left, int64_t stride_z, const double* W,
                             int32_t n_right, int64_t stride_w, double* c, void* workspace,

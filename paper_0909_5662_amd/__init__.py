@@ -101,10 +101,10 @@ def lib() -> ctypes.CDLL:
         L.rot_batch_site.argtypes = [ctypes.POINTER(RotSiteProblem), i32, ctypes.c_int, vp, sz, vp]
         L.rot_site_workspace_size.argtypes = [ctypes.POINTER(RotSiteProblem), i32, ctypes.c_int, i32]
         L.rot_site_workspace_size.restype = sz
-        L.rot_expect_block_workspace_size.argtypes = [i32, i32]
+        L.rot_expect_block_workspace_size.argtypes = [i32, i32, i64, i32]
         L.rot_expect_block_workspace_size.restype = sz
         L.rot_expect_block.argtypes = [vp, i32, i32, i64, vp, i32, i64, ctypes.c_int, vp, vp, sz, vp]
-        L.rot_expect_cross_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.rot_expect_cross_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, i32]
         L.rot_expect_cross_workspace_size.restype = sz
         L.rot_expect_cross.argtypes = [vp, i32, i32, i32, i32, vp, i32, i64, vp, i32, i64, vp, vp, sz, vp]
         L.rot_batch_blocked.argtypes = [ctypes.POINTER(RotBlockedProblem), ctypes.c_int, vp, sz, vp]
@@ -344,7 +344,7 @@ def expect_block(psi: torch.Tensor, Z: torch.Tensor, d: int, stream=None) -> tor
     if psi.shape[0] != m * d:
         raise ValueError("psi must have m*d rows")
     e = torch.empty(n, dtype=torch.float64, device=psi.device)
-    ws = _workspace(lib().rot_expect_block_workspace_size(m, n), psi.device)
+    ws = _workspace(lib().rot_expect_block_workspace_size(m, d, psi.shape[1], n), psi.device)
     prec = ROT_FP64 if Z.dtype == torch.float64 else ROT_FP32
     _check(lib().rot_expect_block(psi.data_ptr(), m, d, psi.shape[1], Z.data_ptr(), n, m * m, prec, e.data_ptr(),
                                   ws.data_ptr(), ws.numel(), _stream(stream)))
@@ -364,7 +364,7 @@ def expect_cross(psi: torch.Tensor, Z: torch.Tensor, W: torch.Tensor, d: int, dR
     if psi.shape != (m * d, dR * mR):
         raise ValueError("psi must be (m*d) x (dR*mR)")
     c = torch.empty((nL, nR), dtype=torch.float64, device=psi.device)
-    ws = _workspace(lib().rot_expect_cross_workspace_size(m, d, mR, dR, nL, ops_per_chunk), psi.device)
+    ws = _workspace(lib().rot_expect_cross_workspace_size(m, d, mR, dR, nL, nR, ops_per_chunk), psi.device)
     _check(lib().rot_expect_cross(psi.data_ptr(), m, d, mR, dR, Z.data_ptr(), nL, m * m, W.data_ptr(), nR, mR * mR,
                                   c.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
     return c

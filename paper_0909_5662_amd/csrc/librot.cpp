@@ -191,6 +191,66 @@ hipError_t gemm(rot_precision prec, const GemmDesc& g, hipStream_t s, const char
     return timed(name.c_str(), s, [&] { return f64 ? gemm_f64(g, s) : gemm_f32(g, s); });
 }
 
+// Split-K for a single GEMM whose output has too few 128 x 128 tiles to fill
+// the chip: K is cut into `parts` equal ranges (the remainder joins part 0),
+// each part's product goes to its own partial sum (parts x M x N), and the
+// partials are added in fixed order.  Returns the number of parts (1: no
+// split) for an output of M x N over K.
+int split_k_parts(int M, int N, int64_t K) {
+    const int64_t tiles = (((int64_t)M + kGemmTile - 1) / kGemmTile) * (((int64_t)N + kGemmTile - 1) / kGemmTile);
+    int64_t parts = (1024 + tiles - 1) / tiles;
+    parts = std::min<int64_t>(parts, 256);
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, K / 256));
+    return (int)std::max<int64_t>(1, parts);
+}
+
+size_t split_k_scratch(int M, int N, int64_t K, size_t es) {
+    const int parts = split_k_parts(M, N, K);
+    return parts > 1 ? align_up((size_t)parts * M * N * es) : 0;
+}
+
+// C = A B (batch = kbatch = 1, no accumulation) through `scratch` of at least
+// split_k_scratch(M, N, K, es) bytes; plain GEMM when no split pays.
+hipError_t gemm_split_k(rot_precision prec, const GemmDesc& g, void* scratch, hipStream_t s, const char* what) {
+    const int parts = split_k_parts(g.M, g.N, g.K);
+    if (parts <= 1) return gemm(prec, g, s, what);
+    const size_t es = elem_size(prec);
+    const int kp = g.K / parts, rem = g.K % parts;
+    GemmDesc p = g;
+    p.K = kp;
+    p.batch = parts;
+    p.a_bs = g.a_kcontig ? kp : (int64_t)kp * g.lda;  // next K range of A
+    p.b_bs = g.b_kcontig ? kp : (int64_t)kp * g.ldb;
+    p.C = scratch;
+    p.ldc = g.N;
+    p.c_bs = (int64_t)g.M * g.N;
+    p.accumulate = false;
+    hipError_t e = gemm(prec, p, s, what);
+    if (e == hipSuccess && rem > 0) {
+        GemmDesc t = p;
+        t.batch = 1;
+        t.K = rem;
+        t.A = static_cast<const char*>(g.A) + (size_t)parts * p.a_bs * es;
+        t.B = static_cast<const char*>(g.B) + (size_t)parts * p.b_bs * es;
+        t.accumulate = true;
+        e = gemm(prec, t, s, what);
+    }
+    if (e != hipSuccess) return e;
+    if (g.ldc == g.N)
+        return timed("split_k_sum", s, [&] {
+            return sum_parts(g.C, scratch, (int64_t)g.M * g.N, parts, (int64_t)g.M * g.N, false, prec == ROT_FP64, s);
+        });
+    // strided C: add the parts row by row
+    return timed("split_k_sum", s, [&] {
+        hipError_t err = hipSuccess;
+        for (int r = 0; r < g.M && err == hipSuccess; r++)
+            err = sum_parts(static_cast<char*>(g.C) + (size_t)r * g.ldc * es,
+                            static_cast<char*>(scratch) + (size_t)r * g.N * es, g.N, parts, (int64_t)g.M * g.N,
+                            false, prec == ROT_FP64, s);
+        return err;
+    });
+}
+
 }  // namespace
 
 rot_status set_error(rot_status s, const char* msg) {
@@ -383,8 +443,11 @@ size_t rot_site_workspace_size(const rot_site_problem* groups, int32_t n_groups,
         if (validate_site(p, prec, gi) != ROT_OK) return 0;
         if (p.n_ops == 0) continue;
         const size_t slot = site_up_bytes(p, prec);
-        const int ops = p.block_kind != ROT_BLOCK_DENSE ? 0
-                        : (ops_per_chunk > 0 ? std::min(ops_per_chunk, p.n_ops) : p.n_ops);
+        if (p.block_kind != ROT_BLOCK_DENSE) {
+            need = std::max(need, slot + split_k_scratch(p.mp, p.mp, (int64_t)p.m * p.d, elem_size(prec)));
+            continue;
+        }
+        const int ops = ops_per_chunk > 0 ? std::min(ops_per_chunk, p.n_ops) : p.n_ops;
         need = std::max(need, slot * (size_t)(1 + ops));
     }
     return need;
@@ -433,10 +496,12 @@ rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_groups, rot_
         p.out = sp.out;
         p.stride_out = sp.stride_out;
         if (sp.block_kind != ROT_BLOCK_DENSE) {
-            // out = U'^T U: stage 2 with U' as A and U itself as B
+            // out = U'^T U: stage 2 with U' as A and U itself as B (split over K
+            // when its mp x mp output has few tiles)
             GemmDesc g = stage2(p, 0, 1, sp.U, es);
             g.A = up;
-            e = gemm(prec, g, s, "site_stage2");
+            g.ldc = sp.mp;
+            e = gemm_split_k(prec, g, up + site_up_bytes(sp, prec), s, "site_stage2");
             if (e != hipSuccess) return hip_fail(e, "rot_batch_site launch");
             continue;
         }
@@ -457,9 +522,10 @@ rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_groups, rot_
     return ROT_OK;
 }
 
-size_t rot_expect_block_workspace_size(int32_t m, int32_t n_ops) {
-    if (m <= 0 || n_ops < 0) return 0;
-    return align_up((size_t)m * m * sizeof(double)) + align_up(expect_dot_scratch(n_ops));
+size_t rot_expect_block_workspace_size(int32_t m, int32_t d, int64_t ncols, int32_t n_ops) {
+    if (m <= 0 || d <= 0 || ncols <= 0 || n_ops < 0) return 0;
+    return align_up((size_t)m * m * sizeof(double)) + align_up(expect_dot_scratch(n_ops)) +
+           split_k_scratch(m, m, (int64_t)d * ncols, sizeof(double));
 }
 
 rot_status rot_expect_block(const double* psi, int32_t m, int32_t d, int64_t ncols, const void* Z, int32_t n_ops,
@@ -473,7 +539,7 @@ rot_status rot_expect_block(const double* psi, int32_t m, int32_t d, int64_t nco
     if (n_ops == 0) return ROT_OK;
     if (!psi || !Z || !e) return fail(ROT_ERR_INVALID_ARG, "null psi, Z or e");
     if (stride_z < (int64_t)m * m) return fail(ROT_ERR_INVALID_ARG, "stride_z must be >= m*m");
-    const size_t need = rot_expect_block_workspace_size(m, n_ops);
+    const size_t need = rot_expect_block_workspace_size(m, d, ncols, n_ops);
     if (!workspace || workspace_bytes < need)
         return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < %zu", workspace_bytes, need);
     if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
@@ -481,13 +547,14 @@ rot_status rot_expect_block(const double* psi, int32_t m, int32_t d, int64_t nco
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* rho = static_cast<double*>(workspace);
     double* partial = reinterpret_cast<double*>(static_cast<char*>(workspace) + align_up((size_t)m * m * 8));
+    char* split = static_cast<char*>(workspace) + align_up((size_t)m * m * 8) + align_up(expect_dot_scratch(n_ops));
     // rho_B[i][i'] = sum over (s, column) of psi[i*d+s][.] psi[i'*d+s][.]: psi viewed as m x (d*ncols)
     GemmDesc g{};
     g.M = m; g.N = m; g.K = (int)(d * ncols); g.batch = 1; g.kbatch = 1;
     g.A = psi; g.lda = d * ncols; g.a_kcontig = true;
     g.B = psi; g.ldb = d * ncols; g.b_kcontig = true;
     g.C = rho; g.ldc = m;
-    hipError_t err = gemm(ROT_FP64, g, s, "expect_rho");
+    hipError_t err = gemm_split_k(ROT_FP64, g, split, s, "expect_rho");
     if (err == hipSuccess)
         err = prof_timed("expect_dots", s, [&] {
             return expect_dots(Z, prec == ROT_FP64, stride_z, (int64_t)m * m, n_ops, rho, partial, e, s);
@@ -496,12 +563,13 @@ rot_status rot_expect_block(const double* psi, int32_t m, int32_t d, int64_t nco
 }
 
 size_t rot_expect_cross_workspace_size(int32_t m, int32_t d, int32_t mR, int32_t dR, int32_t n_left,
-                                       int32_t ops_per_chunk) {
-    if (m <= 0 || d <= 0 || mR <= 0 || dR <= 0 || n_left < 0) return 0;
+                                       int32_t n_right, int32_t ops_per_chunk) {
+    if (m <= 0 || d <= 0 || mR <= 0 || dR <= 0 || n_left < 0 || n_right < 0) return 0;
     const size_t md = (size_t)m * d, mp = (size_t)dR * mR;
     const int ops = ops_per_chunk > 0 ? std::min(ops_per_chunk, std::max(n_left, 1)) : std::max(n_left, 1);
     const size_t per_op = align_up(md * mp * 8) + align_up(mp * mp * 8);
-    return align_up((size_t)n_left * mR * mR * 8) + (size_t)ops * per_op;
+    const size_t split = split_k_scratch(std::max(n_left, 1), std::max(n_right, 1), (int64_t)mR * mR, 8);
+    return align_up((size_t)n_left * mR * mR * 8) + split + (size_t)ops * per_op;
 }
 
 rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR, int32_t dR, const double* Z,
@@ -516,7 +584,7 @@ rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR,
     if (!psi || !Z || !W || !c) return fail(ROT_ERR_INVALID_ARG, "null psi, Z, W or c");
     if (stride_z < (int64_t)m * m || stride_w < (int64_t)mR * mR)
         return fail(ROT_ERR_INVALID_ARG, "stride_z must be >= m*m and stride_w >= mR*mR");
-    const size_t need = rot_expect_cross_workspace_size(m, d, mR, dR, n_left, 1);
+    const size_t need = rot_expect_cross_workspace_size(m, d, mR, dR, n_left, n_right, 1);
     if (!workspace || workspace_bytes < need)
         return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
     if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
@@ -525,9 +593,12 @@ rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR,
     char* base = static_cast<char*>(workspace);
     double* q = reinterpret_cast<double*>(base);
     const size_t q_bytes = align_up((size_t)n_left * mR * mR * 8);
+    char* split = base + q_bytes;
+    const size_t split_bytes = split_k_scratch(n_left, n_right, (int64_t)mR * mR, 8);
     const size_t t_bytes_op = align_up((size_t)md * mp * 8), qq_bytes_op = align_up((size_t)mp * mp * 8);
-    const int chunk = (int)std::min<size_t>((size_t)n_left, (workspace_bytes - q_bytes) / (t_bytes_op + qq_bytes_op));
-    char* T = base + q_bytes;
+    const int chunk = (int)std::min<size_t>((size_t)n_left,
+                                            (workspace_bytes - q_bytes - split_bytes) / (t_bytes_op + qq_bytes_op));
+    char* T = base + q_bytes + split_bytes;
     char* Q = T + (size_t)chunk * t_bytes_op;
     hipError_t err = hipSuccess;
     for (int b0 = 0; b0 < n_left && err == hipSuccess; b0 += chunk) {
@@ -560,7 +631,7 @@ rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR,
         g.A = q; g.lda = (int64_t)mR * mR; g.a_kcontig = true;
         g.B = W; g.ldb = stride_w; g.b_kcontig = true;
         g.C = c; g.ldc = n_right;
-        err = gemm(ROT_FP64, g, s, "expect_pairs");
+        err = gemm_split_k(ROT_FP64, g, split, s, "expect_pairs");
     }
     return err == hipSuccess ? ROT_OK : hip_fail(err, "rot_expect_cross");
 }

@@ -233,7 +233,7 @@ def test_measurement_argument_errors(rotlib):
     assert L.rot_expect_block(FAKE, 8, 4, 8, 2 * FAKE, 1, 64, rotlib.ROT_FP64, 3 * FAKE, ws, 8, None) == -3
     assert L.rot_expect_block(None, 8, 4, 8, 2 * FAKE, 1, 64, rotlib.ROT_FP64, 3 * FAKE, ws, 1 << 30, None) == -1
     assert L.rot_expect_block(None, 8, 4, 8, None, 0, 64, rotlib.ROT_FP64, None, None, 0, None) == 0
-    assert L.rot_expect_block_workspace_size(8, 3) >= 8 * 8 * 8
+    assert L.rot_expect_block_workspace_size(8, 4, 8, 3) >= 8 * 8 * 8
     args = dict(m=8, d=4, mR=6, dR=2, nL=3, sz=64, nR=2, sw=36)
 
     def cross(**kw):
@@ -247,6 +247,6 @@ def test_measurement_argument_errors(rotlib):
     assert cross(sw=35) == -1
     assert cross(wsb=64) == -3
     assert cross(nR=0) == 0
-    one = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 1)
-    allops = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 0)
+    one = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 2, 1)
+    allops = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 2, 0)
     assert allops > one > 0

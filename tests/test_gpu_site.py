@@ -55,7 +55,7 @@ def test_dense_block_site_products(rot, oracle_mod, precision, shape):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("kind", ["identity", "parity"])
-@pytest.mark.parametrize("shape", [(37, 4, 90), (100, 4, 400), (257, 3, 300)])
+@pytest.mark.parametrize("shape", [(37, 4, 90), (100, 4, 400), (257, 3, 300), (250, 4, 200)])
 def test_new_site_operators(rot, oracle_mod, precision, kind, shape):
     m, d, mp = shape
     U, _, S = inputs(m, d, mp, 1, 850 + m, precision)
