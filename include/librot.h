@@ -98,6 +98,21 @@ typedef struct {
 ROT_API rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision prec,
                      void* workspace, size_t workspace_bytes, void* stream);
 
+#define ROT_ASSUME_SYMMETRIC_O 1u
+
+/*
+ * rot_batch with flags (same arguments otherwise; rot_batch is flags = 0).
+ * ROT_ASSUME_SYMMETRIC_O: every O_b is symmetric, so every out_b is
+ * symmetric (U^T (O (x) I) U with O = O^T); stage 2 computes only the output
+ * tiles on and above the diagonal and stores each off-diagonal tile also
+ * transposed: 2 m^2 d m' + about m d m'^2 (1 + 128/m') flops per operator
+ * instead of 2 m^2 d m' + 2 m d m'^2 (the survey's symmetric-output
+ * specialisation).  out_b is then exactly symmetric; for non-symmetric O_b
+ * the result is wrong (only the upper triangle of U^T (O (x) I) U is kept).
+ */
+ROT_API rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precision prec, uint32_t flags,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
 /*
  * Workspace bytes needed by rot_batch / rot_backward for these groups when
  * up to `ops_per_chunk` operators are processed at once (<= 0: all
@@ -130,7 +145,6 @@ ROT_API size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, r
  * of five.
  * Summation order is fixed: results are deterministic.
  */
-#define ROT_ASSUME_SYMMETRIC_O 1u
 ROT_API rot_status rot_backward(const rot_problem* groups, int32_t n_groups,
                         const void* const* dOut, const int64_t* stride_dout,
                         void* const* dO, void* const* dU, uint32_t flags, rot_precision prec,

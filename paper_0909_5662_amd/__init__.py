@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(library_path)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.rot_batch.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, vp, sz, vp]
+        L.rot_batch_ex.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, ctypes.c_uint32, vp, sz, vp]
         L.rot_workspace_size.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, i32, i32]
         L.rot_workspace_size.restype = sz
         L.rot_backward.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
@@ -196,9 +197,12 @@ def rot_workspace_size(groups, prec: int, ops_per_chunk: int = 0, for_backward: 
     return lib().rot_workspace_size(arr, len(groups), prec, ops_per_chunk, int(for_backward))
 
 
-def rot_batch(groups, prec: int, workspace: int, workspace_bytes: int, stream: int) -> None:
+def rot_batch(groups, prec: int, workspace: int, workspace_bytes: int, stream: int, flags: int = 0) -> None:
     arr = (RotProblem * len(groups))(*groups)
-    _check(lib().rot_batch(arr, len(groups), prec, workspace, workspace_bytes, stream))
+    if flags:
+        _check(lib().rot_batch_ex(arr, len(groups), prec, flags, workspace, workspace_bytes, stream))
+    else:
+        _check(lib().rot_batch(arr, len(groups), prec, workspace, workspace_bytes, stream))
 
 
 def rot_backward(groups, dOut, stride_dout, dO, dU, flags: int, prec: int, workspace: int,
@@ -269,8 +273,10 @@ def _check_inputs(U: torch.Tensor, O: torch.Tensor, d: int, prec: int) -> None:
 
 
 def rotate(U: torch.Tensor, O: torch.Tensor, d: int, precision="fp32", out: torch.Tensor | None = None,
-           workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """out_b = U^T (O_b (x) I_d) U for O of shape (n, m, m), U (m*d, mp)."""
+           workspace: torch.Tensor | None = None, stream=None, symmetric_O: bool = False) -> torch.Tensor:
+    """out_b = U^T (O_b (x) I_d) U for O of shape (n, m, m), U (m*d, mp).
+    symmetric_O: every O_b is symmetric; only the upper output triangle is
+    computed (and mirrored)."""
     prec = precision_code(precision)
     _check_inputs(U, O, d, prec)
     n, m, _ = O.shape
@@ -280,7 +286,8 @@ def rotate(U: torch.Tensor, O: torch.Tensor, d: int, precision="fp32", out: torc
     p = _problem(U, O, out, d)
     if workspace is None:
         workspace = _workspace(rot_workspace_size([p], prec), U.device)
-    rot_batch([p], prec, workspace.data_ptr(), workspace.numel(), _stream(stream))
+    rot_batch([p], prec, workspace.data_ptr(), workspace.numel(), _stream(stream),
+              ROT_ASSUME_SYMMETRIC_O if symmetric_O else 0)
     return out
 
 

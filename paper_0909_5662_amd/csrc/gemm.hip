@@ -115,8 +115,21 @@ struct TileCoord {
     int g, m0, n0;
 };
 
-__device__ inline TileCoord tile_coord(int lin, int tiles_m, int tiles_n) {
+__device__ inline TileCoord tile_coord(int lin, int tiles_m, int tiles_n, bool upper) {
     TileCoord t;
+    if (upper) {
+        // tiles (i, j) with i <= j of a tiles_m x tiles_m grid, column by
+        // column (neighbours share the B panel): r -> j(j+1)/2 + i
+        const int per_batch = tiles_m * (tiles_m + 1) / 2;
+        t.g = lin / per_batch;
+        const int r = lin % per_batch;
+        int j = (int)((sqrtf(8.0f * (float)r + 1.0f) - 1.0f) * 0.5f);
+        while (j * (j + 1) / 2 > r) j--;
+        while ((j + 1) * (j + 2) / 2 <= r) j++;
+        t.m0 = (r - j * (j + 1) / 2) * kTile;
+        t.n0 = j * kTile;
+        return t;
+    }
     const int per_batch = tiles_m * tiles_n;
     t.g = lin / per_batch;
     const int r = lin % per_batch;
@@ -135,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
     __shared__ __attribute__((aligned(16))) float As[2][SA::ELEMS];
     __shared__ __attribute__((aligned(16))) float Bs[2][SB::ELEMS];
 
-    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n);
+    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, g.upper);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -215,6 +228,9 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
     }
 
     float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs;
+    // symmetric output: a diagonal tile keeps row <= col and mirrors it, so
+    // the result is exactly symmetric
+    const bool diag = !ACC && g.upper && tc.m0 == tc.n0;
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
@@ -224,12 +240,38 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int row = tc.m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-                if (row < g.M) {
+                if (row < g.M && (!diag || row <= col)) {
                     float* p = Cb + (int64_t)row * g.ldc + col;
                     *p = ACC ? *p + acc[i][k][v] : acc[i][k][v];
+                    if (diag && row < col) Cb[(int64_t)col * g.ldc + row] = acc[i][k][v];
                 }
             }
         }
+    if (!ACC && g.upper && tc.m0 != tc.n0) {
+        // the transposed tile: a lane's rows 8q + 4h .. +3 become four
+        // consecutive entries of row `col`
+        const bool vec4 = (g.ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(Cb) & 15) == 0;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int col = tc.n0 + wn * 64 + k * 32 + c;
+                if (col >= g.N) continue;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int row0 = tc.m0 + wm * 64 + i * 32 + 8 * q + 4 * h;
+                    float* p = Cb + (int64_t)col * g.ldc + row0;
+                    if (vec4 && row0 + 4 <= g.M) {
+                        *reinterpret_cast<f32x4*>(p) =
+                            f32x4{acc[i][k][4 * q], acc[i][k][4 * q + 1], acc[i][k][4 * q + 2], acc[i][k][4 * q + 3]};
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; e++)
+                            if (row0 + e < g.M) p[e] = acc[i][k][4 * q + e];
+                    }
+                }
+            }
+    }
 }
 
 // ---------------------------------------------------------------- FP64 ----
@@ -242,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
     __shared__ __attribute__((aligned(16))) double As[2][SA::ELEMS];
     __shared__ __attribute__((aligned(16))) double Bs[2][SB::ELEMS];
 
-    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n);
+    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, g.upper);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -320,6 +362,10 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
     }
 
     double* Cb = static_cast<double*>(g.C) + (int64_t)tc.g * g.c_bs;
+    // symmetric output: off-diagonal tiles are also stored transposed; a
+    // diagonal tile keeps row <= col and mirrors it (exactly symmetric)
+    const bool mirror = !ACC && g.upper && tc.m0 != tc.n0;
+    const bool diag = !ACC && g.upper && tc.m0 == tc.n0;
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -329,9 +375,10 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
 #pragma unroll
             for (int v = 0; v < 4; v++) {
                 const int row = tc.m0 + wm * 64 + i * 16 + 4 * v + h;
-                if (row < g.M) {
+                if (row < g.M && (!diag || row <= col)) {
                     double* p = Cb + (int64_t)row * g.ldc + col;
                     *p = ACC ? *p + acc[i][k][v] : acc[i][k][v];
+                    if (mirror || (diag && row < col)) Cb[(int64_t)col * g.ldc + row] = acc[i][k][v];
                 }
             }
         }
@@ -376,7 +423,8 @@ template <typename T>
 hipError_t gemm_any(const GemmDesc& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     const int tm = (g.M + kTile - 1) / kTile, tn = (g.N + kTile - 1) / kTile;
-    const int64_t tiles = (int64_t)tm * tn * g.batch;
+    if (g.upper && (g.M != g.N || g.accumulate)) return hipErrorInvalidValue;
+    const int64_t tiles = (g.upper ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn) * g.batch;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles);
     const bool vec = vector_ok<T>(g);

@@ -74,9 +74,12 @@ struct Bf16Desc {
     const uint16_t* b_hi;
     const uint16_t* b_lo;
     int64_t b_bs;
-    // plain epilogue: C[row*ldc + col] (FP32)
+    // plain epilogue: C[row*ldc + col] (FP32); with `upper` (M == N, symmetric
+    // output) only tiles on or above the diagonal are computed and each
+    // off-diagonal one is also stored transposed
     float* c;
     int64_t ldc, c_bs;
+    int upper;
     // split-transposed epilogue: C(n = beta*d + s, i) -> T (t_rows rows,
     // slab layout), element (beta, i*d + s)
     uint16_t* t_hi;
@@ -108,7 +111,7 @@ __device__ inline void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST
 // lane (h, c) of a 32 x 32 block is C(8*(v/4) + 4*h + v%4, c).
 template <int BI, int BJ, bool EPI_T, bool D4>
 __device__ inline void store_tile(const Bf16Desc& g, const f32x16 (&acc)[BI][BJ], int bidx, int row0w, int col0, int h,
-                                  int c) {
+                                  int c, bool mirror, bool diag) {
     if (EPI_T) {
         // C(n = beta*d + s, i) -> T(beta, i*d + s).  The four rows 4q..4q+3 a
         // lane holds in accumulator elements 4q..4q+3 are, for d = 4, the four
@@ -160,9 +163,38 @@ __device__ inline void store_tile(const Bf16Desc& g, const f32x16 (&acc)[BI][BJ]
 #pragma unroll
                 for (int v = 0; v < 16; v++) {
                     const int row = row0w + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-                    if (row < g.M) cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
+                    // a diagonal tile of a symmetric output keeps row <= col and mirrors it
+                    if (row < g.M && (!diag || row <= col)) {
+                        cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
+                        if (diag && row < col) cb[(int64_t)col * g.ldc + row] = acc[i][k][v];
+                    }
                 }
             }
+        if (mirror) {
+            // the transposed tile: a lane's rows 8q + 4h .. +3 are four
+            // consecutive entries of row `col`
+            const bool vec4 = (g.ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(cb) & 15) == 0;
+#pragma unroll
+            for (int i = 0; i < BI; i++)
+#pragma unroll
+                for (int k = 0; k < BJ; k++) {
+                    const int col = col0 + k * 32 + c;
+                    if (col >= g.N) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const int row0 = row0w + i * 32 + 8 * q + 4 * h;
+                        float* p = cb + (int64_t)col * g.ldc + row0;
+                        if (vec4 && row0 + 4 <= g.M) {
+                            *reinterpret_cast<f32x4*>(p) = f32x4{acc[i][k][4 * q], acc[i][k][4 * q + 1],
+                                                                 acc[i][k][4 * q + 2], acc[i][k][4 * q + 3]};
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; e++)
+                                if (row0 + e < g.M) p[e] = acc[i][k][4 * q + e];
+                        }
+                    }
+                }
+        }
     }
 }
 
@@ -195,13 +227,26 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc
     __shared__ __attribute__((aligned(1024))) uint16_t lds[S * STAGE];
 
     const int lin = xcd_linear_id();
-    const int per_batch = tiles_m * tiles_n;
-    const int bidx = lin / per_batch;
-    const int rr = lin % per_batch;
-    // neighbouring workgroups share the B panel (M tiles fastest) or the A
-    // panel (N tiles fastest)
-    const int m0 = (n_fastest ? rr / tiles_n : rr % tiles_m) * T;
-    const int n0 = (n_fastest ? rr % tiles_n : rr / tiles_m) * T;
+    int bidx, m0, n0;
+    if (!EPI_T && g.upper) {
+        // tiles (i, j), i <= j, column by column: r -> j(j+1)/2 + i
+        const int per_batch = tiles_m * (tiles_m + 1) / 2;
+        bidx = lin / per_batch;
+        const int r = lin % per_batch;
+        int j = (int)((sqrtf(8.0f * (float)r + 1.0f) - 1.0f) * 0.5f);
+        while (j * (j + 1) / 2 > r) j--;
+        while ((j + 1) * (j + 2) / 2 <= r) j++;
+        m0 = (r - j * (j + 1) / 2) * T;
+        n0 = j * T;
+    } else {
+        const int per_batch = tiles_m * tiles_n;
+        bidx = lin / per_batch;
+        const int rr = lin % per_batch;
+        // neighbouring workgroups share the B panel (M tiles fastest) or the
+        // A panel (N tiles fastest)
+        m0 = (n_fastest ? rr / tiles_n : rr % tiles_m) * T;
+        n0 = (n_fastest ? rr % tiles_n : rr / tiles_m) * T;
+    }
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -314,7 +359,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc
         step(t, f0, f1);
         if (t + 1 < nk) step(t + 1, f1, f0);
     }
-    store_tile<BI, BJ, EPI_T, D4>(g, acc, bidx, m0 + wm * 32 * BI, n0 + wn * 32 * BJ, h, c);
+    store_tile<BI, BJ, EPI_T, D4>(g, acc, bidx, m0 + wm * 32 * BI, n0 + wn * 32 * BJ, h, c,
+                                  !EPI_T && g.upper && m0 != n0, !EPI_T && g.upper && m0 == n0);
 }
 
 // U (rows = m*d, cols = mp), row r = j*d + s, both split into hi/lo (slab layout):
@@ -420,9 +466,10 @@ hipError_t zero_last_slab(uint16_t* a, uint16_t* l, int64_t rows, int64_t K, int
 
 template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T>
 hipError_t launch_tile(const Bf16Desc& g, hipStream_t s) {
-    constexpr int T = 32 * WGM * WGN;
+    constexpr int T = 32 * WGM * BI;
     const int tm = (g.M + T - 1) / T, tn = (g.N + T - 1) / T;
-    const int64_t tiles = (int64_t)tm * tn * g.batch;
+    if (g.upper && (EPI_T || g.M != g.N)) return hipErrorInvalidValue;
+    const int64_t tiles = (g.upper ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn) * g.batch;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     const char* order = getenv("ROT_BF16_ORDER");
     const int nf = order ? (order[0] == 'n') : 0;
@@ -488,7 +535,7 @@ size_t bf16_group_workspace(int m, int d, int mp, int ops) {
     return L.shared + (size_t)ops * 2 * (L.t_op + L.o_op);
 }
 
-hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream_t stream) {
+hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, hipStream_t stream) {
     const Bf16Layout L = layout(p.m, p.d, p.mp);
     char* base = static_cast<char*>(ws);
     uint16_t* u1h = reinterpret_cast<uint16_t*>(base);
@@ -557,6 +604,7 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream
     b.c = static_cast<float*>(p.out) + (int64_t)b0 * p.stride_out;
     b.ldc = p.mp;
     b.c_bs = p.stride_out;
+    b.upper = symmetric ? 1 : 0;
     return prof_timed("stage2_bf16x3", stream, [&] { return launch_bf16<false>(b, stream); });
 }
 

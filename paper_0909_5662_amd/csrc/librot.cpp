@@ -18,7 +18,7 @@ namespace rot {
 hipError_t split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream);
 size_t bf16_group_workspace(int m, int d, int mp, int ops);
 bool bf16_shape_supported(int m, int d, int mp);
-hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, hipStream_t stream);
+hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, hipStream_t stream);
 size_t blocked_workspace_bytes(const rot_blocked_problem* p);
 rot_status blocked_validate(const rot_blocked_problem* p, std::string* why);
 hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -343,9 +343,16 @@ size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_preci
 
 rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision prec, void* workspace,
                      size_t workspace_bytes, void* stream) {
+    return rot_batch_ex(groups, n_groups, prec, 0u, workspace, workspace_bytes, stream);
+}
+
+rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precision prec, uint32_t flags,
+                        void* workspace, size_t workspace_bytes, void* stream) {
     if (n_groups < 0 || (n_groups > 0 && !groups))
         return fail(ROT_ERR_INVALID_ARG, "groups is null or n_groups negative");
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+    if (flags & ~ROT_ASSUME_SYMMETRIC_O) return fail(ROT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const bool sym = flags & ROT_ASSUME_SYMMETRIC_O;
     for (int gi = 0; gi < n_groups; gi++) {
         rot_status s = validate_group(groups[gi], gi);
         if (s != ROT_OK) return s;
@@ -377,7 +384,7 @@ rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision 
                 chunk++;
             for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
                 const int nb = std::min(chunk, p.n_ops - b0);
-                hipError_t e = rotate_bf16(p, b0, nb, workspace, s);
+                hipError_t e = rotate_bf16(p, b0, nb, workspace, sym, s);
                 if (e != hipSuccess) return hip_fail(e, "rot_batch split-bf16");
             }
             continue;
@@ -387,7 +394,11 @@ rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision 
         for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
             const int nb = std::min(chunk, p.n_ops - b0);
             hipError_t e = gemm(prec, stage1(p, b0, nb, workspace, es), s, "stage1");
-            if (e == hipSuccess) e = gemm(prec, stage2(p, b0, nb, workspace, es), s, "stage2");
+            if (e == hipSuccess) {
+                GemmDesc g2 = stage2(p, b0, nb, workspace, es);
+                g2.upper = sym;
+                e = gemm(prec, g2, s, sym ? "stage2sym" : "stage2");
+            }
             if (e != hipSuccess) return hip_fail(e, "rot_batch launch");
         }
     }

@@ -27,6 +27,9 @@ struct GemmDesc {
     void* C;
     int64_t ldc, c_bs;
     bool a_kcontig, b_kcontig, accumulate;
+    // symmetric output (M == N, no accumulation): only tiles on or above the
+    // diagonal are computed, each off-diagonal one also stored transposed
+    bool upper;
 };
 
 // ---- grouped GEMM over a work-list (grouped.hip) ----

@@ -250,3 +250,10 @@ def test_measurement_argument_errors(rotlib):
     one = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 2, 1)
     allops = L.rot_expect_cross_workspace_size(8, 4, 6, 2, 3, 2, 0)
     assert allops > one > 0
+
+
+def test_batch_ex_flags(rotlib):
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib))
+    assert L.rot_batch_ex(arr, 1, rotlib.ROT_FP32, 2, 4 * FAKE, 1 << 30, None) == -1
+    assert L.rot_batch_ex(arr, 1, rotlib.ROT_FP32, 1, 4 * FAKE, 16, None) == -3
