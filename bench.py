@@ -40,29 +40,37 @@ def parse():
                              "site_m1024_n64", "measure_m1024"],
                     help="default: the headline dense workload; the others time the quantum-number "
                          "blocked batch or the uneven sweep plan")
+    ap.add_argument("--symmetric", action="store_true",
+                    help="time the dense workload with the symmetric-output stage 2 (upper triangle)")
+    ap.add_argument("--no-symmetric", action="store_true",
+                    help="skip the symmetric-output figures of the dense workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
-def flops_per_op(m, d, mp):
-    return 2.0 * m * m * d * mp + 2.0 * m * d * mp * mp
+def flops_per_op(m, d, mp, symmetric=False):
+    """Algorithmic flops of one rotation: stage 1 (2 m^2 d m') plus stage 2,
+    2 m d m'^2 in general or m d m'(m'+1) when only the upper triangle of the
+    symmetric output is formed."""
+    s2 = m * d * mp * (mp + 1) if symmetric else 2.0 * m * d * mp * mp
+    return 2.0 * m * m * d * mp + s2
 
 
-def time_steps(rot, U, O, out, ws, d, precision, steps, warmup, profile):
+def time_steps(rot, U, O, out, ws, d, precision, steps, warmup, profile, symmetric=False):
     """Total ms of `steps` rotations (events on the launch stream around the
     whole loop), the per-step times (one event per step boundary) and the
     kernel timings of librot's profiler."""
     import torch
     for _ in range(warmup):
-        rot.rotate(U, O, d, precision, out=out, workspace=ws)
+        rot.rotate(U, O, d, precision, out=out, workspace=ws, symmetric_O=symmetric)
     torch.cuda.synchronize()
     if profile:
         rot.profile_enable(True)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record()
     for i in range(steps):
-        rot.rotate(U, O, d, precision, out=out, workspace=ws)
+        rot.rotate(U, O, d, precision, out=out, workspace=ws, symmetric_O=symmetric)
         ev[i + 1].record()
     torch.cuda.synchronize()
     kernels = rot.profile_read() if profile else {}
@@ -92,22 +100,25 @@ def recorded_traffic(kernel_kind):
     return None
 
 
-def measure(rot, U, O, out, d, precision, steps, warmup):
-    """Time `steps` rotations of the batch; returns the figures for one precision."""
+def measure(rot, U, O, out, d, precision, steps, warmup, symmetric=False):
+    """Time `steps` rotations of the batch; returns the figures for one precision.
+    symmetric: the operators are symmetric and stage 2 forms only the upper
+    output triangle, counted with its own (smaller) algorithmic flops."""
     import torch
     n, m, _ = O.shape
     mp = U.shape[1]
     p = rot._problem(U, O, out, d)
     prec = rot.precision_code(precision)
     ws = torch.empty(rot.rot_workspace_size([p], prec), dtype=torch.uint8, device=U.device)
-    ms, kernels, per_step = time_steps(rot, U, O, out, ws, d, precision, steps, warmup, True)
+    ms, kernels, per_step = time_steps(rot, U, O, out, ws, d, precision, steps, warmup, True, symmetric)
     del ws
     ops_per_s = n * steps / (ms / 1e3)
-    F = flops_per_op(m, d, mp)
+    F = flops_per_op(m, d, mp, symmetric)
     tflops = F * ops_per_s / 1e12
     peak = PEAK_TFLOPS[precision]
     exec_factor = 3.0 if precision == "split_bf16" else 1.0
-    per_launch_flops = {"stage1": n * 2.0 * m * m * d * mp, "stage2": n * 2.0 * m * d * mp * mp}
+    per_launch_flops = {"stage1": n * 2.0 * m * m * d * mp, "stage2": n * 2.0 * m * d * mp * mp,
+                        "stage2sym": n * 1.0 * m * d * mp * (mp + 1)}
     stage_kernels = {k: v for k, v in kernels.items() if k.split("_")[0] in per_launch_flops}
     dom_name, (dom_count, dom_ms) = max(stage_kernels.items(), key=lambda kv: kv[1][1])
     dom_avg_ms = dom_ms / dom_count
@@ -502,7 +513,7 @@ def main():
     U = torch.from_numpy(case.U).to(dt).to(dev)
     O = torch.from_numpy(case.O).to(dt).to(dev)
     out = torch.empty((n, mp, mp), dtype=dt, device=dev)
-    main_run = measure(rot, U, O, out, d, args.precision, args.steps, args.warmup)
+    main_run = measure(rot, U, O, out, d, args.precision, args.steps, args.warmup, args.symmetric)
 
     result = {
         "metric": METRIC,
@@ -519,6 +530,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "m": m, "d": d, "mp": mp, "n_ops": n,
                    "precision": args.precision, "operators": "symmetric Gaussian / sqrt(m)",
+                   "output": "upper triangle mirrored" if args.symmetric else "full",
                    "U": "QR of seeded 4096x1024 Gaussian"},
         "ms_per_step_median": round(main_run["ms_per_step_median"], 4),
         "ms_per_step_min": round(main_run["ms_per_step_min"], 4),
@@ -529,7 +541,7 @@ def main():
     }
 
     if args.precision == "fp32" and not args.no_split_bf16:
-        b = measure(rot, U, O, out, d, "split_bf16", args.steps, args.warmup)
+        b = measure(rot, U, O, out, d, "split_bf16", args.steps, args.warmup, args.symmetric)
         result["split_bf16"] = {"value": round(b["ops_per_s"], 2), "unit": "operator rotations/s",
                                 "ms_per_step": round(b["ms_per_step"], 4),
                                 "ms_per_step_median": round(b["ms_per_step_median"], 4),
@@ -538,6 +550,19 @@ def main():
                                 "pct_bf16_mfma_peak": round(b["pct_mfma_peak"], 2),
                                 "speedup_vs_fp32": round(b["ops_per_s"] / main_run["ops_per_s"], 3),
                                 "kernels_ms_avg": b["kernels_ms_avg"], "roofline": b["roofline"]}
+
+    if args.precision == "fp32" and not (args.no_split_bf16 or args.symmetric or args.no_symmetric):
+        # the headline operators are symmetric, so the symmetric-output path applies to them
+        sym = {}
+        for prec in ("fp32", "split_bf16"):
+            r = measure(rot, U, O, out, d, prec, args.steps, args.warmup, symmetric=True)
+            sym[prec] = {"value": round(r["ops_per_s"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                         "ms_per_step_median": round(r["ms_per_step_median"], 4),
+                         "tflops_algorithmic": round(r["tflops"], 2),
+                         "kernels_ms_avg": r["kernels_ms_avg"]}
+        sym["unit"] = "operator rotations/s"
+        sym["flops_per_op"] = flops_per_op(m, d, mp, True)
+        result["symmetric_output"] = sym
 
     if not args.no_fp64_reference and args.precision != "fp64":
         U64, O64 = U.double(), O.double()

@@ -605,7 +605,8 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symm
     b.ldc = p.mp;
     b.c_bs = p.stride_out;
     b.upper = symmetric ? 1 : 0;
-    return prof_timed("stage2_bf16x3", stream, [&] { return launch_bf16<false>(b, stream); });
+    return prof_timed(symmetric ? "stage2sym_bf16x3" : "stage2_bf16x3", stream,
+                      [&] { return launch_bf16<false>(b, stream); });
 }
 
 }  // namespace rot
