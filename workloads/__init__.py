@@ -320,3 +320,59 @@ def uneven_case_gpu(sizes, d: int = 4, ops_per_rot: int = 8, cfg: int = 4, devic
         out.append((U, O.contiguous()))
         del G
     return out
+
+
+# ---------------------------------------------------------------------------
+# Superblock state split by quantum numbers, for the density-matrix step.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DensityCase:
+    """psi of [B a | a~ B~] with definite total (N_up, N_down), as one block
+    per system sector Q: psi[k] is n_Q x r_Q (system states of [B a] with
+    numbers Q, environment states of [a~ B~] with the complementary numbers).
+    Only sectors with r_Q > 0 are listed unless keep_empty."""
+    qn: list[tuple[int, int]]
+    psi: list[np.ndarray]
+    m_keep: int
+
+    @property
+    def dims(self) -> list[tuple[int, int]]:
+        return [p.shape for p in self.psi]
+
+
+def enlarged_sector_sizes(sizes, site_qn=HUBBARD_SITE_QN) -> dict[tuple[int, int], int]:
+    """Dimensions of the sectors of [B a] from those of B and the site."""
+    out: dict[tuple[int, int], int] = {}
+    for q, n in sizes:
+        for s in site_qn:
+            key = (q[0] + s[0], q[1] + s[1])
+            out[key] = out.get(key, 0) + n
+    return out
+
+
+def density_case(total: int = 1024, m_keep: int = 1024, target=(26, 26), cfg: int = 6,
+                 decades: float = 16.0, keep_empty: bool = False, sizes=None) -> DensityCase:
+    """System = [B a] with B of `total` states in the Gaussian sector grid of
+    the blocked workload, environment [a~ B~] its mirror image, target total
+    numbers `target`.  Each sector block is psi_Q = A diag(lambda) B^T with A,
+    B orthonormal (QR of Gaussians) and lambda^2 log-uniform over `decades`
+    decades (the decaying weights of a DMRG state), the whole state normalised."""
+    if sizes is None:
+        sizes = gaussian_sector_sizes(total)
+    enl = enlarged_sector_sizes(sizes)
+    g = rng(cfg, 2)
+    qn, parts = [], []
+    for q in sorted(enl):
+        r = enl.get((target[0] - q[0], target[1] - q[1]), 0)
+        if r == 0 and not keep_empty:
+            continue
+        n = enl[q]
+        k = min(n, r)
+        A = isometry(n, k, g) if k else np.zeros((n, 0))
+        B = isometry(r, k, g) if k else np.zeros((r, 0))
+        lam = np.sqrt(10.0 ** (-decades * g.uniform(0.0, 1.0, k)))
+        qn.append(q)
+        parts.append((A * lam[None, :]) @ B.T)
+    norm = math.sqrt(sum(float(np.sum(p * p)) for p in parts))
+    return DensityCase(qn, [p / norm for p in parts], m_keep)
