@@ -52,7 +52,8 @@ typedef enum {
     ROT_ERR_UNSUPPORTED = -2,   /* valid request this library does not implement */
     ROT_ERR_WORKSPACE = -3,     /* workspace smaller than the minimum */
     ROT_ERR_HIP = -4,           /* HIP runtime error (launch, device query) */
-    ROT_ERR_NOT_ISOMETRY = -5   /* rot_check_isometry: max|U^T U - I| above tolerance */
+    ROT_ERR_NOT_ISOMETRY = -5,  /* rot_check_isometry: max|U^T U - I| above tolerance */
+    ROT_ERR_NOT_CONVERGED = -6  /* rot_density_basis: Jacobi sweeps exhausted */
 } rot_status;
 
 typedef enum {
@@ -355,6 +356,50 @@ ROT_API rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols,
                               double tol, double* max_dev_host, void* workspace,
                               size_t workspace_bytes, void* stream);
 ROT_API size_t rot_isometry_workspace_size(int32_t rows, int32_t cols, rot_precision prec);
+
+/*
+ * The system's reduced density matrix and its kept eigenbasis (Sec. 2:
+ * Eq. (2), step 4 of the algorithm, Eq. (3)).  The superblock state arrives
+ * split by the quantum numbers of the system [B a]: sector k holds psi_k,
+ * n x r (FP64, device, row-major, row stride ld_psi >= r), the amplitudes of
+ * its n system states with the r environment states of the complementary
+ * numbers (r = 0 is allowed; psi may then be NULL).  For every sector the
+ * call forms rho_k = psi_k psi_k^T (Eq. (2), real amplitudes) and
+ * diagonalises it in FP64 by two-sided block Jacobi, then writes
+ *   w  (n doubles, device): the eigenvalues, descending (equal values keep
+ *      their order on the diagonal);
+ *   V  (n x n doubles, device, row-major, row stride ld_v >= n): column j is
+ *      the unit eigenvector of w[j].
+ * Then it keeps the m_keep largest eigenvalues over all sectors (equal
+ * values: lower sector index first, then earlier position in w) and writes
+ *   kept (n_sectors int32, device): states kept per sector; the rotation's
+ *      block for sector k is the first kept[k] columns of its V;
+ *   eps  (one double, device): the sum of the eigenvalues left out, which is
+ *      Eq. (3)'s truncation error 1 - sum(kept w) when psi has unit norm.
+ * m_keep >= the total number of states keeps all of them; m_keep >= 0.
+ * Convergence: an off-diagonal entry of rho_k counts as zero once
+ * |rho_pq| <= 2^-52 tr(rho_k); a sector is done after a full cycle of block
+ * pairs without a rotation.  The call synchronises `stream` once per sweep
+ * (a 4-byte read) and returns ROT_ERR_NOT_CONVERGED when a sector is still
+ * rotating after 80 sweeps (outputs then hold the last iterate).
+ * Sizes: 1 <= n <= 4096, r >= 0.  Outputs must not overlap psi or each
+ * other.  workspace: rot_density_workspace_size(sectors, n_sectors) bytes,
+ * 256-byte aligned.  Returns ROT_OK, ROT_ERR_INVALID_ARG, ROT_ERR_WORKSPACE,
+ * ROT_ERR_HIP or ROT_ERR_NOT_CONVERGED.
+ */
+typedef struct {
+    int32_t n, r;
+    const double* psi;
+    int64_t ld_psi;
+    double* w;
+    double* V;
+    int64_t ld_v;
+} rot_dm_sector;
+
+ROT_API size_t rot_density_workspace_size(const rot_dm_sector* sectors, int32_t n_sectors);
+ROT_API rot_status rot_density_basis(const rot_dm_sector* sectors, int32_t n_sectors, int64_t m_keep,
+                                     int32_t* kept, double* eps, void* workspace, size_t workspace_bytes,
+                                     void* stream);
 
 /* Split of float values into bf16 pairs (the split-BF16 operand format):
  * hi[k] = bf16(x[k]), lo[k] = bf16(x[k] - hi[k]), round to nearest even,

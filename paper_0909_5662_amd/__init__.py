@@ -33,12 +33,13 @@ __all__ = [
     "blocked_problem", "rotate_blocked", "Plan", "ROT_PLAN_NO_GRAPH", "ROT_PLAN_NO_TUNE", "ROT_PLAN_RETUNE",
     "RotSiteProblem", "ROT_BLOCK_IDENTITY", "ROT_BLOCK_DIAGONAL", "ROT_BLOCK_DENSE", "rot_batch_site",
     "rot_site_workspace_size", "rotate_site", "expect_block", "expect_cross",
+    "RotDmSector", "rot_density_basis", "density_workspace_size", "density_basis",
 ]
 
 ROT_FP64, ROT_FP32, ROT_SPLIT_BF16 = 0, 1, 2
 ROT_ASSUME_SYMMETRIC_O = 1
 _STATUS = {0: "ROT_OK", -1: "ROT_ERR_INVALID_ARG", -2: "ROT_ERR_UNSUPPORTED", -3: "ROT_ERR_WORKSPACE",
-           -4: "ROT_ERR_HIP", -5: "ROT_ERR_NOT_ISOMETRY"}
+           -4: "ROT_ERR_HIP", -5: "ROT_ERR_NOT_ISOMETRY", -6: "ROT_ERR_NOT_CONVERGED"}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librot.so")
@@ -81,6 +82,11 @@ class RotBlockedProblem(ctypes.Structure):
                 ("out_blk", ctypes.c_void_p), ("out_off", ctypes.POINTER(ctypes.c_int64))]
 
 
+class RotDmSector(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("r", ctypes.c_int32), ("psi", ctypes.c_void_p), ("ld_psi", ctypes.c_int64),
+                ("w", ctypes.c_void_p), ("V", ctypes.c_void_p), ("ld_v", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -119,6 +125,9 @@ def lib() -> ctypes.CDLL:
         L.rot_isometry_workspace_size.argtypes = [i32, i32, ctypes.c_int]
         L.rot_isometry_workspace_size.restype = sz
         L.rot_split_bf16.argtypes = [vp, i64, vp, vp, vp]
+        L.rot_density_workspace_size.argtypes = [ctypes.POINTER(RotDmSector), i32]
+        L.rot_density_workspace_size.restype = sz
+        L.rot_density_basis.argtypes = [ctypes.POINTER(RotDmSector), i32, i64, vp, vp, vp, sz, vp]
         L.rot_status_string.restype = ctypes.c_char_p
         L.rot_status_string.argtypes = [ctypes.c_int]
         L.rot_last_error.restype = ctypes.c_char_p
@@ -356,6 +365,47 @@ def expect_block(psi: torch.Tensor, Z: torch.Tensor, d: int, stream=None) -> tor
     _check(lib().rot_expect_block(psi.data_ptr(), m, d, psi.shape[1], Z.data_ptr(), n, m * m, prec, e.data_ptr(),
                                   ws.data_ptr(), ws.numel(), _stream(stream)))
     return e
+
+
+def density_workspace_size(sectors) -> int:
+    arr = (RotDmSector * len(sectors))(*sectors)
+    return lib().rot_density_workspace_size(arr, len(sectors))
+
+
+def rot_density_basis(sectors, m_keep: int, kept: int, eps: int, workspace: int, workspace_bytes: int,
+                      stream: int) -> None:
+    arr = (RotDmSector * len(sectors))(*sectors)
+    _check(lib().rot_density_basis(arr, len(sectors), m_keep, kept, eps, workspace, workspace_bytes, stream))
+
+
+def density_basis(psi_sectors, m_keep: int, workspace: torch.Tensor | None = None, stream=None):
+    """Reduced density matrix of the system per quantum-number sector, its
+    eigenpairs and the m_keep kept states (FP64).  psi_sectors: list of
+    (n_k, r_k) float64 CUDA tensors (row-major, unit row stride).  Returns
+    (w, V, kept, eps): per sector the descending eigenvalues (n_k,) and the
+    eigenvectors as columns of V (n_k, n_k); kept (int32, one per sector) and
+    eps (the discarded weight) on the device."""
+    if not psi_sectors:
+        raise ValueError("need at least one sector")
+    dev = psi_sectors[0].device
+    secs, w_out, v_out = [], [], []
+    for p in psi_sectors:
+        if p.dtype != torch.float64 or not p.is_cuda or p.dim() != 2 or (p.shape[1] > 0 and p.stride(1) != 1):
+            raise TypeError("each psi sector must be a 2-D float64 CUDA tensor with unit column stride")
+        n, r = p.shape
+        w = torch.empty(n, dtype=torch.float64, device=dev)
+        V = torch.empty((n, n), dtype=torch.float64, device=dev)
+        secs.append(RotDmSector(n, r, p.data_ptr() if r > 0 else None, max(p.stride(0), r), w.data_ptr(),
+                                V.data_ptr(), n))
+        w_out.append(w)
+        v_out.append(V)
+    kept = torch.empty(len(secs), dtype=torch.int32, device=dev)
+    eps = torch.empty(1, dtype=torch.float64, device=dev)
+    if workspace is None:
+        workspace = _workspace(density_workspace_size(secs), dev)
+    rot_density_basis(secs, m_keep, kept.data_ptr(), eps.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                      _stream(stream))
+    return w_out, v_out, kept, eps
 
 
 def expect_cross(psi: torch.Tensor, Z: torch.Tensor, W: torch.Tensor, d: int, dR: int,

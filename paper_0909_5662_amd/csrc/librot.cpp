@@ -22,6 +22,9 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symm
 size_t blocked_workspace_bytes(const rot_blocked_problem* p);
 rot_status blocked_validate(const rot_blocked_problem* p, std::string* why);
 hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_bytes, hipStream_t stream);
+size_t density_workspace_bytes(const rot_dm_sector* sectors, int n_sectors);
+hipError_t density_basis(const rot_dm_sector* sectors, int n_sec, int64_t m_keep, int32_t* kept, double* eps,
+                         void* workspace, hipStream_t stream, bool* converged);
 
 namespace {
 
@@ -276,6 +279,7 @@ const char* rot_status_string(rot_status s) {
         case ROT_ERR_WORKSPACE: return "ROT_ERR_WORKSPACE";
         case ROT_ERR_HIP: return "ROT_ERR_HIP";
         case ROT_ERR_NOT_ISOMETRY: return "ROT_ERR_NOT_ISOMETRY";
+        case ROT_ERR_NOT_CONVERGED: return "ROT_ERR_NOT_CONVERGED";
     }
     return "unknown rot_status";
 }
@@ -821,6 +825,48 @@ rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, rot_pre
     if (e != hipSuccess) return hip_fail(e, "rot_check_isometry");
     if (!(*max_dev_host <= tol))
         return fail(ROT_ERR_NOT_ISOMETRY, "max|U^T U - I| = %.3e exceeds tol %.3e", *max_dev_host, tol);
+    return ROT_OK;
+}
+
+namespace {
+constexpr int kDmMaxStates = 4096;
+
+rot_status validate_dm(const rot_dm_sector* sectors, int32_t n_sectors) {
+    if (!sectors || n_sectors <= 0) return fail(ROT_ERR_INVALID_ARG, "sectors is null or n_sectors <= 0");
+    for (int k = 0; k < n_sectors; k++) {
+        const rot_dm_sector& s = sectors[k];
+        if (s.n < 1 || s.n > kDmMaxStates)
+            return fail(ROT_ERR_INVALID_ARG, "sector %d: n = %d outside 1..%d", k, s.n, kDmMaxStates);
+        if (s.r < 0) return fail(ROT_ERR_INVALID_ARG, "sector %d: negative r", k);
+        if (s.r > 0 && (!s.psi || s.ld_psi < s.r))
+            return fail(ROT_ERR_INVALID_ARG, "sector %d: null psi or ld_psi < r", k);
+        if (!s.w || !s.V || s.ld_v < s.n) return fail(ROT_ERR_INVALID_ARG, "sector %d: null w or V, or ld_v < n", k);
+    }
+    return ROT_OK;
+}
+}  // namespace
+
+size_t rot_density_workspace_size(const rot_dm_sector* sectors, int32_t n_sectors) {
+    if (validate_dm(sectors, n_sectors) != ROT_OK) return 0;
+    return density_workspace_bytes(sectors, n_sectors);
+}
+
+rot_status rot_density_basis(const rot_dm_sector* sectors, int32_t n_sectors, int64_t m_keep, int32_t* kept,
+                             double* eps, void* workspace, size_t workspace_bytes, void* stream) {
+    const rot_status v = validate_dm(sectors, n_sectors);
+    if (v != ROT_OK) return v;
+    if (m_keep < 0) return fail(ROT_ERR_INVALID_ARG, "m_keep must be >= 0");
+    if (!kept || !eps) return fail(ROT_ERR_INVALID_ARG, "null kept or eps");
+    const size_t need = density_workspace_bytes(sectors, n_sectors);
+    if (!workspace || workspace_bytes < need)
+        return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    bool converged = false;
+    const hipError_t e = density_basis(sectors, n_sectors, m_keep, kept, eps, workspace,
+                                       static_cast<hipStream_t>(stream), &converged);
+    if (e != hipSuccess) return hip_fail(e, "rot_density_basis");
+    if (!converged) return fail(ROT_ERR_NOT_CONVERGED, "Jacobi sweeps exhausted before every sector converged");
     return ROT_OK;
 }
 

@@ -257,3 +257,25 @@ def test_batch_ex_flags(rotlib):
     arr = (rotlib.RotProblem * 1)(prob(rotlib))
     assert L.rot_batch_ex(arr, 1, rotlib.ROT_FP32, 2, 4 * FAKE, 1 << 30, None) == -1
     assert L.rot_batch_ex(arr, 1, rotlib.ROT_FP32, 1, 4 * FAKE, 16, None) == -3
+
+
+def _dm(rotlib, n=5, r=3, psi=FAKE, w=2 * FAKE, V=3 * FAKE, ld_psi=None, ld_v=None):
+    return rotlib.RotDmSector(n, r, psi, r if ld_psi is None else ld_psi, w, V, n if ld_v is None else ld_v)
+
+
+def test_density_validation(rotlib):
+    L = rotlib.lib()
+    assert L.rot_status_string(-6) == b"ROT_ERR_NOT_CONVERGED"
+    ok = rotlib.density_workspace_size([_dm(rotlib), _dm(rotlib, n=70, r=0, psi=None)])
+    assert ok > 2 * 128 * 128 * 8
+    for bad in (_dm(rotlib, n=0), _dm(rotlib, n=4097), _dm(rotlib, r=-1), _dm(rotlib, psi=None),
+                _dm(rotlib, ld_psi=2), _dm(rotlib, w=None), _dm(rotlib, V=None), _dm(rotlib, ld_v=4)):
+        assert rotlib.density_workspace_size([bad]) == 0
+        arr = (rotlib.RotDmSector * 1)(bad)
+        assert L.rot_density_basis(arr, 1, 4, 4 * FAKE, 5 * FAKE, 6 * FAKE, 1 << 30, None) == -1
+    arr = (rotlib.RotDmSector * 1)(_dm(rotlib))
+    assert L.rot_density_basis(arr, 0, 4, 4 * FAKE, 5 * FAKE, 6 * FAKE, 1 << 30, None) == -1
+    assert L.rot_density_basis(arr, 1, -1, 4 * FAKE, 5 * FAKE, 6 * FAKE, 1 << 30, None) == -1
+    assert L.rot_density_basis(arr, 1, 4, None, 5 * FAKE, 6 * FAKE, 1 << 30, None) == -1
+    assert L.rot_density_basis(arr, 1, 4, 4 * FAKE, 5 * FAKE, 6 * FAKE, 16, None) == -3
+    assert L.rot_density_basis(arr, 1, 4, 4 * FAKE, 5 * FAKE, 6 * FAKE + 8, 1 << 30, None) == -1

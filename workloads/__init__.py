@@ -376,3 +376,15 @@ def density_case(total: int = 1024, m_keep: int = 1024, target=(26, 26), cfg: in
         parts.append((A * lam[None, :]) @ B.T)
     norm = math.sqrt(sum(float(np.sum(p * p)) for p in parts))
     return DensityCase(qn, [p / norm for p in parts], m_keep)
+
+
+def gaussian_sectors(dims, cfg: int = 7, repeat: dict | None = None) -> list[np.ndarray]:
+    """psi blocks of the given (n, r) shapes with N(0,1) entries, the whole
+    state normalised.  repeat maps a sector index to an earlier one whose
+    block it copies (equal spectra in two sectors)."""
+    g = rng(cfg, 2)
+    parts = [g.standard_normal((n, r)) for n, r in dims]
+    for k, src in (repeat or {}).items():
+        parts[k] = parts[src].copy()
+    norm = math.sqrt(sum(float(np.sum(p * p)) for p in parts))
+    return [p / norm for p in parts]
