@@ -37,7 +37,7 @@ def parse():
                     help="skip timing the plain FP64 GPU rotation (speedup denominator)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "blocked_1024_n400", "uneven_1000", "differentiated_m1024_n64",
-                             "site_m1024_n64", "measure_m1024"],
+                             "site_m1024_n64", "measure_m1024", "density_m1024"],
                     help="default: the headline dense workload; the others time the quantum-number "
                          "blocked batch or the uneven sweep plan")
     ap.add_argument("--symmetric", action="store_true",
@@ -422,6 +422,69 @@ def bench_measure(args, rot, torch, workloads):
     return rec
 
 
+def bench_density(args, rot, torch, workloads):
+    """Density matrix to kept basis (FP64): the enlarged block [B a] of the
+    1024-state sector grid, 47 sectors of 4..246 states (3939 states), a
+    superblock state of decaying weights, m' = 1024 kept.  Each step is one
+    rot_density_basis call (rho per sector, Jacobi, sort, selection), host
+    synchronisations per sweep included."""
+    import time
+
+    import numpy as np
+    case = workloads.density_case()
+    psi = [torch.from_numpy(p).cuda() for p in case.psi]
+    secs, outs = [], []
+    for p in psi:
+        n, r = p.shape
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        V = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        secs.append(rot.RotDmSector(n, r, p.data_ptr(), r, w.data_ptr(), V.data_ptr(), n))
+        outs.append((w, V))
+    kept = torch.empty(len(secs), dtype=torch.int32, device="cuda")
+    eps = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(rot.density_workspace_size(secs), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step():
+        rot.rot_density_basis(secs, case.m_keep, kept.data_ptr(), eps.data_ptr(), ws.data_ptr(), ws.numel(),
+                              stream)
+
+    ms = timed_loop(torch, step, args.steps, args.warmup)
+    rot.profile_enable(True)
+    calls = 2
+    for _ in range(calls):
+        step()
+    torch.cuda.synchronize()
+    kernels = rot.profile_read()
+    rot.profile_enable(False)
+    rounds = kernels.get("dm_jacobi_pairs", (0, 0.0))[0] / calls
+
+    def torch_eigh():
+        for p in psi:
+            torch.linalg.eigh(p @ p.T)
+
+    ms_torch = timed_loop(torch, torch_eigh, max(2, args.steps // 4), 1)
+    t0 = time.perf_counter()
+    import oracle.density as odm
+    ref = odm.density_basis(case.psi, case.m_keep)
+    ms_cpu = (time.perf_counter() - t0) * 1e3
+    n_states = sum(p.shape[0] for p in case.psi)
+    rec = base_record(args, 1e3 / ms, "density-matrix steps/s (3939 states, 47 sectors)", ms,
+                      {"workload": "density_m1024", "sectors": len(psi), "states": n_states,
+                       "largest_sector": max(p.shape[0] for p in case.psi), "m_keep": case.m_keep,
+                       "weights": "Schmidt form, log-uniform over 16 decades"}, dtype="f64")
+    rec.update({"jacobi_rounds_per_call": rounds, "eps_rho": float(eps.cpu()[0]),
+                "eps_rho_oracle": ref["eps"],
+                "kernels_ms_per_call": {k: round(v[1] / calls, 4) for k, v in kernels.items()},
+                "torch_gpu_eigh_ms": round(ms_torch, 3), "speedup_vs_torch_gpu_eigh": round(ms_torch / ms, 2),
+                "cpu_baseline": {"value": round(1e3 / ms_cpu, 3), "unit": "density-matrix steps/s",
+                                 "cores": os.cpu_count(), "kind": "oracle",
+                                 "sample": "the whole workload once (numpy: rho, LAPACK eigh, selection)"},
+                "kept_total": int(kept.sum().item()), "kept_matches_oracle":
+                    bool(np.array_equal(kept.cpu().numpy(), ref["kept"]))})
+    return rec
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -503,7 +566,7 @@ def main():
     if args.workload != WORKLOAD:
         fn = {"blocked_1024_n400": bench_blocked, "uneven_1000": bench_uneven,
               "differentiated_m1024_n64": bench_differentiated, "site_m1024_n64": bench_site,
-              "measure_m1024": bench_measure}[args.workload]
+              "measure_m1024": bench_measure, "density_m1024": bench_density}[args.workload]
         print(json.dumps(fn(args, rot, torch, workloads)), flush=True)
         return
 

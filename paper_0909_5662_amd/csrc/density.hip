@@ -174,10 +174,33 @@ __global__ __launch_bounds__(256) void dm_prep_kernel(const DmSector* __restrict
 // (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c zeroes a_pq of
 // J^T A J, J = [[c, s], [-s, c]] on rows/columns (p, q).  The submatrix is kept
 // exactly symmetric: each 2 x 2 block (kx <= ky) is rotated once and mirrored.
-__global__ __launch_bounds__(256) void dm_pair_kernel(const DmSector* __restrict__ secs,
-                                                      const DmItem* __restrict__ items, double* __restrict__ A,
-                                                      double* __restrict__ Qw, const DmState* __restrict__ st,
-                                                      int* __restrict__ rotated, int round) {
+// Schedule per step: all 528 blocks are rotated (one per thread), then wave 0
+// derives the next step's rotations while the other waves apply this step's
+// to the accumulated Q (parameters double-buffered).
+constexpr int kPairThreads = 1024;
+constexpr int kSteps = kPair - 1;
+constexpr int kBlocks2 = 32 * 33 / 2;
+
+struct Rot2 {
+    double c, s, t;
+};
+
+__device__ inline Rot2 jacobi_rotation(double app, double aqq, double apq, double floor) {
+    Rot2 r{1.0, 0.0, 0.0};
+    if (fabs(apq) > floor) {
+        const double tau = (aqq - app) / (2.0 * apq);
+        r.t = fabs(tau) > 1e150 ? 0.5 / tau : copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        r.c = 1.0 / sqrt(1.0 + r.t * r.t);
+        r.s = r.t * r.c;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* __restrict__ secs,
+                                                               const DmItem* __restrict__ items,
+                                                               double* __restrict__ A, double* __restrict__ Qw,
+                                                               const DmState* __restrict__ st,
+                                                               int* __restrict__ rotated, int round) {
     const DmItem it = items[blockIdx.x];
     const DmSector s = secs[it.sec];
     const int k = it.a;
@@ -192,47 +215,57 @@ __global__ __launch_bounds__(256) void dm_pair_kernel(const DmSector* __restrict
     circle_pair(s.nb, round, k, I, J);
     __shared__ double S[kPair * kLs];
     __shared__ double Q[kPair * kLs];
-    __shared__ double rc[32], rs[32], rt[32];
-    __shared__ int rp[32], rq[32];
+    __shared__ double rc[2][32], rs[2][32], rt[2][32];
+    __shared__ unsigned char tp[kSteps][32], tq[kSteps][32];
     __shared__ int any;
     double* a = A + s.a_off;
     const int64_t np = s.npad;
-    for (int e = tid; e < kPair * kPair; e += 256) {
-        const int x = e >> 6, y = e & 63;
-        S[x * kLs + y] = a[(int64_t)pair_row(I, J, x) * np + pair_row(I, J, y)];
-        Q[x * kLs + y] = x == y ? 1.0 : 0.0;
+    {
+        constexpr int kPer = kPair * kPair / kPairThreads;
+        double sv[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; j++) {
+            const int e = tid + kPairThreads * j, x = e >> 6, y = e & 63;
+            sv[j] = a[(int64_t)pair_row(I, J, x) * np + pair_row(I, J, y)];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; j++) {
+            const int e = tid + kPairThreads * j, x = e >> 6, y = e & 63;
+            S[x * kLs + y] = sv[j];
+            Q[x * kLs + y] = x == y ? 1.0 : 0.0;
+        }
+    }
+    for (int e = tid; e < kSteps * 32; e += kPairThreads) {
+        int p, q;
+        circle_pair(kPair, e >> 5, e & 31, p, q);
+        tp[e >> 5][e & 31] = (unsigned char)p;
+        tq[e >> 5][e & 31] = (unsigned char)q;
     }
     if (tid == 0) any = 0;
     __syncthreads();
-    for (int u = 0; u < kPair - 1; u++) {
-        if (tid < 32) {
-            int p, q;
-            circle_pair(kPair, u, tid, p, q);
-            const double app = S[p * kLs + p], aqq = S[q * kLs + q], apq = S[p * kLs + q];
-            double c = 1.0, sn = 0.0, tt = 0.0;
-            if (fabs(apq) > floor) {
-                const double tau = (aqq - app) / (2.0 * apq);
-                tt = fabs(tau) > 1e150 ? 0.5 / tau : copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                c = 1.0 / sqrt(1.0 + tt * tt);
-                sn = tt * c;
-                any = 1;
-            }
-            rp[tid] = p;
-            rq[tid] = q;
-            rc[tid] = c;
-            rs[tid] = sn;
-            rt[tid] = tt;
-        }
-        __syncthreads();
-        // 2 x 2 blocks (kx, ky), kx <= ky: index b = ky (ky + 1) / 2 + kx
-        for (int b = tid; b < 32 * 33 / 2; b += 256) {
-            int ky = (int)((sqrtf(8.0f * b + 1.0f) - 1.0f) * 0.5f);
-            while (ky * (ky + 1) / 2 > b) ky--;
-            while ((ky + 1) * (ky + 2) / 2 <= b) ky++;
-            const int kx = b - ky * (ky + 1) / 2;
-            const int px = rp[kx], qx = rq[kx], py = rp[ky], qy = rq[ky];
+    if (tid < 32) {
+        const int p = tp[0][tid], q = tq[0][tid];
+        const Rot2 r = jacobi_rotation(S[p * kLs + p], S[q * kLs + q], S[p * kLs + q], floor);
+        rc[0][tid] = r.c;
+        rs[0][tid] = r.s;
+        rt[0][tid] = r.t;
+        if (r.s != 0.0) any = 1;
+    }
+    // this thread's 2 x 2 block: b = ky (ky + 1) / 2 + kx, kx <= ky
+    int kx = 0, ky = 0;
+    if (tid < kBlocks2) {
+        ky = (int)((sqrtf(8.0f * tid + 1.0f) - 1.0f) * 0.5f);
+        while (ky * (ky + 1) / 2 > tid) ky--;
+        while ((ky + 1) * (ky + 2) / 2 <= tid) ky++;
+        kx = tid - ky * (ky + 1) / 2;
+    }
+    __syncthreads();
+    for (int u = 0; u < kSteps; u++) {
+        const int cur = u & 1;
+        if (tid < kBlocks2) {
+            const int px = tp[u][kx], qx = tq[u][kx];
             if (kx == ky) {
-                const double t = rt[kx];
+                const double t = rt[cur][kx];
                 if (t != 0.0) {
                     const double apq = S[px * kLs + qx];
                     S[px * kLs + px] -= t * apq;
@@ -240,39 +273,54 @@ __global__ __launch_bounds__(256) void dm_pair_kernel(const DmSector* __restrict
                     S[px * kLs + qx] = 0.0;
                     S[qx * kLs + px] = 0.0;
                 }
-                continue;
+            } else {
+                const double sx = rs[cur][kx], sy = rs[cur][ky];
+                if (sx != 0.0 || sy != 0.0) {
+                    const int py = tp[u][ky], qy = tq[u][ky];
+                    const double cx = rc[cur][kx], cy = rc[cur][ky];
+                    const double u0 = S[px * kLs + py], v0 = S[px * kLs + qy];
+                    const double x0 = S[qx * kLs + py], y0 = S[qx * kLs + qy];
+                    const double u1 = cx * u0 - sx * x0, x1 = sx * u0 + cx * x0;
+                    const double v1 = cx * v0 - sx * y0, y1 = sx * v0 + cx * y0;
+                    const double u2 = cy * u1 - sy * v1, v2 = sy * u1 + cy * v1;
+                    const double x2 = cy * x1 - sy * y1, y2 = sy * x1 + cy * y1;
+                    S[px * kLs + py] = u2;
+                    S[px * kLs + qy] = v2;
+                    S[qx * kLs + py] = x2;
+                    S[qx * kLs + qy] = y2;
+                    S[py * kLs + px] = u2;
+                    S[qy * kLs + px] = v2;
+                    S[py * kLs + qx] = x2;
+                    S[qy * kLs + qx] = y2;
+                }
             }
-            const double cx = rc[kx], sx = rs[kx], cy = rc[ky], sy = rs[ky];
-            if (sx == 0.0 && sy == 0.0) continue;
-            const double u0 = S[px * kLs + py], v0 = S[px * kLs + qy];
-            const double x0 = S[qx * kLs + py], y0 = S[qx * kLs + qy];
-            const double u1 = cx * u0 - sx * x0, x1 = sx * u0 + cx * x0;
-            const double v1 = cx * v0 - sx * y0, y1 = sx * v0 + cx * y0;
-            const double u2 = cy * u1 - sy * v1, v2 = sy * u1 + cy * v1;
-            const double x2 = cy * x1 - sy * y1, y2 = sy * x1 + cy * y1;
-            S[px * kLs + py] = u2;
-            S[px * kLs + qy] = v2;
-            S[qx * kLs + py] = x2;
-            S[qx * kLs + qy] = y2;
-            S[py * kLs + px] = u2;
-            S[qy * kLs + px] = v2;
-            S[py * kLs + qx] = x2;
-            S[qy * kLs + qx] = y2;
         }
-        // Q <- Q J: columns (p, q) of every row
-        for (int e = tid; e < kPair * 32; e += 256) {
-            const int row = e & 63, kp = e >> 6;
-            const double sn = rs[kp];
-            if (sn == 0.0) continue;
-            const double c = rc[kp];
-            const int p = rp[kp], q = rq[kp];
-            const double qp = Q[row * kLs + p], qq = Q[row * kLs + q];
-            Q[row * kLs + p] = c * qp - sn * qq;
-            Q[row * kLs + q] = sn * qp + c * qq;
+        __syncthreads();
+        if (tid < 64) {
+            if (tid < 32 && u + 1 < kSteps) {
+                const int p = tp[u + 1][tid], q = tq[u + 1][tid];
+                const Rot2 r = jacobi_rotation(S[p * kLs + p], S[q * kLs + q], S[p * kLs + q], floor);
+                rc[cur ^ 1][tid] = r.c;
+                rs[cur ^ 1][tid] = r.s;
+                rt[cur ^ 1][tid] = r.t;
+                if (r.s != 0.0) any = 1;
+            }
+        } else {
+            // Q <- Q J for this step: columns (p, q) of every row
+            for (int e = tid - 64; e < kPair * 32; e += kPairThreads - 64) {
+                const int row = e & 63, kp = e >> 6;
+                const double sn = rs[cur][kp];
+                if (sn == 0.0) continue;
+                const double c = rc[cur][kp];
+                const int p = tp[u][kp], q = tq[u][kp];
+                const double qp = Q[row * kLs + p], qq = Q[row * kLs + q];
+                Q[row * kLs + p] = c * qp - sn * qq;
+                Q[row * kLs + q] = sn * qp + c * qq;
+            }
         }
         __syncthreads();
     }
-    for (int e = tid; e < kPair * kPair; e += 256) {
+    for (int e = tid; e < kPair * kPair; e += kPairThreads) {
         const int x = e >> 6, y = e & 63;
         a[(int64_t)pair_row(I, J, x) * np + pair_row(I, J, y)] = S[x * kLs + y];
         Qw[s.q_off + (int64_t)k * kPair * kPair + e] = Q[x * kLs + y];
@@ -346,11 +394,21 @@ __global__ __launch_bounds__(256) void dm_update_kernel(const DmSector* __restri
         double* a = A + s.a_off;
         const double* q1 = Qw + s.q_off + (int64_t)P1 * kPair * kPair;
         const double* q2 = Qw + s.q_off + (int64_t)P2 * kPair * kPair;
-        for (int e = tid; e < kPair * kPair; e += 256) {
-            const int x = e >> 6, z = e & 63;
-            X[x * kLs + z] = a[(int64_t)pair_row(I1, J1, x) * np + pair_row(I2, J2, z)];
-            if (r1) L[x * kLs + z] = q1[e];
-            if (r2) R[x * kLs + z] = q2[e];
+        // all loads of a thread issued before the first LDS write
+        double xv[16], lv[16], rv[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int e = tid + 256 * j, x = e >> 6, z = e & 63;
+            xv[j] = a[(int64_t)pair_row(I1, J1, x) * np + pair_row(I2, J2, z)];
+            lv[j] = r1 ? q1[e] : 0.0;
+            rv[j] = r2 ? q2[e] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int e = tid + 256 * j, x = e >> 6, z = e & 63;
+            X[x * kLs + z] = xv[j];
+            L[x * kLs + z] = lv[j];
+            R[x * kLs + z] = rv[j];
         }
         __syncthreads();
         if (r2) {
@@ -364,21 +422,18 @@ __global__ __launch_bounds__(256) void dm_update_kernel(const DmSector* __restri
         }
         if (r1) {
             mm64<true>(L, X, y, tx, ty);
-        } else {
+            __syncthreads();
 #pragma unroll
             for (int p = 0; p < 4; p++)
 #pragma unroll
-                for (int q = 0; q < 4; q++) y[p][q] = X[(ty * 4 + p) * kLs + tx * 4 + q];
+                for (int q = 0; q < 4; q++) X[(ty * 4 + p) * kLs + tx * 4 + q] = y[p][q];
+            __syncthreads();
         }
-#pragma unroll
-        for (int p = 0; p < 4; p++) {
-            const int64_t gr = pair_row(I1, J1, ty * 4 + p);
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int64_t gc = pair_row(I2, J2, tx * 4 + q);
-                a[gr * np + gc] = y[p][q];
-                a[gc * np + gr] = y[p][q];
-            }
+        // the block and its mirror, both written along rows
+        for (int e = tid; e < kPair * kPair; e += 256) {
+            const int x = e >> 6, z = e & 63;
+            a[(int64_t)pair_row(I1, J1, x) * np + pair_row(I2, J2, z)] = X[x * kLs + z];
+            a[(int64_t)pair_row(I2, J2, x) * np + pair_row(I1, J1, z)] = X[z * kLs + x];
         }
         return;
     }
@@ -390,10 +445,18 @@ __global__ __launch_bounds__(256) void dm_update_kernel(const DmSector* __restri
     double* v = Vw + s.a_off;
     const double* qm = Qw + s.q_off + (int64_t)P * kPair * kPair;
     const int64_t r0 = (int64_t)it.a * kPair;
-    for (int e = tid; e < kPair * kPair; e += 256) {
-        const int x = e >> 6, z = e & 63;
-        X[x * kLs + z] = v[(r0 + x) * np + pair_row(I, J, z)];
-        R[x * kLs + z] = qm[e];
+    double xv[16], rv[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const int e = tid + 256 * j, x = e >> 6, z = e & 63;
+        xv[j] = v[(r0 + x) * np + pair_row(I, J, z)];
+        rv[j] = qm[e];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const int e = tid + 256 * j, x = e >> 6, z = e & 63;
+        X[x * kLs + z] = xv[j];
+        R[x * kLs + z] = rv[j];
     }
     __syncthreads();
     mm64<false>(X, R, y, tx, ty);
@@ -492,34 +555,52 @@ __device__ inline int dm_count_ge(const double* w, int n, uint64_t c) {
 }
 
 // The m_keep largest eigenvalues over all sectors: the m_keep-th largest key T
-// found bit by bit (largest T with #(key >= T) >= m_keep), all entries above T
-// kept, entries equal to T handed out in sector order; then the weight left
-// out, summed per sector in list order and over sectors in sector order.
-__global__ __launch_bounds__(256) void dm_select_kernel(const DmSector* __restrict__ secs, int n_sec,
-                                                        const double* __restrict__ wall, int64_t m_keep,
-                                                        int64_t total, int* __restrict__ above,
-                                                        int* __restrict__ equal, double* __restrict__ part,
-                                                        int32_t* __restrict__ kept, double* __restrict__ eps) {
-    __shared__ long long red[256];
-    const int tid = threadIdx.x;
+// found bit by bit (largest T with #(key >= T) >= m_keep; each thread counts
+// its share of the concatenated lists, held in registers when they fit), all
+// entries above T kept, entries equal to T handed out in sector order; then
+// the weight left out, per sector by one wave (strided lanes, then a fixed
+// butterfly) and over sectors in sector order.
+constexpr int kSelThreads = 1024;
+constexpr int kSelWaves = kSelThreads / 64;
+constexpr int kSelCache = 16;
+
+__global__ __launch_bounds__(kSelThreads) void dm_select_kernel(const DmSector* __restrict__ secs, int n_sec,
+                                                                const double* __restrict__ wall, int64_t m_keep,
+                                                                int64_t total, int* __restrict__ above,
+                                                                int* __restrict__ equal, double* __restrict__ part,
+                                                                int32_t* __restrict__ kept,
+                                                                double* __restrict__ eps) {
+    __shared__ long long red[2][kSelWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (m_keep >= total || m_keep == 0) {
-        for (int k = tid; k < n_sec; k += 256) kept[k] = m_keep == 0 ? 0 : secs[k].n;
+        for (int k = tid; k < n_sec; k += kSelThreads) kept[k] = m_keep == 0 ? 0 : secs[k].n;
     } else {
+        const bool cached = total <= (int64_t)kSelThreads * kSelCache;
+        uint64_t kc[kSelCache];
+#pragma unroll
+        for (int j = 0; j < kSelCache; j++) {
+            const int64_t e = tid + (int64_t)kSelThreads * j;
+            kc[j] = (cached && e < total) ? dm_key(wall[e]) : 0;  // key 0 is never counted (c >= 1)
+        }
         uint64_t T = 0;
         for (int bit = 63; bit >= 0; bit--) {
             const uint64_t c = T | (1ull << bit);
-            long long cnt = 0;
-            for (int k = tid; k < n_sec; k += 256) cnt += dm_count_ge(wall + secs[k].w_off, secs[k].n, c);
-            red[tid] = cnt;
-            __syncthreads();
-            for (int w = 128; w > 0; w >>= 1) {
-                if (tid < w) red[tid] += red[tid + w];
-                __syncthreads();
+            int cnt = 0;
+            if (cached) {
+#pragma unroll
+                for (int j = 0; j < kSelCache; j++) cnt += kc[j] >= c ? 1 : 0;
+            } else {
+                for (int64_t e = tid; e < total; e += kSelThreads) cnt += dm_key(wall[e]) >= c ? 1 : 0;
             }
-            if (red[0] >= m_keep) T = c;
+            for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+            const int buf = bit & 1;
+            if (lane == 0) red[buf][wave] = cnt;
             __syncthreads();
+            long long tot = 0;
+            for (int w = 0; w < kSelWaves; w++) tot += red[buf][w];
+            if (tot >= m_keep) T = c;
         }
-        for (int k = tid; k < n_sec; k += 256) {
+        for (int k = tid; k < n_sec; k += kSelThreads) {
             const double* w = wall + secs[k].w_off;
             const int ge = dm_count_ge(w, secs[k].n, T);
             const int gt = T == ~0ull ? 0 : dm_count_ge(w, secs[k].n, T + 1);
@@ -538,11 +619,12 @@ __global__ __launch_bounds__(256) void dm_select_kernel(const DmSector* __restri
         }
     }
     __syncthreads();
-    for (int k = tid; k < n_sec; k += 256) {
+    for (int k = wave; k < n_sec; k += kSelWaves) {
         const double* w = wall + secs[k].w_off;
         double acc = 0.0;
-        for (int i = kept[k]; i < secs[k].n; i++) acc += w[i];
-        part[k] = acc;
+        for (int i = kept[k] + lane; i < secs[k].n; i += 64) acc += w[i];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) part[k] = acc;
     }
     __syncthreads();
     if (tid == 0) {
@@ -667,7 +749,7 @@ hipError_t density_basis(const rot_dm_sector* sectors, int n_sec, int64_t m_keep
     for (int sweep = 0; sweep < kMaxSweeps && !*converged; sweep++) {
         for (int r = 0; r < L.max_rounds; r++, round++) {
             e = prof_timed("dm_jacobi_pairs", stream, [&] {
-                hipLaunchKernelGGL(dm_pair_kernel, dim3((unsigned)L.pair_items.size()), dim3(256), 0, stream, secs,
+                hipLaunchKernelGGL(dm_pair_kernel, dim3((unsigned)L.pair_items.size()), dim3(kPairThreads), 0, stream, secs,
                                    pair_items, A, Qw, (const DmState*)st, flags, round);
                 return hipGetLastError();
             });
@@ -695,7 +777,7 @@ hipError_t density_basis(const rot_dm_sector* sectors, int n_sec, int64_t m_keep
                            (const double*)Vw, W);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(dm_select_kernel, dim3(1), dim3(256), 0, stream, secs, n_sec, (const double*)W, m_keep,
+        hipLaunchKernelGGL(dm_select_kernel, dim3(1), dim3(kSelThreads), 0, stream, secs, n_sec, (const double*)W, m_keep,
                            total, reinterpret_cast<int*>(ws + L.off_above), reinterpret_cast<int*>(ws + L.off_equal),
                            reinterpret_cast<double*>(ws + L.off_part), kept, eps);
         return hipGetLastError();

@@ -104,6 +104,18 @@ def test_schmidt_state_full_workload(rot):
     assert int(kept.sum()) == case.m_keep
 
 
+def test_many_sectors_beyond_the_register_cache(rot):
+    """20 000 states in 200 sectors: the selection counts from memory rather
+    than from keys held in registers."""
+    rng = np.random.default_rng(13)
+    dims = [(int(n), int(r)) for n, r in zip(rng.integers(60, 141, 200), rng.integers(0, 120, 200))]
+    psi = workloads.gaussian_sectors(dims, cfg=13)
+    total = sum(n for n, _ in dims)
+    assert total > 16384
+    for m_keep in (3000, 17000):
+        check(psi, m_keep, *run(rot, psi, m_keep))
+
+
 def test_repeatable_bitwise(rot):
     psi = workloads.gaussian_sectors(DIMS[:6], cfg=10)
     a = run(rot, psi, 50)
