@@ -16,6 +16,7 @@ Parity status of each function (what pins it is in tests/test_oracle_*.py):
   rotate, rotate_entries, adjoint, pair_loss, isometry_deviation,
   rotate_blocked, bf16_split, umd_range: pinned.
 The density-matrix step (Eq. (2), Eq. (3)) is in density.py, pinned likewise.
+The superblock matvec of Eq. (9) is in superblock.py, pinned likewise.
 """
 from __future__ import annotations
 
