@@ -326,6 +326,78 @@ ROT_API rot_status rot_batch_blocked(const rot_blocked_problem* p, rot_precision
 ROT_API size_t rot_blocked_workspace_size(const rot_blocked_problem* p);
 
 /*
+ * The superblock Hamiltonian applied to a state (Sec. 3.1: Eq. (9) and its
+ * quantum-number form Eq. (10)), the product the Davidson iteration of step 2
+ * repeats: out = sum over terms of coef * (O_B (x) O_a (x) O_a~ (x) O_B~) psi on
+ * [B a a~ B~], H never formed.
+ *
+ * Blocks B and B~ are given by their (N_up, N_down) sectors (rot_sector, the
+ * offset field unused), the sites a and a~ by the d state numbers site_qn
+ * (host, d pairs).  The system [B a] has a sector for every Q = q + qn(s); its
+ * basis runs over s ascending and, inside, over the states of B sector
+ * Q - qn(s).  The environment [a~ B~] likewise: t (the state of a~) ascending,
+ * then the states of B~ sector P - qn(t).  psi has definite total numbers
+ * `target` and is stored as one dense block per system sector Q whose
+ * partner P = target - Q exists: n_Q x r_P, row-major, in ascending
+ * (N_up, N_down) order of Q, packed back to back (FP64, device).
+ * rot_sb_layout reports the blocks: with arrays of `capacity` entries it
+ * writes each block's numbers (qn, 2 per block), rows, cols and element
+ * offset; *n_blocks and *total (elements) are always written.
+ *
+ * Operators of B: n_left_ops, each with a shift (dN_up, dN_down)
+ * (left_shift, host, 2 per op) and, per source sector k, the block
+ * (q + shift <- q) of dim(q + shift) x dim(q) FP64 values, row-major, at
+ * left_blk + left_off[op * n_left + k] (device data; offsets on the host,
+ * -1 = absent).  Operators of B~ likewise.  Terms (host): coef; left_op and
+ * right_op index those operators (-1 = identity); site_a and site_at are
+ * d x d host matrices (row = new state; NULL = identity) whose non-zero
+ * entries all change the numbers by one shift.  The four shifts of a term
+ * must add to zero.  A term with operators on both B and B~ returns
+ * ROT_ERR_UNSUPPORTED (nearest-neighbour chains have none).
+ *
+ * rot_sb_plan_create checks the problem, builds the work (one list of output
+ * tiles, each with the contributions reaching it in term order) and copies it
+ * to the device; the operator data must stay valid and unchanged while the
+ * plan lives.  rot_sb_apply writes out = H psi (FP64, device, psi's layout,
+ * no overlap with psi) on `stream`, allocates nothing (it can be captured in
+ * a graph) and is bitwise repeatable.  rot_sb_plan_flops: the multiply-add
+ * work of one apply (2 per multiply-add).
+ */
+typedef struct {
+    double coef;
+    int32_t left_op, right_op;
+    const double* site_a;
+    const double* site_at;
+} rot_sb_term;
+typedef struct {
+    int32_t d;
+    const int32_t* site_qn;
+    int32_t n_left;
+    const rot_sector* left;
+    int32_t n_right;
+    const rot_sector* right;
+    int32_t target[2];
+    int32_t n_left_ops;
+    const int32_t* left_shift;
+    const double* left_blk;
+    const int64_t* left_off;
+    int32_t n_right_ops;
+    const int32_t* right_shift;
+    const double* right_blk;
+    const int64_t* right_off;
+    int32_t n_terms;
+    const rot_sb_term* terms;
+} rot_sb_problem;
+typedef struct rot_sb_plan_s* rot_sb_plan;
+
+ROT_API rot_status rot_sb_layout(const rot_sb_problem* p, int32_t capacity, int32_t* n_blocks, int32_t* qn,
+                                 int32_t* rows, int32_t* cols, int64_t* offset, int64_t* total);
+ROT_API rot_status rot_sb_plan_create(const rot_sb_problem* p, rot_sb_plan* plan);
+ROT_API rot_status rot_sb_apply(rot_sb_plan plan, const double* psi, double* out, void* stream);
+ROT_API double rot_sb_plan_flops(rot_sb_plan plan);
+ROT_API rot_status rot_sb_plan_destroy(rot_sb_plan plan);
+
+/*
  * Sum of two-point expectation values over all pairs of rotated operators,
  * Eq. (11): L = sum_i sum_j <psi| X_i X_j |psi> = sum_ij (X_i^T psi).(X_j psi),
  * reduced in FP64 on the GPU whatever the storage type of X.

@@ -40,13 +40,13 @@ def matvec(terms, psi: np.ndarray, m: int, d: int, mR: int, dR: int | None = Non
     for coef, OB, Oa, Oat, OBt in terms:
         Y = X
         if OB is not None:
-            Y = np.einsum("ik,kstj->istj", OB, Y)
+            Y = np.einsum("ik,kstj->istj", OB, Y, optimize=True)
         if Oa is not None:
-            Y = np.einsum("sk,iktj->istj", Oa, Y)
+            Y = np.einsum("sk,iktj->istj", Oa, Y, optimize=True)
         if Oat is not None:
-            Y = np.einsum("tk,iskj->istj", Oat, Y)
+            Y = np.einsum("tk,iskj->istj", Oat, Y, optimize=True)
         if OBt is not None:
-            Y = np.einsum("jk,istk->istj", OBt, Y)
+            Y = np.einsum("jk,istk->istj", OBt, Y, optimize=True)
         out += coef * Y
     return out.reshape(m * d, dR * mR)
 

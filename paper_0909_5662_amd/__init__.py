@@ -34,6 +34,7 @@ __all__ = [
     "RotSiteProblem", "ROT_BLOCK_IDENTITY", "ROT_BLOCK_DIAGONAL", "ROT_BLOCK_DENSE", "rot_batch_site",
     "rot_site_workspace_size", "rotate_site", "expect_block", "expect_cross",
     "RotDmSector", "rot_density_basis", "density_workspace_size", "density_basis",
+    "RotSbTerm", "RotSbProblem", "SuperblockH",
 ]
 
 ROT_FP64, ROT_FP32, ROT_SPLIT_BF16 = 0, 1, 2
@@ -87,6 +88,23 @@ class RotDmSector(ctypes.Structure):
                 ("w", ctypes.c_void_p), ("V", ctypes.c_void_p), ("ld_v", ctypes.c_int64)]
 
 
+class RotSbTerm(ctypes.Structure):
+    _fields_ = [("coef", ctypes.c_double), ("left_op", ctypes.c_int32), ("right_op", ctypes.c_int32),
+                ("site_a", ctypes.POINTER(ctypes.c_double)), ("site_at", ctypes.POINTER(ctypes.c_double))]
+
+
+class RotSbProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("site_qn", ctypes.POINTER(ctypes.c_int32)),
+                ("n_left", ctypes.c_int32), ("left", ctypes.POINTER(RotSector)),
+                ("n_right", ctypes.c_int32), ("right", ctypes.POINTER(RotSector)),
+                ("target", ctypes.c_int32 * 2),
+                ("n_left_ops", ctypes.c_int32), ("left_shift", ctypes.POINTER(ctypes.c_int32)),
+                ("left_blk", ctypes.c_void_p), ("left_off", ctypes.POINTER(ctypes.c_int64)),
+                ("n_right_ops", ctypes.c_int32), ("right_shift", ctypes.POINTER(ctypes.c_int32)),
+                ("right_blk", ctypes.c_void_p), ("right_off", ctypes.POINTER(ctypes.c_int64)),
+                ("n_terms", ctypes.c_int32), ("terms", ctypes.POINTER(RotSbTerm))]
+
+
 _lib = None
 
 
@@ -125,6 +143,13 @@ def lib() -> ctypes.CDLL:
         L.rot_isometry_workspace_size.argtypes = [i32, i32, ctypes.c_int]
         L.rot_isometry_workspace_size.restype = sz
         L.rot_split_bf16.argtypes = [vp, i64, vp, vp, vp]
+        L.rot_sb_layout.argtypes = [ctypes.POINTER(RotSbProblem), i32, ctypes.POINTER(i32), vp, vp, vp, vp,
+                                    ctypes.POINTER(i64)]
+        L.rot_sb_plan_create.argtypes = [ctypes.POINTER(RotSbProblem), ctypes.POINTER(vp)]
+        L.rot_sb_apply.argtypes = [vp, vp, vp, vp]
+        L.rot_sb_plan_flops.argtypes = [vp]
+        L.rot_sb_plan_flops.restype = ctypes.c_double
+        L.rot_sb_plan_destroy.argtypes = [vp]
         L.rot_density_workspace_size.argtypes = [ctypes.POINTER(RotDmSector), i32]
         L.rot_density_workspace_size.restype = sz
         L.rot_density_basis.argtypes = [ctypes.POINTER(RotDmSector), i32, i64, vp, vp, vp, sz, vp]
@@ -406,6 +431,111 @@ def density_basis(psi_sectors, m_keep: int, workspace: torch.Tensor | None = Non
     rot_density_basis(secs, m_keep, kept.data_ptr(), eps.data_ptr(), workspace.data_ptr(), workspace.numel(),
                       _stream(stream))
     return w_out, v_out, kept, eps
+
+
+class SuperblockH:
+    """The superblock Hamiltonian of Eq. (9) over quantum-number blocks, as a
+    plan of librot (rot_sb_plan_create); apply(psi) = H psi in FP64.
+
+    site_qn: d (n_up, n_dn) pairs; left / right: lists of ((n_up, n_dn), dim)
+    sectors of B and B~; target: total numbers; left_ops / right_ops: lists of
+    (shift, {source sector index: dense block (q + shift <- q)}); terms: list
+    of (coef, left_op or -1, site_a or None, site_at or None, right_op or -1).
+    The layout of psi is self.blocks: (numbers, rows, cols, offset) per
+    system sector, self.total elements."""
+
+    def __init__(self, site_qn, left, right, target, left_ops, right_ops, terms, device="cuda",
+                 create_plan: bool = True):
+        import numpy as np
+        self._keep = []
+        d = len(site_qn)
+        qn = np.ascontiguousarray(site_qn, dtype=np.int32).reshape(-1)
+        self._keep.append(qn)
+
+        def sectors(lst):
+            arr = (RotSector * len(lst))(*[RotSector(q[0], q[1], dim, 0) for q, dim in lst])
+            self._keep.append(arr)
+            return arr
+
+        def ops(lst, n_sec):
+            shift = np.ascontiguousarray([sh for sh, _ in lst] or [(0, 0)], dtype=np.int32).reshape(-1)
+            off = np.full(max(len(lst) * n_sec, 1), -1, dtype=np.int64)
+            parts, pos = [], 0
+            for b, (_, blocks) in enumerate(lst):
+                for k, blk in sorted(blocks.items()):
+                    off[b * n_sec + k] = pos
+                    parts.append(np.ascontiguousarray(blk, dtype=np.float64).ravel())
+                    pos += parts[-1].size
+            data = torch.from_numpy(np.concatenate(parts) if parts else np.zeros(1)).to(device)
+            self._keep += [shift, off, data]
+            return shift, off, data
+
+        lsh, loff, ldata = ops(left_ops, len(left))
+        rsh, roff, rdata = ops(right_ops, len(right))
+        tarr = (RotSbTerm * max(len(terms), 1))()
+        for i, (coef, lo, sa, sat, ro) in enumerate(terms):
+            mats = []
+            for S in (sa, sat):
+                if S is None:
+                    mats.append(None)
+                else:
+                    a = np.ascontiguousarray(S, dtype=np.float64).reshape(d, d)
+                    self._keep.append(a)
+                    mats.append(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+            tarr[i] = RotSbTerm(coef, lo, ro, mats[0], mats[1])
+        self._keep.append(tarr)
+        P = RotSbProblem()
+        P.d = d
+        P.site_qn = qn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        P.n_left, P.left = len(left), sectors(left)
+        P.n_right, P.right = len(right), sectors(right)
+        P.target[0], P.target[1] = target
+        P.n_left_ops, P.left_shift = len(left_ops), lsh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        P.left_blk, P.left_off = ldata.data_ptr(), loff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        P.n_right_ops, P.right_shift = len(right_ops), rsh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        P.right_blk, P.right_off = rdata.data_ptr(), roff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        P.n_terms, P.terms = len(terms), tarr
+        self.problem = P
+        nb, total = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().rot_sb_layout(ctypes.byref(P), 0, ctypes.byref(nb), None, None, None, None, ctypes.byref(total)))
+        n = nb.value
+        bq = np.zeros(2 * max(n, 1), dtype=np.int32)
+        br = np.zeros(max(n, 1), dtype=np.int32)
+        bc = np.zeros(max(n, 1), dtype=np.int32)
+        bo = np.zeros(max(n, 1), dtype=np.int64)
+        _check(lib().rot_sb_layout(ctypes.byref(P), n, ctypes.byref(nb), bq.ctypes.data, br.ctypes.data,
+                                   bc.ctypes.data, bo.ctypes.data, ctypes.byref(total)))
+        self.blocks = [((int(bq[2 * k]), int(bq[2 * k + 1])), int(br[k]), int(bc[k]), int(bo[k])) for k in range(n)]
+        self.total = total.value
+        self.device = device
+        self._plan = None
+        if create_plan:
+            plan = ctypes.c_void_p()
+            _check(lib().rot_sb_plan_create(ctypes.byref(P), ctypes.byref(plan)))
+            self._plan = plan
+
+    @property
+    def flops(self) -> float:
+        return lib().rot_sb_plan_flops(self._plan)
+
+    def apply(self, psi: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if psi.dtype != torch.float64 or not psi.is_contiguous() or psi.numel() != self.total:
+            raise TypeError("psi must be a contiguous float64 tensor of the layout's length")
+        if out is None:
+            out = torch.empty_like(psi)
+        _check(lib().rot_sb_apply(self._plan, psi.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_plan", None):
+            lib().rot_sb_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def expect_cross(psi: torch.Tensor, Z: torch.Tensor, W: torch.Tensor, d: int, dR: int,

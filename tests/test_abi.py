@@ -279,3 +279,37 @@ def test_density_validation(rotlib):
     assert L.rot_density_basis(arr, 1, 4, None, 5 * FAKE, 6 * FAKE, 1 << 30, None) == -1
     assert L.rot_density_basis(arr, 1, 4, 4 * FAKE, 5 * FAKE, 6 * FAKE, 16, None) == -3
     assert L.rot_density_basis(arr, 1, 4, 4 * FAKE, 5 * FAKE, 6 * FAKE + 8, 1 << 30, None) == -1
+
+
+def test_superblock_layout_and_validation(rotlib):
+    import numpy as np
+
+    import workloads
+    case = workloads.superblock_hubbard(2, 2, (2, 1))
+    H = rotlib.SuperblockH(case.site_qn, case.left, case.right, case.target, case.left_ops, case.right_ops,
+                           case.terms, device="cpu", create_plan=False)
+    segs = workloads.superblock_segments(case)
+    assert H.blocks == [(b[0], b[1], b[2], b[3]) for b in segs]
+    assert H.total == segs[-1][3] + segs[-1][1] * segs[-1][2]
+    L = rotlib.lib()
+    import ctypes
+    nb, tot = ctypes.c_int32(), ctypes.c_int64()
+    P = H.problem
+    # a term with operators on both blocks is not supported
+    bad = (rotlib.RotSbTerm * 1)(rotlib.RotSbTerm(1.0, 0, 0, None, None))
+    keep = P.terms, P.n_terms
+    P.terms, P.n_terms = bad, 1
+    assert L.rot_sb_layout(ctypes.byref(P), 0, ctypes.byref(nb), None, None, None, None, ctypes.byref(tot)) == -2
+    # shifts that do not add to zero (c+ on B alone)
+    bad[0] = rotlib.RotSbTerm(1.0, 1, -1, None, None)
+    assert L.rot_sb_layout(ctypes.byref(P), 0, ctypes.byref(nb), None, None, None, None, ctypes.byref(tot)) == -1
+    # a site matrix mixing shifts
+    mix = np.eye(4)
+    mix[0, 1] = 1.0
+    bad[0] = rotlib.RotSbTerm(1.0, -1, -1, mix.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None)
+    assert L.rot_sb_layout(ctypes.byref(P), 0, ctypes.byref(nb), None, None, None, None, ctypes.byref(tot)) == -1
+    P.terms, P.n_terms = keep
+    P.d = 0
+    assert L.rot_sb_layout(ctypes.byref(P), 0, ctypes.byref(nb), None, None, None, None, ctypes.byref(tot)) == -1
+    P.d = 4
+    assert L.rot_sb_apply(None, None, None, None) == -1

@@ -388,3 +388,253 @@ def gaussian_sectors(dims, cfg: int = 7, repeat: dict | None = None) -> list[np.
         parts[k] = parts[src].copy()
     norm = math.sqrt(sum(float(np.sum(p * p)) for p in parts))
     return [p / norm for p in parts]
+
+
+# ---------------------------------------------------------------------------
+# Superblock Hamiltonian inputs (the four-factor terms of the Hubbard chain on
+# [B a a~ B~]), in the quantum-number block form of the matvec.
+# ---------------------------------------------------------------------------
+
+def _site_fermions():
+    """Site annihilators on |0>, |up>, |dn>, |up dn> = c+_up c+_dn |0> (the
+    down mode carries the sign of the up occupation) and the site parity."""
+    c_up = np.zeros((4, 4))
+    c_up[0, 1] = c_up[2, 3] = 1.0
+    c_dn = np.zeros((4, 4))
+    c_dn[0, 2] = 1.0
+    c_dn[1, 3] = -1.0
+    return c_up, c_dn, np.diag([1.0, -1.0, -1.0, 1.0])
+
+
+def hubbard_block_dense(L: int, t: float = 1.0, U: float = 8.0):
+    """Exact operators of an L-site Hubbard block in the product basis (site 0
+    slowest): H (hopping between neighbours and U n_up n_dn on every site),
+    the annihilators c[(site, spin)] with the string of parities over earlier
+    sites, the block parity, and the (n_up, n_dn) of every basis state."""
+    c_up, c_dn, Ps = _site_fermions()
+    I4 = np.eye(4)
+
+    def site_op(i, op):
+        out = np.ones((1, 1))
+        for j in range(L):
+            out = np.kron(out, Ps if j < i else (op if j == i else I4))
+        return out
+
+    cs = {}
+    for i in range(L):
+        cs[(i, 0)] = site_op(i, c_up)
+        cs[(i, 1)] = site_op(i, c_dn)
+    n = 4 ** L
+    H = np.zeros((n, n))
+    for i in range(L):
+        H += U * (cs[(i, 0)].T @ cs[(i, 0)]) @ (cs[(i, 1)].T @ cs[(i, 1)])
+        if i + 1 < L:
+            for sp in (0, 1):
+                hop = cs[(i, sp)].T @ cs[(i + 1, sp)]
+                H -= t * (hop + hop.T)
+    P = np.ones((1, 1))
+    for _ in range(L):
+        P = np.kron(P, Ps)
+    digits = np.array([[(x // 4 ** (L - 1 - j)) % 4 for j in range(L)] for x in range(n)])
+    qn = np.stack([(digits & 1).sum(1), (digits >> 1).sum(1)], 1)
+    return H, cs, P, qn
+
+
+def sector_form(qn_states: np.ndarray):
+    """Sectors of a basis with numbers qn_states: [((n_up, n_dn), dim)] sorted
+    by numbers and the basis indices of each sector."""
+    keys = sorted({(int(a), int(b)) for a, b in qn_states})
+    idx = [np.nonzero((qn_states[:, 0] == k[0]) & (qn_states[:, 1] == k[1]))[0] for k in keys]
+    return [(k, len(i)) for k, i in zip(keys, idx)], idx
+
+
+def operator_blocks(O: np.ndarray, sectors, idx):
+    """(shift, {source sector: block (q + shift <- q)}) of a dense operator
+    whose non-zero entries all change the numbers by one shift."""
+    qn_of = np.zeros((O.shape[0], 2), dtype=np.int64)
+    for (q, _), ii in zip(sectors, idx):
+        qn_of[ii] = q
+    nz = np.argwhere(O != 0.0)
+    shifts = {tuple(qn_of[a] - qn_of[b]) for a, b in nz}
+    if len(shifts) > 1:
+        raise ValueError("operator mixes shifts")
+    shift = shifts.pop() if shifts else (0, 0)
+    by_qn = {q: k for k, (q, _) in enumerate(sectors)}
+    blocks = {}
+    for k, (q, _) in enumerate(sectors):
+        tgt = by_qn.get((q[0] + shift[0], q[1] + shift[1]))
+        if tgt is None:
+            continue
+        blk = O[np.ix_(idx[tgt], idx[k])]
+        if np.any(blk != 0.0):
+            blocks[k] = blk
+    return (int(shift[0]), int(shift[1])), blocks
+
+
+@dataclasses.dataclass
+class SuperblockCase:
+    site_qn: list
+    left: list
+    right: list
+    left_idx: list      # basis indices (dense order) of each sector of B
+    right_idx: list
+    m: int
+    mR: int
+    target: tuple
+    left_ops: list      # (shift, {k: block})
+    right_ops: list
+    terms: list         # (coef, left_op, site_a, site_at, right_op)
+
+
+def _hubbard_terms_blocked(t, U, n_left_ops_base=0):
+    c_up, c_dn, Ps = _site_fermions()
+    h_site = U * np.diag([0.0, 0.0, 0.0, 1.0])
+    terms = [(1.0, 0, None, None, -1), (1.0, -1, None, None, 0),
+             (1.0, -1, h_site, None, -1), (1.0, -1, None, h_site, -1)]
+    for sp, c in ((0, c_up), (1, c_dn)):
+        lc, lcd = 1 + 2 * sp, 2 + 2 * sp   # left ops: c+_edge P_B, P_B c_edge
+        rc, rcd = 1 + 2 * sp, 2 + 2 * sp   # right ops: c_edge, c+_edge
+        terms += [(-t, lc, c, None, -1), (-t, lcd, c.T, None, -1),
+                  (-t, -1, c.T @ Ps, c, -1), (-t, -1, Ps @ c, c.T, -1),
+                  (-t, -1, None, c.T @ Ps, rc), (-t, -1, None, Ps @ c, rcd)]
+    return terms
+
+
+def superblock_hubbard(LB: int, LBt: int, target, t: float = 1.0, U: float = 8.0) -> SuperblockCase:
+    """The Hubbard chain of Eq. (4) on [B a a~ B~] with exact blocks of LB and
+    LBt sites.  Left operators: H_B, c+_{edge,up} P_B, P_B c_{edge,up}, the
+    same for down (edge = last site); right operators: H_B~, c_{edge,up},
+    c+_{edge,up}, down likewise (edge = first site)."""
+    HB, cB, PB, qB = hubbard_block_dense(LB, t, U)
+    HR, cR, _, qR = hubbard_block_dense(LBt, t, U)
+    lsec, lidx = sector_form(qB)
+    rsec, ridx = sector_form(qR)
+    eL, eR = LB - 1, 0
+    left_dense = [HB, cB[(eL, 0)].T @ PB, PB @ cB[(eL, 0)], cB[(eL, 1)].T @ PB, PB @ cB[(eL, 1)]]
+    right_dense = [HR, cR[(eR, 0)], cR[(eR, 0)].T, cR[(eR, 1)], cR[(eR, 1)].T]
+    return SuperblockCase(list(HUBBARD_SITE_QN), lsec, rsec, lidx, ridx, 4 ** LB, 4 ** LBt, tuple(target),
+                          [operator_blocks(O, lsec, lidx) for O in left_dense],
+                          [operator_blocks(O, rsec, ridx) for O in right_dense],
+                          _hubbard_terms_blocked(t, U))
+
+
+def superblock_random(total: int = 256, cfg: int = 8, target=None, t: float = 1.0, U: float = 8.0) -> SuperblockCase:
+    """Blocks B and B~ of `total` states in the Gaussian sector grid; random
+    operators with the quantum-number structure of the Hubbard terms: a
+    symmetric number-conserving H_B, and shifting operators X_up, X_dn (shift
+    +1) with their transposes, scaled by 1/sqrt(dim); site matrices and terms
+    as for the chain.  target defaults to the numbers that give the largest
+    state."""
+    sizes = gaussian_sector_sizes(total)
+    secs = [(q, n) for q, n in sizes]
+    g = rng(cfg, 1)
+    by_qn = {q: k for k, (q, _) in enumerate(secs)}
+    scale = 1.0 / math.sqrt(total)
+
+    def ops():
+        H = {}
+        for k, (q, n) in enumerate(secs):
+            a = g.standard_normal((n, n))
+            H[k] = 0.5 * (a + a.T) * scale
+        out = [((0, 0), H)]
+        for sh in ((1, 0), (0, 1)):
+            X, Xt = {}, {}
+            for k, (q, n) in enumerate(secs):
+                tk = by_qn.get((q[0] + sh[0], q[1] + sh[1]))
+                if tk is None:
+                    continue
+                blk = g.standard_normal((secs[tk][1], n)) * scale
+                X[k] = blk
+                Xt[tk] = blk.T.copy()
+            out += [(sh, X), ((-sh[0], -sh[1]), Xt)]
+        return out
+
+    left_ops, right_ops = ops(), ops()
+    # right operators in the chain's order: H, c-like (shift -1), c+-like (shift +1)
+    right_ops = [right_ops[0], right_ops[2], right_ops[1], right_ops[4], right_ops[3]]
+    idx = [np.arange(sum(n for _, n in secs[:k]), sum(n for _, n in secs[:k + 1])) for k in range(len(secs))]
+    if target is None:
+        enl = enlarged_sector_sizes(sizes)
+        best = None
+        for q in enl:
+            for p in enl:
+                tq = (q[0] + p[0], q[1] + p[1])
+                dim = sum(n * enl.get((tq[0] - a[0], tq[1] - a[1]), 0) for a, n in enl.items())
+                if best is None or dim > best[0]:
+                    best = (dim, tq)
+        target = best[1]
+    return SuperblockCase(list(HUBBARD_SITE_QN), secs, secs, idx, idx, total, total, tuple(target),
+                          left_ops, right_ops, _hubbard_terms_blocked(t, U))
+
+
+def superblock_segments(case: SuperblockCase):
+    """The blocks of psi for the case: [(Q, rows, cols, offset, row_segs,
+    col_segs)] with segments (site state, sector index, start, dim), by the
+    rule of the matvec's layout (system basis: site state slow, B state
+    fast; environment: site state slow, B~ state fast)."""
+    def enlarge(secs):
+        by_qn = {q: k for k, (q, _) in enumerate(secs)}
+        Qs = sorted({(q[0] + s[0], q[1] + s[1]) for q, _ in secs for s in case.site_qn})
+        out = {}
+        for Q in Qs:
+            segs, start = [], 0
+            for si, s in enumerate(case.site_qn):
+                k = by_qn.get((Q[0] - s[0], Q[1] - s[1]))
+                if k is None:
+                    continue
+                segs.append((si, k, start, secs[k][1]))
+                start += secs[k][1]
+            out[Q] = (start, segs)
+        return out
+
+    sys_, env = enlarge(case.left), enlarge(case.right)
+    blocks, off = [], 0
+    for Q in sorted(sys_):
+        P = (case.target[0] - Q[0], case.target[1] - Q[1])
+        if P not in env:
+            continue
+        rows, rsegs = sys_[Q]
+        cols, csegs = env[P]
+        blocks.append((Q, rows, cols, off, rsegs, csegs))
+        off += rows * cols
+    return blocks
+
+
+def superblock_to_dense(case: SuperblockCase, flat: np.ndarray) -> np.ndarray:
+    """The packed state as the dense (m d) x (d mR) matrix of the Kronecker
+    order (row i d + s, column t mR + j; i, j the dense block indices)."""
+    d = len(case.site_qn)
+    D = np.zeros((case.m * d, d * case.mR))
+    for Q, rows, cols, off, rsegs, csegs in superblock_segments(case):
+        blk = flat[off:off + rows * cols].reshape(rows, cols)
+        r_idx = np.concatenate([case.left_idx[k] * d + s for s, k, _, _ in rsegs])
+        c_idx = np.concatenate([t * case.mR + case.right_idx[k] for t, k, _, _ in csegs])
+        D[np.ix_(r_idx, c_idx)] = blk
+    return D
+
+
+def superblock_from_dense(case: SuperblockCase, D: np.ndarray) -> np.ndarray:
+    d = len(case.site_qn)
+    parts = []
+    for Q, rows, cols, off, rsegs, csegs in superblock_segments(case):
+        r_idx = np.concatenate([case.left_idx[k] * d + s for s, k, _, _ in rsegs])
+        c_idx = np.concatenate([t * case.mR + case.right_idx[k] for t, k, _, _ in csegs])
+        parts.append(D[np.ix_(r_idx, c_idx)].ravel())
+    return np.concatenate(parts)
+
+
+def superblock_dense_ops(case: SuperblockCase):
+    """Dense matrices of the case's block operators in the dense block basis."""
+    def dense(ops, secs, idx, n):
+        out = []
+        for sh, blocks in ops:
+            by_qn = {q: k for k, (q, _) in enumerate(secs)}
+            O = np.zeros((n, n))
+            for k, blk in blocks.items():
+                q = secs[k][0]
+                tk = by_qn[(q[0] + sh[0], q[1] + sh[1])]
+                O[np.ix_(idx[tk], idx[k])] = blk
+            out.append(O)
+        return out
+    return dense(case.left_ops, case.left, case.left_idx, case.m), dense(case.right_ops, case.right, case.right_idx,
+                                                                          case.mR)
