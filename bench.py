@@ -37,7 +37,7 @@ def parse():
                     help="skip timing the plain FP64 GPU rotation (speedup denominator)")
     ap.add_argument("--workload", default=WORKLOAD,
                     choices=[WORKLOAD, "blocked_1024_n400", "uneven_1000", "differentiated_m1024_n64",
-                             "site_m1024_n64", "measure_m1024", "density_m1024"],
+                             "site_m1024_n64", "measure_m1024", "density_m1024", "superblock_m1024"],
                     help="default: the headline dense workload; the others time the quantum-number "
                          "blocked batch or the uneven sweep plan")
     ap.add_argument("--symmetric", action="store_true",
@@ -485,6 +485,90 @@ def bench_density(args, rot, torch, workloads):
     return rec
 
 
+def bench_superblock(args, rot, torch, workloads):
+    """Superblock Hamiltonian times a state (FP64): blocks B and B~ of 1024
+    states in the Gaussian sector grid (45 sectors each), Hubbard-structured
+    terms (block Hamiltonians, four shifting block operators per side paired
+    with the site fermions, site-site hopping and interaction), the state in
+    the 60 system sectors of total numbers (25, 25).  Each step is one
+    rot_sb_apply."""
+    import time
+
+    import numpy as np
+    case = workloads.superblock_random(1024, cfg=8)
+    H = rot.SuperblockH(case.site_qn, case.left, case.right, case.target, case.left_ops, case.right_ops,
+                        case.terms)
+    psi = torch.from_numpy(np.random.default_rng(96).standard_normal(H.total)).cuda()
+    out = torch.empty_like(psi)
+    ms = timed_loop(torch, lambda: H.apply(psi, out), args.steps, args.warmup)
+    # the same products replayed from a captured graph: device time without host gaps
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    reps = 10
+    with torch.cuda.stream(stream):
+        H.apply(psi, out)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=stream):
+            for _ in range(reps):
+                H.apply(psi, out)
+    torch.cuda.current_stream().wait_stream(stream)
+    ms_graph = timed_loop(torch, graph.replay, max(2, args.steps // 2), 1) / reps
+    rot.profile_enable(True)
+    for _ in range(5):
+        H.apply(psi, out)
+    torch.cuda.synchronize()
+    kernels = rot.profile_read()
+    rot.profile_enable(False)
+    cnt, tot = kernels["sb_matvec"]
+    avg_ms = tot / cnt
+    tflops = H.flops / (avg_ms / 1e3) / 1e12
+    # dense reference on the GPU: the same terms on the dense Kronecker layout, torch FP64
+    L, R = workloads.superblock_dense_ops(case)
+    Ld = [torch.from_numpy(x).cuda() for x in L]
+    Rd = [torch.from_numpy(x).cuda() for x in R]
+    D = torch.from_numpy(workloads.superblock_to_dense(case, psi.cpu().numpy())).cuda().reshape(1024, 4, 4, 1024)
+
+    def dense_step():
+        acc = torch.zeros_like(D)
+        for coef, lo, sa, sat, ro in case.terms:
+            Y = D
+            if lo >= 0:
+                Y = torch.tensordot(Ld[lo], Y, dims=([1], [0]))
+            if sa is not None:
+                Y = torch.einsum("sk,iktj->istj", torch.from_numpy(np.asarray(sa)).cuda(), Y)
+            if sat is not None:
+                Y = torch.einsum("tk,iskj->istj", torch.from_numpy(np.asarray(sat)).cuda(), Y)
+            if ro >= 0:
+                Y = torch.tensordot(Y, Rd[ro], dims=([3], [1]))
+            acc += coef * Y
+        return acc
+
+    ms_dense = timed_loop(torch, dense_step, 3, 1)
+    t0 = time.perf_counter()
+    from oracle import superblock as osb
+    terms = [(coef, L[lo] if lo >= 0 else None, sa, sat, R[ro] if ro >= 0 else None)
+             for coef, lo, sa, sat, ro in case.terms]
+    osb.matvec(terms, D.reshape(4096, 4096).cpu().numpy(), 1024, 4, 1024)
+    ms_cpu = (time.perf_counter() - t0) * 1e3
+    rec = base_record(args, 1e3 / ms, "superblock products H psi per second", ms,
+                      {"workload": "superblock_m1024", "m": 1024, "mR": 1024, "d": 4, "target": list(case.target),
+                       "system_sectors": len(H.blocks), "state_length": H.total, "terms": len(case.terms)},
+                      dtype="f64")
+    rec.update({"flops_per_product": H.flops, "tflops_fp64": round(tflops, 2),
+                "graph_replay_ms_per_product": round(ms_graph, 4),
+                "kernels_ms_avg": {"sb_matvec": round(avg_ms, 4)},
+                "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": 78.6, "unit": "TFLOP/s",
+                             "frac": round(tflops / 78.6, 4), "traffic": None, "kernel": "sb_tile_kernel",
+                             "avg_ms": round(avg_ms, 4)},
+                "torch_dense_fp64_ms": round(ms_dense, 3), "speedup_vs_torch_dense": round(ms_dense / ms, 2),
+                "cpu_baseline": {"value": round(1e3 / ms_cpu, 4), "unit": "superblock products H psi per second",
+                                 "cores": os.cpu_count(), "kind": "oracle",
+                                 "sample": "one product on the dense Kronecker layout (numpy, BLAS contractions)"}})
+    H.close()
+    return rec
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -566,7 +650,8 @@ def main():
     if args.workload != WORKLOAD:
         fn = {"blocked_1024_n400": bench_blocked, "uneven_1000": bench_uneven,
               "differentiated_m1024_n64": bench_differentiated, "site_m1024_n64": bench_site,
-              "measure_m1024": bench_measure, "density_m1024": bench_density}[args.workload]
+              "measure_m1024": bench_measure, "density_m1024": bench_density,
+              "superblock_m1024": bench_superblock}[args.workload]
         print(json.dumps(fn(args, rot, torch, workloads)), flush=True)
         return
 

@@ -32,7 +32,6 @@ namespace rot {
 namespace {
 
 constexpr int kSbTile = 32;
-constexpr int kSbK = 16;
 constexpr int kSbMaxSite = 16;
 
 enum : int { kFromLeft = 0, kFromRight = 1, kCopy = 2 };
@@ -50,71 +49,123 @@ struct SbTile {
     int c_begin, c_end;
 };
 
-// C (rows x cols, 32 x 32 at most) = sum of the tile's contributions; thread
-// (tx, ty) of 16 x 16 holds the 2 x 2 outputs at rows 2 ty, cols 2 tx.
+// C (rows x cols, 32 x 32 at most) = sum of the tile's contributions.  Wave w
+// owns the 16 x 16 quarter (w / 2, w % 2) and multiplies with
+// v_mfma_f64_16x16x4f64 (lane l supplies A(row l%16, k l/16) and B(k l/16,
+// col l%16); accumulator element v is C(4v + l/16, l%16)).  The contributions
+// are walked as one sequence of steps (a 32-wide K slice of a product, or a
+// scaled copy); the operands of the next step are loaded into registers while
+// the current one is multiplied from LDS (two LDS buffers, one barrier per
+// product step), and the step descriptors are read from LDS.
+constexpr int kSbKs = 32;
+constexpr int kSbMaxC = 128;  // contribution descriptors held in LDS at a time
+
+typedef double sb_f64x4 __attribute__((ext_vector_type(4)));
+
+struct SbStep {
+    int ci, k0;
+};
+
+__device__ inline void sb_load(const SbContrib& c, int k0, const SbTile& tl, const double* left_blk,
+                               const double* right_blk, const double* psi, int tid, int wr, int wc, int h, int cl,
+                               double (&av)[4], double (&bv)[4], double (&cv)[4]) {
+    if (c.kind == kCopy) {
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int r = wr * 16 + 4 * v + h, col = wc * 16 + cl;
+            cv[v] = (r < tl.rows && col < tl.cols) ? c.alpha * psi[c.a_off + r * c.lda + col] : 0.0;
+        }
+        return;
+    }
+    const double* A = c.kind == kFromLeft ? left_blk + c.a_off : psi + c.a_off;
+    const double* B = c.kind == kFromLeft ? psi + c.b_off : right_blk + c.b_off;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int e = tid + 256 * j;
+        const int r = e >> 5, k = e & 31;  // A: row r, slice column k
+        av[j] = (r < tl.rows && k0 + k < c.K) ? c.alpha * A[r * c.lda + k0 + k] : 0.0;
+        if (c.kind == kFromLeft) {
+            const int kb = e >> 5, cb = e & 31;  // B: slice row kb, tile column cb
+            bv[j] = (cb < tl.cols && k0 + kb < c.K) ? B[(int64_t)(k0 + kb) * c.ldb + cb] : 0.0;
+        } else {
+            const int cb = e >> 5, kb = e & 31;  // B^T stored: tile column cb, slice row kb
+            bv[j] = (cb < tl.cols && k0 + kb < c.K) ? B[(int64_t)cb * c.ldb + k0 + kb] : 0.0;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void sb_tile_kernel(const SbTile* __restrict__ tiles,
                                                       const SbContrib* __restrict__ contribs,
                                                       const double* __restrict__ left_blk,
                                                       const double* __restrict__ right_blk,
                                                       const double* __restrict__ psi, double* __restrict__ out) {
     const SbTile tl = tiles[blockIdx.x];
-    __shared__ double As[kSbK][kSbTile + 1];
-    __shared__ double Bs[kSbK][kSbTile + 1];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int ci = tl.c_begin; ci < tl.c_end; ci++) {
-        const SbContrib c = contribs[ci];
-        if (c.kind == kCopy) {
+    __shared__ double As[2][kSbKs][kSbTile + 1];  // [buf][k][row]
+    __shared__ double Bs[2][kSbKs][kSbTile + 1];  // [buf][k][col]
+    __shared__ SbContrib cd[kSbMaxC];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1, h = lane >> 4, cl = lane & 15;
+    sb_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    double av[4], bv[4], cv[4];
+    int buf = 0;
+    for (int cb = tl.c_begin; cb < tl.c_end; cb += kSbMaxC) {
+        const int ce = min(cb + kSbMaxC, tl.c_end);
+        __syncthreads();  // the previous chunk's descriptors are no longer read
+        for (int i = tid; i < ce - cb; i += 256) cd[i] = contribs[cb + i];
+        __syncthreads();
+        SbStep st{cb, 0};
+        SbContrib c = cd[0];
+        sb_load(c, 0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, av, bv, cv);
+        while (true) {
+            const bool copy = c.kind == kCopy;
+            const bool from_right = c.kind == kFromRight;
+            if (!copy) {
 #pragma unroll
-            for (int p = 0; p < 2; p++)
-#pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    const int r = 2 * ty + p, col = 2 * tx + q;
-                    if (r < tl.rows && col < tl.cols) acc[p][q] = fma(c.alpha, psi[c.a_off + r * c.lda + col], acc[p][q]);
+                for (int j = 0; j < 4; j++) {
+                    const int e = tid + 256 * j;
+                    As[buf][e & 31][e >> 5] = av[j];
+                    if (from_right) Bs[buf][e & 31][e >> 5] = bv[j];
+                    else Bs[buf][e >> 5][e & 31] = bv[j];
                 }
-            continue;
-        }
-        const double* A = c.kind == kFromLeft ? left_blk + c.a_off : psi + c.a_off;
-        const double* B = c.kind == kFromLeft ? psi + c.b_off : right_blk + c.b_off;
-        for (int k0 = 0; k0 < c.K; k0 += kSbK) {
-            // A: rows of the tile x 16 k (scaled by alpha); B: 16 k x columns of the tile
-            double av[2], bv[2];
+                __syncthreads();
+            } else {
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
-                const int e = tid + 256 * j, r = e >> 4, k = e & 15;
-                av[j] = (r < tl.rows && k0 + k < c.K) ? c.alpha * A[r * c.lda + k0 + k] : 0.0;
-                const int kb = e >> 5, cb = e & 31;
-                double bval = 0.0;
-                if (cb < tl.cols && k0 + kb < c.K)
-                    bval = c.kind == kFromLeft ? B[(int64_t)(k0 + kb) * c.ldb + cb] : B[(int64_t)cb * c.ldb + k0 + kb];
-                bv[j] = bval;
+                for (int v = 0; v < 4; v++) acc[v] += cv[v];
             }
-#pragma unroll
-            for (int j = 0; j < 2; j++) {
-                const int e = tid + 256 * j;
-                As[e & 15][e >> 4] = av[j];
-                Bs[e >> 5][e & 31] = bv[j];
+            // next step, its operands in flight during this step's products
+            SbStep nx = st;
+            if (copy || st.k0 + kSbKs >= c.K) {
+                nx.ci++;
+                nx.k0 = 0;
+            } else {
+                nx.k0 += kSbKs;
             }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kSbK; k++) {
-                const double a0 = As[k][2 * ty], a1 = As[k][2 * ty + 1];
-                const double b0 = Bs[k][2 * tx], b1 = Bs[k][2 * tx + 1];
-                acc[0][0] = fma(a0, b0, acc[0][0]);
-                acc[0][1] = fma(a0, b1, acc[0][1]);
-                acc[1][0] = fma(a1, b0, acc[1][0]);
-                acc[1][1] = fma(a1, b1, acc[1][1]);
+            const bool more = nx.ci < ce;
+            SbContrib cn = c;
+            if (more) {
+                if (nx.ci != st.ci) cn = cd[nx.ci - cb];
+                sb_load(cn, nx.k0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, av, bv, cv);
             }
-            __syncthreads();
+            if (!copy) {
+                // slices past K hold zeros, so whole groups of 4 may overrun it
+                const int kq = (min(kSbKs, c.K - st.k0) + 3) >> 2;
+                for (int q = 0; q < kq; q++) {
+                    const double a = As[buf][4 * q + h][wr * 16 + cl];
+                    const double b = Bs[buf][4 * q + h][wc * 16 + cl];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+                buf ^= 1;
+            }
+            if (!more) break;
+            st = nx;
+            c = cn;
         }
     }
 #pragma unroll
-    for (int p = 0; p < 2; p++)
-#pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const int r = 2 * ty + p, col = 2 * tx + q;
-            if (r < tl.rows && col < tl.cols) out[tl.out_off + r * tl.ldo + col] = acc[p][q];
-        }
+    for (int v = 0; v < 4; v++) {
+        const int r = wr * 16 + 4 * v + h, col = wc * 16 + cl;
+        if (r < tl.rows && col < tl.cols) out[tl.out_off + r * tl.ldo + col] = acc[v];
+    }
 }
 
 rot_status sberr(rot_status s, const char* fmt, ...) {
