@@ -350,9 +350,18 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc
         if (t + 1 < nk) {
             wait_stage(t + 1, S - 3);
             if (t + S - 1 < nk) issue(t + S - 1);
-            read(nxt, t + 1);
         }
+        // the next slab's fragments (on the last step a finished stage is
+        // read and not used), interleaved with this slab's products so the
+        // waves' LDS reads spread over the matrix work instead of arriving
+        // together after the barrier
+        read(nxt, t + 1);
         multiply(cur);
+#pragma unroll
+        for (int i = 0; i < 2 * (BI + BJ); i++) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, (3 * BI * BJ) / (2 * (BI + BJ)), 0);  // matrix instructions
+        }
         compiler_fence();
     };
     for (int t = 0; t < nk; t += 2) {
