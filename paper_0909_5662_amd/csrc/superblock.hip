@@ -54,9 +54,9 @@ struct SbTile {
 // v_mfma_f64_16x16x4f64 (lane l supplies A(row l%16, k l/16) and B(k l/16,
 // col l%16); accumulator element v is C(4v + l/16, l%16)).  The contributions
 // are walked as one sequence of steps (a 32-wide K slice of a product, or a
-// scaled copy); the operands of the next step are loaded into registers while
-// the current one is multiplied from LDS (two LDS buffers, one barrier per
-// product step), and the step descriptors are read from LDS.
+// scaled copy); the operands of the steps one and two ahead are loaded into two
+// register sets while the current one is multiplied from LDS (two LDS buffers,
+// one barrier per product step), and the step descriptors are read from LDS.
 constexpr int kSbKs = 32;
 constexpr int kSbMaxC = 128;  // contribution descriptors held in LDS at a time
 
@@ -66,32 +66,69 @@ struct SbStep {
     int ci, k0;
 };
 
-__device__ inline void sb_load(const SbContrib& c, int k0, const SbTile& tl, const double* left_blk,
-                               const double* right_blk, const double* psi, int tid, int wr, int wc, int h, int cl,
-                               double (&av)[4], double (&bv)[4], double (&cv)[4]) {
+// Operands of step (c, k0) into registers: for a product, this thread's four
+// elements of the A slice (tile row r, slice column k, scaled by alpha) and of
+// the B slice; for a copy, alpha times the psi entries of this lane's four
+// accumulator rows (in av).
+__device__ __attribute__((always_inline)) inline void sb_load(const SbContrib& c, int k0, const SbTile& tl,
+                                                              const double* left_blk, const double* right_blk,
+                                                              const double* psi, int tid, int wr, int wc, int h,
+                                                              int cl, sb_f64x4& av, sb_f64x4& bv) {
     if (c.kind == kCopy) {
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const int r = wr * 16 + 4 * v + h, col = wc * 16 + cl;
-            cv[v] = (r < tl.rows && col < tl.cols) ? c.alpha * psi[c.a_off + r * c.lda + col] : 0.0;
-        }
+        const int col = wc * 16 + cl, r0 = wr * 16 + h;
+        const bool cin = col < tl.cols;
+        const double* src = psi + c.a_off + col;
+        av.x = (cin && r0 < tl.rows) ? c.alpha * src[(int64_t)r0 * c.lda] : 0.0;
+        av.y = (cin && r0 + 4 < tl.rows) ? c.alpha * src[(int64_t)(r0 + 4) * c.lda] : 0.0;
+        av.z = (cin && r0 + 8 < tl.rows) ? c.alpha * src[(int64_t)(r0 + 8) * c.lda] : 0.0;
+        av.w = (cin && r0 + 12 < tl.rows) ? c.alpha * src[(int64_t)(r0 + 12) * c.lda] : 0.0;
         return;
     }
     const double* A = c.kind == kFromLeft ? left_blk + c.a_off : psi + c.a_off;
     const double* B = c.kind == kFromLeft ? psi + c.b_off : right_blk + c.b_off;
+    const bool left = c.kind == kFromLeft;
+    // element j of this thread: e = tid + 256 j, A row e >> 5 (col e & 31);
+    // B: left, slice row e >> 5 and tile column e & 31; right (B^T stored),
+    // tile column e >> 5 and slice row e & 31
+    const int hi = tid >> 5, lo = tid & 31;
+    double a[4], b[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-        const int e = tid + 256 * j;
-        const int r = e >> 5, k = e & 31;  // A: row r, slice column k
-        av[j] = (r < tl.rows && k0 + k < c.K) ? c.alpha * A[r * c.lda + k0 + k] : 0.0;
-        if (c.kind == kFromLeft) {
-            const int kb = e >> 5, cb = e & 31;  // B: slice row kb, tile column cb
-            bv[j] = (cb < tl.cols && k0 + kb < c.K) ? B[(int64_t)(k0 + kb) * c.ldb + cb] : 0.0;
-        } else {
-            const int cb = e >> 5, kb = e & 31;  // B^T stored: tile column cb, slice row kb
-            bv[j] = (cb < tl.cols && k0 + kb < c.K) ? B[(int64_t)cb * c.ldb + k0 + kb] : 0.0;
-        }
+        const int r = hi + 8 * j;
+        a[j] = (r < tl.rows && k0 + lo < c.K) ? c.alpha * A[(int64_t)r * c.lda + k0 + lo] : 0.0;
+        b[j] = left ? ((lo < tl.cols && k0 + r < c.K) ? B[(int64_t)(k0 + r) * c.ldb + lo] : 0.0)
+                    : ((r < tl.cols && k0 + lo < c.K) ? B[(int64_t)r * c.ldb + k0 + lo] : 0.0);
     }
+    av = sb_f64x4{a[0], a[1], a[2], a[3]};
+    bv = sb_f64x4{b[0], b[1], b[2], b[3]};
+}
+
+__device__ __attribute__((always_inline)) inline void sb_stage(double (*As)[kSbTile + 1], double (*Bs)[kSbTile + 1],
+                                                              const sb_f64x4& av, const sb_f64x4& bv, int tid,
+                                                              bool from_right) {
+    const int hi = tid >> 5, lo = tid & 31;
+    As[lo][hi] = av.x;
+    As[lo][hi + 8] = av.y;
+    As[lo][hi + 16] = av.z;
+    As[lo][hi + 24] = av.w;
+    if (from_right) {
+        Bs[lo][hi] = bv.x;
+        Bs[lo][hi + 8] = bv.y;
+        Bs[lo][hi + 16] = bv.z;
+        Bs[lo][hi + 24] = bv.w;
+    } else {
+        Bs[hi][lo] = bv.x;
+        Bs[hi + 8][lo] = bv.y;
+        Bs[hi + 16][lo] = bv.z;
+        Bs[hi + 24][lo] = bv.w;
+    }
+}
+
+// position after step x of the chunk [.., ce) whose descriptors start at cd[0] (index cb)
+__device__ __attribute__((always_inline)) inline SbStep sb_next(const SbContrib* cd, int cb, int ce, SbStep x) {
+    if (x.ci >= ce) return x;
+    const SbContrib& c = cd[x.ci - cb];
+    return (c.kind == kCopy || x.k0 + kSbKs >= c.K) ? SbStep{x.ci + 1, 0} : SbStep{x.ci, x.k0 + kSbKs};
 }
 
 __global__ __launch_bounds__(256) void sb_tile_kernel(const SbTile* __restrict__ tiles,
@@ -106,61 +143,55 @@ __global__ __launch_bounds__(256) void sb_tile_kernel(const SbTile* __restrict__
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1, h = lane >> 4, cl = lane & 15;
     sb_f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-    double av[4], bv[4], cv[4];
+    sb_f64x4 a0, b0, a1, b1;
     int buf = 0;
+// one step from register set (A, B); the set is then refilled with step REFILL
+#define SB_RUN(A, B, X, REFILL)                                                                            \
+    do {                                                                                                      \
+        const SbContrib& c_ = cd[(X).ci - cb];                                                                \
+        if (c_.kind == kCopy) {                                                                               \
+            acc += A;                                                                                         \
+            if ((REFILL).ci < ce)                                                                             \
+                sb_load(cd[(REFILL).ci - cb], (REFILL).k0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, A, \
+                        B);                                                                                \
+        } else {                                                                                              \
+            const bool from_right = c_.kind == kFromRight;                                                    \
+            sb_stage(As[buf], Bs[buf], A, B, tid, from_right);                                                \
+            __syncthreads();                                                                                  \
+            const int kq = (min(kSbKs, c_.K - (X).k0) + 3) >> 2;                                              \
+            if ((REFILL).ci < ce)                                                                             \
+                sb_load(cd[(REFILL).ci - cb], (REFILL).k0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, A, \
+                        B);                                                                                \
+            for (int q = 0; q < kq; q++) {                                                                    \
+                const double a_ = As[buf][4 * q + h][wr * 16 + cl];                                           \
+                const double b_ = Bs[buf][4 * q + h][wc * 16 + cl];                                           \
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a_, b_, acc, 0, 0, 0);                             \
+            }                                                                                                 \
+            buf ^= 1;                                                                                         \
+        }                                                                                                     \
+    } while (0)
     for (int cb = tl.c_begin; cb < tl.c_end; cb += kSbMaxC) {
         const int ce = min(cb + kSbMaxC, tl.c_end);
         __syncthreads();  // the previous chunk's descriptors are no longer read
         for (int i = tid; i < ce - cb; i += 256) cd[i] = contribs[cb + i];
         __syncthreads();
-        SbStep st{cb, 0};
-        SbContrib c = cd[0];
-        sb_load(c, 0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, av, bv, cv);
+        SbStep cur{cb, 0};
+        SbStep s1 = sb_next(cd, cb, ce, cur);
+        sb_load(cd[0], 0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, a0, b0);
+        if (s1.ci < ce) sb_load(cd[s1.ci - cb], s1.k0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, a1, b1);
+        SbStep ld = sb_next(cd, cb, ce, s1);
         while (true) {
-            const bool copy = c.kind == kCopy;
-            const bool from_right = c.kind == kFromRight;
-            if (!copy) {
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int e = tid + 256 * j;
-                    As[buf][e & 31][e >> 5] = av[j];
-                    if (from_right) Bs[buf][e & 31][e >> 5] = bv[j];
-                    else Bs[buf][e >> 5][e & 31] = bv[j];
-                }
-                __syncthreads();
-            } else {
-#pragma unroll
-                for (int v = 0; v < 4; v++) acc[v] += cv[v];
-            }
-            // next step, its operands in flight during this step's products
-            SbStep nx = st;
-            if (copy || st.k0 + kSbKs >= c.K) {
-                nx.ci++;
-                nx.k0 = 0;
-            } else {
-                nx.k0 += kSbKs;
-            }
-            const bool more = nx.ci < ce;
-            SbContrib cn = c;
-            if (more) {
-                if (nx.ci != st.ci) cn = cd[nx.ci - cb];
-                sb_load(cn, nx.k0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, av, bv, cv);
-            }
-            if (!copy) {
-                // slices past K hold zeros, so whole groups of 4 may overrun it
-                const int kq = (min(kSbKs, c.K - st.k0) + 3) >> 2;
-                for (int q = 0; q < kq; q++) {
-                    const double a = As[buf][4 * q + h][wr * 16 + cl];
-                    const double b = Bs[buf][4 * q + h][wc * 16 + cl];
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-                }
-                buf ^= 1;
-            }
-            if (!more) break;
-            st = nx;
-            c = cn;
+            SB_RUN(a0, b0, cur, ld);
+            cur = sb_next(cd, cb, ce, cur);
+            ld = sb_next(cd, cb, ce, ld);
+            if (cur.ci >= ce) break;
+            SB_RUN(a1, b1, cur, ld);
+            cur = sb_next(cd, cb, ce, cur);
+            ld = sb_next(cd, cb, ce, ld);
+            if (cur.ci >= ce) break;
         }
     }
+#undef SB_RUN
 #pragma unroll
     for (int v = 0; v < 4; v++) {
         const int r = wr * 16 + 4 * v + h, col = wc * 16 + cl;
@@ -452,6 +483,20 @@ rot_status rot_sb_plan_create(const rot_sb_problem* p, rot_sb_plan* plan) {
     std::vector<SbContrib> cs;
     auto* P = new rot_sb_plan_s();
     build_work(p, tiles, cs, P->flops, P->total);
+    // heaviest tiles first: all tiles do not fit on the chip at once, and the
+    // ones dispatched last should be short
+    {
+        std::vector<std::pair<int64_t, int>> order(tiles.size());
+        for (size_t i = 0; i < tiles.size(); i++) {
+            int64_t w = 0;
+            for (int c = tiles[i].c_begin; c < tiles[i].c_end; c++) w += cs[c].kind == kCopy ? 1 : (cs[c].K + 31) / 32;
+            order[i] = {-w, (int)i};
+        }
+        std::stable_sort(order.begin(), order.end());
+        std::vector<SbTile> sorted(tiles.size());
+        for (size_t i = 0; i < tiles.size(); i++) sorted[i] = tiles[order[i].second];
+        tiles.swap(sorted);
+    }
     P->n_tiles = (int)tiles.size();
     P->left_blk = p->left_blk;
     P->right_blk = p->right_blk;
