@@ -196,6 +196,15 @@ __device__ inline Rot2 jacobi_rotation(double app, double aqq, double apq, doubl
     return r;
 }
 
+// S is held as its upper triangle (entry (a, b) and (b, a) at su(min, max)):
+// at every step each unordered pair of indices lies in exactly one 2 x 2
+// block, so no mirrored copy has to be written.  Q is held transposed, row
+// stride kLq, so a rotation of columns (p, q) of Q updates two rows of Q^T
+// with 16-byte LDS accesses.
+constexpr int kLq = kPair + 2;
+
+__device__ inline int su(int a, int b) { return a < b ? a * kLs + b : b * kLs + a; }
+
 __global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* __restrict__ secs,
                                                                const DmItem* __restrict__ items,
                                                                double* __restrict__ A, double* __restrict__ Qw,
@@ -214,7 +223,7 @@ __global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* _
     int I, J;
     circle_pair(s.nb, round, k, I, J);
     __shared__ double S[kPair * kLs];
-    __shared__ double Q[kPair * kLs];
+    __shared__ __attribute__((aligned(16))) double Qt[kPair * kLq];
     __shared__ double rc[2][32], rs[2][32], rt[2][32];
     __shared__ unsigned char tp[kSteps][32], tq[kSteps][32];
     __shared__ int any;
@@ -231,8 +240,8 @@ __global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* _
 #pragma unroll
         for (int j = 0; j < kPer; j++) {
             const int e = tid + kPairThreads * j, x = e >> 6, y = e & 63;
-            S[x * kLs + y] = sv[j];
-            Q[x * kLs + y] = x == y ? 1.0 : 0.0;
+            if (x <= y) S[x * kLs + y] = sv[j];
+            Qt[x * kLq + y] = x == y ? 1.0 : 0.0;
         }
     }
     for (int e = tid; e < kSteps * 32; e += kPairThreads) {
@@ -263,7 +272,7 @@ __global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* _
     for (int u = 0; u < kSteps; u++) {
         const int cur = u & 1;
         if (tid < kBlocks2) {
-            const int px = tp[u][kx], qx = tq[u][kx];
+            const int px = tp[u][kx], qx = tq[u][kx];  // px < qx
             if (kx == ky) {
                 const double t = rt[cur][kx];
                 if (t != 0.0) {
@@ -271,27 +280,20 @@ __global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* _
                     S[px * kLs + px] -= t * apq;
                     S[qx * kLs + qx] += t * apq;
                     S[px * kLs + qx] = 0.0;
-                    S[qx * kLs + px] = 0.0;
                 }
             } else {
                 const double sx = rs[cur][kx], sy = rs[cur][ky];
                 if (sx != 0.0 || sy != 0.0) {
                     const int py = tp[u][ky], qy = tq[u][ky];
                     const double cx = rc[cur][kx], cy = rc[cur][ky];
-                    const double u0 = S[px * kLs + py], v0 = S[px * kLs + qy];
-                    const double x0 = S[qx * kLs + py], y0 = S[qx * kLs + qy];
+                    const int iu = su(px, py), iv = su(px, qy), ix = su(qx, py), iy = su(qx, qy);
+                    const double u0 = S[iu], v0 = S[iv], x0 = S[ix], y0 = S[iy];
                     const double u1 = cx * u0 - sx * x0, x1 = sx * u0 + cx * x0;
                     const double v1 = cx * v0 - sx * y0, y1 = sx * v0 + cx * y0;
-                    const double u2 = cy * u1 - sy * v1, v2 = sy * u1 + cy * v1;
-                    const double x2 = cy * x1 - sy * y1, y2 = sy * x1 + cy * y1;
-                    S[px * kLs + py] = u2;
-                    S[px * kLs + qy] = v2;
-                    S[qx * kLs + py] = x2;
-                    S[qx * kLs + qy] = y2;
-                    S[py * kLs + px] = u2;
-                    S[qy * kLs + px] = v2;
-                    S[py * kLs + qx] = x2;
-                    S[qy * kLs + qx] = y2;
+                    S[iu] = cy * u1 - sy * v1;
+                    S[iv] = sy * u1 + cy * v1;
+                    S[ix] = cy * x1 - sy * y1;
+                    S[iy] = sy * x1 + cy * y1;
                 }
             }
         }
@@ -306,24 +308,26 @@ __global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* _
                 if (r.s != 0.0) any = 1;
             }
         } else {
-            // Q <- Q J for this step: columns (p, q) of every row
-            for (int e = tid - 64; e < kPair * 32; e += kPairThreads - 64) {
-                const int row = e & 63, kp = e >> 6;
-                const double sn = rs[cur][kp];
+            // Q <- Q J: rows p, q of Q^T, two entries per access; 32 pairs x 32
+            // row pairs over the 960 threads past wave 0
+            for (int wq = tid - 64; wq < 32 * 32; wq += kPairThreads - 64) {
+                const int kq = wq >> 5, rq2 = wq & 31;
+                const double sn = rs[cur][kq];
                 if (sn == 0.0) continue;
-                const double c = rc[cur][kp];
-                const int p = tp[u][kp], q = tq[u][kp];
-                const double qp = Q[row * kLs + p], qq = Q[row * kLs + q];
-                Q[row * kLs + p] = c * qp - sn * qq;
-                Q[row * kLs + q] = sn * qp + c * qq;
+                const double c = rc[cur][kq];
+                double2* rp = reinterpret_cast<double2*>(Qt + tp[u][kq] * kLq) + rq2;
+                double2* rq = reinterpret_cast<double2*>(Qt + tq[u][kq] * kLq) + rq2;
+                const double2 vp = *rp, vq = *rq;
+                *rp = double2{c * vp.x - sn * vq.x, c * vp.y - sn * vq.y};
+                *rq = double2{sn * vp.x + c * vq.x, sn * vp.y + c * vq.y};
             }
         }
         __syncthreads();
     }
     for (int e = tid; e < kPair * kPair; e += kPairThreads) {
         const int x = e >> 6, y = e & 63;
-        a[(int64_t)pair_row(I, J, x) * np + pair_row(I, J, y)] = S[x * kLs + y];
-        Qw[s.q_off + (int64_t)k * kPair * kPair + e] = Q[x * kLs + y];
+        a[(int64_t)pair_row(I, J, x) * np + pair_row(I, J, y)] = S[su(x, y)];
+        Qw[s.q_off + (int64_t)k * kPair * kPair + e] = Qt[y * kLq + x];
     }
     if (tid == 0) *flag = any;
 }
