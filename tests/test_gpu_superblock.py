@@ -99,3 +99,43 @@ def test_full_size_parity_symmetry_linearity(rot):
     assert float((Hxy - (2.0 * Hx - 3.0 * Hy)).abs().max()) <= 1e-12 * scale * 5
     again = H.apply(x)
     assert torch.equal(again, Hx)
+
+
+def test_graph_replays_match_eager(rot):
+    """rot_sb_apply allocates nothing, so it can be captured: a graph of two
+    products (psi -> out1, out1 -> out2 = H^2 psi) is replayed several times
+    with eager work on psi in between, each replay equal bit for bit to the
+    eager products of the current psi."""
+    case = workloads.superblock_random(256, cfg=8)
+    H = make(rot, case)
+    rng = np.random.default_rng(97)
+    psi = torch.from_numpy(rng.standard_normal(H.total)).cuda()
+    out1 = torch.empty_like(psi)
+    out2 = torch.empty_like(psi)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        H.apply(psi, out1)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=stream):
+            H.apply(psi, out1)
+            H.apply(out1, out2)
+    torch.cuda.current_stream().wait_stream(stream)
+    for rep in range(4):
+        psi.mul_(0.5).add_(torch.from_numpy(rng.standard_normal(H.total)).cuda())  # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        e1 = H.apply(psi)
+        e2 = H.apply(e1)
+        torch.cuda.synchronize()
+        assert torch.equal(out1, e1), rep
+        assert torch.equal(out2, e2), rep
+
+
+def test_no_terms_gives_zero(rot):
+    case = workloads.superblock_hubbard(2, 2, (2, 1))
+    H = rot.SuperblockH(case.site_qn, case.left, case.right, case.target, case.left_ops, case.right_ops, [])
+    out = H.apply(torch.ones(H.total, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
