@@ -172,11 +172,11 @@ __global__ __launch_bounds__(256) void dm_prep_kernel(const DmSector* __restrict
 // 63 steps of 32 disjoint rotations (circle order over the 64 local indices).
 // Rotation (p, q) with tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) /
 // (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c zeroes a_pq of
-// J^T A J, J = [[c, s], [-s, c]] on rows/columns (p, q).  The submatrix is kept
-// exactly symmetric: each 2 x 2 block (kx <= ky) is rotated once and mirrored.
-// Schedule per step: all 528 blocks are rotated (one per thread), then wave 0
-// derives the next step's rotations while the other waves apply this step's
-// to the accumulated Q (parameters double-buffered).
+// J^T A J, J = [[c, s], [-s, c]] on rows/columns (p, q).  Each 2 x 2 block
+// (kx <= ky) of the step's pairs is rotated once, so the submatrix stays exactly
+// symmetric.  Schedule per step: all 528 blocks are rotated (one per thread),
+// then wave 0 derives the next step's rotations while the other waves apply
+// this step's to the accumulated Q (parameters double-buffered).
 constexpr int kPairThreads = 1024;
 constexpr int kSteps = kPair - 1;
 constexpr int kBlocks2 = 32 * 33 / 2;
