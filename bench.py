@@ -558,7 +558,7 @@ def bench_superblock(args, rot, torch, workloads):
     rec.update({"flops_per_product": H.flops, "tflops_fp64": round(tflops, 2),
                 "graph_replay_ms_per_product": round(ms_graph, 4),
                 "kernels_ms_avg": {"sb_matvec": round(avg_ms, 4)},
-                "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": 78.6, "unit": "TFLOP/s",
+                "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 78.6, "unit": "TFLOP/s",
                              "frac": round(tflops / 78.6, 4), "traffic": None, "kernel": "sb_tile_kernel",
                              "avg_ms": round(avg_ms, 4)},
                 "torch_dense_fp64_ms": round(ms_dense, 3), "speedup_vs_torch_dense": round(ms_dense / ms, 2),
