@@ -332,26 +332,50 @@ __global__ __launch_bounds__(kPairThreads) void dm_pair_kernel(const DmSector* _
     if (tid == 0) *flag = any;
 }
 
-// Y (64 x 64, registers 4 x 4 per thread) = op(L) * R with op(L) = L or L^T,
-// both operands in LDS with row stride kLs.
+typedef double dm_f64x4 __attribute__((ext_vector_type(4)));
+
+// Y = op(L) * R (64 x 64, op(L) = L or L^T, operands in LDS with row stride
+// kLs) on v_mfma_f64_16x16x4f64: wave w owns rows 32 (w / 2) .. and columns
+// 32 (w % 2) .. as 2 x 2 blocks of 16 x 16.  Lane l supplies A(row l%16, k l/16)
+// and B(k l/16, col l%16); element v of block (bi, bj) is row
+// 32 wr + 16 bi + 4 v + l/16, column 32 wc + 16 bj + l%16.
 template <bool kTransL>
-__device__ inline void mm64(const double* L, const double* R, double (&y)[4][4], int tx, int ty) {
+__device__ inline void mm64(const double* L, const double* R, dm_f64x4 (&acc)[2][2], int wr, int wc, int h,
+                            int c) {
 #pragma unroll
-    for (int p = 0; p < 4; p++)
+    for (int bi = 0; bi < 2; bi++)
 #pragma unroll
-        for (int q = 0; q < 4; q++) y[p][q] = 0.0;
+        for (int bj = 0; bj < 2; bj++) acc[bi][bj] = dm_f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (int kk = 0; kk < kPair; kk++) {
-        double l[4], r[4];
+    for (int k4 = 0; k4 < kPair / 4; k4++) {
+        const int k = 4 * k4 + h;
+        double a[2], b[2];
 #pragma unroll
-        for (int p = 0; p < 4; p++) l[p] = kTransL ? L[kk * kLs + ty * 4 + p] : L[(ty * 4 + p) * kLs + kk];
+        for (int bi = 0; bi < 2; bi++) {
+            const int row = 32 * wr + 16 * bi + c;
+            a[bi] = kTransL ? L[k * kLs + row] : L[row * kLs + k];
+        }
 #pragma unroll
-        for (int q = 0; q < 4; q++) r[q] = R[kk * kLs + tx * 4 + q];
+        for (int bj = 0; bj < 2; bj++) b[bj] = R[k * kLs + 32 * wc + 16 * bj + c];
 #pragma unroll
-        for (int p = 0; p < 4; p++)
+        for (int bi = 0; bi < 2; bi++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) y[p][q] = fma(l[p], r[q], y[p][q]);
+            for (int bj = 0; bj < 2; bj++)
+                acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
     }
+}
+
+__device__ inline void acc_to_lds(double* X, const dm_f64x4 (&acc)[2][2], int wr, int wc, int h, int c) {
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++) {
+            const int col = 32 * wc + 16 * bj + c;
+            X[(32 * wr + 16 * bi + h) * kLs + col] = acc[bi][bj].x;
+            X[(32 * wr + 16 * bi + 4 + h) * kLs + col] = acc[bi][bj].y;
+            X[(32 * wr + 16 * bi + 8 + h) * kLs + col] = acc[bi][bj].z;
+            X[(32 * wr + 16 * bi + 12 + h) * kLs + col] = acc[bi][bj].w;
+        }
 }
 
 // Applies the rotations of round t: A_{P1,P2} <- Q1^T A_{P1,P2} Q2 for pairs
@@ -365,7 +389,8 @@ __global__ __launch_bounds__(256) void dm_update_kernel(const DmSector* __restri
     const DmItem it = items[blockIdx.x];
     const DmSector s = secs[it.sec];
     const int* rf = rotated + s.flag_off;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1, h = lane >> 4, c = lane & 15;
     if (it.kind == kItemBook) {
         if (tid == 0) {
             DmState x = st[it.sec];
@@ -387,7 +412,7 @@ __global__ __launch_bounds__(256) void dm_update_kernel(const DmSector* __restri
     __shared__ double L[kPair * kLs];
     __shared__ double R[kPair * kLs];
     const int64_t np = s.npad;
-    double y[4][4];
+    dm_f64x4 y[2][2];
     if (it.kind == kItemA) {
         const int P1 = it.a, P2 = it.b;
         const int r1 = rf[P1], r2 = rf[P2];
@@ -416,21 +441,15 @@ __global__ __launch_bounds__(256) void dm_update_kernel(const DmSector* __restri
         }
         __syncthreads();
         if (r2) {
-            mm64<false>(X, R, y, tx, ty);
+            mm64<false>(X, R, y, wr, wc, h, c);
             __syncthreads();
-#pragma unroll
-            for (int p = 0; p < 4; p++)
-#pragma unroll
-                for (int q = 0; q < 4; q++) X[(ty * 4 + p) * kLs + tx * 4 + q] = y[p][q];
+            acc_to_lds(X, y, wr, wc, h, c);
             __syncthreads();
         }
         if (r1) {
-            mm64<true>(L, X, y, tx, ty);
+            mm64<true>(L, X, y, wr, wc, h, c);
             __syncthreads();
-#pragma unroll
-            for (int p = 0; p < 4; p++)
-#pragma unroll
-                for (int q = 0; q < 4; q++) X[(ty * 4 + p) * kLs + tx * 4 + q] = y[p][q];
+            acc_to_lds(X, y, wr, wc, h, c);
             __syncthreads();
         }
         // the block and its mirror, both written along rows
@@ -463,11 +482,18 @@ __global__ __launch_bounds__(256) void dm_update_kernel(const DmSector* __restri
         R[x * kLs + z] = rv[j];
     }
     __syncthreads();
-    mm64<false>(X, R, y, tx, ty);
+    mm64<false>(X, R, y, wr, wc, h, c);
 #pragma unroll
-    for (int p = 0; p < 4; p++)
+    for (int bi = 0; bi < 2; bi++)
 #pragma unroll
-        for (int q = 0; q < 4; q++) v[(r0 + ty * 4 + p) * np + pair_row(I, J, tx * 4 + q)] = y[p][q];
+        for (int bj = 0; bj < 2; bj++) {
+            const int64_t col = pair_row(I, J, 32 * wc + 16 * bj + c);
+            const int64_t row = r0 + 32 * wr + 16 * bi + h;
+            v[row * np + col] = y[bi][bj].x;
+            v[(row + 4) * np + col] = y[bi][bj].y;
+            v[(row + 8) * np + col] = y[bi][bj].z;
+            v[(row + 12) * np + col] = y[bi][bj].w;
+        }
 }
 
 __global__ __launch_bounds__(256) void dm_count_kernel(const DmState* __restrict__ st, int n_sec,
