@@ -53,9 +53,19 @@ struct Slice {
     typedef typename Vec16<T>::type V;
     static constexpr int VW = 16 / sizeof(T);
     static constexpr int CHUNKS = kTile * kSlice / VW / kThreads;
-    static constexpr int PITCH = KCONTIG ? (kSlice + kPadK) : (kTile + kPadMN);
+    // K-contiguous FP32 rows are 16 floats (four 16-byte chunks) unpadded,
+    // chunk q of row r stored in slot q ^ ((r >> 2) & 3): the stores of 16
+    // lanes (4 rows x 4 chunks) and the fragment reads of 16 lanes (16 rows,
+    // one chunk) then each cover all 64 LDS banks once.  Other slices are
+    // padded rows.
+    static constexpr bool SWZ = KCONTIG && sizeof(T) == 4;
+    static constexpr int PITCH = KCONTIG ? (SWZ ? kSlice : kSlice + kPadK) : (kTile + kPadMN);
     static constexpr int ELEMS = KCONTIG ? kTile * PITCH : kSlice * PITCH;
     V r[CHUNKS];
+
+    // element offset of 16-byte chunk q (k = q*VW ..) of row `row` in a
+    // K-contiguous slice
+    __device__ static inline int kc_off(int row, int q) { return row * PITCH + (SWZ ? (q ^ ((row >> 2) & 3)) : q) * VW; }
 
     // base points at element (row 0, k 0) of the operand; rows/ks are the
     // operand's full extents; r0/k0 the slice origin.  A slice wholly inside
@@ -102,7 +112,7 @@ struct Slice {
             const int f = tid + c * kThreads;
             int off;
             if (KCONTIG) {
-                off = (f / (kSlice / VW)) * PITCH + (f % (kSlice / VW)) * VW;
+                off = kc_off(f / (kSlice / VW), f % (kSlice / VW));
             } else {
                 off = (f / (kTile / VW)) * PITCH + (f % (kTile / VW)) * VW;
             }
@@ -191,8 +201,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
         for (int i = 0; i < 2; i++) {
             const int row = wm * 64 + i * 32 + c;
             if (AK) {
-                const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + row * SA::PITCH + h * 8);
-                const f32x4 x1 = *reinterpret_cast<const f32x4*>(a_s + row * SA::PITCH + h * 8 + 4);
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + SA::kc_off(row, 2 * h));
+                const f32x4 x1 = *reinterpret_cast<const f32x4*>(a_s + SA::kc_off(row, 2 * h + 1));
 #pragma unroll
                 for (int e = 0; e < 4; e++) { av[i][e] = x0[e]; av[i][4 + e] = x1[e]; }
             } else {
@@ -204,8 +214,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
         for (int i = 0; i < 2; i++) {
             const int col = wn * 64 + i * 32 + c;
             if (BK) {
-                const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + col * SB::PITCH + h * 8);
-                const f32x4 x1 = *reinterpret_cast<const f32x4*>(b_s + col * SB::PITCH + h * 8 + 4);
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + SB::kc_off(col, 2 * h));
+                const f32x4 x1 = *reinterpret_cast<const f32x4*>(b_s + SB::kc_off(col, 2 * h + 1));
 #pragma unroll
                 for (int e = 0; e < 4; e++) { bv[i][e] = x0[e]; bv[i][4 + e] = x1[e]; }
             } else {
@@ -327,8 +337,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
         for (int i = 0; i < 4; i++) {
             const int row = wm * 64 + i * 16 + c;
             if (AK) {
-                const f64x2 x0 = *reinterpret_cast<const f64x2*>(a_s + row * SA::PITCH + h * 4);
-                const f64x2 x1 = *reinterpret_cast<const f64x2*>(a_s + row * SA::PITCH + h * 4 + 2);
+                const f64x2 x0 = *reinterpret_cast<const f64x2*>(a_s + SA::kc_off(row, 2 * h));
+                const f64x2 x1 = *reinterpret_cast<const f64x2*>(a_s + SA::kc_off(row, 2 * h + 1));
                 av[i][0] = x0[0]; av[i][1] = x0[1]; av[i][2] = x1[0]; av[i][3] = x1[1];
             } else {
 #pragma unroll
@@ -339,8 +349,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
         for (int i = 0; i < 4; i++) {
             const int col = wn * 64 + i * 16 + c;
             if (BK) {
-                const f64x2 x0 = *reinterpret_cast<const f64x2*>(b_s + col * SB::PITCH + h * 4);
-                const f64x2 x1 = *reinterpret_cast<const f64x2*>(b_s + col * SB::PITCH + h * 4 + 2);
+                const f64x2 x0 = *reinterpret_cast<const f64x2*>(b_s + SB::kc_off(col, 2 * h));
+                const f64x2 x1 = *reinterpret_cast<const f64x2*>(b_s + SB::kc_off(col, 2 * h + 1));
                 bv[i][0] = x0[0]; bv[i][1] = x0[1]; bv[i][2] = x1[0]; bv[i][3] = x1[1];
             } else {
 #pragma unroll

@@ -31,10 +31,17 @@ constexpr int kPad = 4;
 template <int R, int NT, bool KCONTIG>
 struct GSlice {
     static constexpr int CHUNKS = R * kSlice / 4 / NT;
-    static constexpr int PITCH = KCONTIG ? (kSlice + kPad) : (R + kPad);
+    // K-contiguous rows are 16 floats (four 16-byte chunks) unpadded, chunk q
+    // of row r in slot q ^ ((r >> 2) & 3), so that 16 lanes storing 4 rows x
+    // 4 chunks, or reading one chunk of 16 rows, each cover all 64 LDS banks
+    // once; M/N-contiguous slices are padded rows.
+    static constexpr int PITCH = KCONTIG ? kSlice : (R + kPad);
     static constexpr int ELEMS = KCONTIG ? R * PITCH : kSlice * PITCH;
     static_assert(CHUNKS >= 1 && CHUNKS * NT * 4 == R * kSlice, "slice must split evenly over threads");
     f32x4 r[CHUNKS];
+
+    // offset of chunk q (k = 4q .. 4q + 3) of row `row` in a K-contiguous slice
+    __device__ static inline int kc_off(int row, int q) { return row * PITCH + (q ^ ((row >> 2) & 3)) * 4; }
 
     // A slice wholly inside the operand (uniform over the workgroup) takes
     // unconditional vector loads; edge slices load element by element.
@@ -76,7 +83,7 @@ struct GSlice {
 #pragma unroll
         for (int c = 0; c < CHUNKS; c++) {
             const int f = tid + c * NT;
-            const int off = KCONTIG ? (f / (kSlice / 4)) * PITCH + (f % (kSlice / 4)) * 4
+            const int off = KCONTIG ? kc_off(f / (kSlice / 4), f % (kSlice / 4))
                                     : (f / (R / 4)) * PITCH + (f % (R / 4)) * 4;
             *reinterpret_cast<f32x4*>(lds + off) = r[c];
         }
@@ -152,8 +159,8 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
             for (int i = 0; i < BI; i++) {
                 const int row = wm * (BM / WM) + i * 32 + c;
                 if (AK) {
-                    const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + row * SA::PITCH + h * 8);
-                    const f32x4 x1 = *reinterpret_cast<const f32x4*>(a_s + row * SA::PITCH + h * 8 + 4);
+                    const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + SA::kc_off(row, 2 * h));
+                    const f32x4 x1 = *reinterpret_cast<const f32x4*>(a_s + SA::kc_off(row, 2 * h + 1));
 #pragma unroll
                     for (int e = 0; e < 4; e++) { av[i][e] = x0[e]; av[i][4 + e] = x1[e]; }
                 } else {
@@ -165,8 +172,8 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
             for (int i = 0; i < BJ; i++) {
                 const int col = wn * (BN / WN) + i * 32 + c;
                 if (BK) {
-                    const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + col * SB::PITCH + h * 8);
-                    const f32x4 x1 = *reinterpret_cast<const f32x4*>(b_s + col * SB::PITCH + h * 8 + 4);
+                    const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + SB::kc_off(col, 2 * h));
+                    const f32x4 x1 = *reinterpret_cast<const f32x4*>(b_s + SB::kc_off(col, 2 * h + 1));
 #pragma unroll
                     for (int e = 0; e < 4; e++) { bv[i][e] = x0[e]; bv[i][4 + e] = x1[e]; }
                 } else {
