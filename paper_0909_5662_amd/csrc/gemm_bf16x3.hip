@@ -39,15 +39,22 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-__device__ inline uint16_t rne_bf16(float x) {
-    const uint32_t b = __float_as_uint(x);
-    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (uint16_t)((b >> 16) | 0x40u);
-    return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
-}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 round to nearest even (the hardware conversion,
+// v_cvt_pk_bf16_f32), as a bit pattern.
+__device__ inline uint16_t rne_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// hi/lo split of two values: {hi pair, lo pair}, each pair packed with the
+// first value in the low half (one conversion instruction per pair).
+__device__ inline u32x2 split2(float a, float b) {
+    const bf16x2 h = {(__bf16)a, (__bf16)b};
+    const bf16x2 l = {(__bf16)(a - (float)h[0]), (__bf16)(b - (float)h[1])};
+    return u32x2{__builtin_bit_cast(uint32_t, h), __builtin_bit_cast(uint32_t, l)};
+}
 
 __device__ inline int xcd_linear_id() {
     const int nwg = gridDim.x, wg = blockIdx.x;
@@ -128,25 +135,20 @@ __device__ inline void store_tile(const Bf16Desc& g, const f32x16 (&acc)[BI][BJ]
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int row0 = row0w + i * 32 + 8 * q + 4 * h;
-                    u16x4 hv, lv;
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const float x = a[4 * q + e];
-                        hv[e] = rne_bf16(x);
-                        lv[e] = rne_bf16(x - bf16_f32(hv[e]));
-                    }
+                    const u32x2 p0 = split2(a[4 * q], a[4 * q + 1]), p1 = split2(a[4 * q + 2], a[4 * q + 3]);
+                    const u32x2 hv = {p0[0], p1[0]}, lv = {p0[1], p1[1]};
                     if (D4 && row0 + 4 <= g.M) {
                         const int64_t off = slab_off(row0 >> 2, (int64_t)col * 4, g.t_rows);
-                        *reinterpret_cast<u16x4*>(th + off) = hv;
-                        *reinterpret_cast<u16x4*>(tl + off) = lv;
+                        *reinterpret_cast<u32x2*>(th + off) = hv;
+                        *reinterpret_cast<u32x2*>(tl + off) = lv;
                     } else if (!D4) {
 #pragma unroll
                         for (int e = 0; e < 4; e++) {
                             const int row = row0 + e;
                             if (row < g.M) {
                                 const int64_t off = slab_off(row / g.d, (int64_t)col * g.d + row % g.d, g.t_rows);
-                                th[off] = hv[e];
-                                tl[off] = lv[e];
+                                th[off] = (uint16_t)(hv[e >> 1] >> (16 * (e & 1)));
+                                tl[off] = (uint16_t)(lv[e >> 1] >> (16 * (e & 1)));
                             }
                         }
                     }
@@ -437,16 +439,17 @@ __global__ __launch_bounds__(256) void split_o_kernel(const float* __restrict__ 
         const int64_t sq = j0 / kSlabK + q;          // global slab index
         if (i >= m || sq >= nslab) continue;
         const int half = slot ^ ((i >> 3) & 1);
-        u16x8 hv, lv;
+        u32x4 hv, lv;
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const float v = tile[row][q * kSlabK + half * 8 + e];
-            hv[e] = rne_bf16(v);
-            lv[e] = rne_bf16(v - bf16_f32(hv[e]));
+        for (int e = 0; e < 4; e++) {
+            const float* src = &tile[row][q * kSlabK + half * 8 + 2 * e];
+            const u32x2 p = split2(src[0], src[1]);
+            hv[e] = p[0];
+            lv[e] = p[1];
         }
         const int64_t off = sq * (int64_t)m * kSlabK + (int64_t)i * kSlabK + slot * 8;
-        *reinterpret_cast<u16x8*>(dh + off) = hv;
-        *reinterpret_cast<u16x8*>(dl + off) = lv;
+        *reinterpret_cast<u32x4*>(dh + off) = hv;
+        *reinterpret_cast<u32x4*>(dl + off) = lv;
     }
 }
 

@@ -10,13 +10,9 @@
 namespace rot {
 namespace {
 
-// IEEE round-to-nearest-even of an FP32 bit pattern to its top 16 bits.
-__device__ inline uint16_t rne_bf16(float x) {
-    const uint32_t b = __float_as_uint(x);
-    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))  // NaN: keep it quiet
-        return (uint16_t)((b >> 16) | 0x40u);
-    return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
-}
+// FP32 -> BF16 round to nearest even (the hardware conversion,
+// v_cvt_pk_bf16_f32), as a bit pattern.
+__device__ inline uint16_t rne_bf16(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
