@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
     const int li = lane & 15, lh = lane >> 4;
     int t = 0;
     if (lane == 0) t = atomicAdd(counter, 1);
-    t = __shfl(t, 0, 64);
+    t = __builtin_amdgcn_readfirstlane(t);  // lane 0's ticket, uniform over the wave
     while (t < n_tasks) {
         const BlkTask T = tasks[t];
         const float* uT = Ut + T.uT_off;
@@ -197,14 +197,23 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
                 const BlkTerm tm = terms[T.term0 + e];
                 const float* o = O + tm.o_off;
                 for (int rb = 0; rb * 16 < tm.a; rb++) {
-                    // stage 1: X_s rows 16 rb.., column blocks cg0 .. cg0+CG-1
+                    // stage 2's U_T values for this row block do not depend on
+                    // stage 1: their loads are issued first and overlap it
+                    f32x4 ut[MAXA];
+#pragma unroll
+                    for (int ca = 0; ca < MAXA; ca++)
+                        if (ca < nba)
+                            ut[ca] = *reinterpret_cast<const f32x4*>(uT + (int64_t)(ca * 16 + li) * T.ldT + tm.rt +
+                                                                     rb * 16 + 4 * lh);
+                    // stage 1: X_s rows 16 rb.., column blocks cg0 .. cg0+CG-1;
+                    // the operands of the next 16 k load while this step multiplies
                     f32x4 x[CG];
 #pragma unroll
                     for (int c = 0; c < CG; c++) x[c] = f32x4{0.f, 0.f, 0.f, 0.f};
                     const int row = rb * 16 + li;
                     const bool rok = row < tm.a;
                     const float* orow = o + (int64_t)row * tm.k;
-                    for (int k0 = 0; k0 < tm.k; k0 += 16) {
+                    auto load_a = [&](int k0) __attribute__((always_inline)) {
                         const int kk = k0 + 4 * lh;  // this lane's k = kk + j at step j
                         f32x4 av;
                         if (rok && kk + 4 <= tm.k) {
@@ -213,29 +222,48 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
 #pragma unroll
                             for (int j = 0; j < 4; j++) av[j] = (rok && kk + j < tm.k) ? orow[kk + j] : 0.f;
                         }
-                        f32x4 bv[CG];
+                        return av;
+                    };
+                    f32x4 av = f32x4{0.f, 0.f, 0.f, 0.f}, bv[CG];
+#pragma unroll
+                    for (int c = 0; c < CG; c++) bv[c] = av;
+                    if (tm.k > 0) {
+                        av = load_a(0);
 #pragma unroll
                         for (int c = 0; c < CG; c++)
                             bv[c] = *reinterpret_cast<const f32x4*>(uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ +
-                                                                    tm.rq + kk);
+                                                                    tm.rq + 4 * lh);
+                    }
+                    for (int k0 = 0; k0 < tm.k; k0 += 16) {
+                        f32x4 av_n = av, bv_n[CG];
+#pragma unroll
+                        for (int c = 0; c < CG; c++) bv_n[c] = bv[c];
+                        if (k0 + 16 < tm.k) {
+                            av_n = load_a(k0 + 16);
+#pragma unroll
+                            for (int c = 0; c < CG; c++)
+                                bv_n[c] = *reinterpret_cast<const f32x4*>(
+                                    uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ + tm.rq + k0 + 16 + 4 * lh);
+                        }
 #pragma unroll
                         for (int j = 0; j < 4; j++)
 #pragma unroll
                             for (int c = 0; c < CG; c++)
                                 x[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[c][j], x[c], 0, 0, 0);
+                        av = av_n;
+#pragma unroll
+                        for (int c = 0; c < CG; c++) bv[c] = bv_n[c];
                     }
                     // stage 2: acc(beta, alpha) += sum_r X_s[r][beta] U_T[rt + r][alpha], the X block
                     // in accumulator layout read with k order 4*(l/16) + j at step j
 #pragma unroll
                     for (int ca = 0; ca < MAXA; ca++) {
                         if (ca < nba) {
-                            const f32x4 bv = *reinterpret_cast<const f32x4*>(
-                                uT + (int64_t)(ca * 16 + li) * T.ldT + tm.rt + rb * 16 + 4 * lh);
 #pragma unroll
                             for (int j = 0; j < 4; j++)
 #pragma unroll
                                 for (int c = 0; c < CG; c++)
-                                    acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], bv[j], acc[c][ca], 0,
+                                    acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], ut[ca][j], acc[c][ca], 0,
                                                                                        0, 0);
                         }
                     }
@@ -257,7 +285,7 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
                 }
         }
         if (lane == 0) t = atomicAdd(counter, 1);
-        t = __shfl(t, 0, 64);
+        t = __builtin_amdgcn_readfirstlane(t);  // lane 0's ticket, uniform over the wave
     }
 }
 

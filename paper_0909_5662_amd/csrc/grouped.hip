@@ -112,7 +112,7 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
     if (DYN) {
         if (tid == 0) s_next = atomicAdd(L.counter, 1);
         __syncthreads();
-        t = s_next;
+        t = __builtin_amdgcn_readfirstlane(s_next);  // the same for every thread: keep it scalar
     } else {
         // static: contiguous runs per XCD (hardware puts workgroup w on XCD w % 8)
         const int nwg = gridDim.x, wg = blockIdx.x;
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
         if (DYN) {
             if (tid == 0) s_next = atomicAdd(L.counter, 1);
             __syncthreads();
-            t = s_next;
+            t = __builtin_amdgcn_readfirstlane(s_next);
             __syncthreads();  // everyone has read s_next before it is overwritten
         } else {
             t += gridDim.x;
