@@ -54,9 +54,10 @@ struct SbTile {
 // v_mfma_f64_16x16x4f64 (lane l supplies A(row l%16, k l/16) and B(k l/16,
 // col l%16); accumulator element v is C(4v + l/16, l%16)).  The contributions
 // are walked as one sequence of steps (a 32-wide K slice of a product, or a
-// scaled copy); the operands of the steps one and two ahead are loaded into two
-// register sets while the current one is multiplied from LDS (two LDS buffers,
-// one barrier per product step), and the step descriptors are read from LDS.
+// scaled copy); the raw operands of the steps one and two ahead are loaded into
+// two register sets while the current one is multiplied from LDS (two LDS
+// buffers, one barrier per product step), and the step descriptors are read
+// from LDS.
 constexpr int kSbKs = 32;
 constexpr int kSbMaxC = 128;  // contribution descriptors held in LDS at a time
 
@@ -66,10 +67,13 @@ struct SbStep {
     int ci, k0;
 };
 
-// Operands of step (c, k0) into registers: for a product, this thread's four
-// elements of the A slice (tile row r, slice column k, scaled by alpha) and of
-// the B slice; for a copy, alpha times the psi entries of this lane's four
-// accumulator rows (in av).
+// Raw operands of step (c, k0) into registers: for a product, this thread's
+// four elements of the A slice (tile row r, slice column k) and of the B
+// slice; for a copy, the psi entries of this lane's four accumulator rows (in
+// av).  Every load is unconditional, from the element's own address when it
+// lies inside the slice and from the slice's first element otherwise, and
+// nothing is computed from the values here, so the loads stay in flight until
+// the step is used; scaling and zeroing happen then (sb_stage, sb_copy).
 __device__ __attribute__((always_inline)) inline void sb_load(const SbContrib& c, int k0, const SbTile& tl,
                                                               const double* left_blk, const double* right_blk,
                                                               const double* psi, int tid, int wr, int wc, int h,
@@ -77,11 +81,11 @@ __device__ __attribute__((always_inline)) inline void sb_load(const SbContrib& c
     if (c.kind == kCopy) {
         const int col = wc * 16 + cl, r0 = wr * 16 + h;
         const bool cin = col < tl.cols;
-        const double* src = psi + c.a_off + col;
-        av.x = (cin && r0 < tl.rows) ? c.alpha * src[(int64_t)r0 * c.lda] : 0.0;
-        av.y = (cin && r0 + 4 < tl.rows) ? c.alpha * src[(int64_t)(r0 + 4) * c.lda] : 0.0;
-        av.z = (cin && r0 + 8 < tl.rows) ? c.alpha * src[(int64_t)(r0 + 8) * c.lda] : 0.0;
-        av.w = (cin && r0 + 12 < tl.rows) ? c.alpha * src[(int64_t)(r0 + 12) * c.lda] : 0.0;
+        const double* src = psi + c.a_off;
+        av.x = src[(cin && r0 < tl.rows) ? (int64_t)r0 * c.lda + col : 0];
+        av.y = src[(cin && r0 + 4 < tl.rows) ? (int64_t)(r0 + 4) * c.lda + col : 0];
+        av.z = src[(cin && r0 + 8 < tl.rows) ? (int64_t)(r0 + 8) * c.lda + col : 0];
+        av.w = src[(cin && r0 + 12 < tl.rows) ? (int64_t)(r0 + 12) * c.lda + col : 0];
         return;
     }
     const double* A = c.kind == kFromLeft ? left_blk + c.a_off : psi + c.a_off;
@@ -95,32 +99,42 @@ __device__ __attribute__((always_inline)) inline void sb_load(const SbContrib& c
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int r = hi + 8 * j;
-        a[j] = (r < tl.rows && k0 + lo < c.K) ? c.alpha * A[(int64_t)r * c.lda + k0 + lo] : 0.0;
-        b[j] = left ? ((lo < tl.cols && k0 + r < c.K) ? B[(int64_t)(k0 + r) * c.ldb + lo] : 0.0)
-                    : ((r < tl.cols && k0 + lo < c.K) ? B[(int64_t)r * c.ldb + k0 + lo] : 0.0);
+        a[j] = A[(r < tl.rows && k0 + lo < c.K) ? (int64_t)r * c.lda + k0 + lo : 0];
+        b[j] = B[left ? ((lo < tl.cols && k0 + r < c.K) ? (int64_t)(k0 + r) * c.ldb + lo : 0)
+                      : ((r < tl.cols && k0 + lo < c.K) ? (int64_t)r * c.ldb + k0 + lo : 0)];
     }
     av = sb_f64x4{a[0], a[1], a[2], a[3]};
     bv = sb_f64x4{b[0], b[1], b[2], b[3]};
 }
 
+// A copy step: alpha times the raw psi entries of this lane's accumulator rows
+// (zero outside the tile), as loaded by sb_load.
+__device__ __attribute__((always_inline)) inline sb_f64x4 sb_copy(const SbContrib& c, const SbTile& tl,
+                                                                  const sb_f64x4& av, int wr, int wc, int h,
+                                                                  int cl) {
+    const int col = wc * 16 + cl, r0 = wr * 16 + h;
+    const bool cin = col < tl.cols;
+    return sb_f64x4{(cin && r0 < tl.rows) ? c.alpha * av.x : 0.0, (cin && r0 + 4 < tl.rows) ? c.alpha * av.y : 0.0,
+                    (cin && r0 + 8 < tl.rows) ? c.alpha * av.z : 0.0,
+                    (cin && r0 + 12 < tl.rows) ? c.alpha * av.w : 0.0};
+}
+
+// A product step's slices into LDS: A scaled by alpha, both zero outside the
+// slice (the raw values there came from the slice's first element).
 __device__ __attribute__((always_inline)) inline void sb_stage(double (*As)[kSbTile + 1], double (*Bs)[kSbTile + 1],
-                                                              const sb_f64x4& av, const sb_f64x4& bv, int tid,
-                                                              bool from_right) {
+                                                              const SbContrib& c, int k0, const SbTile& tl,
+                                                              const sb_f64x4& av, const sb_f64x4& bv, int tid) {
     const int hi = tid >> 5, lo = tid & 31;
-    As[lo][hi] = av.x;
-    As[lo][hi + 8] = av.y;
-    As[lo][hi + 16] = av.z;
-    As[lo][hi + 24] = av.w;
-    if (from_right) {
-        Bs[lo][hi] = bv.x;
-        Bs[lo][hi + 8] = bv.y;
-        Bs[lo][hi + 16] = bv.z;
-        Bs[lo][hi + 24] = bv.w;
-    } else {
-        Bs[hi][lo] = bv.x;
-        Bs[hi + 8][lo] = bv.y;
-        Bs[hi + 16][lo] = bv.z;
-        Bs[hi + 24][lo] = bv.w;
+    const bool left = c.kind == kFromLeft;
+    const double a[4] = {av.x, av.y, av.z, av.w}, b[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int r = hi + 8 * j;
+        As[lo][r] = (r < tl.rows && k0 + lo < c.K) ? c.alpha * a[j] : 0.0;
+        if (left)
+            Bs[r][lo] = (lo < tl.cols && k0 + r < c.K) ? b[j] : 0.0;
+        else
+            Bs[lo][r] = (r < tl.cols && k0 + lo < c.K) ? b[j] : 0.0;
     }
 }
 
@@ -150,13 +164,12 @@ __global__ __launch_bounds__(256) void sb_tile_kernel(const SbTile* __restrict__
     do {                                                                                                      \
         const SbContrib& c_ = cd[(X).ci - cb];                                                                \
         if (c_.kind == kCopy) {                                                                               \
-            acc += A;                                                                                         \
+            acc += sb_copy(c_, tl, A, wr, wc, h, cl);                                                         \
             if ((REFILL).ci < ce)                                                                             \
                 sb_load(cd[(REFILL).ci - cb], (REFILL).k0, tl, left_blk, right_blk, psi, tid, wr, wc, h, cl, A, \
                         B);                                                                                \
         } else {                                                                                              \
-            const bool from_right = c_.kind == kFromRight;                                                    \
-            sb_stage(As[buf], Bs[buf], A, B, tid, from_right);                                                \
+            sb_stage(As[buf], Bs[buf], c_, (X).k0, tl, A, B, tid);                                            \
             __syncthreads();                                                                                  \
             const int kq = (min(kSbKs, c_.K - (X).k0) + 3) >> 2;                                              \
             if ((REFILL).ci < ce)                                                                             \
