@@ -239,7 +239,10 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 
     float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs;
     // symmetric output: a diagonal tile keeps row <= col and mirrors it, so
-    // the result is exactly symmetric
+    // the result is exactly symmetric.  Accumulating: the previous values of
+    // each group of four rows are loaded before the group's stores
+    // (unconditionally, from element 0 outside C), so four loads are in
+    // flight together instead of one load-add-store at a time.
     const bool diag = !ACC && g.upper && tc.m0 == tc.n0;
 #pragma unroll
     for (int i = 0; i < 2; i++)
@@ -248,12 +251,22 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
             const int col = tc.n0 + wn * 64 + k * 32 + c;
             if (col >= g.N) continue;
 #pragma unroll
-            for (int v = 0; v < 16; v++) {
-                const int row = tc.m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-                if (row < g.M && (!diag || row <= col)) {
-                    float* p = Cb + (int64_t)row * g.ldc + col;
-                    *p = ACC ? *p + acc[i][k][v] : acc[i][k][v];
-                    if (diag && row < col) Cb[(int64_t)col * g.ldc + row] = acc[i][k][v];
+            for (int q = 0; q < 4; q++) {
+                const int row0 = tc.m0 + wm * 64 + i * 32 + 8 * q + 4 * h;
+                float old[4];
+                if (ACC) {
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        old[e] = Cb[row0 + e < g.M ? (int64_t)(row0 + e) * g.ldc + col : 0];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int row = row0 + e, v = 4 * q + e;
+                    if (row < g.M && (!diag || row <= col)) {
+                        float* p = Cb + (int64_t)row * g.ldc + col;
+                        *p = ACC ? old[e] + acc[i][k][v] : acc[i][k][v];
+                        if (diag && row < col) Cb[(int64_t)col * g.ldc + row] = acc[i][k][v];
+                    }
                 }
             }
         }
