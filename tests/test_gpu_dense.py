@@ -288,6 +288,32 @@ def test_bf16_split_bit_exact(rot, oracle_mod):
     np.testing.assert_array_equal(lo.cpu().numpy().view(np.uint16), rlo)
 
 
+def test_bf16_split_special_values(rot, oracle_mod):
+    """Zeros, subnormals, the largest finite values (the top ones round to
+    infinity), infinities, NaNs and 200 000 random bit patterns over every
+    exponent: hi and lo equal the oracle's integer rounding bit for bit,
+    except that where both are NaN (a NaN input, or lo = inf - inf for an
+    infinite one) the NaN's sign and payload are not compared."""
+    f32 = np.finfo(np.float32)
+    special = np.array([0.0, -0.0, np.inf, -np.inf, f32.max, -f32.max, 3.3961776e38, -3.3961776e38,
+                        3.3895314e38, f32.tiny, -f32.tiny, f32.tiny / 2, 1e-45, -1e-45, 3e-39, 1.0000001,
+                        65504.0, np.nan, -np.nan], dtype=np.float32)
+    rng = np.random.default_rng(91)
+    x = np.concatenate([special, rng.integers(0, 2 ** 32, 200_000, dtype=np.uint64).astype(np.uint32)
+                        .view(np.float32)])
+    assert np.count_nonzero((x != 0) & (np.abs(x) < f32.tiny)) > 100  # subnormals present
+    hi, lo = rot.split_bf16(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    hi = hi.cpu().numpy().view(np.uint16)
+    lo = lo.cpu().numpy().view(np.uint16)
+    with np.errstate(invalid="ignore", over="ignore"):
+        rhi, rlo = oracle_mod.bf16_split(x)
+    for got, ref in ((hi, rhi), (lo, rlo)):
+        both_nan = np.isnan(oracle_mod.bf16_bits_to_f32(got)) & np.isnan(oracle_mod.bf16_bits_to_f32(ref))
+        bad = (got != ref) & ~both_nan
+        assert not bad.any(), (x[bad][:8], got[bad][:8], ref[bad][:8])
+
+
 # -------------------------------------------------------------- split-BF16 --
 
 def elementwise_bound(oracle_mod, case, unit):
