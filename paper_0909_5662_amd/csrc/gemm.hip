@@ -31,7 +31,6 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kTile = kGemmTile;   // BM = BN
 constexpr int kSlice = 16;   // K elements per LDS slice
-constexpr int kPadK = 4;     // row padding (elements) of K-contiguous LDS tiles
 constexpr int kPadMN = 4;    // row padding (elements) of M/N-contiguous LDS tiles
 
 template <typename T> struct Vec16;
@@ -53,19 +52,21 @@ struct Slice {
     typedef typename Vec16<T>::type V;
     static constexpr int VW = 16 / sizeof(T);
     static constexpr int CHUNKS = kTile * kSlice / VW / kThreads;
-    // K-contiguous FP32 rows are 16 floats (four 16-byte chunks) unpadded,
-    // chunk q of row r stored in slot q ^ ((r >> 2) & 3): the stores of 16
-    // lanes (4 rows x 4 chunks) and the fragment reads of 16 lanes (16 rows,
-    // one chunk) then each cover all 64 LDS banks once.  Other slices are
-    // padded rows.
-    static constexpr bool SWZ = KCONTIG && sizeof(T) == 4;
-    static constexpr int PITCH = KCONTIG ? (SWZ ? kSlice : kSlice + kPadK) : (kTile + kPadMN);
+    // K-contiguous rows are kSlice elements unpadded: NQ 16-byte chunks (4
+    // for FP32, 8 for FP64), RPB = 16 / NQ rows per 256 bytes, chunk q of row
+    // r stored in slot q ^ ((r / RPB) % NQ).  The stores of 16 lanes (RPB
+    // rows x NQ chunks) and the fragment reads of 16 lanes (16 rows, one
+    // chunk) then each cover all 64 LDS banks once.  M/N-contiguous slices
+    // are padded rows.
+    static constexpr int NQ = kSlice / VW;
+    static constexpr int RPB = 16 / NQ;
+    static constexpr int PITCH = KCONTIG ? kSlice : (kTile + kPadMN);
     static constexpr int ELEMS = KCONTIG ? kTile * PITCH : kSlice * PITCH;
     V r[CHUNKS];
 
     // element offset of 16-byte chunk q (k = q*VW ..) of row `row` in a
     // K-contiguous slice
-    __device__ static inline int kc_off(int row, int q) { return row * PITCH + (SWZ ? (q ^ ((row >> 2) & 3)) : q) * VW; }
+    __device__ static inline int kc_off(int row, int q) { return row * PITCH + (q ^ ((row / RPB) % NQ)) * VW; }
 
     // base points at element (row 0, k 0) of the operand; rows/ks are the
     // operand's full extents; r0/k0 the slice origin.  A slice wholly inside
