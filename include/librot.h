@@ -107,8 +107,7 @@ ROT_API rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_pr
  * symmetric (U^T (O (x) I) U with O = O^T); stage 2 computes only the output
  * tiles on and above the diagonal and stores each off-diagonal tile also
  * transposed: 2 m^2 d m' + about m d m'^2 (1 + 128/m') flops per operator
- * instead of 2 m^2 d m' + 2 m d m'^2 (the survey's symmetric-output
- * specialisation).  out_b is then exactly symmetric; for non-symmetric O_b
+ * instead of 2 m^2 d m' + 2 m d m'^2.  out_b is then exactly symmetric; for non-symmetric O_b
  * the result is wrong (only the upper triangle of U^T (O (x) I) U is kept).
  */
 ROT_API rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precision prec, uint32_t flags,
