@@ -411,21 +411,35 @@ __global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ 
 }
 
 // O_b (m x m at O + b*stride_o) -> hi/lo at b*ob in slab layout (m rows,
-// K = m), one 64 x 64 block per workgroup: rows are read contiguously into
-// LDS, then the block's 4 slabs x 64 rows x 2 halves are written as 16-byte
-// chunks in memory order (each slab's part of the block is 2 KB contiguous
-// per array).  Columns past m in the last slab are written as zero.
+// K = m), one 64 x 64 block per workgroup.  Rows are read into LDS (16-byte
+// loads when the block lies inside O and its rows are 16-byte aligned), then
+// each thread converts 8 values (one k half of one row in one slab) and
+// writes them as one 16-byte chunk per array.  Each 16 lanes take 16
+// consecutive rows and the same k half, so with a row pitch of 68 floats
+// both the 16-byte LDS writes and reads touch all 64 banks once.  Columns
+// past m in the last slab are written as zero.
 __global__ __launch_bounds__(256) void split_o_kernel(const float* __restrict__ O, int m, int64_t stride_o,
                                                       uint16_t* __restrict__ oh, uint16_t* __restrict__ ol,
                                                       int64_t ob) {
-    __shared__ float tile[64][64 + 1];
+    __shared__ __attribute__((aligned(16))) float tile[64][68];
     const int b = blockIdx.z, i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
     const float* src = O + (int64_t)b * stride_o;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    if (j0 + 64 <= m && (m & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        const int i = i0 + ty + 4 * k, j = j0 + tx;
-        tile[ty + 4 * k][tx] = (i < m && j < m) ? src[(int64_t)i * m + j] : 0.f;
+        for (int k = 0; k < 4; k++) {
+            const int r = (tid >> 4) + 16 * k, c4 = (tid & 15) * 4, i = i0 + r;
+            f32x4 v = {0.f, 0.f, 0.f, 0.f};
+            if (i < m) v = *reinterpret_cast<const f32x4*>(src + (int64_t)i * m + j0 + c4);
+            *reinterpret_cast<f32x4*>(&tile[r][c4]) = v;
+        }
+    } else {
+        const int tx = tid & 63, ty = tid >> 6;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const int i = i0 + ty + 4 * k, j = j0 + tx;
+            tile[ty + 4 * k][tx] = (i < m && j < m) ? src[(int64_t)i * m + j] : 0.f;
+        }
     }
     __syncthreads();
     uint16_t* dh = oh + (int64_t)b * ob;
@@ -433,20 +447,17 @@ __global__ __launch_bounds__(256) void split_o_kernel(const float* __restrict__ 
     const int64_t nslab = n_slabs(m);
 #pragma unroll
     for (int x = 0; x < 2; x++) {
-        const int ch = threadIdx.x + 256 * x;        // chunk: slab q, row, slot
-        const int q = ch >> 7, row = (ch & 127) >> 1, slot = ch & 1;
+        const int ch = tid + 256 * x;  // slab q, k half, row
+        const int q = ch >> 7, half = (ch >> 6) & 1, row = ch & 63;
         const int i = i0 + row;
-        const int64_t sq = j0 / kSlabK + q;          // global slab index
+        const int64_t sq = j0 / kSlabK + q;  // global slab index
         if (i >= m || sq >= nslab) continue;
-        const int half = slot ^ ((i >> 3) & 1);
-        u32x4 hv, lv;
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const float* src = &tile[row][q * kSlabK + half * 8 + 2 * e];
-            const u32x2 p = split2(src[0], src[1]);
-            hv[e] = p[0];
-            lv[e] = p[1];
-        }
+        const f32x4 v0 = *reinterpret_cast<const f32x4*>(&tile[row][q * kSlabK + half * 8]);
+        const f32x4 v1 = *reinterpret_cast<const f32x4*>(&tile[row][q * kSlabK + half * 8 + 4]);
+        const u32x2 p0 = split2(v0[0], v0[1]), p1 = split2(v0[2], v0[3]);
+        const u32x2 p2 = split2(v1[0], v1[1]), p3 = split2(v1[2], v1[3]);
+        const u32x4 hv = {p0[0], p1[0], p2[0], p3[0]}, lv = {p0[1], p1[1], p2[1], p3[1]};
+        const int slot = half ^ ((i >> 3) & 1);  // slab layout: halves swapped when bit 3 of the row is set
         const int64_t off = sq * (int64_t)m * kSlabK + (int64_t)i * kSlabK + slot * 8;
         *reinterpret_cast<u32x4*>(dh + off) = hv;
         *reinterpret_cast<u32x4*>(dl + off) = lv;
