@@ -444,7 +444,9 @@ double orc_isometry_deviation(int64_t rows, int64_t cols, const double* U) {
             double acc = 0.0;
             for (int64_t r = 0; r < rows; r++) acc += U[r * cols + a] * U[r * cols + b];
             double dev = fabs(acc - (a == b ? 1.0 : 0.0));
-            if (dev > worst) worst = dev;
+            /* a NaN entry makes the deviation undefined: keep the NaN */
+            if (dev != dev || dev > worst) worst = dev;
+            if (worst != worst) return worst;
         }
     return worst;
 }

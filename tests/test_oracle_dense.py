@@ -260,3 +260,19 @@ def test_isometry_deviation(oracle_mod):
     V = U.copy()
     V[:, 3] += 0.01 * V[:, 5]
     assert oracle_mod.isometry_deviation(V) == pytest.approx(0.01, rel=1e-10)
+
+
+def test_isometry_deviation_nan(oracle_mod):
+    """A NaN anywhere in U makes U^T U - I undefined in the NaN's row and
+    column: the deviation must be NaN, never a finite value that would pass
+    a tolerance check (a max that skips NaNs reports 0 here for the
+    otherwise exact isometry)."""
+    U = rand_isometry(40, 12, 15)
+    for r, c in ((0, 0), (17, 5), (39, 11)):
+        V = U.copy()
+        V[r, c] = np.nan
+        assert np.isnan(oracle_mod.isometry_deviation(V))
+    V = U.copy()
+    V[3, 4] = np.inf
+    dev = oracle_mod.isometry_deviation(V)
+    assert np.isnan(dev) or dev == np.inf
