@@ -22,6 +22,9 @@ import time
 METRIC = "operator rotations/s + % MFMA peak, m=1024 d=4, FP32 vs split-BF16 @1e-5"
 PEAK_TFLOPS = {"fp32": 157.3, "split_bf16": 2516.6, "fp64": 78.6}  # dense matrix-core peaks
 WORKLOAD = "dense_m1024_n64"
+# dense shared-U workloads timed by bench_dense: the headline, the 512-state
+# batch of 200 operators and the latency-bound 64-state FP64 batch
+DENSE = (WORKLOAD, "dense_m512_n200", "dense_m64_f64")
 
 
 def parse():
@@ -36,7 +39,7 @@ def parse():
     ap.add_argument("--no-fp64-reference", action="store_true",
                     help="skip timing the plain FP64 GPU rotation (speedup denominator)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "blocked_1024_n400", "uneven_1000", "differentiated_m1024_n64",
+                    choices=[*DENSE, "blocked_1024_n400", "uneven_1000", "differentiated_m1024_n64",
                              "site_m1024_n64", "measure_m1024", "density_m1024", "superblock_m1024"],
                     help="default: the headline dense workload; the others time the quantum-number "
                          "blocked batch or the uneven sweep plan")
@@ -569,6 +572,122 @@ def bench_superblock(args, rot, torch, workloads):
     return rec
 
 
+def bench_dense(args, rot, torch, workloads, name):
+    """The dense shared-U workloads: `name` is the headline batch (m = m' =
+    1024, 64 operators), the 512-state batch of 200 operators, or the
+    64-state FP64 batch of 32 operators (launch-latency bound: also timed as
+    hipGraph replays, with its algorithmic bytes per second)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    case = workloads.named_dense(name)
+    m, d, mp, n = case.m, case.d, case.mp, case.O.shape[0]
+    precision = "fp64" if name == "dense_m64_f64" else args.precision
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    U = torch.from_numpy(case.U).to(dt).to(dev)
+    O = torch.from_numpy(case.O).to(dt).to(dev)
+    out = torch.empty((n, mp, mp), dtype=dt, device=dev)
+    # operators whose outputs are compared with the oracle's (the CPU leg's sample)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    n_ref = n if name != WORKLOAD else max(1, min(n, nthreads))
+    outputs = {}
+    main_run = measure(rot, U, O, out, d, precision, args.steps, args.warmup, args.symmetric)
+    outputs[precision] = out[:n_ref].double().cpu().numpy()
+
+    result = base_record(args, main_run["ops_per_s"], "operator rotations/s", main_run["ms_per_step"],
+                         {"workload": name, "m": m, "d": d, "mp": mp, "n_ops": n, "precision": precision,
+                          "operators": "symmetric Gaussian / sqrt(m)" if name != "dense_m64_f64"
+                          else "symmetric Gaussian",
+                          "output": "upper triangle mirrored" if args.symmetric else "full",
+                          "U": f"QR of seeded {m * d}x{mp} Gaussian"},
+                         dtype={"fp32": "f32", "fp64": "f64", "split_bf16": "bf16x3+f32acc"}[precision])
+    result["metric"] = METRIC
+    result.update({
+        "ms_per_step_median": round(main_run["ms_per_step_median"], 4),
+        "ms_per_step_min": round(main_run["ms_per_step_min"], 4),
+        "tflops": round(main_run["tflops"], 2),
+        "pct_mfma_peak": round(main_run["pct_mfma_peak"], 2),
+        "kernels_ms_avg": main_run["kernels_ms_avg"],
+        "roofline": main_run["roofline"],
+    })
+
+    if name == "dense_m64_f64":
+        # latency bound: per-batch time, graph replays, algorithmic bytes/s
+        nbytes = 8.0 * (m * d * mp + n * m * m + n * mp * mp)
+        p = rot._problem(U, O, out, d)
+        ws = torch.empty(rot.rot_workspace_size([p], rot.ROT_FP64), dtype=torch.uint8, device=dev)
+        stream = torch.cuda.Stream()
+        stream.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(stream):
+            rot.rotate(U, O, d, "fp64", out=out, workspace=ws)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(graph, stream=stream):
+                rot.rotate(U, O, d, "fp64", out=out, workspace=ws)
+        torch.cuda.current_stream().wait_stream(stream)
+        ms_graph = timed_loop(torch, graph.replay, max(args.steps, 50), args.warmup)
+        us = main_run["ms_per_step"] * 1e3
+        result["unit"] = "operator rotations/s"
+        result.update({"us_per_batch": round(us, 2), "us_per_batch_graph_replay": round(ms_graph * 1e3, 2),
+                       "algorithmic_bytes_per_batch": nbytes,
+                       "algorithmic_gb_per_s": round(nbytes / (main_run["ms_per_step"] / 1e3) / 1e9, 2),
+                       "algorithmic_gb_per_s_graph": round(nbytes / (ms_graph / 1e3) / 1e9, 2)})
+        result["roofline"] = {"bound": "hbm", "achieved": result["algorithmic_gb_per_s_graph"],
+                              "peak": 8000.0, "unit": "GB/s",
+                              "frac": round(result["algorithmic_gb_per_s_graph"] / 8000.0, 5), "traffic": None,
+                              "kernel": "whole batch (2 launches)",
+                              "note": "134 MFLOP and 2.23 MB per batch: two dependent launches of 16 tiles "
+                                      "each; the time is launch latency, not bandwidth or matrix throughput"}
+        del graph
+
+    if precision == "fp32" and not args.no_split_bf16:
+        b = measure(rot, U, O, out, d, "split_bf16", args.steps, args.warmup, args.symmetric)
+        outputs["split_bf16"] = out[:n_ref].double().cpu().numpy()
+        result["split_bf16"] = {"value": round(b["ops_per_s"], 2), "unit": "operator rotations/s",
+                                "ms_per_step": round(b["ms_per_step"], 4),
+                                "ms_per_step_median": round(b["ms_per_step_median"], 4),
+                                "ms_per_step_min": round(b["ms_per_step_min"], 4),
+                                "tflops_fp32_equivalent": round(b["tflops"], 2),
+                                "pct_bf16_mfma_peak": round(b["pct_mfma_peak"], 2),
+                                "speedup_vs_fp32": round(b["ops_per_s"] / main_run["ops_per_s"], 3),
+                                "kernels_ms_avg": b["kernels_ms_avg"], "roofline": b["roofline"]}
+
+    if precision == "fp32" and name == WORKLOAD and not (args.no_split_bf16 or args.symmetric or args.no_symmetric):
+        # the headline operators are symmetric, so the symmetric-output path applies to them
+        sym = {}
+        for prec in ("fp32", "split_bf16"):
+            r = measure(rot, U, O, out, d, prec, args.steps, args.warmup, symmetric=True)
+            outputs[prec + "_symmetric_output"] = out[:n_ref].double().cpu().numpy()
+            sym[prec] = {"value": round(r["ops_per_s"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                         "ms_per_step_median": round(r["ms_per_step_median"], 4),
+                         "tflops_algorithmic": round(r["tflops"], 2),
+                         "kernels_ms_avg": r["kernels_ms_avg"]}
+        sym["unit"] = "operator rotations/s"
+        sym["flops_per_op"] = flops_per_op(m, d, mp, True)
+        result["symmetric_output"] = sym
+
+    if not args.no_fp64_reference and precision != "fp64":
+        U64, O64 = U.double(), O.double()
+        out64 = torch.empty((n, mp, mp), dtype=torch.float64, device=dev)
+        r64 = measure(rot, U64, O64, out64, d, "fp64", max(2, args.steps // 5), 1)
+        result["fp64_gpu_ops_per_s"] = round(r64["ops_per_s"], 2)
+        result["speedup_vs_fp64_gpu"] = round(main_run["ops_per_s"] / r64["ops_per_s"], 3)
+        del U64, O64, out64
+        naive = torch_fp64_naive(torch, U, O, d)
+        result["torch_fp64_kron_ops_per_s"] = round(naive, 2)
+        result["speedup_vs_torch_fp64_kron"] = round(main_run["ops_per_s"] / naive, 2)
+
+    if not args.no_cpu_baseline:
+        # the headline batch: one operator per host thread; the smaller
+        # configurations run the oracle on the whole batch
+        rec, ref = cpu_baseline(case, n, n_sample=n_ref, one_thread=name == WORKLOAD)
+        result["cpu_baseline"] = rec
+        result["error"] = {k: parity_error(v, ref) for k, v in outputs.items()}
+        result["error"]["reference"] = (f"oracle (FP64, explicit kron) on the first {n_ref} of {n} operators; "
+                                        "relative Frobenius error per operator")
+        result["error"]["bound"] = 1e-12 if precision == "fp64" else 1e-5
+    return result
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -579,24 +698,36 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(case, n_total):
+def cpu_baseline(case, n_total, n_sample=None, one_thread=True):
     """The oracle, as it stands, on a bounded sample: one operator per host
-    thread (at most the whole batch), all threads of this process; then one
-    operator on one thread."""
+    thread (at most the whole batch; n_sample overrides), all threads of this
+    process; then one operator on one thread.  Returns the record and the
+    oracle's outputs for the sampled operators (the parity reference)."""
     import oracle
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    n_s = max(1, min(n_total, nthreads))
+    n_s = max(1, min(n_total, nthreads if n_sample is None else n_sample))
     t0 = time.perf_counter()
-    oracle.rotate(case.U, case.O[:n_s], case.d, nthreads=nthreads)
+    ref = oracle.rotate(case.U, case.O[:n_s], case.d, nthreads=nthreads)
     dt = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.rotate(case.U, case.O[:1], case.d, nthreads=1)
-    dt1 = time.perf_counter() - t0
-    return {"value": n_s / dt, "unit": "operator rotations/s", "cores": min(nthreads, n_s),
-            "kind": "oracle",
-            "sample": f"{n_s} of {n_total} operators (m=1024, d=4, m'=1024), FP64, explicit kron, "
-                      f"{dt:.1f} s wall; then 1 operator on 1 thread, {dt1:.1f} s",
-            "value_1thread": 1.0 / dt1, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    rec = {"value": n_s / dt, "unit": "operator rotations/s", "cores": min(nthreads, n_s),
+           "kind": "oracle",
+           "sample": f"{n_s} of {n_total} operators (m={case.m}, d={case.d}, m'={case.mp}), FP64, explicit kron, "
+                     f"{dt:.1f} s wall", "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if one_thread:
+        t0 = time.perf_counter()
+        oracle.rotate(case.U, case.O[:1], case.d, nthreads=1)
+        dt1 = time.perf_counter() - t0
+        rec["sample"] += f"; then 1 operator on 1 thread, {dt1:.1f} s"
+        rec["value_1thread"] = 1.0 / dt1
+    return rec, ref
+
+
+def parity_error(got, ref):
+    """Max and median over operators of ||got_b - ref_b||_F / ||ref_b||_F."""
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64)
+    err = np.sqrt(((got - ref) ** 2).sum((1, 2))) / np.sqrt((ref ** 2).sum((1, 2)))
+    return {"max": float(err.max()), "median": float(np.median(err)), "operators": int(err.size)}
 
 
 def torch_fp64_naive(torch, U, O, d, sample=8, reps=3):
@@ -647,7 +778,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}))
         return
 
-    if args.workload != WORKLOAD:
+    if args.workload not in DENSE:
         fn = {"blocked_1024_n400": bench_blocked, "uneven_1000": bench_uneven,
               "differentiated_m1024_n64": bench_differentiated, "site_m1024_n64": bench_site,
               "measure_m1024": bench_measure, "density_m1024": bench_density,
@@ -655,77 +786,7 @@ def main():
         print(json.dumps(fn(args, rot, torch, workloads)), flush=True)
         return
 
-    case = workloads.named_dense(WORKLOAD)
-    m, d, mp, n = case.m, case.d, case.mp, case.O.shape[0]
-    dt = torch.float64 if args.precision == "fp64" else torch.float32
-    U = torch.from_numpy(case.U).to(dt).to(dev)
-    O = torch.from_numpy(case.O).to(dt).to(dev)
-    out = torch.empty((n, mp, mp), dtype=dt, device=dev)
-    main_run = measure(rot, U, O, out, d, args.precision, args.steps, args.warmup, args.symmetric)
-
-    result = {
-        "metric": METRIC,
-        "value": round(main_run["ops_per_s"], 2),
-        "unit": "operator rotations/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(main_run["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "split_bf16": "bf16x3+f32acc"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": WORKLOAD, "m": m, "d": d, "mp": mp, "n_ops": n,
-                   "precision": args.precision, "operators": "symmetric Gaussian / sqrt(m)",
-                   "output": "upper triangle mirrored" if args.symmetric else "full",
-                   "U": "QR of seeded 4096x1024 Gaussian"},
-        "ms_per_step_median": round(main_run["ms_per_step_median"], 4),
-        "ms_per_step_min": round(main_run["ms_per_step_min"], 4),
-        "tflops": round(main_run["tflops"], 2),
-        "pct_mfma_peak": round(main_run["pct_mfma_peak"], 2),
-        "kernels_ms_avg": main_run["kernels_ms_avg"],
-        "roofline": main_run["roofline"],
-    }
-
-    if args.precision == "fp32" and not args.no_split_bf16:
-        b = measure(rot, U, O, out, d, "split_bf16", args.steps, args.warmup, args.symmetric)
-        result["split_bf16"] = {"value": round(b["ops_per_s"], 2), "unit": "operator rotations/s",
-                                "ms_per_step": round(b["ms_per_step"], 4),
-                                "ms_per_step_median": round(b["ms_per_step_median"], 4),
-                                "ms_per_step_min": round(b["ms_per_step_min"], 4),
-                                "tflops_fp32_equivalent": round(b["tflops"], 2),
-                                "pct_bf16_mfma_peak": round(b["pct_mfma_peak"], 2),
-                                "speedup_vs_fp32": round(b["ops_per_s"] / main_run["ops_per_s"], 3),
-                                "kernels_ms_avg": b["kernels_ms_avg"], "roofline": b["roofline"]}
-
-    if args.precision == "fp32" and not (args.no_split_bf16 or args.symmetric or args.no_symmetric):
-        # the headline operators are symmetric, so the symmetric-output path applies to them
-        sym = {}
-        for prec in ("fp32", "split_bf16"):
-            r = measure(rot, U, O, out, d, prec, args.steps, args.warmup, symmetric=True)
-            sym[prec] = {"value": round(r["ops_per_s"], 2), "ms_per_step": round(r["ms_per_step"], 4),
-                         "ms_per_step_median": round(r["ms_per_step_median"], 4),
-                         "tflops_algorithmic": round(r["tflops"], 2),
-                         "kernels_ms_avg": r["kernels_ms_avg"]}
-        sym["unit"] = "operator rotations/s"
-        sym["flops_per_op"] = flops_per_op(m, d, mp, True)
-        result["symmetric_output"] = sym
-
-    if not args.no_fp64_reference and args.precision != "fp64":
-        U64, O64 = U.double(), O.double()
-        out64 = torch.empty((n, mp, mp), dtype=torch.float64, device=dev)
-        r64 = measure(rot, U64, O64, out64, d, "fp64", max(2, args.steps // 5), 1)
-        result["fp64_gpu_ops_per_s"] = round(r64["ops_per_s"], 2)
-        result["speedup_vs_fp64_gpu"] = round(main_run["ops_per_s"] / r64["ops_per_s"], 3)
-        del U64, O64, out64
-        naive = torch_fp64_naive(torch, U, O, d)
-        result["torch_fp64_kron_ops_per_s"] = round(naive, 2)
-        result["speedup_vs_torch_fp64_kron"] = round(main_run["ops_per_s"] / naive, 2)
-
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(case, n)
-    print(json.dumps(result), flush=True)
+    print(json.dumps(bench_dense(args, rot, torch, workloads, args.workload)), flush=True)
 
 
 if __name__ == "__main__":

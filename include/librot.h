@@ -72,19 +72,27 @@ typedef enum {
  *   d      added-site dimension (> 0; 4 for the Hubbard chain of Eq. (4))
  *   mp     number of kept states (0 < mp <= m*d)
  *   n_ops  number of operators (>= 0; 0 is a no-op)
- *   U      (m*d) x mp, contiguous, row r = i*d + s
- *   O      operator b is the contiguous m x m matrix at O + b*stride_o
- *          (stride_o >= m*m, in elements)
- *   out    result b is the contiguous mp x mp matrix at out + b*stride_out
- *          (stride_out >= mp*mp); must not overlap U or O
+ *   U      (m*d) x mp, row r = i*d + s, element (r, a) at U[r*ldu + a];
+ *          ldu >= mp (0 selects mp)
+ *   O      operator b is the m x m matrix at O + b*stride_o, element (i, j)
+ *          at [i*ldo + j]; ldo >= m (0 selects m); stride_o >= (m-1)*ldo + m
+ *   out    result b is the mp x mp matrix at out + b*stride_out, element
+ *          (a, c) at [a*ldout + c]; ldout >= mp (0 selects mp); stride_out
+ *          >= (mp-1)*ldout + mp; must not overlap U or O.  Only the mp
+ *          entries of each row are written: padding between rows is kept.
+ * All leading dimensions and strides are in elements.  16-byte aligned
+ * pointers with leading dimensions and strides that are multiples of 4
+ * (FP32) or 2 (FP64) take the vector load paths; any other layout is
+ * accepted and read element by element at the edges of each tile.
  */
 typedef struct {
     int32_t m, d, mp, n_ops;
     const void* U;
+    int64_t ldu;
     const void* O;
-    int64_t stride_o;
+    int64_t ldo, stride_o;
     void* out;
-    int64_t stride_out;
+    int64_t ldout, stride_out;
 } rot_problem;
 
 /*
@@ -418,13 +426,15 @@ ROT_API size_t rot_pair_loss_workspace_size(int32_t mp, int32_t n_ops);
  * Isometry check of a truncation matrix (Sec. 2: the kept eigenvectors are
  * orthonormal; the block basis is complete only up to the truncation):
  * computes max_{a,b} |(U^T U - I)[a,b]| in FP64 on the GPU for a rows x cols
- * row-major U (float or double per prec).  Synchronises `stream`, stores the
- * deviation in *max_dev_host and returns ROT_ERR_NOT_ISOMETRY when it
- * exceeds `tol` (ROT_OK otherwise).  workspace: at least
+ * row-major U (float or double per prec) with row stride ldu >= cols (0
+ * selects cols).  Synchronises `stream`, stores the deviation in
+ * *max_dev_host and returns ROT_ERR_NOT_ISOMETRY when it exceeds `tol` or
+ * is NaN (a NaN or infinite entry of U makes the deviation NaN or infinite;
+ * ROT_OK otherwise).  workspace: at least
  * rot_isometry_workspace_size(rows, cols, prec) bytes, 256-byte aligned.
  */
-ROT_API rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, rot_precision prec,
-                              double tol, double* max_dev_host, void* workspace,
+ROT_API rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, int64_t ldu,
+                              rot_precision prec, double tol, double* max_dev_host, void* workspace,
                               size_t workspace_bytes, void* stream);
 ROT_API size_t rot_isometry_workspace_size(int32_t rows, int32_t cols, rot_precision prec);
 

@@ -25,7 +25,7 @@ import torch
 
 __all__ = [
     "ROT_FP64", "ROT_FP32", "ROT_SPLIT_BF16", "ROT_ASSUME_SYMMETRIC_O", "RotError",
-    "RotProblem", "RotSector", "RotBlockedProblem", "lib", "library_path",
+    "RotProblem", "problem", "RotSector", "RotBlockedProblem", "lib", "library_path",
     "rot_batch", "rot_backward", "rot_batch_blocked", "rot_pair_loss", "rot_check_isometry",
     "rot_split_bf16", "rot_workspace_size", "rot_blocked_workspace_size",
     "rotate", "rotate_backward", "pair_loss", "check_isometry", "split_bf16",
@@ -53,9 +53,19 @@ class RotError(RuntimeError):
 
 
 class RotProblem(ctypes.Structure):
+    """rot_problem: leading dimensions ldu, ldo, ldout of 0 select the packed values."""
     _fields_ = [("m", ctypes.c_int32), ("d", ctypes.c_int32), ("mp", ctypes.c_int32),
-                ("n_ops", ctypes.c_int32), ("U", ctypes.c_void_p), ("O", ctypes.c_void_p),
-                ("stride_o", ctypes.c_int64), ("out", ctypes.c_void_p), ("stride_out", ctypes.c_int64)]
+                ("n_ops", ctypes.c_int32), ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+                ("O", ctypes.c_void_p), ("ldo", ctypes.c_int64), ("stride_o", ctypes.c_int64),
+                ("out", ctypes.c_void_p), ("ldout", ctypes.c_int64), ("stride_out", ctypes.c_int64)]
+
+
+def problem(m: int, d: int, mp: int, n_ops: int, U: int, O: int, out: int, ldu: int = 0, ldo: int = 0,
+            stride_o: int | None = None, ldout: int = 0, stride_out: int | None = None) -> RotProblem:
+    """A rot_problem from raw device addresses (packed layouts by default)."""
+    lo, lout = ldo or m, ldout or mp
+    return RotProblem(m, d, mp, n_ops, U, ldu, O, ldo, (m - 1) * lo + m if stride_o is None else stride_o,
+                      out, ldout, (mp - 1) * lout + mp if stride_out is None else stride_out)
 
 
 ROT_BLOCK_IDENTITY, ROT_BLOCK_DIAGONAL, ROT_BLOCK_DENSE = 0, 1, 2
@@ -138,7 +148,7 @@ def lib() -> ctypes.CDLL:
         L.rot_pair_loss.argtypes = [vp, i32, i32, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz, vp]
         L.rot_pair_loss_workspace_size.argtypes = [i32, i32]
         L.rot_pair_loss_workspace_size.restype = sz
-        L.rot_check_isometry.argtypes = [vp, i32, i32, ctypes.c_int, ctypes.c_double,
+        L.rot_check_isometry.argtypes = [vp, i32, i32, i64, ctypes.c_int, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_double), vp, sz, vp]
         L.rot_isometry_workspace_size.argtypes = [i32, i32, ctypes.c_int]
         L.rot_isometry_workspace_size.restype = sz
@@ -269,9 +279,9 @@ def rot_pair_loss(X: int, mp: int, n_ops: int, stride_x: int, prec: int, psi: in
 
 
 def rot_check_isometry(U: int, rows: int, cols: int, prec: int, tol: float, workspace: int,
-                       workspace_bytes: int, stream: int) -> tuple[int, float]:
+                       workspace_bytes: int, stream: int, ldu: int = 0) -> tuple[int, float]:
     dev = ctypes.c_double(float("nan"))
-    st = lib().rot_check_isometry(U, rows, cols, prec, tol, ctypes.byref(dev), workspace,
+    st = lib().rot_check_isometry(U, rows, cols, ldu, prec, tol, ctypes.byref(dev), workspace,
                                   workspace_bytes, stream)
     if st not in (0, -5):
         _check(st)
@@ -288,22 +298,60 @@ def _dtype_for(prec: int):
     return torch.float64 if prec == ROT_FP64 else torch.float32
 
 
+def _row_layout(t: torch.Tensor, name: str) -> tuple[int, int]:
+    """(row stride, matrix stride) of a 2-D matrix or 3-D batch of matrices
+    whose rows are contiguous (unit last stride), rows and matrices not
+    overlapping: the layouts the C ABI's leading dimensions describe."""
+    if t.dim() not in (2, 3) or any(n <= 0 for n in t.shape):
+        raise ValueError(f"{name}: expected a non-empty 2-D or 3-D tensor, got shape {tuple(t.shape)}")
+    rows, cols = t.shape[-2], t.shape[-1]
+    if t.stride(-1) != 1 and cols > 1:
+        raise ValueError(f"{name}: rows must be contiguous (unit last stride)")
+    ld = t.stride(-2) if rows > 1 else cols
+    if ld < cols:
+        raise ValueError(f"{name}: row stride {ld} below the row length {cols}")
+    extent = (rows - 1) * ld + cols
+    bs = extent
+    if t.dim() == 3:
+        bs = t.stride(0) if t.shape[0] > 1 else extent
+        if bs < extent:
+            raise ValueError(f"{name}: matrices overlap (stride {bs} < {extent})")
+    return ld, bs
+
+
 def _problem(U: torch.Tensor, O: torch.Tensor, out: torch.Tensor, d: int) -> RotProblem:
     n, m, _ = O.shape
-    return RotProblem(m, d, U.shape[1], n, U.data_ptr(), O.data_ptr(), m * m, out.data_ptr(),
-                      out.shape[1] * out.shape[2])
+    ldu, _ = _row_layout(U, "U")
+    ldo, so = _row_layout(O, "O")
+    ldout, sout = _row_layout(out, "out")
+    return RotProblem(m, d, U.shape[1], n, U.data_ptr(), ldu, O.data_ptr(), ldo, so, out.data_ptr(), ldout, sout)
 
 
 def _check_inputs(U: torch.Tensor, O: torch.Tensor, d: int, prec: int) -> None:
     dt = _dtype_for(prec)
     if U.dtype != dt or O.dtype != dt:
         raise TypeError(f"precision {prec} needs {dt} tensors, got {U.dtype}/{O.dtype}")
-    if not (U.is_cuda and O.is_cuda):
-        raise ValueError("U and O must be device tensors")
-    if not (U.is_contiguous() and O.is_contiguous()):
-        raise ValueError("U and O must be contiguous")
+    if not (U.is_cuda and O.is_cuda) or U.device != O.device:
+        raise ValueError("U and O must be tensors on one GPU")
     if O.dim() != 3 or O.shape[1] != O.shape[2] or U.dim() != 2 or U.shape[0] != O.shape[1] * d:
         raise ValueError("expected O (n, m, m) and U (m*d, mp)")
+    _row_layout(U, "U")
+    _row_layout(O, "O")
+
+
+def _check_like(t: torch.Tensor, U: torch.Tensor, shape: tuple, name: str, contiguous: bool = True) -> None:
+    """t must live on U's device with U's dtype and exactly `shape`; checked
+    before anything is launched."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if not t.is_cuda or t.device != U.device:
+        raise ValueError(f"{name} must be on {U.device}, got {t.device}")
+    if t.dtype != U.dtype:
+        raise TypeError(f"{name} must have dtype {U.dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if contiguous and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
 
 
 def rotate(U: torch.Tensor, O: torch.Tensor, d: int, precision="fp32", out: torch.Tensor | None = None,
@@ -317,6 +365,9 @@ def rotate(U: torch.Tensor, O: torch.Tensor, d: int, precision="fp32", out: torc
     mp = U.shape[1]
     if out is None:
         out = torch.empty((n, mp, mp), dtype=U.dtype, device=U.device)
+    else:
+        _check_like(out, U, (n, mp, mp), "out", contiguous=False)
+        _row_layout(out, "out")
     p = _problem(U, O, out, d)
     if workspace is None:
         workspace = _workspace(rot_workspace_size([p], prec), U.device)
@@ -566,11 +617,11 @@ def rotate_backward(U: torch.Tensor, O: torch.Tensor, d: int, dOut: torch.Tensor
     _check_inputs(U, O, d, prec)
     n, m, _ = O.shape
     mp = U.shape[1]
-    if not dOut.is_contiguous() or dOut.dtype != U.dtype:
-        raise ValueError("dOut must be contiguous with the dtype of U")
+    _check_like(dOut, U, (mp, mp) if dOut.dim() == 2 else (n, mp, mp), "dOut")
     sd = 0 if dOut.dim() == 2 else mp * mp
-    dO = torch.empty_like(O) if need_dO else None
-    dU = torch.empty_like(U) if need_dU else None
+    # the adjoint writes packed outputs: dO (n, m, m) and dU (m*d, mp)
+    dO = torch.empty((n, m, m), dtype=O.dtype, device=O.device) if need_dO else None
+    dU = torch.empty((m * d, mp), dtype=U.dtype, device=U.device) if need_dU else None
     dummy = torch.empty((1, mp, mp), dtype=U.dtype, device=U.device)
     p = _problem(U, O, dummy, d)
     if workspace is None:
@@ -589,7 +640,11 @@ def pair_loss(X: torch.Tensor, psi: torch.Tensor, want_pairs: bool = False, want
         ROT_FP64 if X.dtype == torch.float64 else ROT_FP32)
     if X.dtype != _dtype_for(prec) or psi.dtype != torch.float64 or not X.is_contiguous():
         raise TypeError("X must be contiguous float32/float64 matching precision; psi float64")
+    if not X.is_cuda or X.dim() != 3 or X.shape[1] != X.shape[2] or X.shape[0] < 1:
+        raise ValueError("X must be a (n, mp, mp) device tensor with n >= 1")
     n, mp, _ = X.shape
+    if not psi.is_cuda or psi.device != X.device or tuple(psi.shape) != (mp,):
+        raise ValueError(f"psi must be a ({mp},) float64 tensor on {X.device}")
     loss = torch.empty((), dtype=torch.float64, device=X.device)
     pairs = torch.empty((n, n), dtype=torch.float64, device=X.device) if want_pairs else None
     grad = torch.empty((mp, mp), dtype=X.dtype, device=X.device) if want_grad else None
@@ -600,12 +655,16 @@ def pair_loss(X: torch.Tensor, psi: torch.Tensor, want_pairs: bool = False, want
 
 
 def check_isometry(U: torch.Tensor, tol: float = 1e-6, stream=None) -> tuple[bool, float]:
-    """(ok, max|U^T U - I|) computed in FP64 on the GPU."""
+    """(ok, max|U^T U - I|) computed in FP64 on the GPU; U may have padded
+    rows (unit last stride)."""
     prec = ROT_FP64 if U.dtype == torch.float64 else ROT_FP32
+    if U.dtype not in (torch.float32, torch.float64) or not U.is_cuda:
+        raise TypeError("U must be a float32/float64 device tensor")
     rows, cols = U.shape
+    ldu, _ = _row_layout(U, "U")
     ws = _workspace(lib().rot_isometry_workspace_size(rows, cols, prec), U.device)
-    st, dev = rot_check_isometry(U.contiguous().data_ptr(), rows, cols, prec, tol, ws.data_ptr(), ws.numel(),
-                                 _stream(stream))
+    st, dev = rot_check_isometry(U.data_ptr(), rows, cols, prec, tol, ws.data_ptr(), ws.numel(), _stream(stream),
+                                 ldu=ldu)
     return st == 0, dev
 
 
@@ -740,10 +799,10 @@ class RotateFn(torch.autograd.Function):
     def backward(ctx, dOut):
         U, O = ctx.saved_tensors
         prec = precision_code(ctx.precision)
-        bprec = ROT_FP32 if prec == ROT_SPLIT_BF16 else prec
         if dOut.dim() == 3 and dOut.stride(0) == 0 and dOut[0].is_contiguous():
             dOut = dOut[0]  # one matrix broadcast to every operator: pass stride 0
-        dO, dU = rotate_backward(U, O, ctx.d, dOut.contiguous(), bprec, ctx.needs_input_grad[1],
+        # the adjoint runs in the forward's own arithmetic (FP64, FP32 or split-BF16)
+        dO, dU = rotate_backward(U, O, ctx.d, dOut.contiguous(), prec, ctx.needs_input_grad[1],
                                  ctx.needs_input_grad[0], ctx.symmetric_O)
         return dU, dO, None, None, None
 

@@ -374,12 +374,13 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc
                                   !EPI_T && g.upper && m0 != n0, !EPI_T && g.upper && m0 == n0);
 }
 
-// U (rows = m*d, cols = mp), row r = j*d + s, both split into hi/lo (slab layout):
+// U (rows = m*d, cols = mp, row stride ldu), row r = j*d + s, both split
+// into hi/lo (slab layout):
 //   U1 (d*mp rows, K = m):   element (beta*d + s, j) = U[j*d+s][beta]
 //   U2 (mp rows, K = m*d):   element (alpha, r)      = U[r][alpha]
 // 64 x 64 tiles through LDS.
-__global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ U, int rows, int cols, int d,
-                                                      uint16_t* __restrict__ u1h, uint16_t* __restrict__ u1l,
+__global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ U, int rows, int cols, int64_t ldu,
+                                                      int d, uint16_t* __restrict__ u1h, uint16_t* __restrict__ u1l,
                                                       uint16_t* __restrict__ u2h, uint16_t* __restrict__ u2l) {
     __shared__ float tile[64][65];
     const int r0 = blockIdx.y * 64, a0 = blockIdx.x * 64;
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         const int r = r0 + ty + 4 * k, a = a0 + tx;
-        tile[ty + 4 * k][tx] = (r < rows && a < cols) ? U[(int64_t)r * cols + a] : 0.f;
+        tile[ty + 4 * k][tx] = (r < rows && a < cols) ? U[(int64_t)r * ldu + a] : 0.f;
     }
     __syncthreads();
     const int r = r0 + tx;
@@ -410,27 +411,27 @@ __global__ __launch_bounds__(256) void split_u_kernel(const float* __restrict__ 
     }
 }
 
-// O_b (m x m at O + b*stride_o) -> hi/lo at b*ob in slab layout (m rows,
-// K = m), one 64 x 64 block per workgroup.  Rows are read into LDS (16-byte
+// O_b (m x m at O + b*stride_o, row stride ldo) -> hi/lo at b*ob in slab
+// layout (m rows, K = m), one 64 x 64 block per workgroup.  Rows are read into LDS (16-byte
 // loads when the block lies inside O and its rows are 16-byte aligned), then
 // each thread converts 8 values (one k half of one row in one slab) and
 // writes them as one 16-byte chunk per array.  Each 16 lanes take 16
 // consecutive rows and the same k half, so with a row pitch of 68 floats
 // both the 16-byte LDS writes and reads touch all 64 banks once.  Columns
 // past m in the last slab are written as zero.
-__global__ __launch_bounds__(256) void split_o_kernel(const float* __restrict__ O, int m, int64_t stride_o,
-                                                      uint16_t* __restrict__ oh, uint16_t* __restrict__ ol,
-                                                      int64_t ob) {
+__global__ __launch_bounds__(256) void split_o_kernel(const float* __restrict__ O, int m, int64_t ldo,
+                                                      int64_t stride_o, uint16_t* __restrict__ oh,
+                                                      uint16_t* __restrict__ ol, int64_t ob) {
     __shared__ __attribute__((aligned(16))) float tile[64][68];
     const int b = blockIdx.z, i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
     const float* src = O + (int64_t)b * stride_o;
     const int tid = threadIdx.x;
-    if (j0 + 64 <= m && (m & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    if (j0 + 64 <= m && (ldo & 3) == 0 && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const int r = (tid >> 4) + 16 * k, c4 = (tid & 15) * 4, i = i0 + r;
             f32x4 v = {0.f, 0.f, 0.f, 0.f};
-            if (i < m) v = *reinterpret_cast<const f32x4*>(src + (int64_t)i * m + j0 + c4);
+            if (i < m) v = *reinterpret_cast<const f32x4*>(src + (int64_t)i * ldo + j0 + c4);
             *reinterpret_cast<f32x4*>(&tile[r][c4]) = v;
         }
     } else {
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(256) void split_o_kernel(const float* __restrict__ 
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             const int i = i0 + ty + 4 * k, j = j0 + tx;
-            tile[ty + 4 * k][tx] = (i < m && j < m) ? src[(int64_t)i * m + j] : 0.f;
+            tile[ty + 4 * k][tx] = (i < m && j < m) ? src[(int64_t)i * ldo + j] : 0.f;
         }
     }
     __syncthreads();
@@ -558,6 +559,7 @@ size_t bf16_group_workspace(int m, int d, int mp, int ops) {
     return L.shared + (size_t)ops * 2 * (L.t_op + L.o_op);
 }
 
+// p has its leading dimensions resolved.
 hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, hipStream_t stream) {
     const Bf16Layout L = layout(p.m, p.d, p.mp);
     char* base = static_cast<char*>(ws);
@@ -577,7 +579,7 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symm
             if (err == hipSuccess) err = zero_last_slab(u2h, u2l, L.u2_rows, rows, 0, 1, stream);
             if (err != hipSuccess) return err;
             hipLaunchKernelGGL(split_u_kernel, grid, dim3(256), 0, stream, static_cast<const float*>(p.U), rows,
-                               p.mp, p.d, u1h, u1l, u2h, u2l);
+                               p.mp, p.ldu, p.d, u1h, u1l, u2h, u2l);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
@@ -605,7 +607,7 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symm
         if (err != hipSuccess) return err;
         const float* Ob = static_cast<const float*>(p.O) + (int64_t)b0 * p.stride_o;
         const dim3 grid((p.m + 63) / 64, (p.m + 63) / 64, nb);
-        hipLaunchKernelGGL(split_o_kernel, grid, dim3(256), 0, stream, Ob, p.m, p.stride_o, oh, ol,
+        hipLaunchKernelGGL(split_o_kernel, grid, dim3(256), 0, stream, Ob, p.m, p.ldo, p.stride_o, oh, ol,
                            (int64_t)(L.o_op / 2));
         return hipGetLastError();
     });
@@ -625,7 +627,7 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symm
     b.b_lo = tl;
     b.b_bs = (int64_t)(L.t_op / 2);
     b.c = static_cast<float*>(p.out) + (int64_t)b0 * p.stride_out;
-    b.ldc = p.mp;
+    b.ldc = p.ldout;
     b.c_bs = p.stride_out;
     b.upper = symmetric ? 1 : 0;
     return prof_timed(symmetric ? "stage2sym_bf16x3" : "stage2_bf16x3", stream,

@@ -91,9 +91,32 @@ size_t elem_size(rot_precision p) { return p == ROT_FP64 ? 8 : 4; }
 
 bool valid_precision(int p) { return p == ROT_FP64 || p == ROT_FP32 || p == ROT_SPLIT_BF16; }
 
-// Bytes of one operator's stage-1 intermediate T_b ((m*d) x mp).
+// A group with its leading dimensions resolved (0 selects the packed value).
+rot_problem resolved(const rot_problem& p) {
+    rot_problem q = p;
+    if (q.ldu == 0) q.ldu = q.mp;
+    if (q.ldo == 0) q.ldo = q.m;
+    if (q.ldout == 0) q.ldout = q.mp;
+    return q;
+}
+
+std::vector<rot_problem> resolved_all(const rot_problem* groups, int n) {
+    std::vector<rot_problem> v(groups, groups + std::max(n, 0));
+    for (auto& q : v) q = resolved(q);
+    return v;
+}
+
+// Bytes of one operator's stage-1 intermediate T_b ((m*d) x mp, row stride
+// ldu: T_b takes U's row layout so stage 1 can read U_r with one leading
+// dimension, see stage1()).
 size_t t_bytes(const rot_problem& p, rot_precision prec) {
-    return align_up((size_t)p.m * p.d * p.mp * elem_size(prec));
+    return align_up((size_t)p.m * p.d * p.ldu * elem_size(prec));
+}
+
+// Bytes of U packed to row stride mp (the adjoint's products read U_r, the
+// m x d*mp view, which only a packed U provides).
+size_t packed_u_bytes(const rot_problem& p, rot_precision prec) {
+    return p.ldu == p.mp ? 0 : align_up((size_t)p.m * p.d * p.mp * elem_size(prec));
 }
 
 // The dU reduction of rot_backward is one GEMM with M = m, N = d*mp and a K
@@ -110,6 +133,7 @@ int du_split_parts(const rot_problem& p, int ops) {
     return parts > 1 ? parts : 0;
 }
 
+// p must be resolved (leading dimensions filled in).
 rot_status validate_group(const rot_problem& p, int gi) {
     if (p.m <= 0 || p.d <= 0 || p.mp <= 0)
         return fail(ROT_ERR_INVALID_ARG, "group %d: m, d, mp must be positive (m=%d d=%d mp=%d)", gi,
@@ -121,10 +145,16 @@ rot_status validate_group(const rot_problem& p, int gi) {
     if (p.n_ops < 0) return fail(ROT_ERR_INVALID_ARG, "group %d: negative n_ops", gi);
     if (p.n_ops == 0) return ROT_OK;
     if (!p.U || !p.O || !p.out) return fail(ROT_ERR_INVALID_ARG, "group %d: null U, O or out", gi);
-    if (p.stride_o < (int64_t)p.m * p.m)
-        return fail(ROT_ERR_INVALID_ARG, "group %d: stride_o %lld < m*m", gi, (long long)p.stride_o);
-    if (p.stride_out < (int64_t)p.mp * p.mp)
-        return fail(ROT_ERR_INVALID_ARG, "group %d: stride_out %lld < mp*mp", gi, (long long)p.stride_out);
+    if (p.ldu < p.mp || p.ldo < p.m || p.ldout < p.mp)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: leading dimensions ldu=%lld ldo=%lld ldout=%lld below mp, m, mp",
+                    gi, (long long)p.ldu, (long long)p.ldo, (long long)p.ldout);
+    if (p.ldu > INT32_MAX || (int64_t)p.d * p.ldu > INT32_MAX)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: d*ldu exceeds 2^31-1", gi);
+    if (p.stride_o < (int64_t)(p.m - 1) * p.ldo + p.m)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: stride_o %lld < (m-1)*ldo + m", gi, (long long)p.stride_o);
+    if (p.stride_out < (int64_t)(p.mp - 1) * p.ldout + p.mp)
+        return fail(ROT_ERR_INVALID_ARG, "group %d: stride_out %lld < (mp-1)*ldout + mp", gi,
+                    (long long)p.stride_out);
     return ROT_OK;
 }
 
@@ -136,37 +166,42 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 rot_status validate_outputs_disjoint(const rot_problem& p, rot_precision prec, int gi) {
     const size_t es = elem_size(prec);
-    const size_t n_out = ((size_t)(p.n_ops - 1) * p.stride_out + (size_t)p.mp * p.mp) * es;
-    const size_t n_o = ((size_t)(p.n_ops - 1) * p.stride_o + (size_t)p.m * p.m) * es;
-    const size_t n_u = (size_t)p.m * p.d * p.mp * es;
+    const size_t n_out = ((size_t)(p.n_ops - 1) * p.stride_out + (size_t)(p.mp - 1) * p.ldout + p.mp) * es;
+    const size_t n_o = ((size_t)(p.n_ops - 1) * p.stride_o + (size_t)(p.m - 1) * p.ldo + p.m) * es;
+    const size_t n_u = ((size_t)p.m * p.d - 1) * p.ldu * es + (size_t)p.mp * es;
     if (ranges_overlap(p.out, n_out, p.O, n_o) || ranges_overlap(p.out, n_out, p.U, n_u))
         return fail(ROT_ERR_INVALID_ARG, "group %d: out overlaps U or O", gi);
     return ROT_OK;
 }
 
-// Stage 1: T_b = O_b * U_r for nb operators from b0 (T batch stride m*d*mp).
+// Stage 1: T_b = O_b * U_r for nb operators from b0.  With row stride ldu,
+// U_r(j, c) = U[j*d*ldu + c] for c = s*ldu + beta is one matrix of row stride
+// d*ldu; its columns beta >= mp of s < d-1 are U's row padding, so the
+// product spans N = (d-1)*ldu + mp columns and T_b gets U's row layout
+// ((m*d) x ldu, batch stride m*d*ldu).  Padding columns of T_b hold products
+// with U's padding and are never read.
 GemmDesc stage1(const rot_problem& p, int b0, int nb, void* T, size_t es) {
     GemmDesc g{};
     g.M = p.m;
-    g.N = p.d * p.mp;
+    g.N = (int)((int64_t)(p.d - 1) * p.ldu + p.mp);
     g.K = p.m;
     g.batch = nb;
     g.kbatch = 1;
     g.A = static_cast<const char*>(p.O) + (size_t)b0 * p.stride_o * es;
-    g.lda = p.m;
+    g.lda = p.ldo;
     g.a_bs = p.stride_o;
-    g.a_kcontig = true;  // O_b(i, j) at O_b[i*m + j]
+    g.a_kcontig = true;  // O_b(i, j) at O_b[i*ldo + j]
     g.B = p.U;
-    g.ldb = (int64_t)p.d * p.mp;
+    g.ldb = (int64_t)p.d * p.ldu;
     g.b_bs = 0;
-    g.b_kcontig = false;  // U_r(j, (s,beta)) at U[j*d*mp + s*mp + beta]
+    g.b_kcontig = false;  // U_r(j, c) at U[j*d*ldu + c]
     g.C = T;
-    g.ldc = (int64_t)p.d * p.mp;
-    g.c_bs = (int64_t)p.m * p.d * p.mp;
+    g.ldc = (int64_t)p.d * p.ldu;
+    g.c_bs = (int64_t)p.m * p.d * p.ldu;
     return g;
 }
 
-// Stage 2: out_b = U^T * T_b, T_b viewed as (m*d) x mp.
+// Stage 2: out_b = U^T * T_b, T_b viewed as (m*d) x mp with row stride ldu.
 GemmDesc stage2(const rot_problem& p, int b0, int nb, const void* T, size_t es) {
     GemmDesc g{};
     g.M = p.mp;
@@ -175,15 +210,15 @@ GemmDesc stage2(const rot_problem& p, int b0, int nb, const void* T, size_t es) 
     g.batch = nb;
     g.kbatch = 1;
     g.A = p.U;
-    g.lda = p.mp;
+    g.lda = p.ldu;
     g.a_bs = 0;
-    g.a_kcontig = false;  // A(alpha, r) = U[r*mp + alpha]
+    g.a_kcontig = false;  // A(alpha, r) = U[r*ldu + alpha]
     g.B = T;
-    g.ldb = p.mp;
-    g.b_bs = (int64_t)p.m * p.d * p.mp;
-    g.b_kcontig = false;  // T_b(r, beta) at T_b[r*mp + beta]
+    g.ldb = p.ldu;
+    g.b_bs = (int64_t)p.m * p.d * p.ldu;
+    g.b_kcontig = false;  // T_b(r, beta) at T_b[r*ldu + beta]
     g.C = static_cast<char*>(p.out) + (size_t)b0 * p.stride_out * es;
-    g.ldc = p.mp;
+    g.ldc = p.ldout;
     g.c_bs = p.stride_out;
     return g;
 }
@@ -329,17 +364,21 @@ size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_preci
     if (n_groups < 0 || (n_groups > 0 && !groups) || !valid_precision(prec)) return 0;
     size_t need = 0;
     for (int gi = 0; gi < n_groups; gi++) {
-        const rot_problem& p = groups[gi];
+        const rot_problem p = resolved(groups[gi]);
         if (validate_group(p, gi) != ROT_OK) return 0;
         if (p.n_ops == 0) continue;
         const int ops = ops_per_chunk > 0 ? std::min(ops_per_chunk, p.n_ops) : p.n_ops;
+        const rot_precision tp = prec == ROT_FP64 ? ROT_FP64 : ROT_FP32;
         size_t g;
-        if (prec == ROT_SPLIT_BF16 && !for_backward)
+        if (prec == ROT_SPLIT_BF16 && !for_backward) {
             g = bf16_group_workspace(p.m, p.d, p.mp, ops);
-        else if (for_backward)
-            g = (size_t)(ops + du_split_parts(p, ops)) * t_bytes(p, prec == ROT_FP64 ? ROT_FP64 : ROT_FP32);
-        else
-            g = (size_t)ops * t_bytes(p, prec == ROT_FP64 ? ROT_FP64 : ROT_FP32);
+        } else if (for_backward) {
+            rot_problem packed = p;
+            packed.ldu = p.mp;  // the adjoint works on U packed to row stride mp
+            g = packed_u_bytes(p, tp) + (size_t)(ops + du_split_parts(p, ops)) * t_bytes(packed, tp);
+        } else {
+            g = (size_t)ops * t_bytes(p, tp);
+        }
         need = std::max(need, g);
     }
     return need;
@@ -357,11 +396,12 @@ rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precisi
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
     if (flags & ~ROT_ASSUME_SYMMETRIC_O) return fail(ROT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     const bool sym = flags & ROT_ASSUME_SYMMETRIC_O;
+    const std::vector<rot_problem> rg = resolved_all(groups, n_groups);
     for (int gi = 0; gi < n_groups; gi++) {
-        rot_status s = validate_group(groups[gi], gi);
+        rot_status s = validate_group(rg[gi], gi);
         if (s != ROT_OK) return s;
-        if (groups[gi].n_ops > 0) {
-            s = validate_outputs_disjoint(groups[gi], prec, gi);
+        if (rg[gi].n_ops > 0) {
+            s = validate_outputs_disjoint(rg[gi], prec, gi);
             if (s != ROT_OK) return s;
             if (prec == ROT_SPLIT_BF16 && !bf16_shape_supported(groups[gi].m, groups[gi].d, groups[gi].mp))
                 return fail(ROT_ERR_UNSUPPORTED,
@@ -380,7 +420,7 @@ rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precisi
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t es = elem_size(prec);
     for (int gi = 0; gi < n_groups; gi++) {
-        const rot_problem& p = groups[gi];
+        const rot_problem& p = rg[gi];
         if (p.n_ops == 0) continue;
         if (prec == ROT_SPLIT_BF16) {
             int chunk = 1;
@@ -510,6 +550,7 @@ rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_groups, rot_
         p.stride_o = sp.stride_x;
         p.out = sp.out;
         p.stride_out = sp.stride_out;
+        p = resolved(p);  // packed U, X and out
         if (sp.block_kind != ROT_BLOCK_DENSE) {
             // out = U'^T U: stage 2 with U' as A and U itself as B (split over K
             // when its mp x mp output has few tiles)
@@ -623,6 +664,7 @@ rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR,
         p.m = m; p.d = d; p.mp = (int32_t)mp; p.n_ops = nb;
         p.U = psi; p.O = Z + (size_t)b0 * stride_z; p.stride_o = stride_z;
         p.out = Q; p.stride_out = mp * mp;
+        p = resolved(p);  // packed psi, Z and Q
         GemmDesc g1 = stage1(p, 0, nb, T, 8);
         g1.c_bs = (int64_t)(t_bytes_op / 8);
         err = gemm(ROT_FP64, g1, s, "expect_stage1");
@@ -653,14 +695,15 @@ rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR,
 
 rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void* const* dOut,
                         const int64_t* stride_dout, void* const* dO, void* const* dU, uint32_t flags,
-                        rot_precision prec, void* workspace, size_t workspace_bytes, void* stream) {
+                        rot_precision prec, void* workspace0, size_t workspace_bytes0, void* stream) {
     if (n_groups < 0 || (n_groups > 0 && (!groups || !dOut || !stride_dout)))
         return fail(ROT_ERR_INVALID_ARG, "null groups/dOut/stride_dout or negative n_groups");
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
     if (prec == ROT_SPLIT_BF16) return fail(ROT_ERR_UNSUPPORTED, "rot_backward: split-bf16 not implemented; use ROT_FP32");
     if (flags & ~ROT_ASSUME_SYMMETRIC_O) return fail(ROT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const std::vector<rot_problem> rg = resolved_all(groups, n_groups);
     for (int gi = 0; gi < n_groups; gi++) {
-        const rot_problem& p = groups[gi];
+        const rot_problem& p = rg[gi];
         rot_status st = validate_group(p, gi);
         if (st != ROT_OK) return st;
         if (p.n_ops == 0) continue;
@@ -670,16 +713,16 @@ rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void*
     }
     const size_t min_ws = rot_workspace_size(groups, n_groups, prec, 1, 1);
     if (min_ws > 0) {
-        if (!workspace || workspace_bytes < min_ws)
-            return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, min_ws);
-        if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        if (!workspace0 || workspace_bytes0 < min_ws)
+            return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes0, min_ws);
+        if (reinterpret_cast<uintptr_t>(workspace0) % kAlign)
             return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t es = elem_size(prec);
     const bool sym = flags & ROT_ASSUME_SYMMETRIC_O;
     for (int gi = 0; gi < n_groups; gi++) {
-        const rot_problem& p = groups[gi];
+        rot_problem p = rg[gi];
         void* dOg = dO ? dO[gi] : nullptr;
         void* dUg = dU ? dU[gi] : nullptr;
         if (p.n_ops == 0) {
@@ -691,6 +734,19 @@ rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void*
         }
         if (!dOg && !dUg) continue;
         const int64_t md = (int64_t)p.m * p.d, tsz = md * p.mp;
+        // U with padded rows is packed first: dO_b reads U_r (m x d*mp)
+        const size_t ub = packed_u_bytes(p, prec);
+        void* workspace = static_cast<char*>(workspace0) + ub;
+        const size_t workspace_bytes = workspace_bytes0 - ub;
+        if (ub) {
+            hipError_t e = prof_timed("adj_pack_u", s, [&] {
+                return hipMemcpy2DAsync(workspace0, (size_t)p.mp * es, p.U, (size_t)p.ldu * es, (size_t)p.mp * es,
+                                        (size_t)md, hipMemcpyDeviceToDevice, s);
+            });
+            if (e != hipSuccess) return hip_fail(e, "rot_backward pack U");
+            p.U = workspace0;
+            p.ldu = p.mp;
+        }
         const size_t per_op = t_bytes(p, prec);
         const size_t slots = workspace_bytes / per_op;
         // Chunk size, leaving `parts` slots for the partial dU sums when dU is
@@ -743,9 +799,9 @@ rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void*
                 auto reduce = [&](bool o_transposed, bool acc_first) -> hipError_t {
                     GemmDesc c{};
                     c.M = p.m; c.N = p.d * p.mp; c.K = p.m; c.batch = np; c.kbatch = q;
-                    c.A = static_cast<const char*>(p.O) + (size_t)b0 * p.stride_o * es; c.lda = p.m;
+                    c.A = static_cast<const char*>(p.O) + (size_t)b0 * p.stride_o * es; c.lda = p.ldo;
                     c.a_ks = p.stride_o; c.a_bs = q * p.stride_o;
-                    c.a_kcontig = !o_transposed;  // A(i, j) = O_b[i][j], or O_b[j][i]
+                    c.a_kcontig = !o_transposed;  // A(i, j) = O_b[i*ldo + j], or O_b[j*ldo + i]
                     c.B = workspace; c.ldb = (int64_t)p.d * p.mp; c.b_ks = tsz; c.b_bs = q * tsz;
                     c.b_kcontig = false;
                     c.C = np > 1 ? static_cast<void*>(partial) : dUg; c.ldc = (int64_t)p.d * p.mp;
@@ -807,11 +863,14 @@ size_t rot_isometry_workspace_size(int32_t rows, int32_t cols, rot_precision pre
     return isometry_workspace_bytes(rows, cols, prec == ROT_FP64);
 }
 
-rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, rot_precision prec, double tol,
-                              double* max_dev_host, void* workspace, size_t workspace_bytes, void* stream) {
+rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, int64_t ldu, rot_precision prec,
+                              double tol, double* max_dev_host, void* workspace, size_t workspace_bytes,
+                              void* stream) {
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
     if (!U || !max_dev_host || rows <= 0 || cols <= 0 || cols > rows)
         return fail(ROT_ERR_INVALID_ARG, "need U, max_dev_host and 0 < cols <= rows");
+    if (ldu == 0) ldu = cols;
+    if (ldu < cols || ldu > INT32_MAX) return fail(ROT_ERR_INVALID_ARG, "ldu %lld must be >= cols", (long long)ldu);
     const size_t need = isometry_workspace_bytes(rows, cols, prec == ROT_FP64);
     if (!workspace || workspace_bytes < need)
         return fail(ROT_ERR_WORKSPACE, "workspace %zu bytes < minimum %zu", workspace_bytes, need);
@@ -819,7 +878,7 @@ rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, rot_pre
         return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* ws = static_cast<double*>(workspace);
-    hipError_t e = isometry_deviation(U, rows, cols, prec == ROT_FP64, ws, s);
+    hipError_t e = isometry_deviation(U, rows, cols, ldu, prec == ROT_FP64, ws, s);
     if (e == hipSuccess) e = hipMemcpyAsync(max_dev_host, ws, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "rot_check_isometry");

@@ -265,17 +265,25 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
     if (flags & ~(ROT_PLAN_NO_GRAPH | ROT_PLAN_NO_TUNE | ROT_PLAN_RETUNE))
         return perr(ROT_ERR_INVALID_ARG, "unknown plan flags 0x%x", flags);
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return perr(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    // validation (same rules as rot_batch)
+    // validation (same rules as rot_batch); leading dimensions 0 select the packed values
+    std::vector<rot_problem> rg(groups, groups + n_groups);
     size_t min_ws = 0;
     for (int gi = 0; gi < n_groups; gi++) {
-        const rot_problem& p = groups[gi];
+        rot_problem& p = rg[gi];
+        if (p.ldu == 0) p.ldu = p.mp;
+        if (p.ldo == 0) p.ldo = p.m;
+        if (p.ldout == 0) p.ldout = p.mp;
         if (p.m <= 0 || p.d <= 0 || p.mp <= 0 || p.n_ops < 0 || (int64_t)p.m * p.d > INT32_MAX ||
             (int64_t)p.d * p.mp > INT32_MAX || p.mp > (int64_t)p.m * p.d)
             return perr(ROT_ERR_INVALID_ARG, "group %d: need m, d, mp > 0, mp <= m*d, n_ops >= 0", gi);
         if (p.n_ops == 0) continue;
-        if (!p.U || !p.O || !p.out || p.stride_o < (int64_t)p.m * p.m || p.stride_out < (int64_t)p.mp * p.mp)
-            return perr(ROT_ERR_INVALID_ARG, "group %d: null buffer or stride too small", gi);
-        min_ws = std::max(min_ws, ((size_t)p.m * p.d * p.mp * 4 + 255) / 256 * 256);
+        if (!p.U || !p.O || !p.out)
+            return perr(ROT_ERR_INVALID_ARG, "group %d: null buffer", gi);
+        if (p.ldu < p.mp || p.ldo < p.m || p.ldout < p.mp || (int64_t)p.d * p.ldu > INT32_MAX)
+            return perr(ROT_ERR_INVALID_ARG, "group %d: leading dimensions below mp, m, mp (or d*ldu >= 2^31)", gi);
+        if (p.stride_o < (int64_t)(p.m - 1) * p.ldo + p.m || p.stride_out < (int64_t)(p.mp - 1) * p.ldout + p.mp)
+            return perr(ROT_ERR_INVALID_ARG, "group %d: operator stride too small", gi);
+        min_ws = std::max(min_ws, ((size_t)p.m * p.d * p.ldu * 4 + 255) / 256 * 256);
     }
     if (min_ws > 0 && (!workspace || workspace_bytes < min_ws))
         return perr(ROT_ERR_WORKSPACE, "workspace %zu bytes < one operator's intermediate (%zu)", workspace_bytes, min_ws);
@@ -301,7 +309,7 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
     std::map<std::pair<int, int>, int> cls_of;
     std::vector<std::vector<int>> members;
     for (int gi = 0; gi < n_groups; gi++) {
-        const rot_problem& p = groups[gi];
+        const rot_problem& p = rg[gi];
         if (p.n_ops == 0) continue;
         const std::pair<int, int> key{ceil_log2((int64_t)p.m * p.d), ceil_log2(p.mp)};
         auto it = cls_of.find(key);
@@ -354,8 +362,10 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
             return hipSuccess;
         };
         for (int gi : members[ci]) {
-            const rot_problem& p = groups[gi];
-            const size_t tb = ((size_t)p.m * p.d * p.mp * 4 + 255) / 256 * 256;
+            const rot_problem& p = rg[gi];
+            // T_b takes U's row layout ((m*d) x ldu), so stage 1 reads U_r as
+            // one matrix of row stride d*ldu over (d-1)*ldu + mp columns
+            const size_t tb = ((size_t)p.m * p.d * p.ldu * 4 + 255) / 256 * 256;
             for (int b = 0; b < p.n_ops; b++) {
                 if (used + tb > workspace_bytes) {
                     e = flush();
@@ -368,26 +378,26 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
                 auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
                 GroupedProblem g1{};
                 g1.M = p.m;
-                g1.N = p.d * p.mp;
+                g1.N = (int)((int64_t)(p.d - 1) * p.ldu + p.mp);
                 g1.K = p.m;
                 g1.a_off = (int64_t) reinterpret_cast<uintptr_t>(O);
-                g1.lda = p.m;
+                g1.lda = p.ldo;
                 g1.b_off = (int64_t) reinterpret_cast<uintptr_t>(U);
-                g1.ldb = (int64_t)p.d * p.mp;
+                g1.ldb = (int64_t)p.d * p.ldu;
                 g1.c_off = (int64_t) reinterpret_cast<uintptr_t>(T);
-                g1.ldc = (int64_t)p.d * p.mp;
-                g1.flags = (al(O) && al(U) && p.m % 4 == 0 && (p.d * p.mp) % 4 == 0) ? kGroupedVec : 0;
+                g1.ldc = (int64_t)p.d * p.ldu;
+                g1.flags = (al(O) && al(U) && p.ldo % 4 == 0 && (p.d * p.ldu) % 4 == 0) ? kGroupedVec : 0;
                 GroupedProblem g2{};
                 g2.M = p.mp;
                 g2.N = p.mp;
                 g2.K = p.m * p.d;
                 g2.a_off = (int64_t) reinterpret_cast<uintptr_t>(U);
-                g2.lda = p.mp;
+                g2.lda = p.ldu;
                 g2.b_off = (int64_t) reinterpret_cast<uintptr_t>(T);
-                g2.ldb = p.mp;
+                g2.ldb = p.ldu;
                 g2.c_off = (int64_t) reinterpret_cast<uintptr_t>(out);
-                g2.ldc = p.mp;
-                g2.flags = (al(U) && p.mp % 4 == 0) ? kGroupedVec : 0;
+                g2.ldc = p.ldout;
+                g2.flags = (al(U) && p.ldu % 4 == 0) ? kGroupedVec : 0;
                 s1.push_back(g1);
                 s2.push_back(g2);
                 used += tb;

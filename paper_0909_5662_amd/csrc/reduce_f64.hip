@@ -110,11 +110,16 @@ __global__ void loss_grad(const double* __restrict__ psi, const double* __restri
     grad[idx] = (T)(psi[a] * sw[c] + sv[a] * psi[c]);
 }
 
+// y (rows x cols, packed) = x (rows x cols, row stride ld) widened to FP64
 template <typename T>
-__global__ void widen(const T* __restrict__ x, double* __restrict__ y, int64_t n) {
+__global__ void widen(const T* __restrict__ x, int64_t ld, int cols, double* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = (double)x[i];
+    if (i < n) y[i] = (double)x[(i / cols) * ld + i % cols];
 }
+
+// max that keeps a NaN from either side (fmax would drop it, and a U with a
+// NaN entry would then pass the isometry check)
+__device__ inline double max_keep_nan(double a, double b) { return (b > a || b != b) ? b : a; }
 
 // partial[block] = max |G[a][b] - delta_ab| over a grid-stride range
 __global__ __launch_bounds__(256) void max_dev_partial(const double* __restrict__ G, int cols,
@@ -123,13 +128,13 @@ __global__ __launch_bounds__(256) void max_dev_partial(const double* __restrict_
     double worst = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int64_t a = i / cols, b = i % cols;
-        worst = fmax(worst, fabs(G[i] - (a == b ? 1.0 : 0.0)));
+        worst = max_keep_nan(worst, fabs(G[i] - (a == b ? 1.0 : 0.0)));
     }
     __shared__ double red[256];
     red[threadIdx.x] = worst;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        if (threadIdx.x < s) red[threadIdx.x] = max_keep_nan(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
@@ -138,7 +143,7 @@ __global__ __launch_bounds__(256) void max_dev_partial(const double* __restrict_
 __global__ void max_final(const double* __restrict__ partial, int n, double* out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         double worst = 0.0;
-        for (int i = 0; i < n; i++) worst = fmax(worst, partial[i]);
+        for (int i = 0; i < n; i++) worst = max_keep_nan(worst, partial[i]);
         *out = worst;
     }
 }
@@ -200,23 +205,25 @@ size_t isometry_workspace_bytes(int64_t rows, int cols, bool is_double) {
 }
 
 // G = U^T U in FP64 (matrix cores), then max |G - I| into ws[0].
-hipError_t isometry_deviation(const void* U, int rows, int cols, bool is_double, double* ws,
+hipError_t isometry_deviation(const void* U, int rows, int cols, int64_t ldu, bool is_double, double* ws,
                               hipStream_t stream) {
     double* dev = ws;
     double* partial = ws + 32;
     double* G = partial + round256(kDevBlocks);
     double* Ud = G + round256((size_t)cols * cols);
     const double* src = static_cast<const double*>(U);
+    int64_t ld = ldu;
     if (!is_double) {
         const int64_t n = (int64_t)rows * cols;
         hipLaunchKernelGGL(widen<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                           static_cast<const float*>(U), Ud, n);
+                           static_cast<const float*>(U), ldu, cols, Ud, n);
         src = Ud;
+        ld = cols;
     }
     GemmDesc g{};
     g.M = cols; g.N = cols; g.K = rows; g.batch = 1; g.kbatch = 1;
-    g.A = src; g.lda = cols; g.a_kcontig = false;  // A(a, r) = U[r][a]
-    g.B = src; g.ldb = cols; g.b_kcontig = false;  // B(r, b) = U[r][b]
+    g.A = src; g.lda = ld; g.a_kcontig = false;  // A(a, r) = U[r][a]
+    g.B = src; g.ldb = ld; g.b_kcontig = false;  // B(r, b) = U[r][b]
     g.C = G; g.ldc = cols;
     hipError_t e = gemm_f64(g, stream);
     if (e != hipSuccess) return e;

@@ -108,7 +108,7 @@ hipError_t pair_loss(const void* X, int mp, int n_ops, int64_t stride, bool is_d
                      hipStream_t stream);
 size_t isometry_workspace_bytes(int64_t rows, int cols, bool is_double);
 // Result (max |U^T U - I|) lands in ws[0] (device).
-hipError_t isometry_deviation(const void* U, int rows, int cols, bool is_double, double* ws,
+hipError_t isometry_deviation(const void* U, int rows, int cols, int64_t ldu, bool is_double, double* ws,
                               hipStream_t stream);
 
 }  // namespace rot

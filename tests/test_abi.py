@@ -42,14 +42,18 @@ def test_status_strings_and_version(rotlib):
 FAKE = 1 << 20  # host-side stand-in addresses: validation compares, never dereferences
 
 
-def prob(rot, m=8, d=4, mp=8, n=2, U=FAKE, O=2 * FAKE, so=None, out=3 * FAKE, sout=None):
-    return rot.RotProblem(m, d, mp, n, U, O, m * m if so is None else so, out, mp * mp if sout is None else sout)
+def prob(rot, m=8, d=4, mp=8, n=2, U=FAKE, O=2 * FAKE, so=None, out=3 * FAKE, sout=None, ldu=0, ldo=0, ldout=0):
+    return rot.problem(m, d, mp, n, U, O, out, ldu=ldu, ldo=ldo, stride_o=so, ldout=ldout, stride_out=sout)
 
 
 @pytest.mark.parametrize("kw,expect", [
     (dict(m=0), -1), (dict(d=0), -1), (dict(mp=0), -1), (dict(mp=33), -1), (dict(n=-1), -1),
     (dict(U=0), -1), (dict(O=0), -1), (dict(out=0), -1), (dict(so=63), -1), (dict(sout=10), -1),
     (dict(out=2 * FAKE + 8), -1),  # out overlaps O
+    # leading dimensions below the row length, or strides that make matrices overlap
+    (dict(ldu=7), -1), (dict(ldo=7), -1), (dict(ldout=5), -1), (dict(ldu=-8), -1),
+    (dict(ldo=10, so=77), -1), (dict(ldout=12, sout=91), -1),
+    (dict(out=2 * FAKE + 600, ldo=10), -1),  # out overlaps the padded O batch (624 bytes)
 ])
 def test_rot_batch_rejects_bad_groups(rotlib, kw, expect):
     L = rotlib.lib()
@@ -125,8 +129,10 @@ def test_reduction_argument_errors(rotlib):
     assert L.rot_pair_loss(FAKE, 8, 2, 63, 1, FAKE, FAKE, None, None, FAKE, 1 << 30, None) == -1
     assert L.rot_pair_loss(FAKE, 8, 2, 64, 1, FAKE, FAKE, None, None, FAKE, 8, None) == -3
     dev = ctypes.c_double()
-    assert L.rot_check_isometry(FAKE, 4, 8, 1, 1e-6, ctypes.byref(dev), FAKE, 1 << 30, None) == -1
-    assert L.rot_check_isometry(FAKE, 8, 4, 1, 1e-6, ctypes.byref(dev), FAKE, 8, None) == -3
+    assert L.rot_check_isometry(FAKE, 4, 8, 0, 1, 1e-6, ctypes.byref(dev), FAKE, 1 << 30, None) == -1
+    assert L.rot_check_isometry(FAKE, 8, 4, 0, 1, 1e-6, ctypes.byref(dev), FAKE, 8, None) == -3
+    assert L.rot_check_isometry(FAKE, 8, 4, 3, 1, 1e-6, ctypes.byref(dev), FAKE, 1 << 30, None) == -1  # ldu < cols
+    assert L.rot_check_isometry(FAKE, 8, 4, -4, 1, 1e-6, ctypes.byref(dev), FAKE, 1 << 30, None) == -1
     assert L.rot_split_bf16(None, 5, None, None, None) == -1
     assert L.rot_split_bf16(None, 0, None, None, None) == 0
 
@@ -313,3 +319,64 @@ def test_superblock_layout_and_validation(rotlib):
     assert L.rot_sb_layout(ctypes.byref(P), 0, ctypes.byref(nb), None, None, None, None, ctypes.byref(tot)) == -1
     P.d = 4
     assert L.rot_sb_apply(None, None, None, None) == -1
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(ldu=9), dict(ldo=11, so=11 * 8), dict(ldout=16)])
+def test_padded_layouts_are_accepted(rotlib, kw):
+    """Valid padded leading dimensions pass validation: with a null stream
+    and a too-small workspace the call stops at the workspace check."""
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib, U=FAKE, O=8 * FAKE, out=16 * FAKE, **kw))
+    need = L.rot_workspace_size(arr, 1, rotlib.ROT_FP32, 1, 0)
+    assert need > 0
+    assert L.rot_batch(arr, 1, rotlib.ROT_FP32, 32 * FAKE, need - 1, None) == -3
+
+
+def test_padded_u_sizes_the_intermediate(rotlib):
+    """T_b takes U's row layout, so its workspace slot grows with ldu; the
+    adjoint packs a padded U into its workspace first."""
+    L = rotlib.lib()
+    m, d, mp = 100, 4, 90
+    packed = (rotlib.RotProblem * 1)(prob(rotlib, m=m, d=d, mp=mp, n=3))
+    padded = (rotlib.RotProblem * 1)(prob(rotlib, m=m, d=d, mp=mp, n=3, ldu=96))
+    a = L.rot_workspace_size(packed, 1, rotlib.ROT_FP32, 1, 0)
+    b = L.rot_workspace_size(padded, 1, rotlib.ROT_FP32, 1, 0)
+    assert a == -(-m * d * mp * 4 // 256) * 256
+    assert b == -(-m * d * 96 * 4 // 256) * 256
+    fa = L.rot_workspace_size(packed, 1, rotlib.ROT_FP32, 1, 1)
+    fb = L.rot_workspace_size(padded, 1, rotlib.ROT_FP32, 1, 1)
+    assert fb == fa + a  # one packed copy of U ahead of the intermediates
+
+
+def test_row_layout_of_tensors(rotlib):
+    """The binding maps strided tensors to (leading dimension, matrix stride)
+    and rejects layouts the C ABI cannot describe (CPU tensors: no launch)."""
+    import torch
+    rl = rotlib._row_layout
+    x = torch.zeros(3, 5, 7)
+    assert rl(x, "x") == (7, 35)
+    big = torch.zeros(3, 6, 10)
+    assert rl(big[:, :5, :7], "v") == (10, 60)
+    assert rl(torch.zeros(1, 4, 4)[:, :, :3], "w") == (4, 15)
+    assert rl(torch.zeros(9, 4)[:, :3], "u") == (4, 8 * 4 + 3)
+    with pytest.raises(ValueError):
+        rl(torch.zeros(4, 5).t(), "t")  # columns contiguous
+    with pytest.raises(ValueError):
+        rl(torch.zeros(5, 5).expand(3, 5, 5), "e")  # matrices overlap (stride 0)
+    with pytest.raises(ValueError):
+        rl(torch.zeros(0, 5), "z")
+
+
+def test_binding_rejects_host_tensors_before_launch(rotlib):
+    """Tensor helpers check devices before any launch: host tensors raise."""
+    import torch
+    U = torch.zeros(16, 4)
+    O = torch.zeros(2, 4, 4)
+    with pytest.raises(ValueError):
+        rotlib.rotate(U, O, 4, "fp32")
+    with pytest.raises(ValueError):
+        rotlib.rotate_backward(U, O, 4, torch.zeros(4, 4), "fp32")
+    with pytest.raises((TypeError, ValueError)):
+        rotlib.pair_loss(torch.zeros(2, 4, 4, dtype=torch.float64), torch.zeros(4, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        rotlib.check_isometry(torch.zeros(8, 4))
