@@ -275,41 +275,46 @@ def bench_uneven(args, rot, torch, workloads):
 
 
 def bench_differentiated(args, rot, torch, workloads):
-    """Forward (FP32) + FP64 pair loss + adjoint (FP32, nothing stored)
-    through torch.autograd, m = m' = 1024, d = 4, 64 symmetric operators."""
+    """Forward + FP64 pair loss + adjoint (nothing stored) through
+    torch.autograd, m = m' = 1024, d = 4, 64 symmetric operators; the forward
+    and adjoint in FP32 (the line's value) and in split-BF16."""
     case = workloads.named_dense(WORKLOAD)
     psi = torch.from_numpy(workloads.psi_vector(case.mp, workloads.rng(5, 2))).cuda()
     U = torch.from_numpy(case.U).float().cuda().requires_grad_(True)
     O = torch.from_numpy(case.O).float().cuda().requires_grad_(True)
-
-    def step():
-        U.grad = None
-        O.grad = None
-        X = rot.RotateFn.apply(U, O, 4, "fp32", True)
-        L = rot.PairLossFn.apply(X, psi)
-        L.backward()
-        return L
-
-    for _ in range(max(1, args.warmup)):
-        step()
-    torch.cuda.synchronize()
-    rot.profile_enable(True)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    kernels = rot.profile_read()
-    rot.profile_enable(False)
-    ms = t0.elapsed_time(t1) / args.steps
     n, m, mp, d = 64, 1024, 1024, 4
     f_fwd = n * flops_per_op(m, d, mp)
-    # backward per symmetric operator: P = U dOut and P += U dOut^T (2 md mp^2
-    # each), dO = P_r U_r^T and dU_r += O P_r (2 m^2 d mp each)
+    # backward per symmetric operator: P = U dOut and (P + Q) = U (dOut + dOut^T)
+    # (2 md mp^2 each), dO = P_r U_r^T and dU_r += O (P + Q)_r (2 m^2 d mp each)
     f_bwd = n * (4.0 * m * d * mp * mp + 4.0 * m * m * d * mp)
-    tflops = (f_fwd + f_bwd) / (ms / 1e3) / 1e12
+
+    def run(precision):
+        def step():
+            U.grad = None
+            O.grad = None
+            X = rot.RotateFn.apply(U, O, 4, precision, True)
+            L = rot.PairLossFn.apply(X, psi)
+            L.backward()
+            return L
+
+        for _ in range(max(1, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        rot.profile_enable(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(args.steps):
+            step()
+        t1.record()
+        torch.cuda.synchronize()
+        kernels = rot.profile_read()
+        rot.profile_enable(False)
+        ms = t0.elapsed_time(t1) / args.steps
+        tflops = (f_fwd + f_bwd) / (ms / 1e3) / 1e12
+        return ms, tflops, kernels
+
+    ms, tflops, kernels = run("fp32")
     rec = base_record(args, n / (ms / 1e3), "operator rotations/s (forward + loss + adjoint)", ms,
                       {"workload": "differentiated_m1024_n64", "m": m, "d": d, "mp": mp, "n_ops": n,
                        "precision": "fp32 forward/adjoint, fp64 loss"})
@@ -317,6 +322,12 @@ def bench_differentiated(args, rot, torch, workloads):
                 "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2),
                 "kernels_ms_avg": {k: round(v[1] / v[0], 4) for k, v in kernels.items()},
                 "kernels_ms_total_per_step": {k: round(v[1] / args.steps, 4) for k, v in kernels.items()}})
+    ms_b, tflops_b, kernels_b = run("split_bf16")
+    rec["split_bf16"] = {"value": round(n / (ms_b / 1e3), 2), "unit": "operator rotations/s (forward + loss + adjoint)",
+                         "ms_per_step": round(ms_b, 4), "tflops_fp32_equivalent": round(tflops_b, 2),
+                         "pct_bf16_mfma_peak_executed": round(100 * 3 * tflops_b / 2516.6, 2),
+                         "speedup_vs_fp32": round(ms / ms_b, 3),
+                         "kernels_ms_total_per_step": {k: round(v[1] / args.steps, 4) for k, v in kernels_b.items()}}
     return rec
 
 

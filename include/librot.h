@@ -251,7 +251,8 @@ ROT_API rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int
  * captures all launches in a hipGraph.  Only ROT_FP32.
  *   groups, workspace: as for rot_batch; every buffer (U, O, out, workspace)
  *       is bound to the plan by address and must stay valid, unmoved and
- *       unoverlapped until rot_plan_destroy.
+ *       unoverlapped until rot_plan_destroy or until rot_plan_rebind binds
+ *       other U, O and out buffers.
  *   stream: pending work on it is waited for before tuning writes to out and
  *       the workspace; create returns after its own device work has finished.
  *   flags: ROT_PLAN_NO_GRAPH (issue launches directly on execute),
@@ -273,6 +274,20 @@ ROT_API rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, 
                                    void* workspace, size_t workspace_bytes, uint32_t flags,
                                    void* stream, rot_plan* plan);
 ROT_API rot_status rot_plan_execute(rot_plan plan, void* stream);
+/*
+ * rot_plan_rebind: point the plan at new U, O and out buffers (a DMRG step
+ * rotates the same shapes with new data; Sec. 3.2).  groups must match the
+ * plan's groups one by one in m, d, mp, n_ops, leading dimensions and
+ * strides; the workspace stays bound.  The plan's work-list descriptors are
+ * recomputed on the host and copied into its device tables on `stream`, so
+ * executions enqueued on `stream` before the rebind use the old buffers and
+ * those after it the new ones (graph, tiles and tuned choices are kept: no
+ * capture or tuning is repeated).  An execution in flight on another stream
+ * must be ordered against the rebind by the caller.  The first rebind
+ * allocates a pinned staging buffer; each rebind waits for the previous
+ * rebind's copies to leave it.
+ */
+ROT_API rot_status rot_plan_rebind(rot_plan plan, const rot_problem* groups, int32_t n_groups, void* stream);
 ROT_API int32_t rot_plan_describe(rot_plan plan, char* buf, size_t len);
 ROT_API rot_status rot_plan_destroy(rot_plan plan);
 
@@ -303,12 +318,19 @@ ROT_API rot_status rot_plan_destroy(rot_plan plan);
  *                dim(Q)); -1 means not requested.  A requested block whose
  *                target sector is not kept is an error.
  * Only ROT_FP32 is supported.  workspace: at least
- * rot_blocked_workspace_size(p) bytes.  The first call for a block structure
- * (sector tables, offsets and buffers) times the available execution paths
- * (one fused kernel in two register layouts, or two grouped launches) and
- * keeps the fastest for later calls with the same structure; every call's
- * result comes from the kept path, so repeated calls agree bit for bit.
- * ROT_BLOCKED_PATH=fused|fused_wide|grouped in the environment forces one.
+ * rot_blocked_workspace_size(p) bytes; it also holds the call's tile-queue
+ * counter, so calls on different streams with different workspaces are
+ * independent (one workspace must not serve two calls in flight).  The first
+ * call for a block structure (sector tables, offsets and buffer alignment)
+ * builds its work-lists in library-owned device memory, times the available
+ * execution paths (one fused kernel in two register layouts, or two grouped
+ * launches) and keeps the fastest for later calls with the same structure;
+ * every call's result comes from the kept path, so repeated calls agree bit
+ * for bit.  ROT_BLOCKED_PATH=fused|fused_wide|grouped in the environment
+ * forces one.  Work-lists are cached for the 8 most recently used structures;
+ * a structure used while `stream` is being captured into a graph is kept for
+ * the life of the process (the graph refers to its work-lists), and its
+ * first call must happen outside capture (ROT_ERR_UNSUPPORTED otherwise).
  */
 typedef struct { int32_t n_up, n_dn, dim; int64_t offset; } rot_sector;
 typedef struct {

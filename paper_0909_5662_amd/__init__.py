@@ -171,6 +171,8 @@ def lib() -> ctypes.CDLL:
         L.rot_plan_create.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, vp, sz, ctypes.c_uint32, vp,
                                       ctypes.POINTER(vp)]
         L.rot_plan_create.restype = ctypes.c_int
+        L.rot_plan_rebind.argtypes = [vp, ctypes.POINTER(RotProblem), i32, vp]
+        L.rot_plan_rebind.restype = ctypes.c_int
         L.rot_plan_execute.argtypes = [vp, vp]
         L.rot_plan_execute.restype = ctypes.c_int
         L.rot_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
@@ -762,6 +764,19 @@ class Plan:
 
     def execute(self, stream=None) -> None:
         _check(lib().rot_plan_execute(self._h, _stream(stream)))
+
+    def rebind(self, groups, stream=None) -> None:
+        """Bind new (U, O, out, d) tensors of the same shapes and layouts
+        (rot_plan_rebind): later executions on `stream` use them."""
+        groups = list(groups)
+        probs = []
+        for U, O, out, d in groups:
+            _check_inputs(U, O, d, ROT_FP32)
+            probs.append(_problem(U, O, out, d))
+        arr = (RotProblem * len(probs))(*probs)
+        _check(lib().rot_plan_rebind(self._h, arr, len(probs), _stream(stream)))
+        self._groups = groups
+        self._probs = arr
 
     def describe(self) -> dict:
         import json

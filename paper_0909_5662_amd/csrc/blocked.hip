@@ -24,11 +24,13 @@
 #include <string>
 #include <vector>
 
+#include "pinned_lru.h"
 #include "rot_internal.h"
 
 namespace rot {
 namespace {
 
+// cached block structures kept beyond those pinned by graph capture
 constexpr size_t kPlanCacheSize = 8;
 
 struct QN {
@@ -497,9 +499,8 @@ struct DeviceLists {
 };
 
 struct Plan {
-    std::vector<unsigned char> sig;
     DeviceLists s1, s2;
-    int* counter = nullptr;
+    int64_t counter_off = 0;  // bytes into the caller's workspace: the tile queue of this call
     int64_t x_elems = 0;
     BlkTask* f_tasks = nullptr;
     BlkTerm* f_terms = nullptr;
@@ -515,7 +516,6 @@ struct Plan {
         (void)hipFree(s1.tiles);
         (void)hipFree(s2.probs);
         (void)hipFree(s2.tiles);
-        (void)hipFree(counter);
         (void)hipFree(f_tasks);
         (void)hipFree(f_terms);
         (void)hipFree(f_segs);
@@ -523,7 +523,7 @@ struct Plan {
 };
 
 std::mutex g_mu;
-std::list<std::unique_ptr<Plan>> g_plans;  // most recent first
+PinnedLru<std::vector<unsigned char>, Plan> g_plans(kPlanCacheSize);
 
 template <class T>
 void put(std::vector<unsigned char>& v, const T* p, size_t n) {
@@ -577,15 +577,22 @@ hipError_t upload(const std::vector<GroupedProblem>& probs, const std::vector<Gr
 
 GroupedShape blocked_shape() { return GroupedShape::k32; }
 
+// Bytes of X (grouped path) and the transposed U blocks (fused path); the
+// call's tile-queue counter follows, 256-byte aligned.
+int64_t counter_offset(int64_t x_elems, int64_t ut_elems) {
+    return ((x_elems + 63) / 64 * 64 + ut_elems) * (int64_t)sizeof(float) / 256 * 256 + 256;
+}
+
 }  // namespace
 
-// X of the grouped path, then the transposed U blocks of the fused path.
+// X of the grouped path, then the transposed U blocks of the fused path, then
+// the call's tile-queue counter (in the caller's workspace, so calls with
+// different workspaces never share a queue).
 size_t blocked_workspace_bytes(const rot_blocked_problem* p) {
     Structure st;
     std::string why;
     if (!build_structure(p, &st, &why)) return 0;
-    const int64_t x = (x_elements(p, st) + 63) / 64 * 64;
-    return (size_t)(x + ut_layout(p, st).elems) * sizeof(float);
+    return (size_t)counter_offset(x_elements(p, st), ut_layout(p, st).elems) + 256;
 }
 
 rot_status blocked_validate(const rot_blocked_problem* p, std::string* why) {
@@ -608,7 +615,7 @@ hipError_t run_grouped(const rot_blocked_problem* p, Plan* plan, void* ws, Group
     a.dynamic = true;
     a.shape = shape;
     a.grid = 2048;  // persistent: 8 single-wave workgroups per CU
-    a.counter = plan->counter;
+    a.counter = reinterpret_cast<int*>(static_cast<char*>(ws) + plan->counter_off);
     hipError_t e = prof_timed("blocked_stage1_fp32", stream, [&] { return grouped_gemm_f32(a, stream); });
     if (e != hipSuccess) return e;
     GroupedLaunch b = a;
@@ -627,10 +634,10 @@ hipError_t run_grouped(const rot_blocked_problem* p, Plan* plan, void* ws, Group
 // pass); `wide` keeps every column block of a task in one pass (fewest
 // operand fetches), otherwise fewer per pass (more resident waves).
 template <int MAXA, int CG>
-void launch_fused(Plan* plan, const float* ut, const rot_blocked_problem* p, hipStream_t stream) {
+void launch_fused(Plan* plan, const float* ut, const rot_blocked_problem* p, int* counter, hipStream_t stream) {
     const int grid = 256 * 4;  // 4 workgroups of 4 waves per CU, each wave a task queue consumer
     hipLaunchKernelGGL((blocked_fused_kernel<MAXA, CG>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
-                       plan->f_n_tasks, plan->f_terms, ut, p->O_blk, p->out_blk, plan->counter);
+                       plan->f_n_tasks, plan->f_terms, ut, p->O_blk, p->out_blk, counter);
 }
 
 hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, void* ws, hipStream_t stream) {
@@ -644,14 +651,15 @@ hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, void* 
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
+    int* counter = reinterpret_cast<int*>(static_cast<char*>(ws) + plan->counter_off);
     return prof_timed("blocked_fused_fp32", stream, [&] {
-        hipLaunchKernelGGL(reset_fused_counter, dim3(1), dim3(64), 0, stream, plan->counter);
+        hipLaunchKernelGGL(reset_fused_counter, dim3(1), dim3(64), 0, stream, counter);
         if (plan->f_max_mT <= 64) {
-            if (wide) launch_fused<4, 4>(plan, ut, p, stream); else launch_fused<4, 2>(plan, ut, p, stream);
+            if (wide) launch_fused<4, 4>(plan, ut, p, counter, stream); else launch_fused<4, 2>(plan, ut, p, counter, stream);
         } else if (plan->f_max_mT <= 80) {
-            if (wide) launch_fused<5, 3>(plan, ut, p, stream); else launch_fused<5, 2>(plan, ut, p, stream);
+            if (wide) launch_fused<5, 3>(plan, ut, p, counter, stream); else launch_fused<5, 2>(plan, ut, p, counter, stream);
         } else {
-            if (wide) launch_fused<8, 3>(plan, ut, p, stream); else launch_fused<8, 2>(plan, ut, p, stream);
+            if (wide) launch_fused<8, 3>(plan, ut, p, counter, stream); else launch_fused<8, 2>(plan, ut, p, counter, stream);
         }
         return hipGetLastError();
     });
@@ -683,14 +691,18 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
     const GroupedShape shape = blocked_shape();
     const int forced = forced_path();
     std::vector<unsigned char> sig = signature(p, ws, shape);
-    Plan* plan = nullptr;
+    // Under stream capture the graph keeps the plan's device work-lists: the
+    // plan is pinned (never evicted), and a structure not seen before cannot
+    // be planned (its lists are copied to the device synchronously).
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
     std::lock_guard<std::mutex> lk(g_mu);
-    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
-        if ((*it)->sig == sig) {
-            g_plans.splice(g_plans.begin(), g_plans, it);
-            plan = g_plans.front().get();
-            break;
-        }
+    Plan* plan = g_plans.find(sig);
+    if (!plan && capturing) {
+        set_error(ROT_ERR_UNSUPPORTED,
+                  "rot_batch_blocked: the first call for a block structure must run outside stream capture "
+                  "(it builds and uploads the work-lists); call it once eagerly before capturing");
+        return hipErrorStreamCaptureUnsupported;
     }
     if (!plan) {
         Structure st;
@@ -702,17 +714,16 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         FusedLists F;
         build_fused(p, st, ut, &F);
         auto np = std::make_unique<Plan>();
-        np->sig = std::move(sig);
         np->x_elems = L.x_elems;
         const int edge = grouped_tile_edge(shape);
         hipError_t e = upload(L.p1, make_tiles(L.p1, edge), &np->s1);
         if (e == hipSuccess) e = upload(L.p2, make_tiles(L.p2, edge), &np->s2);
-        if (e == hipSuccess) e = hipMalloc(&np->counter, sizeof(int));
         np->f_n_tasks = (int)F.tasks.size();
         np->f_max_mT = F.max_mT;
         np->f_n_segs = (int)ut.segs.size();
         np->ut_base = (L.x_elems + 63) / 64 * 64;
         np->ut_elems = ut.elems;
+        np->counter_off = counter_offset(L.x_elems, ut.elems);
         if (e == hipSuccess && !ut.segs.empty()) e = hipMalloc(&np->f_segs, sizeof(UtSeg) * ut.segs.size());
         if (e == hipSuccess && !ut.segs.empty())
             e = hipMemcpy(np->f_segs, ut.segs.data(), sizeof(UtSeg) * ut.segs.size(), hipMemcpyHostToDevice);
@@ -724,9 +735,12 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
             e = hipMemcpy(np->f_terms, F.terms.data(), sizeof(BlkTerm) * F.terms.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return e;
         if (F.max_mT > 128) np->path = 0;  // the fused kernel keeps at most 8 x 16 output rows per lane set
-        g_plans.push_front(std::move(np));
-        if (g_plans.size() > kPlanCacheSize) g_plans.pop_back();
-        plan = g_plans.front().get();
+        plan = g_plans.insert(std::move(sig), std::move(np));
+    }
+    if (capturing) {
+        g_plans.pin(plan);
+        // no timing under capture: the fused path unless the structure needs the grouped one
+        if (plan->path < 0 && forced < 0) plan->path = plan->f_max_mT > 128 ? 0 : 1;
     }
     int path = forced >= 0 ? forced : plan->path;
     if (path >= 1 && plan->f_max_mT > 128) path = 0;

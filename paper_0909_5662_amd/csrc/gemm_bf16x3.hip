@@ -544,6 +544,89 @@ Bf16Layout layout(int m, int d, int mp) {
     return L;
 }
 
+// X (R x C FP32 per batch element, row stride ldx, batch stride bsx; with
+// SYM, R == C and the values are X + X^T) split into hi/lo slab layouts:
+//   rows layout (R rows, K = C): element (r, c) -> rh/rl + b*rbs
+//   cols layout (C rows, K = R): element (c, r) -> ch/cl + b*cbs
+// Either pair may be null.  The K padding of each layout's last slab is
+// written as zero, so operands concatenated along K (one slab array after
+// the other) multiply to exact zeros there.  One 64 x 64 tile per workgroup
+// through LDS (with SYM also the mirror tile); each thread then converts 8
+// consecutive k of one row of a layout and stores them as one 16-byte chunk
+// per array.
+template <bool SYM>
+__global__ __launch_bounds__(256) void split_layouts_kernel(const float* __restrict__ X, int R, int C, int64_t ldx,
+                                                            int64_t bsx, uint16_t* __restrict__ rh,
+                                                            uint16_t* __restrict__ rl, int64_t rbs,
+                                                            uint16_t* __restrict__ ch, uint16_t* __restrict__ cl,
+                                                            int64_t cbs) {
+    __shared__ float tile[64][65];
+    __shared__ float mir[SYM ? 64 : 1][65];
+    const int b = blockIdx.z, r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const float* src = X + (int64_t)b * bsx;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int r = r0 + ty + 4 * k, c = c0 + tx;
+        tile[ty + 4 * k][tx] = (r < R && c < C) ? src[(int64_t)r * ldx + c] : 0.f;
+        if (SYM) {
+            // mir[i][j] = X(c0 + i, r0 + j): rows of the mirror block, coalesced
+            const int mr = c0 + ty + 4 * k, mc = r0 + tx;
+            mir[ty + 4 * k][tx] = (mr < C && mc < R) ? src[(int64_t)mr * ldx + mc] : 0.f;
+        }
+    }
+    __syncthreads();
+    auto value = [&](int i, int j) {  // element (r0 + i, c0 + j)
+        return SYM ? tile[i][j] + mir[j][i] : tile[i][j];
+    };
+    auto store8 = [&](uint16_t* hi, uint16_t* lo, int64_t off, const float (&v)[8]) {
+        const u32x2 p0 = split2(v[0], v[1]), p1 = split2(v[2], v[3]);
+        const u32x2 p2 = split2(v[4], v[5]), p3 = split2(v[6], v[7]);
+        *reinterpret_cast<u32x4*>(hi + off) = u32x4{p0[0], p1[0], p2[0], p3[0]};
+        *reinterpret_cast<u32x4*>(lo + off) = u32x4{p0[1], p1[1], p2[1], p3[1]};
+    };
+    if (rh) {
+        const int kpad = (int)(n_slabs(C) * kSlabK);
+#pragma unroll
+        for (int x = 0; x < 2; x++) {
+            const int q = tid + 256 * x, i = q & 63, k8 = (q >> 6) * 8;
+            const int r = r0 + i, k0 = c0 + k8;
+            if (r >= R || k0 >= kpad) continue;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[e] = value(i, k8 + e);
+            store8(rh + (int64_t)b * rbs, rl + (int64_t)b * rbs, slab_off(r, k0, R), v);
+        }
+    }
+    if (ch) {
+        const int kpad = (int)(n_slabs(R) * kSlabK);
+#pragma unroll
+        for (int x = 0; x < 2; x++) {
+            const int q = tid + 256 * x, j = q & 63, k8 = (q >> 6) * 8;
+            const int c = c0 + j, k0 = r0 + k8;
+            if (c >= C || k0 >= kpad) continue;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[e] = value(k8 + e, j);
+            store8(ch + (int64_t)b * cbs, cl + (int64_t)b * cbs, slab_off(c, k0, C), v);
+        }
+    }
+}
+
+// Enqueue split_layouts_kernel over `batch` matrices.
+hipError_t split_layouts(const float* X, int R, int C, int64_t ldx, int64_t bsx, int batch, bool sym, uint16_t* rh,
+                         uint16_t* rl, int64_t rbs, uint16_t* ch, uint16_t* cl, int64_t cbs, hipStream_t s) {
+    if (R <= 0 || C <= 0 || batch <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((C + 63) / 64), (unsigned)((R + 63) / 64), (unsigned)batch);
+    if (sym)
+        hipLaunchKernelGGL(split_layouts_kernel<true>, grid, dim3(256), 0, s, X, R, C, ldx, bsx, rh, rl, rbs, ch, cl,
+                           cbs);
+    else
+        hipLaunchKernelGGL(split_layouts_kernel<false>, grid, dim3(256), 0, s, X, R, C, ldx, bsx, rh, rl, rbs, ch,
+                           cl, cbs);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Every split operand array, with one tile (256 rows) of overhang, must stay
@@ -632,6 +715,205 @@ hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symm
     b.upper = symmetric ? 1 : 0;
     return prof_timed(symmetric ? "stage2sym_bf16x3" : "stage2_bf16x3", stream,
                       [&] { return launch_bf16<false>(b, stream); });
+}
+
+
+// ---------------------------------------------------------------------------
+// Split-BF16 adjoint.  With P_b = U dOut_b and Q_b = U dOut_b^T ((m*d) x mp,
+// viewed as m x d*mp through the row index i*d + s):
+//   dO_b = P_b,r U_r^T
+//   dU_r = sum_b O_b^T P_b,r + O_b Q_b,r    (symmetric O_b: sum_b O_b (P_b + Q_b)_r)
+// Every product is a split-BF16 GEMM (three BF16 products per operand pair,
+// FP32 accumulation) whose operands are FP32 values split into the slab
+// layout: U and U_r once per call, dOut_b (transposed; rows for Q, or
+// dOut_b + dOut_b^T for the symmetric sum), P/Q (rows and transposed
+// layouts) and O_b per operator chunk.  The dU operator sum is one GEMM
+// whose K runs over (operator, i) of every term, cut into parts whose
+// partial sums are added in a fixed order.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Bf16Bwd {
+    int64_t mK;          // m rounded up to a whole slab
+    size_t ua, ur;       // one hi or lo array: U (m*d rows, K = mp), U_r (m rows, K = d*mp)
+    size_t dq;           // dOut_b in one layout (mp rows, K = mp)
+    size_t p32;          // P_b or Q_b in FP32 ((m*d) x mp)
+    size_t pa;           // P_b,r rows layout (m rows, K = d*mp)
+    size_t pb;           // P_b,r / Q_b,r transposed layout (d*mp rows, K = m)
+    size_t os;           // O_b (or O_b^T) (m rows, K = m)
+    size_t part;         // a partial dU (FP32, (m*d) x mp)
+    size_t shared() const { return 2 * ua + 2 * ur; }
+    size_t per_op() const { return 4 * dq + p32 + 2 * pa + 4 * pb + 4 * os; }
+};
+
+Bf16Bwd bwd_layout(int m, int d, int mp) {
+    Bf16Bwd L;
+    const int64_t md = (int64_t)m * d, dmp = (int64_t)d * mp;
+    L.mK = n_slabs(m) * kSlabK;
+    L.ua = al256((size_t)(n_slabs(mp) * md * kSlabK * 2));
+    L.ur = al256((size_t)(n_slabs(dmp) * m * kSlabK * 2));
+    L.dq = al256((size_t)(n_slabs(mp) * mp * kSlabK * 2));
+    L.p32 = al256((size_t)md * mp * 4);
+    L.pa = L.ur;
+    // arrays concatenated along K must follow each other with no gap: their
+    // sizes are whole slabs of whole rows (multiples of 32 bytes), not rounded
+    L.pb = (size_t)(n_slabs(m) * dmp * kSlabK * 2);
+    L.os = (size_t)(n_slabs(m) * m * kSlabK * 2);
+    L.part = al256((size_t)md * mp * 4);
+    return L;
+}
+
+constexpr size_t kOperandLimit = ((size_t)1 << 31) - 256 * kSlabK * 2;  // 32-bit byte offsets
+
+// Parts of the dU sum over `terms` (operator, factor) terms: enough output
+// tiles to fill the chip, at most 8, and each part's operands below 2 GiB.
+int bwd_parts(const Bf16Bwd& L, int m, int d, int mp, int terms) {
+    const int64_t dmp = (int64_t)d * mp;
+    const int T = (m >= 256 && dmp >= 256) ? 256 : 128;
+    const int64_t tiles = ((m + T - 1) / T) * ((dmp + T - 1) / T);
+    int parts = (int)std::min<int64_t>(8, (1024 + tiles - 1) / tiles);
+    const size_t biggest = std::max(L.pb, L.os);
+    const int per_part_max = (int)std::max<size_t>(1, kOperandLimit / biggest);
+    parts = std::max(parts, (terms + per_part_max - 1) / per_part_max);
+    return std::max(1, std::min(parts, terms));
+}
+
+Bf16Desc plain_desc(int M, int N, int K, int batch, const uint16_t* ah, const uint16_t* al, int64_t abs_,
+                    const uint16_t* bh, const uint16_t* bl, int64_t bbs, float* c, int64_t ldc, int64_t cbs) {
+    Bf16Desc g{};
+    g.M = M; g.N = N; g.K = K; g.batch = batch;
+    g.a_hi = ah; g.a_lo = al; g.a_bs = abs_;
+    g.b_hi = bh; g.b_lo = bl; g.b_bs = bbs;
+    g.c = c; g.ldc = ldc; g.c_bs = cbs;
+    return g;
+}
+
+}  // namespace
+
+bool bf16_backward_supported(int m, int d, int mp) {
+    const Bf16Bwd L = bwd_layout(m, d, mp);
+    return L.ua < kOperandLimit && L.ur < kOperandLimit && L.pb < kOperandLimit && L.dq < kOperandLimit &&
+           L.os < kOperandLimit;
+}
+
+// Workspace for `ops` operators per chunk (general operators: both dU terms).
+size_t bf16_backward_workspace(int m, int d, int mp, int ops) {
+    const Bf16Bwd L = bwd_layout(m, d, mp);
+    // the four concatenated operand regions are each rounded up to 256 bytes
+    return L.shared() + (size_t)ops * L.per_op() + 4 * 256 + (size_t)bwd_parts(L, m, d, mp, 2 * ops) * L.part;
+}
+
+// One chunk of nb operators from b0 (p resolved, U packed to row stride mp).
+// dOut_b at dout + (b0 + b)*sd (sd = 0: one matrix for all).  dO/dU may be
+// null.  dU accumulates when b0 > 0.
+hipError_t backward_bf16(const rot_problem& p, int b0, int nb, const float* dout, int64_t sd, float* dO, float* dU,
+                         bool sym, void* ws, hipStream_t s) {
+    const Bf16Bwd L = bwd_layout(p.m, p.d, p.mp);
+    const int m = p.m, d = p.d, mp = p.mp;
+    const int md = m * d, dmp = d * mp;
+    char* base = static_cast<char*>(ws);
+    auto take = [&](size_t bytes) {
+        uint16_t* q = reinterpret_cast<uint16_t*>(base);
+        base += bytes;
+        return q;
+    };
+    uint16_t *uah = take(L.ua), *ual = take(L.ua), *urh = take(L.ur), *url = take(L.ur);
+    uint16_t *dth = take(nb * L.dq), *dtl = take(nb * L.dq), *dsh = take(nb * L.dq), *dsl = take(nb * L.dq);
+    float* P = reinterpret_cast<float*>(take(nb * L.p32));
+    uint16_t *pah = take(nb * L.pa), *pal = take(nb * L.pa);
+    uint16_t *pbh = take(al256(2 * nb * L.pb)), *pbl = take(al256(2 * nb * L.pb));
+    uint16_t *osh = take(al256(2 * nb * L.os)), *osl = take(al256(2 * nb * L.os));
+    float* part = reinterpret_cast<float*>(base);
+    const float* U = static_cast<const float*>(p.U);
+    const int64_t e_dq = (int64_t)(L.dq / 2), e_pa = (int64_t)(L.pa / 2), e_pb = (int64_t)(L.pb / 2),
+                  e_os = (int64_t)(L.os / 2), e_p32 = (int64_t)(L.p32 / 4);
+    const int nd = sd == 0 ? 1 : nb;  // distinct upstream gradients in this chunk
+    const int64_t bd = sd == 0 ? 0 : e_dq;
+    hipError_t e = hipSuccess;
+    if (b0 == 0) {
+        // U (m*d rows, K = mp) and U_r (m rows, K = d*mp), both row layouts
+        e = prof_timed("adj_split_u_bf16x3", s, [&] {
+            hipError_t err = split_layouts(U, md, mp, mp, 0, 1, false, uah, ual, 0, nullptr, nullptr, 0, s);
+            if (err == hipSuccess)
+                err = split_layouts(U, m, dmp, dmp, 0, 1, false, urh, url, 0, nullptr, nullptr, 0, s);
+            return err;
+        });
+        if (e != hipSuccess) return e;
+    }
+    const float* g0 = dout + (int64_t)b0 * sd;
+    // dOut_b transposed (B of P = U dOut_b), and for dU the B of the second
+    // term: dOut_b itself (Q = U dOut_b^T) or dOut_b + dOut_b^T (symmetric O)
+    e = prof_timed("adj_split_dout_bf16x3", s, [&] {
+        hipError_t err = split_layouts(g0, mp, mp, mp, sd, nd, false, nullptr, nullptr, 0, dth, dtl, e_dq, s);
+        if (err == hipSuccess && dU)
+            err = split_layouts(g0, mp, mp, mp, sd, nd, sym, dsh, dsl, e_dq, nullptr, nullptr, 0, s);
+        return err;
+    });
+    if (e != hipSuccess) return e;
+    const bool need_p = dO || (dU && !sym);
+    if (need_p) {
+        // P_b = U dOut_b (FP32), then P_b,r in the layouts its products read
+        e = prof_timed("adj_P_bf16x3", s, [&] {
+            return launch_bf16<false>(plain_desc(md, mp, mp, nb, uah, ual, 0, dth, dtl, bd, P, mp, e_p32), s);
+        });
+        if (e == hipSuccess)
+            e = prof_timed("adj_split_p_bf16x3", s, [&] {
+                return split_layouts(P, m, dmp, dmp, e_p32, nb, false, dO ? pah : nullptr, pal, e_pa,
+                                     (dU && !sym) ? pbh : nullptr, pbl, e_pb, s);
+            });
+        if (e != hipSuccess) return e;
+    }
+    if (dO) {
+        e = prof_timed("adj_dO_bf16x3", s, [&] {
+            return launch_bf16<false>(plain_desc(m, m, dmp, nb, pah, pal, e_pa, urh, url, 0,
+                                                 dO + (int64_t)b0 * m * m, m, (int64_t)m * m), s);
+        });
+        if (e != hipSuccess) return e;
+    }
+    if (!dU) return hipSuccess;
+    // second term: Q_b = U dOut_b^T, or (P + Q)_b for symmetric operators,
+    // transposed P_r layout after the first term's (general) or alone
+    const int64_t qoff = sym ? 0 : (int64_t)nb * e_pb;
+    e = prof_timed(sym ? "adj_PQ_bf16x3" : "adj_Q_bf16x3", s, [&] {
+        return launch_bf16<false>(plain_desc(md, mp, mp, nb, uah, ual, 0, dsh, dsl, bd, P, mp, e_p32), s);
+    });
+    if (e == hipSuccess)
+        e = prof_timed("adj_split_p_bf16x3", s, [&] {
+            return split_layouts(P, m, dmp, dmp, e_p32, nb, false, nullptr, nullptr, 0, pbh + qoff, pbl + qoff,
+                                 e_pb, s);
+        });
+    // A operands: O_b^T for the first term, O_b for the second (rows j, K i)
+    if (e == hipSuccess)
+        e = prof_timed("adj_split_o_bf16x3", s, [&] {
+            const float* O = static_cast<const float*>(p.O) + (int64_t)b0 * p.stride_o;
+            const int64_t ooff = sym ? 0 : (int64_t)nb * e_os;
+            return split_layouts(O, m, m, p.ldo, p.stride_o, nb, false, osh + ooff, osl + ooff, e_os,
+                                 sym ? nullptr : osh, osl, e_os, s);
+        });
+    if (e != hipSuccess) return e;
+    // dU_r = sum over the terms t of A_t (m x mK) B_t^T (d*mp rows, K = mK),
+    // K concatenated over terms and cut into np parts of q or q + 1 terms
+    const int terms = sym ? nb : 2 * nb;
+    const int np = bwd_parts(L, m, d, mp, terms);
+    const int q = terms / np, r = terms % np;
+    const int64_t mK = L.mK;
+    e = prof_timed("adj_dU_bf16x3", s, [&] {
+        hipError_t err = hipSuccess;
+        if (r > 0)
+            err = launch_bf16<false>(plain_desc(m, dmp, (int)((q + 1) * mK), r, osh, osl, (q + 1) * e_os, pbh, pbl,
+                                                (q + 1) * e_pb, part, dmp, e_p32), s);
+        if (err == hipSuccess) {
+            const int64_t t0 = (int64_t)r * (q + 1);
+            err = launch_bf16<false>(plain_desc(m, dmp, (int)(q * mK), np - r, osh + t0 * e_os, osl + t0 * e_os,
+                                                q * e_os, pbh + t0 * e_pb, pbl + t0 * e_pb, q * e_pb,
+                                                part + (int64_t)r * e_p32, dmp, e_p32), s);
+        }
+        return err;
+    });
+    if (e != hipSuccess) return e;
+    return prof_timed("adj_dU_sum", s, [&] {
+        return sum_parts(dU, part, (int64_t)md * mp, np, e_p32, b0 > 0, false, s);
+    });
 }
 
 }  // namespace rot

@@ -19,6 +19,10 @@ hipError_t split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hip
 size_t bf16_group_workspace(int m, int d, int mp, int ops);
 bool bf16_shape_supported(int m, int d, int mp);
 hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, hipStream_t stream);
+bool bf16_backward_supported(int m, int d, int mp);
+size_t bf16_backward_workspace(int m, int d, int mp, int ops);
+hipError_t backward_bf16(const rot_problem& p, int b0, int nb, const float* dout, int64_t sd, float* dO, float* dU,
+                         bool sym, void* ws, hipStream_t s);
 size_t blocked_workspace_bytes(const rot_blocked_problem* p);
 rot_status blocked_validate(const rot_blocked_problem* p, std::string* why);
 hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -372,6 +376,8 @@ size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_preci
         size_t g;
         if (prec == ROT_SPLIT_BF16 && !for_backward) {
             g = bf16_group_workspace(p.m, p.d, p.mp, ops);
+        } else if (prec == ROT_SPLIT_BF16) {
+            g = packed_u_bytes(p, tp) + bf16_backward_workspace(p.m, p.d, p.mp, ops);
         } else if (for_backward) {
             rot_problem packed = p;
             packed.ldu = p.mp;  // the adjoint works on U packed to row stride mp
@@ -699,7 +705,6 @@ rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void*
     if (n_groups < 0 || (n_groups > 0 && (!groups || !dOut || !stride_dout)))
         return fail(ROT_ERR_INVALID_ARG, "null groups/dOut/stride_dout or negative n_groups");
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
-    if (prec == ROT_SPLIT_BF16) return fail(ROT_ERR_UNSUPPORTED, "rot_backward: split-bf16 not implemented; use ROT_FP32");
     if (flags & ~ROT_ASSUME_SYMMETRIC_O) return fail(ROT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     const std::vector<rot_problem> rg = resolved_all(groups, n_groups);
     for (int gi = 0; gi < n_groups; gi++) {
@@ -710,6 +715,10 @@ rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void*
         if (!dOut[gi]) return fail(ROT_ERR_INVALID_ARG, "group %d: null dOut", gi);
         if (stride_dout[gi] != 0 && stride_dout[gi] < (int64_t)p.mp * p.mp)
             return fail(ROT_ERR_INVALID_ARG, "group %d: stride_dout must be 0 or >= mp*mp", gi);
+        if (prec == ROT_SPLIT_BF16 && !bf16_backward_supported(p.m, p.d, p.mp))
+            return fail(ROT_ERR_UNSUPPORTED,
+                        "group %d: split-bf16 adjoint operands must stay below 2 GiB (m=%d d=%d mp=%d); use ROT_FP32",
+                        gi, p.m, p.d, p.mp);
     }
     const size_t min_ws = rot_workspace_size(groups, n_groups, prec, 1, 1);
     if (min_ws > 0) {
@@ -746,6 +755,17 @@ rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void*
             if (e != hipSuccess) return hip_fail(e, "rot_backward pack U");
             p.U = workspace0;
             p.ldu = p.mp;
+        }
+        if (prec == ROT_SPLIT_BF16) {
+            int chunk = 1;
+            while (chunk < p.n_ops && bf16_backward_workspace(p.m, p.d, p.mp, chunk + 1) <= workspace_bytes) chunk++;
+            for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
+                const int nb = std::min(chunk, p.n_ops - b0);
+                hipError_t e = backward_bf16(p, b0, nb, static_cast<const float*>(dOut[gi]), stride_dout[gi],
+                                             static_cast<float*>(dOg), static_cast<float*>(dUg), sym, workspace, s);
+                if (e != hipSuccess) return hip_fail(e, "rot_backward split-bf16 launch");
+            }
+            continue;
         }
         const size_t per_op = t_bytes(p, prec);
         const size_t slots = workspace_bytes / per_op;
@@ -955,6 +975,7 @@ rot_status rot_batch_blocked(const rot_blocked_problem* p, rot_precision prec, v
     if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
         return fail(ROT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     hipError_t e = rotate_blocked(p, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+    if (e == hipErrorStreamCaptureUnsupported) return ROT_ERR_UNSUPPORTED;  // message already set
     return e == hipSuccess ? ROT_OK : hip_fail(e, "rot_batch_blocked");
 }
 

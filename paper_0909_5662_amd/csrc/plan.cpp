@@ -41,6 +41,8 @@ struct rot_plan_s {
         int n_tiles = 0;
         int* counter = nullptr;
         double flops = 0;
+        std::vector<std::pair<int, int>> src;  // (group, operator) of each problem
+        std::vector<const float*> t;           // its stage-1 intermediate
     };
     struct Class {
         std::string key;
@@ -54,10 +56,16 @@ struct rot_plan_s {
     std::vector<Class> classes;
     std::vector<Launch> launches;
     std::vector<std::vector<rot::GroupedProblem>> host_probs;  // per launch (tiles rebuilt on shape change)
+    std::vector<rot_problem> groups;  // resolved shapes and the bound buffers
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool use_graph = true;
+    // rot_plan_rebind: pinned staging of the problem tables and the event of
+    // the last copy out of it
+    rot::GroupedProblem* staging = nullptr;
+    size_t staging_count = 0;
+    hipEvent_t staged = nullptr;
     std::string error;
 };
 
@@ -122,6 +130,44 @@ void tune_store_locked() {
               << ' ' << kv.second.grid << '\n';
     }
     std::rename(tmp.c_str(), path);
+}
+
+// The grouped-GEMM problem of stage 1 or 2 for operator b of group p (p
+// resolved), with T its stage-1 intermediate.  Positions are absolute
+// addresses (the launches' base pointers are null).  T_b takes U's row
+// layout ((m*d) x ldu): stage 1 reads U_r as one matrix of row stride d*ldu
+// over (d-1)*ldu + mp columns.
+GroupedProblem stage_problem(const rot_problem& p, int b, const float* T, int stage) {
+    const float* O = static_cast<const float*>(p.O) + (int64_t)b * p.stride_o;
+    float* out = static_cast<float*>(p.out) + (int64_t)b * p.stride_out;
+    const float* U = static_cast<const float*>(p.U);
+    auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+    auto addr = [](const void* q) { return (int64_t) reinterpret_cast<uintptr_t>(q); };
+    GroupedProblem g{};
+    if (stage == 1) {
+        g.M = p.m;
+        g.N = (int)((int64_t)(p.d - 1) * p.ldu + p.mp);
+        g.K = p.m;
+        g.a_off = addr(O);
+        g.lda = p.ldo;
+        g.b_off = addr(U);
+        g.ldb = (int64_t)p.d * p.ldu;
+        g.c_off = addr(T);
+        g.ldc = (int64_t)p.d * p.ldu;
+        g.flags = (al(O) && al(U) && p.ldo % 4 == 0 && (p.d * p.ldu) % 4 == 0) ? kGroupedVec : 0;
+    } else {
+        g.M = p.mp;
+        g.N = p.mp;
+        g.K = p.m * p.d;
+        g.a_off = addr(U);
+        g.lda = p.ldu;
+        g.b_off = addr(T);
+        g.ldb = p.ldu;
+        g.c_off = addr(out);
+        g.ldc = p.ldout;
+        g.flags = (al(U) && p.ldu % 4 == 0) ? kGroupedVec : 0;
+    }
+    return g;
 }
 
 std::vector<GroupedTile> tiles_for(const std::vector<GroupedProblem>& probs, int edge) {
@@ -245,6 +291,11 @@ void destroy(rot_plan_s* P) {
         (void)hipFree(L.tiles);
         (void)hipFree(L.counter);
     }
+    if (P->staged) {
+        (void)hipEventSynchronize(P->staged);
+        (void)hipEventDestroy(P->staged);
+    }
+    if (P->staging) (void)hipHostFree(P->staging);
     if (P->stream) (void)hipStreamDestroy(P->stream);
     delete P;
 }
@@ -290,6 +341,7 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
 
     rot_plan_s* P = new rot_plan_s();
     P->use_graph = !(flags & ROT_PLAN_NO_GRAPH);
+    P->groups = rg;
     // the caller's pending work on its buffers finishes before tuning writes
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
@@ -337,6 +389,8 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
     char* ws = static_cast<char*>(workspace);
     for (int ci : order) {
         std::vector<GroupedProblem> s1, s2;
+        std::vector<std::pair<int, int>> srcs;
+        std::vector<const float*> ts;
         size_t used = 0;
         double chunk_flops = 0;
         auto flush = [&]() -> hipError_t {
@@ -346,6 +400,8 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
                 L.cls = ci;
                 L.stage = stage;
                 L.flops = chunk_flops / 2;
+                L.src = srcs;
+                L.t = ts;
                 const std::vector<GroupedProblem>& v = stage == 1 ? s1 : s2;
                 hipError_t err = hipMalloc(&L.probs, sizeof(GroupedProblem) * v.size());
                 if (err == hipSuccess)
@@ -357,6 +413,8 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
             }
             s1.clear();
             s2.clear();
+            srcs.clear();
+            ts.clear();
             used = 0;
             chunk_flops = 0;
             return hipSuccess;
@@ -371,35 +429,11 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
                     e = flush();
                     if (e != hipSuccess) break;
                 }
-                const float* O = static_cast<const float*>(p.O) + (int64_t)b * p.stride_o;
-                float* out = static_cast<float*>(p.out) + (int64_t)b * p.stride_out;
-                const float* U = static_cast<const float*>(p.U);
                 const float* T = reinterpret_cast<const float*>(ws + used);
-                auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
-                GroupedProblem g1{};
-                g1.M = p.m;
-                g1.N = (int)((int64_t)(p.d - 1) * p.ldu + p.mp);
-                g1.K = p.m;
-                g1.a_off = (int64_t) reinterpret_cast<uintptr_t>(O);
-                g1.lda = p.ldo;
-                g1.b_off = (int64_t) reinterpret_cast<uintptr_t>(U);
-                g1.ldb = (int64_t)p.d * p.ldu;
-                g1.c_off = (int64_t) reinterpret_cast<uintptr_t>(T);
-                g1.ldc = (int64_t)p.d * p.ldu;
-                g1.flags = (al(O) && al(U) && p.ldo % 4 == 0 && (p.d * p.ldu) % 4 == 0) ? kGroupedVec : 0;
-                GroupedProblem g2{};
-                g2.M = p.mp;
-                g2.N = p.mp;
-                g2.K = p.m * p.d;
-                g2.a_off = (int64_t) reinterpret_cast<uintptr_t>(U);
-                g2.lda = p.ldu;
-                g2.b_off = (int64_t) reinterpret_cast<uintptr_t>(T);
-                g2.ldb = p.ldu;
-                g2.c_off = (int64_t) reinterpret_cast<uintptr_t>(out);
-                g2.ldc = p.ldout;
-                g2.flags = (al(U) && p.ldu % 4 == 0) ? kGroupedVec : 0;
-                s1.push_back(g1);
-                s2.push_back(g2);
+                s1.push_back(stage_problem(p, b, T, 1));
+                s2.push_back(stage_problem(p, b, T, 2));
+                srcs.emplace_back(gi, b);
+                ts.push_back(T);
                 used += tb;
                 chunk_flops += 2.0 * p.m * p.m * p.d * p.mp + 2.0 * p.m * p.d * (double)p.mp * p.mp;
             }
@@ -467,6 +501,53 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
         }
     }
     *out = P;
+    return ROT_OK;
+}
+
+rot_status rot_plan_rebind(rot_plan plan, const rot_problem* groups, int32_t n_groups, void* stream) {
+    if (!plan) return perr(ROT_ERR_INVALID_ARG, "null plan");
+    if (n_groups != (int32_t)plan->groups.size() || (n_groups > 0 && !groups))
+        return perr(ROT_ERR_INVALID_ARG, "rebind needs the plan's %zu groups", plan->groups.size());
+    std::vector<rot_problem> rg(groups, groups + n_groups);
+    for (int gi = 0; gi < n_groups; gi++) {
+        rot_problem& p = rg[gi];
+        if (p.ldu == 0) p.ldu = p.mp;
+        if (p.ldo == 0) p.ldo = p.m;
+        if (p.ldout == 0) p.ldout = p.mp;
+        const rot_problem& q = plan->groups[gi];
+        if (p.m != q.m || p.d != q.d || p.mp != q.mp || p.n_ops != q.n_ops || p.ldu != q.ldu || p.ldo != q.ldo ||
+            p.ldout != q.ldout || p.stride_o != q.stride_o || p.stride_out != q.stride_out)
+            return perr(ROT_ERR_INVALID_ARG, "group %d: shape, leading dimensions or strides differ from the plan's",
+                        gi);
+        if (p.n_ops > 0 && (!p.U || !p.O || !p.out)) return perr(ROT_ERR_INVALID_ARG, "group %d: null buffer", gi);
+    }
+    size_t total = 0;
+    for (auto& L : plan->launches) total += L.src.size();
+    hipError_t e = hipSuccess;
+    if (!plan->staging) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&plan->staging), sizeof(GroupedProblem) * std::max<size_t>(total, 1));
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming);
+        if (e != hipSuccess) return perr(ROT_ERR_HIP, "rot_plan_rebind setup: %s", hipGetErrorString(e));
+        plan->staging_count = total;
+    }
+    // the previous rebind's copies must have left the staging buffer
+    e = hipEventSynchronize(plan->staged);
+    if (e != hipSuccess) return perr(ROT_ERR_HIP, "rot_plan_rebind: %s", hipGetErrorString(e));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t at = 0;
+    for (size_t li = 0; li < plan->launches.size() && e == hipSuccess; li++) {
+        auto& L = plan->launches[li];
+        GroupedProblem* dst = plan->staging + at;
+        for (size_t k = 0; k < L.src.size(); k++)
+            dst[k] = stage_problem(rg[L.src[k].first], L.src[k].second, L.t[k], L.stage);
+        plan->host_probs[li].assign(dst, dst + L.src.size());
+        // in stream order: replays enqueued before this call read the old tables
+        e = hipMemcpyAsync(L.probs, dst, sizeof(GroupedProblem) * L.src.size(), hipMemcpyHostToDevice, s);
+        at += L.src.size();
+    }
+    if (e == hipSuccess) e = hipEventRecord(plan->staged, s);
+    if (e != hipSuccess) return perr(ROT_ERR_HIP, "rot_plan_rebind: %s", hipGetErrorString(e));
+    plan->groups = rg;
     return ROT_OK;
 }
 

@@ -115,7 +115,9 @@ def test_backward_argument_errors(rotlib):
     vp = ctypes.c_void_p
     dout = (vp * 1)(5 * FAKE)
     sd = (ctypes.c_int64 * 1)(0)
-    assert L.rot_backward(arr, 1, dout, sd, None, None, 0, rotlib.ROT_SPLIT_BF16, 4 * FAKE, 1 << 30, None) == -2
+    need_bf = L.rot_workspace_size(arr, 1, rotlib.ROT_SPLIT_BF16, 1, 1)
+    assert need_bf > 0
+    assert L.rot_backward(arr, 1, dout, sd, None, None, 0, rotlib.ROT_SPLIT_BF16, 4 * FAKE, need_bf - 1, None) == -3
     assert L.rot_backward(arr, 1, dout, sd, None, None, 8, rotlib.ROT_FP32, 4 * FAKE, 1 << 30, None) == -1
     sd_bad = (ctypes.c_int64 * 1)(3)
     assert L.rot_backward(arr, 1, dout, sd_bad, None, None, 0, rotlib.ROT_FP32, 4 * FAKE, 1 << 30, None) == -1
@@ -380,3 +382,24 @@ def test_binding_rejects_host_tensors_before_launch(rotlib):
         rotlib.pair_loss(torch.zeros(2, 4, 4, dtype=torch.float64), torch.zeros(4, dtype=torch.float64))
     with pytest.raises(TypeError):
         rotlib.check_isometry(torch.zeros(8, 4))
+
+
+def test_split_bf16_backward_workspace(rotlib):
+    """The split-BF16 adjoint needs the pre-split U once plus per-operator
+    split operands: more operators per chunk need more workspace, and one
+    operator per chunk is the minimum rot_backward accepts."""
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib, m=96, d=4, mp=80, n=5))
+    sizes = [L.rot_workspace_size(arr, 1, rotlib.ROT_SPLIT_BF16, k, 1) for k in (1, 2, 5)]
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    assert L.rot_workspace_size(arr, 1, rotlib.ROT_SPLIT_BF16, 0, 1) == sizes[2]
+    padded = (rotlib.RotProblem * 1)(prob(rotlib, m=96, d=4, mp=80, n=5, ldu=84))
+    extra = L.rot_workspace_size(padded, 1, rotlib.ROT_SPLIT_BF16, 1, 1) - sizes[0]
+    assert extra == -(-96 * 4 * 80 * 4 // 256) * 256  # U packed first
+
+
+def test_plan_rebind_argument_errors(rotlib):
+    """rot_plan_rebind refuses a null plan on the host."""
+    L = rotlib.lib()
+    arr = (rotlib.RotProblem * 1)(prob(rotlib))
+    assert L.rot_plan_rebind(None, arr, 1, None) == -1

@@ -183,3 +183,89 @@ def test_blocked_call_in_hip_graph_replays_match_eager(rot):
         assert torch.equal(~torch.isnan(out_blk), written)
         assert torch.equal(out_blk[written], eager[written])
     del keep
+
+
+def blocked_setup(rot, case):
+    pk = workloads.pack_blocked(case)
+    dev = torch.device("cuda")
+    U_blk = torch.from_numpy(pk.U_blk).float().to(dev)
+    O_blk = torch.from_numpy(pk.O_blk).float().to(dev)
+    out_blk = torch.full((pk.out_size,), float("nan"), device=dev)
+    p, keep = rot.blocked_problem(pk.site_qn, pk.old, pk.new, pk.shift, U_blk, pk.U_off, O_blk, pk.O_off,
+                                  pk.out_off, out_blk)
+    ws = torch.empty(max(256, rot.rot_blocked_workspace_size(p)), dtype=torch.uint8, device=dev)
+    return p, (keep, U_blk, O_blk), out_blk, ws
+
+
+def sized_case(k, cfg):
+    """A block structure of its own for each k (the last sector's size)."""
+    sizes = [((0, 0), 2), ((1, 0), 3), ((0, 1), 2), ((1, 1), 4), ((2, 1), 2), ((1, 2), 3), ((2, 2), k)]
+    return workloads.blocked_case(sizes=sizes, n_conserving=2, n_up_shift=1, n_dn_shift=1, cfg=cfg)
+
+
+def test_blocked_graph_survives_cache_eviction(rot):
+    """A captured blocked call keeps its work-lists: after more distinct block
+    structures than the cache holds have been used, replays of the graph still
+    equal the eager call bit for bit."""
+    p, hold, out_blk, ws = blocked_setup(rot, sized_case(1, 70))
+    stream = lambda: torch.cuda.current_stream().cuda_stream
+    rot.rot_batch_blocked(p, rot.ROT_FP32, ws.data_ptr(), ws.numel(), stream())
+    torch.cuda.synchronize()
+    eager = out_blk.clone()
+    written = ~torch.isnan(eager)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rot.rot_batch_blocked(p, rot.ROT_FP32, ws.data_ptr(), ws.numel(), stream())
+    for k in range(2, 14):  # 12 other structures: more than the 8 unpinned entries kept
+        q, qhold, qout, qws = blocked_setup(rot, sized_case(k, 70 + k))
+        rot.rot_batch_blocked(q, rot.ROT_FP32, qws.data_ptr(), qws.numel(), stream())
+    torch.cuda.synchronize()
+    for _ in range(3):
+        out_blk.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_blk[written], eager[written])
+        assert torch.isnan(out_blk[~written]).all()
+
+
+def test_blocked_first_call_under_capture_is_refused(rot):
+    """The first call for a structure builds its work-lists with synchronous
+    copies, which capture forbids: it is refused with ROT_ERR_UNSUPPORTED
+    before anything is enqueued, and the structure still works afterwards."""
+    p, hold, out_blk, ws = blocked_setup(rot, sized_case(31, 71))
+    graph = torch.cuda.CUDAGraph()
+    x = torch.zeros(16, device="cuda")
+    with torch.cuda.graph(graph):
+        x.add_(1.0)
+        with pytest.raises(rot.RotError) as ei:
+            rot.rot_batch_blocked(p, rot.ROT_FP32, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+    assert ei.value.status == -2
+    graph.replay()
+    rot.rot_batch_blocked(p, rot.ROT_FP32, ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(x, torch.ones(16, device="cuda"))
+    assert torch.isfinite(out_blk).any()
+
+
+def test_blocked_two_streams_own_workspaces(rot):
+    """The same block structure on two streams at once, each call with its own
+    workspace (and so its own tile queue): both equal the eager result."""
+    case = sized_case(5, 72)
+    p, hold, out_a, ws_a = blocked_setup(rot, case)
+    q, hold_q, out_b, ws_b = blocked_setup(rot, case)
+    rot.rot_batch_blocked(p, rot.ROT_FP32, ws_a.data_ptr(), ws_a.numel(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    eager = out_a.clone()
+    written = ~torch.isnan(eager)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(5):
+        out_a.fill_(float("nan"))
+        out_b.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            rot.rot_batch_blocked(p, rot.ROT_FP32, ws_a.data_ptr(), ws_a.numel(), s1.cuda_stream)
+        with torch.cuda.stream(s2):
+            rot.rot_batch_blocked(q, rot.ROT_FP32, ws_b.data_ptr(), ws_b.numel(), s2.cuda_stream)
+        torch.cuda.synchronize()
+        assert torch.equal(out_a[written], eager[written])
+        assert torch.equal(out_b[written], eager[written])

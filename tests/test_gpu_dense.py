@@ -150,7 +150,7 @@ def test_padded_leading_dimensions(rot, oracle_mod, precision, shape, pads):
     assert torch.all(outbuf[mask] == 7.0)  # padding between and after rows kept
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "split_bf16"])
 @pytest.mark.parametrize("symmetric", [True, False])
 def test_adjoint_padded_inputs(rot, oracle_mod, precision, symmetric):
     """The adjoint with a padded U (packed into the workspace first) and padded
@@ -160,7 +160,7 @@ def test_adjoint_padded_inputs(rot, oracle_mod, precision, symmetric):
     case = workloads.dense_case(m, d, mp, n, cfg=330, dtype="f64" if precision == "fp64" else "f32",
                                 symmetric=symmetric)
     G = np.random.default_rng(12).standard_normal((n, mp, mp))
-    if precision == "fp32":
+    if precision != "fp64":
         G = G.astype(np.float32).astype(np.float64)
     _, U = padded(case.U, dtype, pad_cols=6)
     _, O = padded(case.O, dtype, pad_rows=1, pad_cols=3)
@@ -249,17 +249,17 @@ def test_deterministic(rot):
 
 # ----------------------------------------------------------------- adjoint --
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "split_bf16"])
 @pytest.mark.parametrize("symmetric", [True, False])
-@pytest.mark.parametrize("shape", [(96, 4, 80, 3), (130, 3, 140, 2)])
+@pytest.mark.parametrize("shape", [(96, 4, 80, 3), (130, 3, 140, 2), (300, 4, 270, 3), (17, 2, 9, 2)])
 def test_adjoint_parity(rot, oracle_mod, precision, symmetric, shape):
     m, d, mp, n = shape
-    case = workloads.dense_case(m, d, mp, n, cfg=600 + m, dtype="f32" if precision == "fp32" else "f64",
+    case = workloads.dense_case(m, d, mp, n, cfg=600 + m, dtype="f64" if precision == "fp64" else "f32",
                                 symmetric=symmetric)
     G = np.random.default_rng(7).standard_normal((n, mp, mp))
-    if precision == "fp32":
+    if precision != "fp64":
         G = G.astype(np.float32).astype(np.float64)
-    dt = torch.float32 if precision == "fp32" else torch.float64
+    dt = torch.float64 if precision == "fp64" else torch.float32
     U, O, Gd = to_dev(case.U, dt), to_dev(case.O, dt), to_dev(G, dt)
     dO, dU = rot.rotate_backward(U, O, d, Gd, precision, symmetric_O=symmetric)
     torch.cuda.synchronize()
@@ -269,16 +269,55 @@ def test_adjoint_parity(rot, oracle_mod, precision, symmetric, shape):
     assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= tol
 
 
-def test_adjoint_broadcast_gradient(rot, oracle_mod):
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_adjoint_broadcast_gradient(rot, oracle_mod, precision, symmetric):
     m, d, mp, n = 64, 4, 70, 4
-    case = workloads.dense_case(m, d, mp, n, cfg=650, symmetric=True)
+    case = workloads.dense_case(m, d, mp, n, cfg=650, symmetric=symmetric)
     G = np.random.default_rng(8).standard_normal((mp, mp)).astype(np.float32).astype(np.float64)
     U, O, Gd = to_dev(case.U, torch.float32), to_dev(case.O, torch.float32), to_dev(G, torch.float32)
-    dO, dU = rot.rotate_backward(U, O, d, Gd, "fp32", symmetric_O=True)
+    dO, dU = rot.rotate_backward(U, O, d, Gd, precision, symmetric_O=symmetric)
     torch.cuda.synchronize()
     rdO, rdU = oracle_mod.adjoint(case.U, case.O, G, d)
     assert rel_fro(dO.double().cpu().numpy(), rdO).max() <= TOL32
     assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= TOL32
+
+
+@pytest.mark.parametrize("chunk", [None, 4, 1])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_adjoint_split_bf16_chunks(rot, oracle_mod, chunk, symmetric):
+    """Split-BF16 adjoint of 11 operators with the whole batch in one chunk
+    (the dU sum cut into parts), chunks of 4 and chunks of 1 (dU accumulated
+    over chunks): every layout matches the oracle, repeated calls give
+    identical bits, and a workspace of NaN patterns changes nothing."""
+    m, d, mp, n = 96, 4, 80, 11
+    case = workloads.dense_case(m, d, mp, n, cfg=661, symmetric=symmetric)
+    G = np.random.default_rng(10).standard_normal((n, mp, mp)).astype(np.float32).astype(np.float64)
+    U, O, Gd = to_dev(case.U, torch.float32), to_dev(case.O, torch.float32), to_dev(G, torch.float32)
+    p = rot._problem(U, O, torch.empty((1, mp, mp), device=U.device), d)
+    need = rot.rot_workspace_size([p], rot.ROT_SPLIT_BF16, ops_per_chunk=chunk or 0, for_backward=True)
+    ws = torch.full((need,), 0xFF, dtype=torch.uint8, device=U.device)
+    dO, dU = rot.rotate_backward(U, O, d, Gd, "split_bf16", symmetric_O=symmetric, workspace=ws)
+    dO2, dU2 = rot.rotate_backward(U, O, d, Gd, "split_bf16", symmetric_O=symmetric, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(dU, dU2) and torch.equal(dO, dO2)
+    rdO, rdU = oracle_mod.adjoint(case.U, case.O, G, d)
+    assert rel_fro(dO.double().cpu().numpy(), rdO).max() <= TOL32
+    assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= TOL32
+
+
+def test_adjoint_split_bf16_only_one_output(rot, oracle_mod):
+    """dO alone and dU alone equal the corresponding outputs of the full call."""
+    m, d, mp, n = 70, 4, 66, 3
+    case = workloads.dense_case(m, d, mp, n, cfg=662, symmetric=False)
+    G = np.random.default_rng(11).standard_normal((n, mp, mp)).astype(np.float32)
+    U, O, Gd = to_dev(case.U, torch.float32), to_dev(case.O, torch.float32), to_dev(G, torch.float32)
+    dO, dU = rot.rotate_backward(U, O, d, Gd, "split_bf16")
+    dO1, none1 = rot.rotate_backward(U, O, d, Gd, "split_bf16", need_dU=False)
+    none2, dU1 = rot.rotate_backward(U, O, d, Gd, "split_bf16", need_dO=False)
+    torch.cuda.synchronize()
+    assert none1 is None and none2 is None
+    assert torch.equal(dO, dO1) and torch.equal(dU, dU1)
 
 
 @pytest.mark.parametrize("slots", [None, 13, 3, 1])

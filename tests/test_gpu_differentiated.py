@@ -1,8 +1,8 @@
 """Differentiated rotation at full size: m = m' = 1024, d = 4, 64 symmetric
 operators, loss L = sum_ij <psi|O'_i O'_j|psi> reduced in FP64 (Eq. (11)).
 
-The FP32 forward and adjoint run through torch.autograd (RotateFn,
-PairLossFn); gradients are checked
+The forward and adjoint run through torch.autograd (RotateFn, PairLossFn),
+both in FP32 or both in split-BF16; gradients are checked
   * against central finite differences (h = 1e-6) evaluated with the FP64 GPU
     forward and FP64 reduction, along seeded unit directions: 8 for U and one
     per operator O_b (L is quadratic in each O_b, so the central difference
@@ -37,12 +37,14 @@ def loss64(rot, U64, O64, psi):
     return L.item()
 
 
-@pytest.fixture(scope="module")
-def grads(rot, problem):
+@pytest.fixture(scope="module", params=["fp32", "split_bf16"])
+def grads(rot, problem, request):
+    """Forward and adjoint in one arithmetic (FP32, or split-BF16 for both),
+    the loss reduced in FP64."""
     case, U, O, psi = problem
     Ur = U.clone().requires_grad_(True)
     Or = O.clone().requires_grad_(True)
-    X = rot.RotateFn.apply(Ur, Or, 4, "fp32", True)
+    X = rot.RotateFn.apply(Ur, Or, 4, request.param, True)
     L = rot.PairLossFn.apply(X, psi)
     L.backward()
     torch.cuda.synchronize()

@@ -90,25 +90,37 @@ def test_m512_n200_full_frobenius(rot, m512, precision):
     assert err.max() <= TOL32, err
 
 
-@pytest.mark.timeout(300)
-@pytest.mark.parametrize("symmetric", [True, False])
-def test_adjoint_m1024_subset_vs_oracle(rot, oracle_mod, symmetric):
-    """dO_b and dU of the FP32 adjoint for 4 operators of the headline batch
-    (the oracle's adjoint costs about 110 GFLOP per operator at this size),
-    upstream gradient a seeded Gaussian per operator."""
+@pytest.fixture(scope="module")
+def adjoint_ref(oracle_mod):
+    """The oracle's adjoint for 4 operators of the headline size, symmetric
+    (the headline's own operators) and general, seeded upstream gradients."""
     case = workloads.named_dense("dense_m1024_n64")
     n = 4
-    O = case.O[:n] if symmetric else workloads.dense_case(1024, 4, 1024, n, cfg=905, symmetric=False).O
     G = workloads.rng(905, 4).standard_normal((n, case.mp, case.mp)).astype(np.float32).astype(np.float64)
+    refs = {}
+    for symmetric in (True, False):
+        O = case.O[:n] if symmetric else workloads.dense_case(1024, 4, 1024, n, cfg=905, symmetric=False).O
+        refs[symmetric] = (O, oracle_mod.adjoint(case.U, O, G, 4, nthreads=min(n, oracle_threads())))
+    return case, G, refs
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_adjoint_m1024_subset_vs_oracle(rot, adjoint_ref, precision, symmetric):
+    """dO_b and dU of the adjoint for 4 operators of the headline batch
+    (the oracle's adjoint costs about 110 GFLOP per operator at this size),
+    upstream gradient a seeded Gaussian per operator."""
+    case, G, refs = adjoint_ref
+    O, (rdO, rdU) = refs[symmetric]
     U = torch.from_numpy(case.U).float().cuda()
     dO, dU = rot.rotate_backward(U, torch.from_numpy(O).float().cuda(), 4, torch.from_numpy(G).float().cuda(),
-                                 "fp32", symmetric_O=symmetric)
+                                 precision, symmetric_O=symmetric)
     torch.cuda.synchronize()
-    rdO, rdU = oracle_mod.adjoint(case.U, O, G, 4, nthreads=min(n, oracle_threads()))
     e_o = rel_fro(dO.double().cpu().numpy(), rdO)
     e_u = rel_fro(dU.double().cpu().numpy()[None], rdU[None])
-    report(f"adjoint m1024 dO symmetric={symmetric}", e_o)
-    report(f"adjoint m1024 dU symmetric={symmetric}", e_u)
+    report(f"adjoint m1024 {precision} dO symmetric={symmetric}", e_o)
+    report(f"adjoint m1024 {precision} dU symmetric={symmetric}", e_u)
     assert e_o.max() <= TOL32 and e_u.max() <= TOL32
 
 

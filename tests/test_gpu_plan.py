@@ -80,3 +80,67 @@ def test_plan_small_workspace_many_chunks(rot):
         assert ((g[2] - r).norm() / r.norm()).item() <= 1e-6
     big.close()
     small.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_plan_rebind_new_buffers(rot, graph):
+    """A plan rebound to new U, O and out tensors of the same shapes rotates
+    the new data (graph replay or direct launches, no re-capture); the old
+    outputs are left alone; rebinding back restores the first binding;
+    mismatched shapes are refused."""
+    sizes = [128, 200, 96]
+    ga = make_groups(sizes, cfg=84, ops=3, mp_of=lambda m: m - 3, symmetric=False)
+    gb = make_groups(sizes, cfg=85, ops=3, mp_of=lambda m: m - 3, symmetric=False)
+    eager_a = [rot.rotate(U, O, d, "fp32") for U, O, _, d in ga]
+    eager_b = [rot.rotate(U, O, d, "fp32") for U, O, _, d in gb]
+    plan = rot.Plan(ga, graph=graph)
+    plan.execute()
+    torch.cuda.synchronize()
+    for (_, _, out, _), e in zip(ga, eager_a):
+        assert torch.equal(out, e)
+    plan.rebind(gb)
+    for _ in range(2):
+        for _, _, out, _ in gb:
+            out.fill_(float("nan"))
+        plan.execute()
+        torch.cuda.synchronize()
+        for (_, _, out, _), e in zip(gb, eager_b):
+            assert torch.equal(out, e)
+    for (_, _, out, _), e in zip(ga, eager_a):
+        assert torch.equal(out, e)  # first outputs untouched
+    for _, _, out, _ in ga:
+        out.fill_(float("nan"))
+    plan.rebind(ga)
+    plan.execute()
+    torch.cuda.synchronize()
+    for (_, _, out, _), e in zip(ga, eager_a):
+        assert torch.equal(out, e)
+    bad = make_groups([128, 200, 97], cfg=86, ops=3, mp_of=lambda m: m - 3, symmetric=False)
+    with pytest.raises(rot.RotError):
+        plan.rebind(bad)
+    with pytest.raises(rot.RotError):
+        plan.rebind(ga[:2])
+    plan.close()
+
+
+def test_plan_rebind_is_stream_ordered(rot):
+    """Executions enqueued before a rebind use the old buffers, those after it
+    the new ones, all on one stream without synchronising in between."""
+    ga = make_groups([256, 128], cfg=87, ops=4)
+    gb = make_groups([256, 128], cfg=88, ops=4)
+    eager_a = [rot.rotate(U, O, d, "fp32") for U, O, _, d in ga]
+    eager_b = [rot.rotate(U, O, d, "fp32") for U, O, _, d in gb]
+    plan = rot.Plan(ga, graph=True)
+    torch.cuda.synchronize()
+    for g in ga + gb:
+        g[2].fill_(float("nan"))
+    plan.execute()
+    plan.rebind(gb)
+    plan.execute()
+    plan.rebind(ga)
+    torch.cuda.synchronize()
+    for (_, _, out, _), e in zip(ga, eager_a):
+        assert torch.equal(out, e)
+    for (_, _, out, _), e in zip(gb, eager_b):
+        assert torch.equal(out, e)
+    plan.close()
