@@ -64,6 +64,7 @@ __device__ inline int xcd_linear_id() {
 }
 
 constexpr int kSlabK = 16;  // k per slab
+constexpr int kDefaultOrder = 0;  // tile order of gemm_bf16x3_kernel (see launch_tile)
 
 inline __host__ __device__ int64_t n_slabs(int64_t K) { return (K + kSlabK - 1) / kSlabK; }
 
@@ -216,7 +217,7 @@ __device__ inline void store_tile(const Bf16Desc& g, const f32x16 (&acc)[BI][BJ]
 // second register set while slab t is multiplied.
 template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T, bool D4>
 __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc g, int tiles_m, int tiles_n,
-                                                                         int n_fastest) {
+                                                                         int order) {
     constexpr int NW = WGM * WGN;
     constexpr int T = 32 * WGM * BI;
     static_assert(32 * WGN * BJ == T, "square tile");
@@ -240,14 +241,29 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc
         while ((j + 1) * (j + 2) / 2 <= r) j++;
         m0 = (r - j * (j + 1) / 2) * T;
         n0 = j * T;
+    } else if (order > 0) {
+        // grouped order: the columns of every batch element side by side
+        // (column = bidx * tiles_n + n tile); workgroups sweep them in groups
+        // of `order` M tiles, M tiles fastest, so a run of consecutive
+        // workgroups (which run together on one XCD) shares `order` A panels
+        // and about run/order B panels
+        const int cols = tiles_n * (int)(gridDim.x / (tiles_m * tiles_n));
+        const int per_group = order * cols;
+        const int grp = lin / per_group, first = grp * order;
+        const int gsize = min(tiles_m - first, order);
+        const int r = lin % per_group;
+        m0 = (first + r % gsize) * T;
+        const int col = r / gsize;
+        bidx = col / tiles_n;
+        n0 = (col % tiles_n) * T;
     } else {
         const int per_batch = tiles_m * tiles_n;
         bidx = lin / per_batch;
         const int rr = lin % per_batch;
         // neighbouring workgroups share the B panel (M tiles fastest) or the
-        // A panel (N tiles fastest)
-        m0 = (n_fastest ? rr / tiles_n : rr % tiles_m) * T;
-        n0 = (n_fastest ? rr % tiles_n : rr / tiles_m) * T;
+        // A panel (N tiles fastest, order < 0)
+        m0 = (order < 0 ? rr / tiles_n : rr % tiles_m) * T;
+        n0 = (order < 0 ? rr % tiles_n : rr / tiles_m) * T;
     }
 
     const int tid = threadIdx.x;
@@ -495,8 +511,11 @@ hipError_t launch_tile(const Bf16Desc& g, hipStream_t s) {
     if (g.upper && (EPI_T || g.M != g.N)) return hipErrorInvalidValue;
     const int64_t tiles = (g.upper ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn) * g.batch;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    const char* order = getenv("ROT_BF16_ORDER");
-    const int nf = order ? (order[0] == 'n') : 0;
+    // tile order (measurement knob ROT_BF16_ORDER: "n" N tiles fastest, "m"
+    // M tiles fastest per batch element, an integer G > 0 groups of G M tiles)
+    const char* env = getenv("ROT_BF16_ORDER");
+    int nf = kDefaultOrder;
+    if (env) nf = env[0] == 'n' ? -1 : env[0] == 'm' ? 0 : std::max(0, atoi(env));
     // with d = 4 the row extent d*mp is a multiple of 4, so every group of
     // four rows is complete and the vector store path covers all of them
     if (EPI_T && g.d == 4)

@@ -41,6 +41,7 @@ rot_status fail(rot_status s, const char* fmt, ...) {
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
     g_last_error = buf;
+    log_msg(1, "%s: %s", rot_status_string(s), buf);
     return s;
 }
 
@@ -297,6 +298,7 @@ hipError_t gemm_split_k(rot_precision prec, const GemmDesc& g, void* scratch, hi
 
 rot_status set_error(rot_status s, const char* msg) {
     g_last_error = msg;
+    log_msg(1, "%s: %s", rot_status_string(s), msg);
     return s;
 }
 
@@ -397,6 +399,7 @@ rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision 
 
 rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precision prec, uint32_t flags,
                         void* workspace, size_t workspace_bytes, void* stream) {
+    rot::TraceRange trace_("rot_batch_ex");
     if (n_groups < 0 || (n_groups > 0 && !groups))
         return fail(ROT_ERR_INVALID_ARG, "groups is null or n_groups negative");
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
@@ -516,6 +519,7 @@ size_t rot_site_workspace_size(const rot_site_problem* groups, int32_t n_groups,
 
 rot_status rot_batch_site(const rot_site_problem* groups, int32_t n_groups, rot_precision prec, void* workspace,
                           size_t workspace_bytes, void* stream) {
+    rot::TraceRange trace_("rot_batch_site");
     if (n_groups < 0 || (n_groups > 0 && !groups))
         return fail(ROT_ERR_INVALID_ARG, "null groups or negative n_groups");
     if (prec != ROT_FP32 && prec != ROT_FP64)
@@ -593,6 +597,7 @@ size_t rot_expect_block_workspace_size(int32_t m, int32_t d, int64_t ncols, int3
 rot_status rot_expect_block(const double* psi, int32_t m, int32_t d, int64_t ncols, const void* Z, int32_t n_ops,
                             int64_t stride_z, rot_precision prec, double* e, void* workspace, size_t workspace_bytes,
                             void* stream) {
+    rot::TraceRange trace_("rot_expect_block");
     if (m <= 0 || d <= 0 || ncols <= 0 || n_ops < 0)
         return fail(ROT_ERR_INVALID_ARG, "m, d, ncols must be positive and n_ops >= 0");
     if (prec != ROT_FP64 && prec != ROT_FP32) return fail(ROT_ERR_INVALID_ARG, "Z must be FP64 or FP32");
@@ -637,6 +642,7 @@ size_t rot_expect_cross_workspace_size(int32_t m, int32_t d, int32_t mR, int32_t
 rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR, int32_t dR, const double* Z,
                             int32_t n_left, int64_t stride_z, const double* W, int32_t n_right, int64_t stride_w,
                             double* c, void* workspace, size_t workspace_bytes, void* stream) {
+    rot::TraceRange trace_("rot_expect_cross");
     if (m <= 0 || d <= 0 || mR <= 0 || dR <= 0 || n_left < 0 || n_right < 0)
         return fail(ROT_ERR_INVALID_ARG, "m, d, mR, dR must be positive, operator counts >= 0");
     const int64_t md = (int64_t)m * d, mp = (int64_t)dR * mR;
@@ -702,6 +708,7 @@ rot_status rot_expect_cross(const double* psi, int32_t m, int32_t d, int32_t mR,
 rot_status rot_backward(const rot_problem* groups, int32_t n_groups, const void* const* dOut,
                         const int64_t* stride_dout, void* const* dO, void* const* dU, uint32_t flags,
                         rot_precision prec, void* workspace0, size_t workspace_bytes0, void* stream) {
+    rot::TraceRange trace_("rot_backward");
     if (n_groups < 0 || (n_groups > 0 && (!groups || !dOut || !stride_dout)))
         return fail(ROT_ERR_INVALID_ARG, "null groups/dOut/stride_dout or negative n_groups");
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
@@ -865,6 +872,7 @@ size_t rot_pair_loss_workspace_size(int32_t mp, int32_t n_ops) {
 rot_status rot_pair_loss(const void* X, int32_t mp, int32_t n_ops, int64_t stride_x, rot_precision prec,
                          const double* psi, double* loss, double* pairs, void* grad, void* workspace,
                          size_t workspace_bytes, void* stream) {
+    rot::TraceRange trace_("rot_pair_loss");
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
     if (mp <= 0 || n_ops <= 0 || n_ops > 65535)
         return fail(ROT_ERR_INVALID_ARG, "need mp > 0 and 0 < n_ops <= 65535");
@@ -886,6 +894,7 @@ size_t rot_isometry_workspace_size(int32_t rows, int32_t cols, rot_precision pre
 rot_status rot_check_isometry(const void* U, int32_t rows, int32_t cols, int64_t ldu, rot_precision prec,
                               double tol, double* max_dev_host, void* workspace, size_t workspace_bytes,
                               void* stream) {
+    rot::TraceRange trace_("rot_check_isometry");
     if (!valid_precision(prec)) return fail(ROT_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
     if (!U || !max_dev_host || rows <= 0 || cols <= 0 || cols > rows)
         return fail(ROT_ERR_INVALID_ARG, "need U, max_dev_host and 0 < cols <= rows");
@@ -932,6 +941,7 @@ size_t rot_density_workspace_size(const rot_dm_sector* sectors, int32_t n_sector
 
 rot_status rot_density_basis(const rot_dm_sector* sectors, int32_t n_sectors, int64_t m_keep, int32_t* kept,
                              double* eps, void* workspace, size_t workspace_bytes, void* stream) {
+    rot::TraceRange trace_("rot_density_basis");
     const rot_status v = validate_dm(sectors, n_sectors);
     if (v != ROT_OK) return v;
     if (m_keep < 0) return fail(ROT_ERR_INVALID_ARG, "m_keep must be >= 0");
@@ -950,6 +960,7 @@ rot_status rot_density_basis(const rot_dm_sector* sectors, int32_t n_sectors, in
 }
 
 rot_status rot_split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, void* stream) {
+    rot::TraceRange trace_("rot_split_bf16");
     if (n < 0 || (n > 0 && (!x || !hi || !lo))) return fail(ROT_ERR_INVALID_ARG, "null buffer or n < 0");
     if (n == 0) return ROT_OK;
     hipError_t e = split_bf16(x, n, hi, lo, static_cast<hipStream_t>(stream));
@@ -964,6 +975,7 @@ size_t rot_blocked_workspace_size(const rot_blocked_problem* p) {
 
 rot_status rot_batch_blocked(const rot_blocked_problem* p, rot_precision prec, void* workspace,
                              size_t workspace_bytes, void* stream) {
+    rot::TraceRange trace_("rot_batch_blocked");
     if (!p) return fail(ROT_ERR_INVALID_ARG, "null problem");
     if (prec != ROT_FP32) return fail(ROT_ERR_UNSUPPORTED, "rot_batch_blocked supports ROT_FP32 only");
     std::string why;

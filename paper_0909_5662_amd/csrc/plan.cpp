@@ -309,6 +309,7 @@ extern "C" {
 
 rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_precision prec, void* workspace,
                            size_t workspace_bytes, uint32_t flags, void* stream, rot_plan* out) {
+    rot::TraceRange trace_("rot_plan_create");
     if (!out) return perr(ROT_ERR_INVALID_ARG, "null plan output");
     *out = nullptr;
     if (n_groups < 0 || (n_groups > 0 && !groups)) return perr(ROT_ERR_INVALID_ARG, "null groups or n_groups < 0");
@@ -340,7 +341,7 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
         return perr(ROT_ERR_WORKSPACE, "workspace %zu bytes < one operator's intermediate (%zu)", workspace_bytes, min_ws);
 
     rot_plan_s* P = new rot_plan_s();
-    P->use_graph = !(flags & ROT_PLAN_NO_GRAPH);
+    P->use_graph = !(flags & ROT_PLAN_NO_GRAPH) && !graphs_disabled();
     P->groups = rg;
     // the caller's pending work on its buffers finishes before tuning writes
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
@@ -473,6 +474,15 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
         }
         if (dirty) tune_store_locked();
     }
+    const int sched = forced_schedule();
+    for (auto& c : P->classes) {
+        if (sched >= 0) {
+            c.dynamic = sched == 1;
+            if (c.dynamic && c.grid <= 0) c.grid = 2 * n_cu;  // the queue needs persistent workgroups
+        }
+        log_msg(2, "plan class %s: %d operators, tile %s, %s schedule, grid %d%s", c.key.c_str(), c.n_ops,
+                shape_name(c.shape), c.dynamic ? "dynamic" : "static", c.grid, c.tuned ? " (tuned now)" : "");
+    }
     for (size_t li = 0; li < P->launches.size() && e == hipSuccess; li++)
         e = upload_tiles(P->launches[li], P->host_probs[li], P->classes[P->launches[li].cls].shape);
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
@@ -505,6 +515,7 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
 }
 
 rot_status rot_plan_rebind(rot_plan plan, const rot_problem* groups, int32_t n_groups, void* stream) {
+    rot::TraceRange trace_("rot_plan_rebind");
     if (!plan) return perr(ROT_ERR_INVALID_ARG, "null plan");
     if (n_groups != (int32_t)plan->groups.size() || (n_groups > 0 && !groups))
         return perr(ROT_ERR_INVALID_ARG, "rebind needs the plan's %zu groups", plan->groups.size());
@@ -552,6 +563,7 @@ rot_status rot_plan_rebind(rot_plan plan, const rot_problem* groups, int32_t n_g
 }
 
 rot_status rot_plan_execute(rot_plan plan, void* stream) {
+    rot::TraceRange trace_("rot_plan_execute");
     if (!plan) return perr(ROT_ERR_INVALID_ARG, "null plan");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = plan->use_graph ? prof_timed("plan_graph_fp32", s, [&] { return hipGraphLaunch(plan->exec, s); })

@@ -66,6 +66,24 @@ hipError_t grouped_gemm_f32(const GroupedLaunch& L, hipStream_t stream);
 // returns `s`.
 rot_status set_error(rot_status s, const char* msg);
 
+// Environment switches (env.cpp): ROT_LOG_LEVEL, ROT_TRACE, ROT_DISABLE_GRAPH,
+// ROT_SCHEDULE.
+int log_level();
+void log_msg(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+bool graphs_disabled();
+int forced_schedule();  // -1 none, 0 static, 1 dynamic
+// roctx range around an entry point while ROT_TRACE is set
+class TraceRange {
+   public:
+    explicit TraceRange(const char* name);
+    ~TraceRange();
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+
+   private:
+    bool active_ = false;
+};
+
 // Runs `launch` (which enqueues kernels on `stream`); when per-kernel timing
 // is enabled (rot_profile_enable) it is bracketed by HIP events recorded on
 // `stream` and filed under `name`.

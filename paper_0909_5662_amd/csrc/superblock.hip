@@ -488,6 +488,7 @@ rot_status rot_sb_layout(const rot_sb_problem* p, int32_t capacity, int32_t* n_b
 }
 
 rot_status rot_sb_plan_create(const rot_sb_problem* p, rot_sb_plan* plan) {
+    rot::TraceRange trace_("rot_sb_plan_create");
     if (!plan) return sberr(ROT_ERR_INVALID_ARG, "null plan output");
     *plan = nullptr;
     const rot_status v = validate_sb(p);
@@ -530,6 +531,7 @@ rot_status rot_sb_plan_create(const rot_sb_problem* p, rot_sb_plan* plan) {
 }
 
 rot_status rot_sb_apply(rot_sb_plan plan, const double* psi, double* out, void* stream) {
+    rot::TraceRange trace_("rot_sb_apply");
     if (!plan) return sberr(ROT_ERR_INVALID_ARG, "null plan");
     if (plan->total == 0) return ROT_OK;
     if (!psi || !out) return sberr(ROT_ERR_INVALID_ARG, "null psi or out");

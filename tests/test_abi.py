@@ -403,3 +403,36 @@ def test_plan_rebind_argument_errors(rotlib):
     L = rotlib.lib()
     arr = (rotlib.RotProblem * 1)(prob(rotlib))
     assert L.rot_plan_rebind(None, arr, 1, None) == -1
+
+
+def _run_child(code, **env):
+    import subprocess
+    import sys
+    e = dict(os.environ)
+    e.update(env)
+    return subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=e, cwd=ROOT, timeout=120)
+
+
+CHILD = """
+import ctypes, paper_0909_5662_amd as rot
+L = rot.lib()
+arr = (rot.RotProblem * 1)(rot.problem(0, 4, 8, 2, 1 << 20, 2 << 20, 3 << 20))
+print(L.rot_batch(arr, 1, rot.ROT_FP32, 4 << 20, 1 << 30, None))
+"""
+
+
+def test_log_level_writes_failures_to_stderr():
+    """ROT_LOG_LEVEL=1 writes each failure (status and detail) to stderr; the
+    default is silent.  The failing call is argument validation: no device."""
+    quiet = _run_child(CHILD)
+    assert quiet.returncode == 0 and quiet.stdout.strip() == "-1" and "[librot]" not in quiet.stderr
+    loud = _run_child(CHILD, ROT_LOG_LEVEL="1")
+    assert loud.returncode == 0 and loud.stdout.strip() == "-1"
+    assert "[librot] ROT_ERR_INVALID_ARG" in loud.stderr and "m, d, mp must be positive" in loud.stderr
+
+
+def test_trace_switch_is_harmless_without_a_profiler():
+    """ROT_TRACE=1 loads roctx and brackets the entry point with a range; with
+    no profiler attached the call behaves exactly as without it."""
+    res = _run_child(CHILD, ROT_TRACE="1", ROT_LOG_LEVEL="1")
+    assert res.returncode == 0 and res.stdout.strip() == "-1", res.stderr

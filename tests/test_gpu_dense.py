@@ -264,7 +264,7 @@ def test_adjoint_parity(rot, oracle_mod, precision, symmetric, shape):
     dO, dU = rot.rotate_backward(U, O, d, Gd, precision, symmetric_O=symmetric)
     torch.cuda.synchronize()
     rdO, rdU = oracle_mod.adjoint(case.U, case.O, G, d)
-    tol = TOL32 if precision == "fp32" else TOL64
+    tol = TOL64 if precision == "fp64" else TOL32
     assert rel_fro(dO.double().cpu().numpy(), rdO).max() <= tol
     assert rel_fro(dU.double().cpu().numpy()[None], rdU[None]).max() <= tol
 
