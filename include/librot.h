@@ -122,6 +122,24 @@ ROT_API rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * rot_batch_ex without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a fixed device array
+ * of rot_noalloc_scratch_bytes() bytes (128 MiB) inside the library: each GPU
+ * the library runs on holds its own copy until the process ends.  The call
+ * allocates nothing (its first call on a device looks the array's address
+ * up once).  Groups whose single-operator workspace (rot_workspace_size with
+ * ops_per_chunk = 1) exceeds the array return ROT_ERR_WORKSPACE; smaller ones
+ * run in operator chunks that fit it.  Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be serialised by the caller; calls on one stream
+ * are ordered and safe.  Results equal rot_batch_ex's for the same chunking.
+ */
+ROT_API rot_status rot_batch_noalloc(const rot_problem* groups, int32_t n_groups, rot_precision prec, uint32_t flags,
+                                     void* stream);
+ROT_API size_t rot_noalloc_scratch_bytes(void);
+
+/*
  * Workspace bytes needed by rot_batch / rot_backward for these groups when
  * up to `ops_per_chunk` operators are processed at once (<= 0: all
  * operators of the largest group).  `for_backward` != 0 sizes it for

@@ -26,7 +26,7 @@ import torch
 __all__ = [
     "ROT_FP64", "ROT_FP32", "ROT_SPLIT_BF16", "ROT_ASSUME_SYMMETRIC_O", "RotError",
     "RotProblem", "problem", "RotSector", "RotBlockedProblem", "lib", "library_path",
-    "rot_batch", "rot_backward", "rot_batch_blocked", "rot_pair_loss", "rot_check_isometry",
+    "rot_batch", "rot_batch_noalloc", "rot_backward", "rot_batch_blocked", "rot_pair_loss", "rot_check_isometry",
     "rot_split_bf16", "rot_workspace_size", "rot_blocked_workspace_size",
     "rotate", "rotate_backward", "pair_loss", "check_isometry", "split_bf16",
     "RotateFn", "PairLossFn", "precision_code", "profile_enable", "profile_read",
@@ -128,6 +128,10 @@ def lib() -> ctypes.CDLL:
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.rot_batch.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, vp, sz, vp]
         L.rot_batch_ex.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, ctypes.c_uint32, vp, sz, vp]
+        L.rot_batch_noalloc.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, ctypes.c_uint32, vp]
+        L.rot_batch_noalloc.restype = ctypes.c_int
+        L.rot_noalloc_scratch_bytes.argtypes = []
+        L.rot_noalloc_scratch_bytes.restype = sz
         L.rot_workspace_size.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.c_int, i32, i32]
         L.rot_workspace_size.restype = sz
         L.rot_backward.argtypes = [ctypes.POINTER(RotProblem), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
@@ -249,6 +253,12 @@ def rot_batch(groups, prec: int, workspace: int, workspace_bytes: int, stream: i
         _check(lib().rot_batch_ex(arr, len(groups), prec, flags, workspace, workspace_bytes, stream))
     else:
         _check(lib().rot_batch(arr, len(groups), prec, workspace, workspace_bytes, stream))
+
+
+def rot_batch_noalloc(groups, prec: int, stream: int, flags: int = 0) -> None:
+    """rot_batch_ex on the library's fixed device scratch (no allocation)."""
+    arr = (RotProblem * len(groups))(*groups)
+    _check(lib().rot_batch_noalloc(arr, len(groups), prec, flags, stream))
 
 
 def rot_backward(groups, dOut, stride_dout, dO, dU, flags: int, prec: int, workspace: int,

@@ -398,11 +398,21 @@ def test_split_bf16_backward_workspace(rotlib):
     assert extra == -(-96 * 4 * 80 * 4 // 256) * 256  # U packed first
 
 
-def test_plan_rebind_argument_errors(rotlib):
-    """rot_plan_rebind refuses a null plan on the host."""
+def test_plan_rebind_and_noalloc_argument_errors(rotlib):
+    """rot_plan_rebind refuses a null plan; rot_batch_noalloc validates like
+    rot_batch and refuses groups whose one-operator workspace exceeds its
+    fixed scratch, all on the host."""
     L = rotlib.lib()
     arr = (rotlib.RotProblem * 1)(prob(rotlib))
     assert L.rot_plan_rebind(None, arr, 1, None) == -1
+    assert L.rot_noalloc_scratch_bytes() == 128 << 20
+    bad = (rotlib.RotProblem * 1)(prob(rotlib, m=0))
+    assert L.rot_batch_noalloc(bad, 1, rotlib.ROT_FP32, 0, None) == -1
+    huge = (rotlib.RotProblem * 1)(prob(rotlib, m=4096, mp=4096, n=1, U=FAKE, O=FAKE << 12, out=FAKE << 13))
+    assert L.rot_batch_noalloc(huge, 1, rotlib.ROT_FP32, 0, None) == -3
+    empty = (rotlib.RotProblem * 1)(prob(rotlib, n=0, U=0, O=0, out=0))
+    assert L.rot_batch_noalloc(empty, 1, rotlib.ROT_FP32, 0, None) == 0
+    assert L.rot_batch_noalloc(arr, 1, rotlib.ROT_FP32, 4, None) == -1  # unknown flag
 
 
 def _run_child(code, **env):
