@@ -240,10 +240,22 @@ def bench_uneven(args, rot, torch, workloads):
     data = workloads.uneven_case_gpu(sizes, d=4, ops_per_rot=8, cfg=4)
     groups = [(U, O, torch.empty((8, U.shape[1], U.shape[1]), device=U.device), 4) for U, O in data]
     torch.cuda.synchronize()
+    # plan creation with an empty tuning cache (times the candidates per size
+    # class and writes ROT_TUNE_CACHE), then again with the cache warm
+    cache = os.environ.get("ROT_TUNE_CACHE")
+    cache_entries = None
     c0 = time.perf_counter()
     plan = rot.Plan(groups, workspace_bytes=32 << 30)  # size classes, tuning, graph capture
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - c0
+    tuned_now = sum(1 for c in plan.describe()["classes"] if c["tuned_now"])
+    plan.close()
+    c0 = time.perf_counter()
+    plan = rot.Plan(groups, workspace_bytes=32 << 30)
+    torch.cuda.synchronize()
+    plan_warm_s = time.perf_counter() - c0
+    if cache and os.path.exists(cache):
+        cache_entries = sum(1 for line in open(cache) if line.strip() and not line.startswith("#"))
     flops = sum(8 * flops_per_op(m, 4, m) for m in sizes)
     c0 = time.perf_counter()
     plan.execute()
@@ -265,6 +277,8 @@ def bench_uneven(args, rot, torch, workloads):
                       {"workload": "uneven_1000", "rotations": 1000, "ops_per_rotation": 8, "d": 4,
                        "m_classes": [128, 256, 512, 1024, 2048], "precision": "fp32"})
     rec.update({"timing": "hipGraph replays of the plan", "plan_create_s": round(plan_s, 2),
+                "plan_create_warm_cache_s": round(plan_warm_s, 2), "classes_tuned_on_first_create": tuned_now,
+                "tune_cache_file": cache, "tune_cache_entries": cache_entries,
                 "cold_first_execute_ms": round(cold_ms, 1),
                 "tflop_per_step": round(flops / 1e12, 2), "tflops": round(tflops, 2),
                 "pct_fp32_mfma_peak": round(100 * tflops / 157.3, 2), "plan": plan.describe(),
@@ -773,6 +787,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the rotation shards by "
               "operators across GPUs but no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "uneven_1000" and not os.environ.get("ROT_TUNE_CACHE"):
+        # a fresh tuning cache file for this run (written by the first plan, read by the second)
+        import tempfile
+        os.environ["ROT_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="rot_tune_"), "tune_cache.txt")
     import torch
 
     import paper_0909_5662_amd as rot

@@ -505,17 +505,12 @@ hipError_t zero_last_slab(uint16_t* a, uint16_t* l, int64_t rows, int64_t K, int
 }
 
 template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T>
-hipError_t launch_tile(const Bf16Desc& g, hipStream_t s) {
+hipError_t launch_tile(const Bf16Desc& g, int nf, hipStream_t s) {
     constexpr int T = 32 * WGM * BI;
     const int tm = (g.M + T - 1) / T, tn = (g.N + T - 1) / T;
     if (g.upper && (EPI_T || g.M != g.N)) return hipErrorInvalidValue;
     const int64_t tiles = (g.upper ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn) * g.batch;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    // tile order (measurement knob ROT_BF16_ORDER: "n" N tiles fastest, "m"
-    // M tiles fastest per batch element, an integer G > 0 groups of G M tiles)
-    const char* env = getenv("ROT_BF16_ORDER");
-    int nf = kDefaultOrder;
-    if (env) nf = env[0] == 'n' ? -1 : env[0] == 'm' ? 0 : std::max(0, atoi(env));
     // with d = 4 the row extent d*mp is a multiple of 4, so every group of
     // four rows is complete and the vector store path covers all of them
     if (EPI_T && g.d == 4)
@@ -527,19 +522,39 @@ hipError_t launch_tile(const Bf16Desc& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-// 256 x 256 tiles (eight waves of 128 x 64, two per SIMD; a ring of 4 stages
-// of 32 KB) when both output extents reach 256, else 128 x 128 (four waves
-// of 64 x 64; 4 stages of 16 KB).  Environment ROT_BF16_CFG=128 forces the
-// small tile and ROT_BF16_CFG=ring5 a ring of 5 stages (measurement knobs).
+// A launch configuration: tile edge (256: eight waves of 128 x 64, two per
+// SIMD, ring stages of 32 KB; 128: four waves of 64 x 64, stages of 16 KB),
+// ring depth (4 or 5 stages) and tile order (0: M tiles fastest per batch
+// element; -1: N tiles fastest; G > 0: groups of G M tiles across all
+// columns).  256 applies only when both output extents reach 256.
+struct Bf16Cfg {
+    int tile = 256, ring = 4, order = kDefaultOrder;
+};
+
+// The environment's measurement knobs override a configuration:
+// ROT_BF16_CFG=128 | ring5, ROT_BF16_ORDER=m | n | G.
+Bf16Cfg with_env(Bf16Cfg c) {
+    const char* env = getenv("ROT_BF16_CFG");
+    if (env && !strcmp(env, "128")) c.tile = 128;
+    if (env && !strcmp(env, "ring5")) c.ring = 5;
+    const char* ord = getenv("ROT_BF16_ORDER");
+    if (ord) c.order = ord[0] == 'n' ? -1 : ord[0] == 'm' ? 0 : std::max(0, atoi(ord));
+    return c;
+}
+
+template <bool EPI_T>
+hipError_t launch_bf16(const Bf16Desc& g, const Bf16Cfg& cfg0, hipStream_t s) {
+    const Bf16Cfg cfg = with_env(cfg0);
+    if (cfg.tile == 256 && g.M >= 256 && g.N >= 256) {
+        if (cfg.ring == 5) return launch_tile<2, 4, 4, 2, 5, EPI_T>(g, cfg.order, s);
+        return launch_tile<2, 4, 4, 2, 4, EPI_T>(g, cfg.order, s);
+    }
+    return launch_tile<2, 2, 2, 2, 4, EPI_T>(g, cfg.order, s);
+}
+
 template <bool EPI_T>
 hipError_t launch_bf16(const Bf16Desc& g, hipStream_t s) {
-    const char* env = getenv("ROT_BF16_CFG");
-    const bool small = env && !strcmp(env, "128");
-    if (!small && g.M >= 256 && g.N >= 256) {
-        if (env && !strcmp(env, "ring5")) return launch_tile<2, 4, 4, 2, 5, EPI_T>(g, s);
-        return launch_tile<2, 4, 4, 2, 4, EPI_T>(g, s);
-    }
-    return launch_tile<2, 2, 2, 2, 4, EPI_T>(g, s);
+    return launch_bf16<EPI_T>(g, Bf16Cfg{}, s);
 }
 
 struct Bf16Layout {

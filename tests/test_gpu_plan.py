@@ -172,3 +172,56 @@ def test_plan_environment_switches(rot, monkeypatch):
         for (_, _, out, _), e in zip(groups, eager):
             assert close(out, e)
         plan.close()
+
+
+TUNE_CHILD = r"""
+import json, sys, torch
+sys.path.insert(0, {root!r})
+import paper_0909_5662_amd as rot, workloads
+data = workloads.uneven_case_gpu([128, 256, 200], d=4, ops_per_rot=2, cfg=90)
+groups = [(U, O, torch.empty((2, U.shape[1], U.shape[1]), device="cuda"), 4) for U, O in data]
+plan = rot.Plan(groups, tune={tune})
+plan.execute()
+torch.cuda.synchronize()
+err = max(((out - rot.rotate(U, O, d, "fp32")).norm() / rot.rotate(U, O, d, "fp32").norm()).item()
+          for U, O, out, d in groups)
+print(json.dumps({{"classes": plan.describe()["classes"], "err": err}}))
+"""
+
+
+def _plan_child(tmp_path, cache, tune):
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, ROT_TUNE_CACHE=str(cache))
+    env.pop("ROT_SCHEDULE", None)
+    res = subprocess.run([sys.executable, "-c", TUNE_CHILD.format(root=root, tune=tune)], capture_output=True,
+                         text=True, env=env, timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+@pytest.mark.timeout(600)
+def test_tune_cache_file_written_read_and_corrupt(rot, tmp_path):
+    """One process tunes and writes ROT_TUNE_CACHE; a fresh process that may
+    not tune reads the same choices from the file; a corrupt file is ignored
+    line by line and the plan falls back to the defaults (128 x 128 tiles, static
+    schedule, one workgroup per tile).  Every plan's result is right."""
+    cache = tmp_path / "tune_cache.txt"
+    first = _plan_child(tmp_path, cache, True)
+    assert first["err"] <= 1e-6 and all(c["tuned_now"] for c in first["classes"])
+    text = cache.read_text()
+    assert all(c["key"] in text for c in first["classes"])
+    second = _plan_child(tmp_path, cache, False)
+    assert second["err"] <= 1e-6
+    for a, b in zip(first["classes"], second["classes"]):
+        assert not b["tuned_now"] and (a["tile"], a["schedule"], a["grid"]) == (b["tile"], b["schedule"], b["grid"])
+    bad = tmp_path / "corrupt.txt"
+    keys = [c["key"] for c in first["classes"]]
+    bad.write_text("garbage without fields\n\x00\x01\x02 nonsense 12 x\n" + keys[0] + " 17\n" + keys[-1] + "\n")
+    third = _plan_child(tmp_path, bad, False)
+    assert third["err"] <= 1e-6
+    for c in third["classes"]:
+        assert not c["tuned_now"] and (c["tile"], c["schedule"], c["grid"]) == (128, "static", 0)
