@@ -101,8 +101,19 @@ typedef struct {
  * Z_i Z_j of a step share R).
  * workspace: device memory of at least rot_workspace_size(..., 1) bytes,
  * 256-byte aligned; operators are processed in chunks that fit it (larger
- * workspaces give larger, faster chunks).  Groups may have different m, d,
- * mp.  Returns ROT_OK, ROT_ERR_INVALID_ARG, ROT_ERR_WORKSPACE, ROT_ERR_HIP.
+ * workspaces give larger, faster chunks).  When a group's stage-2 output has
+ * few tiles (fewer than 256 of 128 x 128) and the workspace holds the whole
+ * group with rot_workspace_size(..., 0)'s room for partial sums, FP32 and
+ * FP64 stage 2 is split over K into parts added in a fixed order: results
+ * are deterministic for a given workspace size but may differ in the last
+ * bits from a call whose workspace is too small to split.  Groups may have
+ * different m, d, mp.  ROT_SPLIT_BF16 picks each stage's tile configuration per shape (m, d,
+ * mp, chunk): from the tuning cache (in memory, and in the file named by
+ * ROT_TUNE_CACHE), else on the shape's first call by timing the candidates
+ * on the first chunk, which synchronises `stream` once (not under stream
+ * capture, nor with ROT_AUTOTUNE=0: the defaults are used then); every
+ * configuration gives the same bits.  Returns ROT_OK, ROT_ERR_INVALID_ARG,
+ * ROT_ERR_WORKSPACE, ROT_ERR_HIP.
  */
 ROT_API rot_status rot_batch(const rot_problem* groups, int32_t n_groups, rot_precision prec,
                      void* workspace, size_t workspace_bytes, void* stream);
@@ -341,11 +352,12 @@ ROT_API rot_status rot_plan_destroy(rot_plan plan);
  * independent (one workspace must not serve two calls in flight).  The first
  * call for a block structure (sector tables, offsets and buffer alignment)
  * builds its work-lists in library-owned device memory, times the available
- * execution paths (one fused kernel in two register layouts, or two grouped
- * launches) and keeps the fastest for later calls with the same structure;
- * every call's result comes from the kept path, so repeated calls agree bit
- * for bit.  ROT_BLOCKED_PATH=fused|fused_wide|grouped in the environment
- * forces one.  Work-lists are cached for the 8 most recently used structures;
+ * execution paths (one fused kernel in two register layouts, its variant
+ * that loads whole row blocks of operator rows, or two grouped launches) and
+ * keeps the fastest for later calls with the same structure; every call's
+ * result comes from the kept path, so repeated calls agree bit for bit.
+ * ROT_BLOCKED_PATH=fused|fused_wide|rowblock|rowblock_wide|grouped in the
+ * environment forces one.  Work-lists are cached for the 8 most recently used structures;
  * a structure used while `stream` is being captured into a graph is kept for
  * the life of the process (the graph refers to its work-lists), and its
  * first call must happen outside capture (ROT_ERR_UNSUPPORTED otherwise).

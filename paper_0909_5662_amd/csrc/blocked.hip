@@ -291,6 +291,124 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
     }
 }
 
+// Variant of blocked_fused_kernel that loads the operator rows of a whole
+// (term, row block) pair at once, before the pair's first U^T_Q values: the
+// operator block comes from HBM, and with every k step's rows requested
+// together the pair waits for one HBM round trip instead of one per 16-wide
+// k step.  U^T_Q values (L2-resident) are still fetched one k step ahead.
+// Needs every term's stage-1 K <= 16 * KS.
+template <int MAXA, int CG, int KS>
+__global__ __launch_bounds__(256) void blocked_rowblock_kernel(const BlkTask* __restrict__ tasks, int n_tasks,
+                                                               const BlkTerm* __restrict__ terms,
+                                                               const float* __restrict__ Ut,
+                                                               const float* __restrict__ O, float* __restrict__ out,
+                                                               int* __restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lh = lane >> 4;
+    int t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    while (t < n_tasks) {
+        const BlkTask T = tasks[t];
+        const float* uT = Ut + T.uT_off;
+        const float* uQ = Ut + T.uQ_off;
+        const int nbc = (T.mQ + 15) >> 4, nba = (T.mT + 15) >> 4;
+        for (int cg0 = 0; cg0 < nbc; cg0 += CG) {
+            f32x4 acc[CG][MAXA];
+#pragma unroll
+            for (int c = 0; c < CG; c++)
+#pragma unroll
+                for (int ca = 0; ca < MAXA; ca++) acc[c][ca] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int e = 0; e < T.n_terms; e++) {
+                const BlkTerm tm = terms[T.term0 + e];
+                const int nks = (tm.k + 15) >> 4;
+                for (int rb = 0; rb * 16 < tm.a; rb++) {
+                    f32x4 ut[MAXA];
+#pragma unroll
+                    for (int ca = 0; ca < MAXA; ca++)
+                        if (ca < nba)
+                            ut[ca] = *reinterpret_cast<const f32x4*>(uT + (int64_t)(ca * 16 + li) * T.ldT + tm.rt +
+                                                                     rb * 16 + 4 * lh);
+                    // the row block's operator rows, every k step
+                    const int row = rb * 16 + li;
+                    const bool rok = row < tm.a;
+                    const float* orow = O + tm.o_off + (int64_t)row * tm.k;
+                    f32x4 a[KS];
+#pragma unroll
+                    for (int ks = 0; ks < KS; ks++) {
+                        const int kk = ks * 16 + 4 * lh;
+                        if (ks < nks) {
+                            if (rok && kk + 4 <= tm.k) {
+                                a[ks] = *reinterpret_cast<const f32x4u*>(orow + kk);
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < 4; j++) a[ks][j] = (rok && kk + j < tm.k) ? orow[kk + j] : 0.f;
+                            }
+                        }
+                    }
+                    f32x4 x[CG], bv[CG];
+#pragma unroll
+                    for (int c = 0; c < CG; c++) x[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    if (nks > 0) {
+#pragma unroll
+                        for (int c = 0; c < CG; c++)
+                            bv[c] = *reinterpret_cast<const f32x4*>(uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ +
+                                                                    tm.rq + 4 * lh);
+                    }
+#pragma unroll
+                    for (int ks = 0; ks < KS; ks++) {
+                        if (ks < nks) {
+                            f32x4 bv_n[CG];
+                            if (ks + 1 < nks) {
+#pragma unroll
+                                for (int c = 0; c < CG; c++)
+                                    bv_n[c] = *reinterpret_cast<const f32x4*>(
+                                        uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ + tm.rq + (ks + 1) * 16 + 4 * lh);
+                            }
+#pragma unroll
+                            for (int j = 0; j < 4; j++)
+#pragma unroll
+                                for (int c = 0; c < CG; c++)
+                                    x[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][j], bv[c][j], x[c], 0, 0, 0);
+                            if (ks + 1 < nks) {
+#pragma unroll
+                                for (int c = 0; c < CG; c++) bv[c] = bv_n[c];
+                            }
+                        }
+                    }
+                    // stage 2 (as in blocked_fused_kernel)
+#pragma unroll
+                    for (int ca = 0; ca < MAXA; ca++) {
+                        if (ca < nba) {
+#pragma unroll
+                            for (int j = 0; j < 4; j++)
+#pragma unroll
+                                for (int c = 0; c < CG; c++)
+                                    acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], ut[ca][j], acc[c][ca], 0,
+                                                                                       0, 0);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CG; c++)
+#pragma unroll
+                for (int ca = 0; ca < MAXA; ca++) {
+                    const int alpha = ca * 16 + li;
+                    if (ca < nba && alpha < T.mT) {
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const int b = (cg0 + c) * 16 + 4 * lh + v;
+                            if (b < T.mQ) out[T.out_off + (int64_t)alpha * T.mQ + b] = acc[c][ca][v];
+                        }
+                    }
+                }
+        }
+        if (lane == 0) t = atomicAdd(counter, 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+    }
+}
+
 __global__ void reset_fused_counter(int* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
@@ -364,6 +482,7 @@ struct FusedLists {
     std::vector<BlkTask> tasks;
     std::vector<BlkTerm> terms;
     int max_mT = 0;
+    int max_k = 0;  // widest stage-1 K (old sector) of any term
 };
 
 void build_fused(const rot_blocked_problem* p, const Structure& st, const UtLayout& ut, FusedLists* F) {
@@ -403,6 +522,7 @@ void build_fused(const rot_blocked_problem* p, const Structure& st, const UtLayo
                 tm.rq = ut.pstart[k][s];
                 tm.o_off = oo;
                 terms.push_back(tm);
+                F->max_k = std::max(F->max_k, tm.k);
                 cost += (double)tm.a * tm.k * Q.dim + (double)Tsec.dim * tm.a * Q.dim;
             }
             task.n_terms = (int)terms.size() - task.term0;
@@ -508,9 +628,10 @@ struct Plan {
     int f_n_tasks = 0;
     int f_n_segs = 0;
     int f_max_mT = 0;
+    int f_max_k = 0;
     int64_t ut_base = 0;   // transposed U area in the workspace (elements)
     int64_t ut_elems = 0;  // its size, slack included
-    int path = -1;  // 0 grouped two-stage, 1 fused, 2 fused wide; -1 not chosen yet
+    int path = -1;  // 0 grouped two-stage, 1 fused, 2 fused wide, 3/4 row-block operands (narrow/wide); -1 not chosen yet
     ~Plan() {
         (void)hipFree(s1.probs);
         (void)hipFree(s1.tiles);
@@ -640,7 +761,21 @@ void launch_fused(Plan* plan, const float* ut, const rot_blocked_problem* p, int
                        plan->f_n_tasks, plan->f_terms, ut, p->O_blk, p->out_blk, counter);
 }
 
-hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, void* ws, hipStream_t stream) {
+template <int MAXA, int CG>
+void launch_rowblock(Plan* plan, const float* ut, const rot_blocked_problem* p, int* counter, hipStream_t stream) {
+    const int grid = 256 * 4;
+    hipLaunchKernelGGL((blocked_rowblock_kernel<MAXA, CG, MAXA>), dim3(grid), dim3(256), 0, stream, plan->f_tasks,
+                       plan->f_n_tasks, plan->f_terms, ut, p->O_blk, p->out_blk, counter);
+}
+
+// The row-block variant holds up to 16 * MAXA stage-1 K values per lane
+// (MAXA = 4 or 5: output and stage-1 extents up to 64 or 80).
+bool rowblock_ok(const Plan* plan) {
+    return plan->f_max_mT <= 80 && plan->f_max_k <= (plan->f_max_mT <= 64 ? 64 : 80);
+}
+
+hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, bool rowblock, void* ws,
+                     hipStream_t stream) {
     if (plan->f_n_tasks == 0) return hipSuccess;
     float* ut = static_cast<float*>(ws) + plan->ut_base;
     hipError_t e = prof_timed("blocked_transpose_u", stream, [&] {
@@ -654,7 +789,13 @@ hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, void* 
     int* counter = reinterpret_cast<int*>(static_cast<char*>(ws) + plan->counter_off);
     return prof_timed("blocked_fused_fp32", stream, [&] {
         hipLaunchKernelGGL(reset_fused_counter, dim3(1), dim3(64), 0, stream, counter);
-        if (plan->f_max_mT <= 64) {
+        if (rowblock) {
+            if (plan->f_max_mT <= 64) {
+                if (wide) launch_rowblock<4, 4>(plan, ut, p, counter, stream); else launch_rowblock<4, 2>(plan, ut, p, counter, stream);
+            } else {
+                if (wide) launch_rowblock<5, 3>(plan, ut, p, counter, stream); else launch_rowblock<5, 2>(plan, ut, p, counter, stream);
+            }
+        } else if (plan->f_max_mT <= 64) {
             if (wide) launch_fused<4, 4>(plan, ut, p, counter, stream); else launch_fused<4, 2>(plan, ut, p, counter, stream);
         } else if (plan->f_max_mT <= 80) {
             if (wide) launch_fused<5, 3>(plan, ut, p, counter, stream); else launch_fused<5, 2>(plan, ut, p, counter, stream);
@@ -665,22 +806,26 @@ hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, void* 
     });
 }
 
-// Paths: 0 two grouped launches, 1 fused (narrow passes), 2 fused (wide).
-// ROT_BLOCKED_PATH = grouped | fused | fused_wide forces one; otherwise all
-// are timed once per block structure and the fastest is kept.
+// Paths: 0 two grouped launches, 1 fused (narrow passes), 2 fused (wide),
+// 3 / 4 the fused kernel with whole row blocks of operator rows (narrow /
+// wide).  ROT_BLOCKED_PATH = grouped | fused | fused_wide | rowblock |
+// rowblock_wide forces one; otherwise every applicable path is timed once
+// per block structure and the fastest is kept.
 int forced_path() {
     const char* e = getenv("ROT_BLOCKED_PATH");
     if (!e) return -1;
     if (!strcmp(e, "grouped")) return 0;
     if (!strcmp(e, "fused")) return 1;
     if (!strcmp(e, "fused_wide")) return 2;
+    if (!strcmp(e, "rowblock")) return 3;
+    if (!strcmp(e, "rowblock_wide")) return 4;
     return -1;
 }
 
 hipError_t run_path(const rot_blocked_problem* p, Plan* plan, void* ws, GroupedShape shape, int path,
                     hipStream_t stream) {
     if (path == 0) return run_grouped(p, plan, ws, shape, stream);
-    return run_fused(p, plan, path == 2, ws, stream);
+    return run_fused(p, plan, path == 2 || path == 4, path >= 3, ws, stream);
 }
 
 }  // namespace
@@ -720,6 +865,7 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         if (e == hipSuccess) e = upload(L.p2, make_tiles(L.p2, edge), &np->s2);
         np->f_n_tasks = (int)F.tasks.size();
         np->f_max_mT = F.max_mT;
+        np->f_max_k = F.max_k;
         np->f_n_segs = (int)ut.segs.size();
         np->ut_base = (L.x_elems + 63) / 64 * 64;
         np->ut_elems = ut.elems;
@@ -743,13 +889,14 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         if (plan->path < 0 && forced < 0) plan->path = plan->f_max_mT > 128 ? 0 : 1;
     }
     int path = forced >= 0 ? forced : plan->path;
+    if (path >= 3 && !rowblock_ok(plan)) path = path - 2;
     if (path >= 1 && plan->f_max_mT > 128) path = 0;
     if (path < 0) {
-        // time each path (second run, after a warm-up run)
-        const int n_paths = plan->f_max_mT > 128 ? 1 : 3;
-        hipEvent_t ev[4];
+        // time each applicable path (second run, after a warm-up run)
+        const int n_paths = plan->f_max_mT > 128 ? 1 : rowblock_ok(plan) ? 5 : 3;
+        hipEvent_t ev[6];
         hipError_t e = hipSuccess;
-        for (int i = 0; i < 4 && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
+        for (int i = 0; i < 6 && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
         for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
             for (int q = 0; q < n_paths && e == hipSuccess; q++) {
                 e = hipEventRecord(ev[q], stream);
@@ -768,7 +915,7 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
                 best_q = q;
             }
         }
-        for (int i = 0; i < 4; i++) (void)hipEventDestroy(ev[i]);
+        for (int i = 0; i < 6; i++) (void)hipEventDestroy(ev[i]);
         if (e != hipSuccess) return e;
         plan->path = best_q;
         log_msg(2, "blocked structure of %d operators: execution path %d (%.3f ms when timed)", p->n_ops, best_q,

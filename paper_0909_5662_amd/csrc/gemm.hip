@@ -159,7 +159,13 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
     __shared__ __attribute__((aligned(16))) float As[2][SA::ELEMS];
     __shared__ __attribute__((aligned(16))) float Bs[2][SB::ELEMS];
 
-    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, g.upper);
+    int lin = xcd_linear_id(), part = 0;
+    if (g.parts > 1) {
+        const int per = gridDim.x / g.parts;
+        part = lin / per;
+        lin -= part * per;
+    }
+    const TileCoord tc = tile_coord(lin, tiles_m, tiles_n, g.upper);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -167,7 +173,15 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 
     const float* Ab = static_cast<const float*>(g.A) + (int64_t)tc.g * g.a_bs;
     const float* Bb = static_cast<const float*>(g.B) + (int64_t)tc.g * g.b_bs;
-    const int nk = (g.K + kSlice - 1) / kSlice;
+    int K = g.K;
+    if (g.parts > 1) {
+        // this part's K range
+        const int k0 = part * g.kp;
+        K = min(g.kp, g.K - k0);
+        Ab += g.a_kcontig ? (int64_t)k0 : (int64_t)k0 * g.lda;
+        Bb += g.b_kcontig ? (int64_t)k0 : (int64_t)k0 * g.ldb;
+    }
+    const int nk = (K + kSlice - 1) / kSlice;
     const int total = nk * g.kbatch;
 
     SA la;
@@ -182,8 +196,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 
     auto fetch = [&](int t) {
         const int kb = t / nk, k0 = (t % nk) * kSlice;
-        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, g.K, tid);
-        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, g.K, tid);
+        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, K, tid);
+        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, K, tid);
     };
 
     fetch(0);
@@ -238,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
         __syncthreads();
     }
 
-    float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs;
+    float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs + (int64_t)part * g.c_ps;
     // symmetric output: a diagonal tile keeps row <= col and mirrors it, so
     // the result is exactly symmetric.  Accumulating: the previous values of
     // each group of four rows are loaded before the group's stores
@@ -308,7 +322,13 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
     __shared__ __attribute__((aligned(16))) double As[2][SA::ELEMS];
     __shared__ __attribute__((aligned(16))) double Bs[2][SB::ELEMS];
 
-    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, g.upper);
+    int lin = xcd_linear_id(), part = 0;
+    if (g.parts > 1) {
+        const int per = gridDim.x / g.parts;
+        part = lin / per;
+        lin -= part * per;
+    }
+    const TileCoord tc = tile_coord(lin, tiles_m, tiles_n, g.upper);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -316,7 +336,15 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
 
     const double* Ab = static_cast<const double*>(g.A) + (int64_t)tc.g * g.a_bs;
     const double* Bb = static_cast<const double*>(g.B) + (int64_t)tc.g * g.b_bs;
-    const int nk = (g.K + kSlice - 1) / kSlice;
+    int K = g.K;
+    if (g.parts > 1) {
+        // this part's K range
+        const int k0 = part * g.kp;
+        K = min(g.kp, g.K - k0);
+        Ab += g.a_kcontig ? (int64_t)k0 : (int64_t)k0 * g.lda;
+        Bb += g.b_kcontig ? (int64_t)k0 : (int64_t)k0 * g.ldb;
+    }
+    const int nk = (K + kSlice - 1) / kSlice;
     const int total = nk * g.kbatch;
 
     SA la;
@@ -331,8 +359,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
 
     auto fetch = [&](int t) {
         const int kb = t / nk, k0 = (t % nk) * kSlice;
-        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, g.K, tid);
-        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, g.K, tid);
+        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, K, tid);
+        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, K, tid);
     };
 
     fetch(0);
@@ -385,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
         __syncthreads();
     }
 
-    double* Cb = static_cast<double*>(g.C) + (int64_t)tc.g * g.c_bs;
+    double* Cb = static_cast<double*>(g.C) + (int64_t)tc.g * g.c_bs + (int64_t)part * g.c_ps;
     // symmetric output: off-diagonal tiles are also stored transposed; a
     // diagonal tile keeps row <= col and mirrors it (exactly symmetric)
     const bool mirror = !ACC && g.upper && tc.m0 != tc.n0;
@@ -413,7 +441,7 @@ bool vector_ok(const GemmDesc& g) {
     const int64_t vw = 16 / sizeof(T);
     auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     return al(g.A) && al(g.B) && g.lda % vw == 0 && g.ldb % vw == 0 && g.a_bs % vw == 0 &&
-           g.b_bs % vw == 0 && g.a_ks % vw == 0 && g.b_ks % vw == 0;
+           g.b_bs % vw == 0 && g.a_ks % vw == 0 && g.b_ks % vw == 0 && (g.parts <= 1 || g.kp % vw == 0);
 }
 
 #define ROT_DISPATCH(KERNEL)                                                                       \
@@ -448,7 +476,10 @@ hipError_t gemm_any(const GemmDesc& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
     const int tm = (g.M + kTile - 1) / kTile, tn = (g.N + kTile - 1) / kTile;
     if (g.upper && (g.M != g.N || g.accumulate)) return hipErrorInvalidValue;
-    const int64_t tiles = (g.upper ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn) * g.batch;
+    const int parts = g.parts > 1 ? g.parts : 1;
+    if (parts > 1 && (g.upper || g.accumulate || g.kbatch != 1 || g.kp <= 0 || (int64_t)g.kp * (parts - 1) >= g.K))
+        return hipErrorInvalidValue;
+    const int64_t tiles = (g.upper ? (int64_t)tm * (tm + 1) / 2 : (int64_t)tm * tn) * g.batch * parts;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles);
     const bool vec = vector_ok<T>(g);

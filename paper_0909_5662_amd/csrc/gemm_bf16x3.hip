@@ -30,6 +30,9 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
 
 #include "rot_internal.h"
 
@@ -527,9 +530,7 @@ hipError_t launch_tile(const Bf16Desc& g, int nf, hipStream_t s) {
 // ring depth (4 or 5 stages) and tile order (0: M tiles fastest per batch
 // element; -1: N tiles fastest; G > 0: groups of G M tiles across all
 // columns).  256 applies only when both output extents reach 256.
-struct Bf16Cfg {
-    int tile = 256, ring = 4, order = kDefaultOrder;
-};
+// (Bf16Cfg and Bf16Choice are declared in rot_internal.h.)
 
 // The environment's measurement knobs override a configuration:
 // ROT_BF16_CFG=128 | ring5, ROT_BF16_ORDER=m | n | G.
@@ -676,79 +677,204 @@ size_t bf16_group_workspace(int m, int d, int mp, int ops) {
     return L.shared + (size_t)ops * 2 * (L.t_op + L.o_op);
 }
 
-// p has its leading dimensions resolved.
-hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, hipStream_t stream) {
-    const Bf16Layout L = layout(p.m, p.d, p.mp);
+namespace {
+
+// Pointers into the split-BF16 workspace for a chunk of nb operators.
+struct Bf16Ws {
+    uint16_t *u1h, *u1l, *u2h, *u2l, *th, *tl, *oh, *ol;
+};
+
+Bf16Ws carve(const Bf16Layout& L, void* ws, int nb) {
     char* base = static_cast<char*>(ws);
-    uint16_t* u1h = reinterpret_cast<uint16_t*>(base);
-    uint16_t* u1l = reinterpret_cast<uint16_t*>(base + L.u1);
-    uint16_t* u2h = reinterpret_cast<uint16_t*>(base + 2 * L.u1);
-    uint16_t* u2l = reinterpret_cast<uint16_t*>(base + 2 * L.u1 + L.u2);
-    uint16_t* th = reinterpret_cast<uint16_t*>(base + L.shared);
-    uint16_t* tl = reinterpret_cast<uint16_t*>(base + L.shared + (size_t)nb * L.t_op);
-    uint16_t* oh = reinterpret_cast<uint16_t*>(base + L.shared + 2 * (size_t)nb * L.t_op);
-    uint16_t* ol = reinterpret_cast<uint16_t*>(base + L.shared + 2 * (size_t)nb * L.t_op + (size_t)nb * L.o_op);
+    Bf16Ws w;
+    w.u1h = reinterpret_cast<uint16_t*>(base);
+    w.u1l = reinterpret_cast<uint16_t*>(base + L.u1);
+    w.u2h = reinterpret_cast<uint16_t*>(base + 2 * L.u1);
+    w.u2l = reinterpret_cast<uint16_t*>(base + 2 * L.u1 + L.u2);
+    w.th = reinterpret_cast<uint16_t*>(base + L.shared);
+    w.tl = reinterpret_cast<uint16_t*>(base + L.shared + (size_t)nb * L.t_op);
+    w.oh = reinterpret_cast<uint16_t*>(base + L.shared + 2 * (size_t)nb * L.t_op);
+    w.ol = reinterpret_cast<uint16_t*>(base + L.shared + 2 * (size_t)nb * L.t_op + (size_t)nb * L.o_op);
+    return w;
+}
+
+// U split once per call (b0 == 0), then the chunk's O split and the K
+// padding of its Tt.
+hipError_t split_inputs(const rot_problem& p, const Bf16Layout& L, const Bf16Ws& w, int b0, int nb,
+                        hipStream_t stream) {
     const int rows = p.m * p.d;
     if (b0 == 0) {
         const dim3 grid((p.mp + 63) / 64, (rows + 63) / 64);
         hipError_t e = prof_timed("split_u_bf16x3", stream, [&] {
-            hipError_t err = zero_last_slab(u1h, u1l, L.u1_rows, p.m, 0, 1, stream);
-            if (err == hipSuccess) err = zero_last_slab(u2h, u2l, L.u2_rows, rows, 0, 1, stream);
+            hipError_t err = zero_last_slab(w.u1h, w.u1l, L.u1_rows, p.m, 0, 1, stream);
+            if (err == hipSuccess) err = zero_last_slab(w.u2h, w.u2l, L.u2_rows, rows, 0, 1, stream);
             if (err != hipSuccess) return err;
             hipLaunchKernelGGL(split_u_kernel, grid, dim3(256), 0, stream, static_cast<const float*>(p.U), rows,
-                               p.mp, p.ldu, p.d, u1h, u1l, u2h, u2l);
+                               p.mp, p.ldu, p.d, w.u1h, w.u1l, w.u2h, w.u2l);
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
     }
-    // stage 1, transposed: C(beta*d+s, i) = sum_j U1(beta*d+s, j) O_b(i, j) = T_b(i, beta*d+s)
+    return prof_timed("split_o_bf16x3", stream, [&] {
+        // Tt's K padding (stage 1 writes only k < m*d); O's is written by the split
+        hipError_t err = zero_last_slab(w.th, w.tl, p.mp, rows, (int64_t)(L.t_op / 2), nb, stream);
+        if (err != hipSuccess) return err;
+        const float* Ob = static_cast<const float*>(p.O) + (int64_t)b0 * p.stride_o;
+        const dim3 grid((p.m + 63) / 64, (p.m + 63) / 64, nb);
+        hipLaunchKernelGGL(split_o_kernel, grid, dim3(256), 0, stream, Ob, p.m, p.ldo, p.stride_o, w.oh, w.ol,
+                           (int64_t)(L.o_op / 2));
+        return hipGetLastError();
+    });
+}
+
+// stage 1, transposed: C(beta*d+s, i) = sum_j U1(beta*d+s, j) O_b(i, j) = T_b(i, beta*d+s)
+Bf16Desc stage1_desc(const rot_problem& p, const Bf16Layout& L, const Bf16Ws& w, int nb) {
     Bf16Desc a{};
     a.M = p.d * p.mp;
     a.N = p.m;
     a.K = p.m;
     a.batch = nb;
-    a.a_hi = u1h;
-    a.a_lo = u1l;
+    a.a_hi = w.u1h;
+    a.a_lo = w.u1l;
     a.a_bs = 0;
-    a.b_hi = oh;
-    a.b_lo = ol;
+    a.b_hi = w.oh;
+    a.b_lo = w.ol;
     a.b_bs = (int64_t)(L.o_op / 2);
-    a.t_hi = th;
-    a.t_lo = tl;
+    a.t_hi = w.th;
+    a.t_lo = w.tl;
     a.d = p.d;
     a.t_rows = p.mp;
     a.t_bs = (int64_t)(L.t_op / 2);
-    hipError_t e = prof_timed("split_o_bf16x3", stream, [&] {
-        // Tt's K padding (stage 1 writes only k < m*d); O's is written by the split
-        hipError_t err = zero_last_slab(th, tl, p.mp, rows, (int64_t)(L.t_op / 2), nb, stream);
-        if (err != hipSuccess) return err;
-        const float* Ob = static_cast<const float*>(p.O) + (int64_t)b0 * p.stride_o;
-        const dim3 grid((p.m + 63) / 64, (p.m + 63) / 64, nb);
-        hipLaunchKernelGGL(split_o_kernel, grid, dim3(256), 0, stream, Ob, p.m, p.ldo, p.stride_o, oh, ol,
-                           (int64_t)(L.o_op / 2));
-        return hipGetLastError();
-    });
-    if (e != hipSuccess) return e;
-    e = prof_timed("stage1_bf16x3", stream, [&] { return launch_bf16<true>(a, stream); });
-    if (e != hipSuccess) return e;
-    // stage 2: out_b(alpha, beta) = sum_r U2(alpha, r) Tt_b(beta, r)
+    return a;
+}
+
+// stage 2: out_b(alpha, beta) = sum_r U2(alpha, r) Tt_b(beta, r)
+Bf16Desc stage2_desc(const rot_problem& p, const Bf16Layout& L, const Bf16Ws& w, int b0, int nb, bool symmetric) {
     Bf16Desc b{};
     b.M = p.mp;
     b.N = p.mp;
     b.K = p.m * p.d;
     b.batch = nb;
-    b.a_hi = u2h;
-    b.a_lo = u2l;
+    b.a_hi = w.u2h;
+    b.a_lo = w.u2l;
     b.a_bs = 0;
-    b.b_hi = th;
-    b.b_lo = tl;
+    b.b_hi = w.th;
+    b.b_lo = w.tl;
     b.b_bs = (int64_t)(L.t_op / 2);
     b.c = static_cast<float*>(p.out) + (int64_t)b0 * p.stride_out;
     b.ldc = p.ldout;
     b.c_bs = p.stride_out;
     b.upper = symmetric ? 1 : 0;
+    return b;
+}
+
+const Bf16Cfg kCandidates[] = {{256, 4, kDefaultOrder}, {256, 5, kDefaultOrder}, {128, 4, kDefaultOrder}};
+
+std::string cfg_token(const Bf16Cfg& c) { return std::to_string(c.tile) + "r" + std::to_string(c.ring); }
+
+bool parse_cfg(const std::string& t, Bf16Cfg* c) {
+    for (const Bf16Cfg& k : kCandidates)
+        if (t == cfg_token(k)) {
+            *c = k;
+            return true;
+        }
+    return false;
+}
+
+// Device name and compute-unit count of the current device, for tuning keys.
+std::string device_tag() {
+    int dev = 0, n_cu = 0;
+    hipDeviceProp_t props;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess ||
+        hipGetDeviceProperties(&props, dev) != hipSuccess)
+        return "unknown";
+    std::string arch = props.gcnArchName;
+    return arch.substr(0, arch.find(':')) + "|cu" + std::to_string(n_cu);
+}
+
+// Milliseconds of `launch` on `stream` (one warm-up run, then the mean of two).
+float time_ms(hipStream_t stream, const std::function<hipError_t()>& launch, hipError_t* err) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(a, stream);
+    for (int r = 0; r < 2 && e == hipSuccess; r++) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 1e30f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    *err = e;
+    return ms / 2;
+}
+
+}  // namespace
+
+// The launch configurations of the two stages for this shape: from the tuning
+// cache, else (when `may_tune` and no measurement knob is set) by timing
+// every candidate on the first chunk of nb operators (its results are
+// overwritten by the call that follows), else the defaults.  Every
+// configuration gives the same bits: each output element sums the same
+// products slab by slab in the same order, whatever the tile.
+hipError_t bf16_choice(const rot_problem& p, int nb, bool symmetric, void* ws, bool may_tune, hipStream_t stream,
+                       Bf16Choice* choice) {
+    *choice = Bf16Choice{};
+    const std::string key = "bf16|" + device_tag() + "|m" + std::to_string(p.m) + "|d" + std::to_string(p.d) +
+                            "|mp" + std::to_string(p.mp) + "|nb" + std::to_string(nb) + (symmetric ? "|sym" : "");
+    std::vector<std::string> t;
+    if (tune_get(key, &t) && t.size() == 2 && parse_cfg(t[0], &choice->s1) && parse_cfg(t[1], &choice->s2))
+        return hipSuccess;
+    const char* off = getenv("ROT_AUTOTUNE");
+    if (!may_tune || (off && !strcmp(off, "0")) || getenv("ROT_BF16_CFG") || getenv("ROT_BF16_ORDER"))
+        return hipSuccess;
+    const Bf16Layout L = layout(p.m, p.d, p.mp);
+    const Bf16Ws w = carve(L, ws, nb);
+    const Bf16Desc a = stage1_desc(p, L, w, nb), b = stage2_desc(p, L, w, 0, nb, symmetric);
+    // below 256 in both extents of both stages only the 128 tile applies
+    if ((a.M < 256 || a.N < 256) && (b.M < 256 || b.N < 256)) return hipSuccess;
+    hipError_t e = split_inputs(p, L, w, 0, nb, stream);
+    if (e != hipSuccess) return e;
+    float best1 = 1e30f, best2 = 1e30f;
+    for (const Bf16Cfg& c : kCandidates) {
+        if (c.tile == 256 && !(a.M >= 256 && a.N >= 256)) continue;
+        const float ms = time_ms(stream, [&] { return launch_bf16<true>(a, c, stream); }, &e);
+        if (e != hipSuccess) return e;
+        if (ms < best1) {
+            best1 = ms;
+            choice->s1 = c;
+        }
+    }
+    for (const Bf16Cfg& c : kCandidates) {
+        if (c.tile == 256 && !(b.M >= 256 && b.N >= 256)) continue;
+        const float ms = time_ms(stream, [&] { return launch_bf16<false>(b, c, stream); }, &e);
+        if (e != hipSuccess) return e;
+        if (ms < best2) {
+            best2 = ms;
+            choice->s2 = c;
+        }
+    }
+    log_msg(2, "%s: stage 1 %s (%.3f ms), stage 2 %s (%.3f ms)", key.c_str(), cfg_token(choice->s1).c_str(), best1,
+            cfg_token(choice->s2).c_str(), best2);
+    tune_put(key, {cfg_token(choice->s1), cfg_token(choice->s2)});
+    return hipSuccess;
+}
+
+// p has its leading dimensions resolved.
+hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, const Bf16Choice& choice,
+                       hipStream_t stream) {
+    const Bf16Layout L = layout(p.m, p.d, p.mp);
+    const Bf16Ws w = carve(L, ws, nb);
+    hipError_t e = split_inputs(p, L, w, b0, nb, stream);
+    if (e != hipSuccess) return e;
+    const Bf16Desc a = stage1_desc(p, L, w, nb);
+    e = prof_timed("stage1_bf16x3", stream, [&] { return launch_bf16<true>(a, choice.s1, stream); });
+    if (e != hipSuccess) return e;
+    const Bf16Desc b = stage2_desc(p, L, w, b0, nb, symmetric);
     return prof_timed(symmetric ? "stage2sym_bf16x3" : "stage2_bf16x3", stream,
-                      [&] { return launch_bf16<false>(b, stream); });
+                      [&] { return launch_bf16<false>(b, choice.s2, stream); });
 }
 
 

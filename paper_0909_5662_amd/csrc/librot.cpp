@@ -18,7 +18,10 @@ namespace rot {
 hipError_t split_bf16(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t stream);
 size_t bf16_group_workspace(int m, int d, int mp, int ops);
 bool bf16_shape_supported(int m, int d, int mp);
-hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, hipStream_t stream);
+hipError_t bf16_choice(const rot_problem& p, int nb, bool symmetric, void* ws, bool may_tune, hipStream_t stream,
+                       Bf16Choice* choice);
+hipError_t rotate_bf16(const rot_problem& p, int b0, int nb, void* ws, bool symmetric, const Bf16Choice& choice,
+                       hipStream_t stream);
 bool bf16_backward_supported(int m, int d, int mp);
 size_t bf16_backward_workspace(int m, int d, int mp, int ops);
 hipError_t backward_bf16(const rot_problem& p, int b0, int nb, const float* dout, int64_t sd, float* dO, float* dU,
@@ -122,6 +125,29 @@ size_t t_bytes(const rot_problem& p, rot_precision prec) {
 // m x d*mp view, which only a packed U provides).
 size_t packed_u_bytes(const rot_problem& p, rot_precision prec) {
     return p.ldu == p.mp ? 0 : align_up((size_t)p.m * p.d * p.mp * elem_size(prec));
+}
+
+// Stage 2 split over K for small outputs: when the chunk's stage-2 output
+// has fewer than 256 tiles of 128 x 128 (too few workgroups to fill the chip)
+// and K = m*d is long, K is cut into parts of kp (a multiple of 16, at least
+// 64) computed by separate workgroups into partial sums that are added in a
+// fixed order.  Returns the number of parts (1: no split) for `ops` operators.
+int stage2_parts(const rot_problem& p, int ops, int* kp) {
+    const int64_t t = (p.mp + kGemmTile - 1) / kGemmTile;
+    const int64_t tiles = t * t * ops;
+    const int64_t K = (int64_t)p.m * p.d;
+    *kp = (int)K;
+    if (tiles >= 256 || K < 128) return 1;
+    int64_t parts = std::min<int64_t>({8, (512 + tiles - 1) / tiles, K / 64});
+    if (parts < 2) return 1;
+    const int64_t k = ((K + parts - 1) / parts + 15) / 16 * 16;
+    *kp = (int)k;
+    return (int)((K + k - 1) / k);
+}
+
+// Bytes of one operator's partial stage-2 sums when split into `parts`.
+size_t stage2_part_bytes(const rot_problem& p, int parts, size_t es) {
+    return parts > 1 ? (size_t)parts * p.mp * p.mp * es : 0;
 }
 
 // The dU reduction of rot_backward is one GEMM with M = m, N = d*mp and a K
@@ -385,7 +411,10 @@ size_t rot_workspace_size(const rot_problem* groups, int32_t n_groups, rot_preci
             packed.ldu = p.mp;  // the adjoint works on U packed to row stride mp
             g = packed_u_bytes(p, tp) + (size_t)(ops + du_split_parts(p, ops)) * t_bytes(packed, tp);
         } else {
-            g = (size_t)ops * t_bytes(p, tp);
+            // with more than one operator per chunk, room for the split stage-2 partial sums
+            int kp = 0;
+            const int parts = ops > 1 || ops_per_chunk <= 0 ? stage2_parts(p, ops, &kp) : 1;
+            g = (size_t)ops * t_bytes(p, tp) + align_up((size_t)ops * stage2_part_bytes(p, parts, elem_size(tp)));
         }
         need = std::max(need, g);
     }
@@ -435,19 +464,48 @@ rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precisi
             int chunk = 1;
             while (chunk < p.n_ops && bf16_group_workspace(p.m, p.d, p.mp, chunk + 1) <= workspace_bytes)
                 chunk++;
+            // tile configuration per stage: cached, or timed on this shape's first
+            // call (never while the stream is being captured)
+            hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+            const bool capturing = hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+            Bf16Choice choice;
+            hipError_t e = bf16_choice(p, chunk, sym, workspace, !capturing, s, &choice);
+            if (e != hipSuccess) return hip_fail(e, "rot_batch split-bf16 tuning");
             for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
                 const int nb = std::min(chunk, p.n_ops - b0);
-                hipError_t e = rotate_bf16(p, b0, nb, workspace, sym, s);
+                e = rotate_bf16(p, b0, nb, workspace, sym, choice, s);
                 if (e != hipSuccess) return hip_fail(e, "rot_batch split-bf16");
             }
             continue;
         }
         const size_t per_op = t_bytes(p, prec);
-        const int chunk = (int)std::min<size_t>((size_t)p.n_ops, workspace_bytes / per_op);
+        // split-K stage 2 (general output only) when the workspace holds the
+        // whole batch with its partial sums
+        int kp = 0;
+        int parts = sym ? 1 : stage2_parts(p, p.n_ops, &kp);
+        const size_t need_split = (size_t)p.n_ops * per_op + align_up((size_t)p.n_ops * stage2_part_bytes(p, parts, es));
+        if (parts > 1 && workspace_bytes < need_split) parts = 1;
+        const int chunk = parts > 1 ? p.n_ops : (int)std::min<size_t>((size_t)p.n_ops, workspace_bytes / per_op);
         for (int b0 = 0; b0 < p.n_ops; b0 += chunk) {
             const int nb = std::min(chunk, p.n_ops - b0);
             hipError_t e = gemm(prec, stage1(p, b0, nb, workspace, es), s, "stage1");
-            if (e == hipSuccess) {
+            if (e == hipSuccess && parts > 1) {
+                // parts x nb packed mp x mp partial products after the intermediates
+                char* partial = static_cast<char*>(workspace) + (size_t)nb * per_op;
+                GemmDesc g2 = stage2(p, b0, nb, workspace, es);
+                g2.C = partial;
+                g2.ldc = p.mp;
+                g2.c_bs = (int64_t)p.mp * p.mp;
+                g2.parts = parts;
+                g2.kp = kp;
+                g2.c_ps = (int64_t)nb * p.mp * p.mp;
+                e = gemm(prec, g2, s, "stage2");
+                if (e == hipSuccess)
+                    e = timed("stage2_sum", s, [&] {
+                        return sum_parts_2d(static_cast<char*>(p.out) + (size_t)b0 * p.stride_out * es, p.ldout,
+                                            p.stride_out, partial, p.mp, p.mp, nb, parts, g2.c_ps, prec == ROT_FP64, s);
+                    });
+            } else if (e == hipSuccess) {
                 GemmDesc g2 = stage2(p, b0, nb, workspace, es);
                 g2.upper = sym;
                 e = gemm(prec, g2, s, sym ? "stage2sym" : "stage2");

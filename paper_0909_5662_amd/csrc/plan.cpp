@@ -88,48 +88,22 @@ int ceil_log2(int64_t x) {
 }
 
 // ---------------------------------------------------------------- tuning --
-struct TuneEntry {
-    GroupedShape shape;
-    bool dynamic;
-    int grid;
-};
-std::mutex g_tune_mu;
-std::map<std::string, TuneEntry> g_tune;
-bool g_tune_loaded = false;
-
 const char* shape_name(GroupedShape s) { return s == GroupedShape::k128 ? "128" : s == GroupedShape::k64 ? "64" : "32"; }
 
-void tune_load_locked() {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char* path = getenv("ROT_TUNE_CACHE");
-    if (!path || !*path) return;
-    std::ifstream f(path);
-    std::string line;
-    while (std::getline(f, line)) {
-        if (line.empty() || line[0] == '#') continue;
-        std::istringstream is(line);
-        std::string key, shape, sched;
-        int grid = 0;
-        if (!(is >> key >> shape >> sched >> grid)) continue;  // corrupt lines are ignored
-        TuneEntry e{shape == "64" ? GroupedShape::k64 : shape == "32" ? GroupedShape::k32 : GroupedShape::k128,
-                    sched == "dynamic", grid};
-        g_tune[key] = e;
-    }
-}
-
-void tune_store_locked() {
-    const char* path = getenv("ROT_TUNE_CACHE");
-    if (!path || !*path) return;
-    std::string tmp = std::string(path) + ".tmp";
-    {
-        std::ofstream f(tmp);
-        f << "# librot tuning cache: key tile-edge schedule persistent-grid\n";
-        for (auto& kv : g_tune)
-            f << kv.first << ' ' << shape_name(kv.second.shape) << ' ' << (kv.second.dynamic ? "dynamic" : "static")
-              << ' ' << kv.second.grid << '\n';
-    }
-    std::rename(tmp.c_str(), path);
+// A plan class's cached choice: tokens "tile-edge schedule persistent-grid";
+// false when absent or not of that form.
+bool cached_choice(const std::string& key, GroupedShape* shape, bool* dynamic, int* grid) {
+    std::vector<std::string> t;
+    if (!tune_get(key, &t) || t.size() != 3) return false;
+    if (t[0] != "128" && t[0] != "64" && t[0] != "32") return false;
+    if (t[1] != "static" && t[1] != "dynamic") return false;
+    char* end = nullptr;
+    const long g = strtol(t[2].c_str(), &end, 10);
+    if (!end || *end || g < 0 || g > (1 << 24)) return false;
+    *shape = t[0] == "64" ? GroupedShape::k64 : t[0] == "32" ? GroupedShape::k32 : GroupedShape::k128;
+    *dynamic = t[1] == "dynamic";
+    *grid = (int)g;
+    return true;
 }
 
 // The grouped-GEMM problem of stage 1 or 2 for operator b of group p (p
@@ -450,29 +424,25 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
 
     // 4. tile shape and schedule per class
     {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        bool dirty = false;
         for (int ci = 0; ci < (int)P->classes.size() && e == hipSuccess; ci++) {
             rot_plan_s::Class& c = P->classes[ci];
-            auto it = g_tune.find(c.key);
-            if (it != g_tune.end() && !(flags & ROT_PLAN_RETUNE)) {
-                c.shape = it->second.shape;
-                c.dynamic = it->second.dynamic;
-                c.grid = it->second.grid;
+            GroupedShape shape;
+            bool dynamic;
+            int grid;
+            if (!(flags & ROT_PLAN_RETUNE) && cached_choice(c.key, &shape, &dynamic, &grid)) {
+                c.shape = shape;
+                c.dynamic = dynamic;
+                c.grid = grid;
             } else if (!(flags & ROT_PLAN_NO_TUNE)) {
                 e = tune_class(P, ci, n_cu);
-                if (e == hipSuccess) {
-                    g_tune[c.key] = TuneEntry{c.shape, c.dynamic, c.grid};
-                    dirty = true;
-                }
+                if (e == hipSuccess)
+                    tune_put(c.key, {shape_name(c.shape), c.dynamic ? "dynamic" : "static", std::to_string(c.grid)});
             } else {
                 c.shape = GroupedShape::k128;  // default: one workgroup per 128 x 128 tile
                 c.dynamic = false;
                 c.grid = 0;
             }
         }
-        if (dirty) tune_store_locked();
     }
     const int sched = forced_schedule();
     for (auto& c : P->classes) {

@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <functional>
+#include <string>
+#include <vector>
 
 #include "librot.h"
 
@@ -30,6 +32,11 @@ struct GemmDesc {
     // symmetric output (M == N, no accumulation): only tiles on or above the
     // diagonal are computed, each off-diagonal one also stored transposed
     bool upper;
+    // split K (parts > 1; kbatch == 1, no upper, no accumulate): part p
+    // multiplies K range [p*kp, min(K, (p+1)*kp)) and writes its product to
+    // C + p*c_ps; the caller adds the parts
+    int parts, kp;
+    int64_t c_ps;
 };
 
 // ---- grouped GEMM over a work-list (grouped.hip) ----
@@ -66,6 +73,11 @@ hipError_t grouped_gemm_f32(const GroupedLaunch& L, hipStream_t stream);
 // returns `s`.
 rot_status set_error(rot_status s, const char* msg);
 
+// Tuning cache (tune_cache.cpp): key -> tokens, in memory and in the file
+// named by ROT_TUNE_CACHE.
+bool tune_get(const std::string& key, std::vector<std::string>* tokens);
+void tune_put(const std::string& key, const std::vector<std::string>& tokens);
+
 // Environment switches (env.cpp): ROT_LOG_LEVEL, ROT_TRACE, ROT_DISABLE_GRAPH,
 // ROT_SCHEDULE.
 int log_level();
@@ -94,6 +106,18 @@ constexpr int kGemmTile = 128;  // output tile edge of gemm_f32 / gemm_f64
 hipError_t gemm_f32(const GemmDesc& g, hipStream_t stream);
 hipError_t gemm_f64(const GemmDesc& g, hipStream_t stream);
 
+// Split-BF16 launch configuration (gemm_bf16x3.hip): tile edge 256 (eight
+// waves of 128 x 64) or 128 (four waves of 64 x 64), LDS ring depth 4 or 5,
+// tile order (0: M tiles fastest per batch element; -1: N tiles fastest;
+// G > 0: groups of G M tiles across all columns); and the choice of the two
+// rotation stages for one shape.
+struct Bf16Cfg {
+    int tile = 256, ring = 4, order = 0;
+};
+struct Bf16Choice {
+    Bf16Cfg s1, s2;
+};
+
 // Zero `bytes` bytes with a fill kernel (safe under stream capture).
 hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream);
 
@@ -114,6 +138,10 @@ struct SiteMatrix {
 // Up = (diag(x) (x) S^T) U for U with m*d rows of mp (x may be null: identity).
 hipError_t site_mix(const void* U, int m, int d, int mp, const SiteMatrix& S, const void* x, void* Up,
                     bool is_double, hipStream_t stream);
+// dst[b] (rows x cols, row stride ld, matrix stride bs; nmat matrices) =
+// sum over p of the packed matrices at src + p*pstride, in ascending p.
+hipError_t sum_parts_2d(void* dst, int64_t ld, int64_t bs, const void* src, int rows, int cols, int nmat, int parts,
+                        int64_t pstride, bool is_double, hipStream_t stream);
 // dst (+)= sum of `parts` arrays of n elements at src + p*stride, summed in
 // ascending p (deterministic).
 hipError_t sum_parts(void* dst, const void* src, int64_t n, int parts, int64_t stride, bool accumulate,

@@ -51,7 +51,36 @@ __global__ void sum_parts_kernel(T* __restrict__ dst, const T* __restrict__ src,
     }
 }
 
+// dst[b][r][c] (row stride ld, matrix stride bs) = sum over p of
+// src[p*pstride + (b*rows + r)*cols + c], in ascending p (deterministic).
+template <typename T>
+__global__ void sum_parts_2d_kernel(T* __restrict__ dst, int64_t ld, int64_t bs, const T* __restrict__ src, int rows,
+                                    int cols, int64_t n, int parts, int64_t pstride) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / ((int64_t)rows * cols);
+        const int64_t rc = i - b * rows * cols;
+        const int64_t r = rc / cols, c = rc - r * cols;
+        T acc = T(0);
+        for (int p = 0; p < parts; p++) acc += src[i + p * pstride];
+        dst[b * bs + r * ld + c] = acc;
+    }
+}
+
 }  // namespace
+
+hipError_t sum_parts_2d(void* dst, int64_t ld, int64_t bs, const void* src, int rows, int cols, int nmat, int parts,
+                        int64_t pstride, bool is_double, hipStream_t stream) {
+    const int64_t n = (int64_t)rows * cols * nmat;
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 8192));
+    if (is_double)
+        hipLaunchKernelGGL(sum_parts_2d_kernel<double>, grid, dim3(256), 0, stream, static_cast<double*>(dst), ld, bs,
+                           static_cast<const double*>(src), rows, cols, n, parts, pstride);
+    else
+        hipLaunchKernelGGL(sum_parts_2d_kernel<float>, grid, dim3(256), 0, stream, static_cast<float*>(dst), ld, bs,
+                           static_cast<const float*>(src), rows, cols, n, parts, pstride);
+    return hipGetLastError();
+}
 
 hipError_t sum_parts(void* dst, const void* src, int64_t n, int parts, int64_t stride, bool accumulate,
                      bool is_double, hipStream_t stream) {

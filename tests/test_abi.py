@@ -82,12 +82,19 @@ def test_rot_batch_workspace_and_precision_errors(rotlib):
 
 
 def test_workspace_size_scales_with_chunk(rotlib):
+    """One stage-1 intermediate per operator of the chunk; a chunk of the
+    whole batch also holds the partial sums of the split stage 2 when its
+    output has few tiles (here 7 tiles, K = 400: 5 parts of 80)."""
     L = rotlib.lib()
     arr = (rotlib.RotProblem * 1)(prob(rotlib, m=100, mp=90, n=7))
     one = L.rot_workspace_size(arr, 1, rotlib.ROT_FP32, 1, 0)
     allops = L.rot_workspace_size(arr, 1, rotlib.ROT_FP32, 0, 0)
-    assert one >= 100 * 4 * 90 * 4 and allops == 7 * one
+    assert one == -(-100 * 4 * 90 * 4 // 256) * 256
+    assert allops == 7 * one + -(-7 * 5 * 90 * 90 * 4 // 256) * 256
     assert L.rot_workspace_size(arr, 1, rotlib.ROT_FP64, 1, 0) >= 2 * 100 * 4 * 90 * 4 - 256
+    # many output tiles: no split, the chunk is only intermediates
+    big = (rotlib.RotProblem * 1)(prob(rotlib, m=1024, mp=1024, n=64))
+    assert L.rot_workspace_size(big, 1, rotlib.ROT_FP32, 0, 0) == 64 * L.rot_workspace_size(big, 1, rotlib.ROT_FP32, 1, 0)
 
 
 def test_backward_workspace_reserves_dU_parts(rotlib):

@@ -123,7 +123,7 @@ def test_blocked_repeat_uses_cached_plan_and_is_deterministic(rot):
     np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped"])
+@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped", "rowblock", "rowblock_wide"])
 def test_blocked_each_path_vs_oracle(rot, oracle_mod, monkeypatch, path):
     """Both execution paths (one fused wave per output block; two grouped
     launches through an intermediate) against the oracle, on sectors up to
@@ -138,7 +138,7 @@ def test_blocked_each_path_vs_oracle(rot, oracle_mod, monkeypatch, path):
     check(case, pk, flat, ref, range(len(case.shifts)))
 
 
-@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped"])
+@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped", "rowblock", "rowblock_wide"])
 def test_blocked_1024_each_path_sampled(rot, oracle_mod, monkeypatch, path):
     monkeypatch.setenv("ROT_BLOCKED_PATH", path)
     case = workloads.blocked_case()
@@ -269,3 +269,21 @@ def test_blocked_two_streams_own_workspaces(rot):
         torch.cuda.synchronize()
         assert torch.equal(out_a[written], eager[written])
         assert torch.equal(out_b[written], eager[written])
+
+
+@pytest.mark.parametrize("path", ["rowblock", "rowblock_wide"])
+@pytest.mark.parametrize("max_dim", [40, 64, 80])
+def test_blocked_rowblock_paths_vs_oracle(rot, oracle_mod, monkeypatch, path, max_dim):
+    """The row-block variants (whole row blocks of operator rows per
+    load) against the oracle on sectors up to 40, 64 (four 16-wide k steps
+    and output row blocks) and 80 states (five), with ragged sizes."""
+    monkeypatch.setenv("ROT_BLOCKED_PATH", path)
+    total, sigma = (420, 1.3) if max_dim == 40 else (800, 1.2)  # largest sectors reach max_dim
+    sizes = workloads.gaussian_sector_sizes(total, sigma=sigma, min_dim=3, max_dim=max_dim)
+    assert max(s for _, s in sizes) == max_dim
+    kept = [(qn, max(1, s - 2)) for qn, s in sizes]
+    case = workloads.blocked_case(sizes=sizes, kept_sizes=kept, n_conserving=3, n_up_shift=2, n_dn_shift=2,
+                                  cfg=56 + max_dim)
+    pk, flat = run_blocked(rot, case)
+    ref, _ = oracle_mod.rotate_blocked(case)
+    check(case, pk, flat, ref, range(len(case.shifts)))
