@@ -353,11 +353,12 @@ ROT_API rot_status rot_plan_destroy(rot_plan plan);
  * call for a block structure (sector tables, offsets and buffer alignment)
  * builds its work-lists in library-owned device memory, times the available
  * execution paths (one fused kernel in two register layouts, its variant
- * that loads whole row blocks of operator rows, or two grouped launches) and
- * keeps the fastest for later calls with the same structure; every call's
- * result comes from the kept path, so repeated calls agree bit for bit.
- * ROT_BLOCKED_PATH=fused|fused_wide|rowblock|rowblock_wide|grouped in the
- * environment forces one.  Work-lists are cached for the 8 most recently used structures;
+ * that loads whole row blocks of operator rows, two grouped launches, or two
+ * launches that stack each shift's operators into one product per sector
+ * combination) and keeps the fastest for later calls with the same
+ * structure; every call's result comes from the kept path, so repeated calls
+ * agree bit for bit.  ROT_BLOCKED_PATH=fused|fused_wide|rowblock|
+ * rowblock_wide|grouped|stacked in the environment forces one.  Work-lists are cached for the 8 most recently used structures;
  * a structure used while `stream` is being captured into a graph is kept for
  * the life of the process (the graph refers to its work-lists), and its
  * first call must happen outside capture (ROT_ERR_UNSUPPORTED otherwise).

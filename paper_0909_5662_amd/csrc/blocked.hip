@@ -170,6 +170,16 @@ __global__ __launch_bounds__(256) void transpose_u_kernel(const UtSeg* __restric
     }
 }
 
+// Four consecutive floats at row + kk when `full`, else zero.  The address
+// falls back to `safe` (a readable 16-byte location) so that the load is
+// unconditional and the choice a select, not a branch.
+template <bool VEC>
+__device__ __forceinline__ f32x4 quad_or_zero(const float* row, int kk, bool full, const float* safe) {
+    const float* a = full ? row + kk : safe;
+    const f32x4 v = VEC ? *reinterpret_cast<const f32x4*>(a) : *reinterpret_cast<const f32x4u*>(a);
+    return full ? v : f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
 // MAXA: most 16-wide blocks of output rows (kept dim of T) a task can have;
 // CG: output column blocks (kept dim of Q) handled together, so each value of
 // the operator block fetched in stage 1 feeds CG instructions and each value
@@ -217,12 +227,11 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
                     const float* orow = o + (int64_t)row * tm.k;
                     auto load_a = [&](int k0) __attribute__((always_inline)) {
                         const int kk = k0 + 4 * lh;  // this lane's k = kk + j at step j
-                        f32x4 av;
-                        if (rok && kk + 4 <= tm.k) {
-                            av = *reinterpret_cast<const f32x4u*>(orow + kk);
-                        } else {
+                        f32x4 av = quad_or_zero<false>(orow, kk, rok && kk + 4 <= tm.k, Ut);
+                        if ((tm.k & 3) != 0 && rok && kk < tm.k && kk + 4 > tm.k) {
+                            // the row's last, partial quad
 #pragma unroll
-                            for (int j = 0; j < 4; j++) av[j] = (rok && kk + j < tm.k) ? orow[kk + j] : 0.f;
+                            for (int j = 0; j < 4; j++) av[j] = kk + j < tm.k ? orow[kk + j] : 0.f;
                         }
                         return av;
                     };
@@ -292,19 +301,42 @@ __global__ __launch_bounds__(256) void blocked_fused_kernel(const BlkTask* __res
 }
 
 // Variant of blocked_fused_kernel that loads the operator rows of a whole
-// (term, row block) pair at once, before the pair's first U^T_Q values: the
-// operator block comes from HBM, and with every k step's rows requested
-// together the pair waits for one HBM round trip instead of one per 16-wide
-// k step.  U^T_Q values (L2-resident) are still fetched one k step ahead.
-// Needs every term's stage-1 K <= 16 * KS.
+// (term, row block) pair at once (every k step's rows requested together),
+// and requests the next pair's rows while the current pair multiplies: the
+// operator blocks come from HBM, and the wave then waits for an HBM round
+// trip only at the first pair of a pass.  U^T_Q values (L2-resident) are
+// fetched one k step ahead.  Needs every term's stage-1 K <= 16 * KS.
 template <int MAXA, int CG, int KS>
-__global__ __launch_bounds__(256) void blocked_rowblock_kernel(const BlkTask* __restrict__ tasks, int n_tasks,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void blocked_rowblock_kernel(const BlkTask* __restrict__ tasks, int n_tasks,
                                                                const BlkTerm* __restrict__ terms,
                                                                const float* __restrict__ Ut,
                                                                const float* __restrict__ O, float* __restrict__ out,
                                                                int* __restrict__ counter) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lh = lane >> 4;
+    // the operator rows of row block rb of term tm, every k step (zero past
+    // the block)
+    auto load_rows = [&](const BlkTerm& tm, int rb, f32x4* a) __attribute__((always_inline)) {
+        const int nks = (tm.k + 15) >> 4;
+        const int row = rb * 16 + li;
+        const bool rok = row < tm.a;
+        const float* orow = O + tm.o_off + (int64_t)(rok ? row : 0) * tm.k;
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++) {
+            const int kk = ks * 16 + 4 * lh;
+            if (ks < nks) a[ks] = quad_or_zero<false>(orow, kk, rok && kk + 4 <= tm.k, Ut);
+        }
+        // the row's last, partial quad (K not a multiple of 4)
+        const int kt = 16 * (nks - 1) + 4 * lh;
+        if ((tm.k & 3) != 0 && rok && kt < tm.k && kt + 4 > tm.k) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ks++)
+                if (ks == nks - 1) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) a[ks][j] = kt + j < tm.k ? orow[kt + j] : 0.f;
+                }
+        }
+    };
     int t = 0;
     if (lane == 0) t = atomicAdd(counter, 1);
     t = __builtin_amdgcn_readfirstlane(t);
@@ -319,76 +351,80 @@ __global__ __launch_bounds__(256) void blocked_rowblock_kernel(const BlkTask* __
             for (int c = 0; c < CG; c++)
 #pragma unroll
                 for (int ca = 0; ca < MAXA; ca++) acc[c][ca] = f32x4{0.f, 0.f, 0.f, 0.f};
-            for (int e = 0; e < T.n_terms; e++) {
-                const BlkTerm tm = terms[T.term0 + e];
+            // walk the (term, row block) pairs of the task in order
+            int e = 0, rb = 0;
+            BlkTerm tm{};
+            f32x4 a[KS];
+            if (T.n_terms > 0) {
+                tm = terms[T.term0];
+                load_rows(tm, 0, a);
+            }
+            while (e < T.n_terms) {
+                // the pair after this one
+                int e2 = e, rb2 = rb + 1;
+                BlkTerm tm2 = tm;
+                if (rb2 * 16 >= tm.a) {
+                    e2 = e + 1;
+                    rb2 = 0;
+                    if (e2 < T.n_terms) tm2 = terms[T.term0 + e2];
+                }
                 const int nks = (tm.k + 15) >> 4;
-                for (int rb = 0; rb * 16 < tm.a; rb++) {
-                    f32x4 ut[MAXA];
+                f32x4 ut[MAXA];
 #pragma unroll
-                    for (int ca = 0; ca < MAXA; ca++)
-                        if (ca < nba)
-                            ut[ca] = *reinterpret_cast<const f32x4*>(uT + (int64_t)(ca * 16 + li) * T.ldT + tm.rt +
-                                                                     rb * 16 + 4 * lh);
-                    // the row block's operator rows, every k step
-                    const int row = rb * 16 + li;
-                    const bool rok = row < tm.a;
-                    const float* orow = O + tm.o_off + (int64_t)row * tm.k;
-                    f32x4 a[KS];
+                for (int ca = 0; ca < MAXA; ca++)
+                    if (ca < nba)
+                        ut[ca] = *reinterpret_cast<const f32x4*>(uT + (int64_t)(ca * 16 + li) * T.ldT + tm.rt +
+                                                                 rb * 16 + 4 * lh);
+                f32x4 x[CG], bv[CG];
 #pragma unroll
-                    for (int ks = 0; ks < KS; ks++) {
-                        const int kk = ks * 16 + 4 * lh;
-                        if (ks < nks) {
-                            if (rok && kk + 4 <= tm.k) {
-                                a[ks] = *reinterpret_cast<const f32x4u*>(orow + kk);
-                            } else {
+                for (int c = 0; c < CG; c++) x[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (nks > 0) {
 #pragma unroll
-                                for (int j = 0; j < 4; j++) a[ks][j] = (rok && kk + j < tm.k) ? orow[kk + j] : 0.f;
-                            }
+                    for (int c = 0; c < CG; c++)
+                        bv[c] = *reinterpret_cast<const f32x4*>(uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ + tm.rq +
+                                                                4 * lh);
+                }
+                // the next pair's operator rows load while this pair multiplies
+                f32x4 an[KS];
+                if (e2 < T.n_terms) load_rows(tm2, rb2, an);
+#pragma unroll
+                for (int ks = 0; ks < KS; ks++) {
+                    if (ks < nks) {
+                        f32x4 bv_n[CG];
+                        if (ks + 1 < nks) {
+#pragma unroll
+                            for (int c = 0; c < CG; c++)
+                                bv_n[c] = *reinterpret_cast<const f32x4*>(
+                                    uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ + tm.rq + (ks + 1) * 16 + 4 * lh);
                         }
-                    }
-                    f32x4 x[CG], bv[CG];
 #pragma unroll
-                    for (int c = 0; c < CG; c++) x[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    if (nks > 0) {
+                        for (int j = 0; j < 4; j++)
 #pragma unroll
-                        for (int c = 0; c < CG; c++)
-                            bv[c] = *reinterpret_cast<const f32x4*>(uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ +
-                                                                    tm.rq + 4 * lh);
-                    }
+                            for (int c = 0; c < CG; c++)
+                                x[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][j], bv[c][j], x[c], 0, 0, 0);
+                        if (ks + 1 < nks) {
 #pragma unroll
-                    for (int ks = 0; ks < KS; ks++) {
-                        if (ks < nks) {
-                            f32x4 bv_n[CG];
-                            if (ks + 1 < nks) {
-#pragma unroll
-                                for (int c = 0; c < CG; c++)
-                                    bv_n[c] = *reinterpret_cast<const f32x4*>(
-                                        uQ + (int64_t)((cg0 + c) * 16 + li) * T.ldQ + tm.rq + (ks + 1) * 16 + 4 * lh);
-                            }
-#pragma unroll
-                            for (int j = 0; j < 4; j++)
-#pragma unroll
-                                for (int c = 0; c < CG; c++)
-                                    x[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][j], bv[c][j], x[c], 0, 0, 0);
-                            if (ks + 1 < nks) {
-#pragma unroll
-                                for (int c = 0; c < CG; c++) bv[c] = bv_n[c];
-                            }
-                        }
-                    }
-                    // stage 2 (as in blocked_fused_kernel)
-#pragma unroll
-                    for (int ca = 0; ca < MAXA; ca++) {
-                        if (ca < nba) {
-#pragma unroll
-                            for (int j = 0; j < 4; j++)
-#pragma unroll
-                                for (int c = 0; c < CG; c++)
-                                    acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], ut[ca][j], acc[c][ca], 0,
-                                                                                       0, 0);
+                            for (int c = 0; c < CG; c++) bv[c] = bv_n[c];
                         }
                     }
                 }
+                // stage 2 (as in blocked_fused_kernel)
+#pragma unroll
+                for (int ca = 0; ca < MAXA; ca++) {
+                    if (ca < nba) {
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+#pragma unroll
+                            for (int c = 0; c < CG; c++)
+                                acc[c][ca] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[c][j], ut[ca][j], acc[c][ca], 0,
+                                                                                   0, 0);
+                    }
+                }
+                e = e2;
+                rb = rb2;
+                tm = tm2;
+#pragma unroll
+                for (int ks = 0; ks < KS; ks++) a[ks] = an[ks];
             }
 #pragma unroll
             for (int c = 0; c < CG; c++)
@@ -406,6 +442,296 @@ __global__ __launch_bounds__(256) void blocked_rowblock_kernel(const BlkTask* __
         }
         if (lane == 0) t = atomicAdd(counter, 1);
         t = __builtin_amdgcn_readfirstlane(t);
+    }
+}
+
+// ---------------------------------------------------------- stacked path --
+// Operators with the same shift Delta share every block of U, so each
+// stage's small products over all of them form one GEMM per sector
+// combination, with the operators stacked along N:
+//   stage 1, per (Q, s, Delta):
+//     Xt_b[beta][row of s in T] = sum_k U_Q[s rows][k][beta] O_b(q_s+Delta <- q_s)[i][k]
+//   stage 2, per (Q, Delta):
+//     out_b(T <- Q)[alpha][beta] = sum_r U_T[r][alpha] Xt_b[beta][r]
+// Both are C[m][n] = sum_k A[m][k] B[n][k]: A is a row of the transposed-U
+// area shared by the group, B and C rows belong to operator j = n / nb.  The
+// 16-wide instruction tiles then pad only one extent per stage (M, a kept
+// sector dimension) instead of all three, and each wave runs a whole k loop
+// with 20 instructions per 16 k.  Xt_b (mQ rows of the padded row count of
+// U^T_T) lives in the workspace; its padding columns are written as zeros.
+struct StkGroup {
+    int M, N, K;    // C is M x N, contraction length K
+    int nb;         // columns per operator: n = j nb + i
+    int nvalid;     // B rows with i >= nvalid are zero
+    int lda, ldb;   // A row stride; B row stride inside an operator block
+    int ldcm;       // C stride per row m
+    int64_t a_off;  // A row 0 in the transposed-U area
+    int64_t tab;    // first entry of the group in the per-operator tables
+};
+struct StkTile {
+    int group, m0, n0, pad;
+};
+constexpr int kStkMB = 5;  // 16-row blocks per wave tile (80 rows)
+constexpr int kStkNB = 4;  // 16-column blocks per wave tile (64 columns)
+
+// One wave per tile part (a 16 NB-column share of a 64-column tile), four
+// waves per workgroup.  boff[tab + j] locates operator j's B block (-1:
+// absent, zero rows), coff[tab + j] its C block (-1: not written).  PF: 16-wide k steps whose
+// loads are in flight while a step multiplies.  BVEC: B rows are 16-byte
+// aligned (stage 2); otherwise only 4-byte aligned.
+template <int NB, int PF, bool BVEC>
+__global__ __launch_bounds__(256) void blocked_stacked_kernel(const StkTile* __restrict__ tiles, int n_tiles,
+                                                              const StkGroup* __restrict__ groups,
+                                                              const int64_t* __restrict__ boff,
+                                                              const int64_t* __restrict__ coff,
+                                                              const float* __restrict__ A,
+                                                              const float* __restrict__ B, float* __restrict__ C) {
+    constexpr int MB = kStkMB;
+    constexpr int PARTS = kStkNB / NB;
+    static_assert(kStkNB % NB == 0, "whole column parts");
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lh = lane >> 4;
+    const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int t = w / PARTS;
+    if (t >= n_tiles) return;
+    const StkTile tl = tiles[t];
+    const StkGroup g = groups[tl.group];
+    const int n0 = tl.n0 + (w % PARTS) * 16 * NB;
+    if (n0 >= g.N) return;
+    const int nbm = min(MB, (g.M - tl.m0 + 15) >> 4);
+    const int nbn = min(NB, (g.N - n0 + 15) >> 4);
+    // this lane's A row in each row block and B / C row in each column block
+    const float* arow[MB];
+    bool aok[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+        const int m = tl.m0 + mb * 16 + li;
+        aok[mb] = m < g.M;
+        arow[mb] = A + g.a_off + (int64_t)(aok[mb] ? m : 0) * g.lda;
+    }
+    const float* brow[NB];
+    float* crow[NB];
+    bool bok[NB], cok[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+        const int n = n0 + nb * 16 + li;
+        cok[nb] = n < g.N;
+        const int j = cok[nb] ? n / g.nb : 0;
+        const int i = n - j * g.nb;
+        const int64_t bo = cok[nb] ? boff[g.tab + j] : -1;
+        bok[nb] = cok[nb] && i < g.nvalid && bo >= 0;
+        brow[nb] = B + (bok[nb] ? bo + (int64_t)i * g.ldb : 0);
+        const int64_t co = cok[nb] ? coff[g.tab + j] : -1;
+        cok[nb] = co >= 0;  // no output block: nothing to write
+        crow[nb] = C + (cok[nb] ? co + i : 0);
+    }
+    const int K = g.K;
+    const int nks = (K + 15) >> 4;
+    struct Ops {
+        f32x4 a[MB], b[NB];
+    };
+    // lane group lh takes k = 16 s + 4 lh + q at instruction q of step s.  A
+    // rows (the transposed-U area) are zero-padded to a multiple of 4, so a
+    // quad starting below K is whole; B rows end at K: a quad crossing K (K
+    // not a multiple of 4, last step only) is read element by element.
+    auto fetch = [&](Ops& o, int s) __attribute__((always_inline)) {
+        const int kk = 16 * s + 4 * lh;
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++)
+            if (mb < nbm) o.a[mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++)
+            if (nb < nbn) o.b[nb] = quad_or_zero<BVEC>(brow[nb], kk, bok[nb] && kk + 4 <= K, A);
+        if ((K & 3) != 0 && s == nks - 1 && kk < K && kk + 4 > K) {
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++)
+                if (nb < nbn && bok[nb]) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) o.b[nb][q] = kk + q < K ? brow[nb][kk + q] : 0.f;
+                }
+        }
+    };
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto multiply = [&](const Ops& o) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+                for (int nb = 0; nb < NB; nb++)
+                    if (mb < nbm && nb < nbn)
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[mb][q], o.b[nb][q], acc[mb][nb], 0, 0, 0);
+    };
+    // step s multiplies `cur` after issuing the loads of step s + PF into `dst`
+    auto step = [&](int s, const Ops& cur, Ops& dst) __attribute__((always_inline)) {
+        if (s + PF < nks) fetch(dst, s + PF);
+        multiply(cur);
+    };
+    // ring of PF + 1 operand sets, unrolled so every set is a fixed register set
+    Ops o[PF + 1];
+#pragma unroll
+    for (int s = 0; s < PF; s++)
+        if (s < nks) fetch(o[s], s);
+    for (int s0 = 0; s0 < nks; s0 += PF + 1) {
+#pragma unroll
+        for (int r = 0; r <= PF; r++)
+            if (s0 + r < nks) step(s0 + r, o[r], o[(r + PF) % (PF + 1)]);
+    }
+    // accumulator element v of lane l: C(m0 + 16 mb + 4 (l / 16) + v, column l % 16 of block nb)
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++)
+            if (mb < nbm && nb < nbn && cok[nb]) {
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int m = tl.m0 + mb * 16 + 4 * lh + v;
+                    if (m < g.M) crow[nb][(int64_t)m * g.ldcm] = acc[mb][nb][v];
+                }
+            }
+}
+
+// Stage 1 with the operator rows resident in registers (stage-1 K <= 80):
+// one group per (shift, source sector q) stacks the operators' blocks
+// O(q + Delta <- q) along N, and each wave keeps its 16 NB columns of them
+// for every k while it multiplies them by every member: the U^T_Q rows of
+// each site state s whose kept sector Q = q + qn(s) has output blocks (row
+// tiles of at most 80).  The operator rows are fetched once per wave instead
+// of once per site state, and the U^T values (L2-resident) one k step ahead.
+struct StkMember {
+    int M;          // rows of this member tile (<= 80)
+    int lda, ldcm;  // A row stride; C stride per row (padded row count of U^T_T)
+    int pad;
+    int64_t a_off;  // A row 0 in the transposed-U area
+    int64_t tab;    // per-operator C offsets into Xt (-1: operator has no output block)
+};
+struct StkGroupR {
+    int N, K, nb, nvalid;  // C columns, contraction length, columns per operator, non-zero rows of each
+    int mem0, n_mem;       // members
+    int64_t tab;           // per-operator B offsets into O_blk (-1: block absent)
+};
+constexpr int kStkResK = 5;  // 16-wide k steps held per lane (K <= 80)
+
+template <int NB>
+__global__ __launch_bounds__(256) void blocked_stacked_res_kernel(const StkTile* __restrict__ tiles, int n_tiles,
+                                                                  const StkGroupR* __restrict__ groups,
+                                                                  const StkMember* __restrict__ members,
+                                                                  const int64_t* __restrict__ boff,
+                                                                  const int64_t* __restrict__ coff,
+                                                                  const float* __restrict__ A,
+                                                                  const float* __restrict__ B, float* __restrict__ C) {
+    constexpr int MB = kStkMB, KS = kStkResK;
+    constexpr int PARTS = kStkNB / NB;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lh = lane >> 4;
+    const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int t = w / PARTS;
+    if (t >= n_tiles) return;
+    const StkTile tl = tiles[t];
+    const StkGroupR g = groups[tl.group];
+    const int n0 = tl.n0 + (w % PARTS) * 16 * NB;
+    if (n0 >= g.N) return;
+    const int nbn = min(NB, (g.N - n0 + 15) >> 4);
+    const int K = g.K;
+    const int nks = (K + 15) >> 4;
+    // this lane's operator row in each column block, every k step (quads as
+    // in blocked_stacked_kernel: the one crossing K element by element)
+    int jn[NB], in_[NB];
+    bool cok[NB];
+    f32x4 b[KS][NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+        const int n = n0 + nb * 16 + li;
+        cok[nb] = n < g.N;
+        jn[nb] = cok[nb] ? n / g.nb : 0;
+        in_[nb] = n - jn[nb] * g.nb;
+        const int64_t bo = cok[nb] ? boff[g.tab + jn[nb]] : -1;
+        const bool bok = cok[nb] && in_[nb] < g.nvalid && bo >= 0;
+        const float* brow = B + (bok ? bo + (int64_t)in_[nb] * K : 0);
+#pragma unroll
+        for (int s = 0; s < KS; s++) {
+            const int kk = 16 * s + 4 * lh;
+            if (s < nks && nb < nbn) b[s][nb] = quad_or_zero<false>(brow, kk, bok && kk + 4 <= K, A);
+        }
+        const int kt = 16 * (nks - 1) + 4 * lh;
+        if ((K & 3) != 0 && bok && nb < nbn && kt < K && kt + 4 > K) {
+#pragma unroll
+            for (int s = 0; s < KS; s++)
+                if (s == nks - 1) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) b[s][nb][q] = kt + q < K ? brow[kt + q] : 0.f;
+                }
+        }
+    }
+    for (int mi = 0; mi < g.n_mem; mi++) {
+        const StkMember mem = members[g.mem0 + mi];
+        const int nbm = min(MB, (mem.M + 15) >> 4);
+        const float* arow[MB];
+        bool aok[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++) {
+            const int m = mb * 16 + li;
+            aok[mb] = m < mem.M;
+            arow[mb] = A + mem.a_off + (int64_t)(aok[mb] ? m : 0) * mem.lda;
+        }
+        float* crow[NB];
+        bool wok[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) {
+            const int64_t co = cok[nb] ? coff[mem.tab + jn[nb]] : -1;
+            wok[nb] = co >= 0;
+            crow[nb] = C + (wok[nb] ? co + in_[nb] : 0);
+        }
+        f32x4 acc[MB][NB];
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 a[MB], an[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++)
+            if (mb < nbm && nks > 0) a[mb] = quad_or_zero<true>(arow[mb], 4 * lh, aok[mb] && 4 * lh < K, A);
+#pragma unroll
+        for (int s = 0; s < KS; s++) {
+            if (s < nks) {
+                if (s + 1 < nks) {
+#pragma unroll
+                    for (int mb = 0; mb < MB; mb++)
+                        if (mb < nbm) {
+                            const int kk = 16 * (s + 1) + 4 * lh;
+                            an[mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+                        }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+                        for (int nb = 0; nb < NB; nb++)
+                            if (mb < nbm && nb < nbn)
+                                acc[mb][nb] =
+                                    __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][q], b[s][nb][q], acc[mb][nb], 0, 0, 0);
+                if (s + 1 < nks) {
+#pragma unroll
+                    for (int mb = 0; mb < MB; mb++) a[mb] = an[mb];
+                }
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++)
+                if (mb < nbm && nb < nbn && wok[nb]) {
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int m = mb * 16 + 4 * lh + v;
+                        if (m < mem.M) crow[nb][(int64_t)m * mem.ldcm] = acc[mb][nb][v];
+                    }
+                }
     }
 }
 
@@ -463,8 +789,10 @@ UtLayout ut_layout(const rot_blocked_problem* p, const Structure& st) {
     return L;
 }
 
-// Workspace of the grouped path's intermediate X (elements).
-int64_t x_elements(const rot_blocked_problem* p, const Structure& st) {
+// Workspace of the intermediate (elements): the stacked path's Xt (mQ rows
+// of the padded row count of U^T_T per output block), which is never smaller
+// than the grouped path's X (M_T x mQ per output block).
+int64_t x_elements(const rot_blocked_problem* p, const Structure& st, const UtLayout& ut) {
     int64_t x = 0;
     for (int b = 0; b < p->n_ops; b++) {
         const int du = p->shift[2 * b], dd = p->shift[2 * b + 1];
@@ -472,7 +800,7 @@ int64_t x_elements(const rot_blocked_problem* p, const Structure& st) {
             if (p->out_off[(int64_t)b * p->n_new + k] < 0) continue;
             const rot_sector& Q = p->new_sec[k];
             const int kt = st.new_idx.at(QN{Q.n_up + du, Q.n_dn + dd});
-            x += (st.M[kt] * Q.dim + 63) / 64 * 64;
+            x += ((int64_t)ut.ld[kt] * Q.dim + 63) / 64 * 64;
         }
     }
     return x;
@@ -534,6 +862,194 @@ void build_fused(const rot_blocked_problem* p, const Structure& st, const UtLayo
     std::stable_sort(work.begin(), work.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
     for (auto& w : work) F->tasks.push_back(w.second);
     F->terms = std::move(terms);
+}
+
+// Work-lists of the stacked path.  Xt offsets are relative to the workspace.
+struct StackedLists {
+    std::vector<StkGroup> g1, g2;      // streamed stage-1 groups (K > 80, or K = 0: zero rows); stage 2
+    std::vector<StkTile> t1, t2;
+    std::vector<StkGroupR> gr;         // stage 1 with resident operator rows
+    std::vector<StkMember> mem;
+    std::vector<StkTile> tr;
+    std::vector<int64_t> boff, coff;
+    int64_t x_elems = 0;
+};
+
+void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLayout& ut, StackedLists* S) {
+    std::vector<std::pair<int, int>> shifts;  // distinct shifts, first-appearance order
+    for (int b = 0; b < p->n_ops; b++) {
+        const std::pair<int, int> sh{p->shift[2 * b], p->shift[2 * b + 1]};
+        if (std::find(shifts.begin(), shifts.end(), sh) == shifts.end()) shifts.push_back(sh);
+    }
+    // Xt block of (operator b, kept sector k): mQ rows of the padded row count
+    // of U^T_T, allocated per (shift, kept sector) group, operators in order
+    std::vector<int64_t> xbase((size_t)p->n_ops * p->n_new, -1);
+    std::vector<std::pair<int, StkTile>> o1, o2;  // (work, tile): longest first
+    for (int si = 0; si < (int)shifts.size(); si++) {
+        const int du = shifts[si].first, dd = shifts[si].second;
+        std::vector<int> ops;  // every operator of this shift
+        for (int b = 0; b < p->n_ops; b++)
+            if (p->shift[2 * b] == du && p->shift[2 * b + 1] == dd) ops.push_back(b);
+        // stage 2 per kept sector Q (and the Xt blocks it reads)
+        for (int k = 0; k < p->n_new; k++) {
+            const rot_sector& Q = p->new_sec[k];
+            auto itT = st.new_idx.find(QN{Q.n_up + du, Q.n_dn + dd});
+            if (itT == st.new_idx.end()) continue;
+            const int kt = itT->second;
+            const rot_sector& T = p->new_sec[kt];
+            std::vector<int> J;
+            for (int b : ops)
+                if (p->out_off[(int64_t)b * p->n_new + k] >= 0) J.push_back(b);
+            if (J.empty()) continue;
+            const int ldT = ut.ld[kt];
+            const int n = (int)J.size();
+            StkGroup g2{};
+            g2.M = T.dim;
+            g2.N = n * Q.dim;
+            g2.K = ldT;
+            g2.nb = g2.nvalid = Q.dim;
+            g2.lda = ldT;
+            g2.ldb = ldT;
+            g2.ldcm = Q.dim;
+            g2.a_off = ut.off[kt];
+            g2.tab = (int64_t)S->boff.size();
+            for (int j = 0; j < n; j++) {
+                const int64_t x = S->x_elems;
+                S->x_elems += ((int64_t)Q.dim * ldT + 63) / 64 * 64;  // keep 256-byte alignment
+                xbase[(size_t)J[j] * p->n_new + k] = x;
+                S->boff.push_back(x);
+                S->coff.push_back(p->out_off[(int64_t)J[j] * p->n_new + k]);
+            }
+            const int gi2 = (int)S->g2.size();
+            S->g2.push_back(g2);
+            for (int m0 = 0; m0 < g2.M; m0 += 16 * kStkMB)
+                for (int n0 = 0; n0 < g2.N; n0 += 16 * kStkNB) o2.push_back({g2.K, StkTile{gi2, m0, n0, 0}});
+            // Xt columns of site states whose source sector q_s = Q - qn(s) is
+            // absent while q_s + Delta exists: zero (streamed groups with K = 0)
+            for (int s = 0; s < p->d; s++) {
+                if (st.rowstart[kt][s] < 0 || st.rowstart[k][s] >= 0) continue;
+                const QN qt{T.n_up - p->site_qn[2 * s], T.n_dn - p->site_qn[2 * s + 1]};
+                const int a = p->old_sec[st.old_idx.at(qt)].dim;
+                StkGroup g1{};
+                g1.M = Q.dim;
+                g1.N = n * ((a + 3) / 4 * 4);
+                g1.K = 0;
+                g1.nb = (a + 3) / 4 * 4;
+                g1.nvalid = a;
+                g1.lda = g1.ldb = 1;
+                g1.ldcm = ldT;
+                g1.tab = (int64_t)S->boff.size();
+                for (int j = 0; j < n; j++) {
+                    S->boff.push_back(-1);
+                    S->coff.push_back(xbase[(size_t)J[j] * p->n_new + k] + ut.pstart[kt][s]);
+                }
+                const int gi1 = (int)S->g1.size();
+                S->g1.push_back(g1);
+                for (int m0 = 0; m0 < g1.M; m0 += 16 * kStkMB)
+                    for (int n0 = 0; n0 < g1.N; n0 += 16 * kStkNB) o1.push_back({0, StkTile{gi1, m0, n0, 0}});
+            }
+        }
+        // stage 1 per source sector q: every operator's block O(q + Delta <- q)
+        // times U^T_Q of each site state s with Q = q + qn(s)
+        for (int kq = 0; kq < p->n_old; kq++) {
+            const rot_sector& q = p->old_sec[kq];
+            auto itA = st.old_idx.find(QN{q.n_up + du, q.n_dn + dd});
+            if (itA == st.old_idx.end()) continue;  // no operator block maps q anywhere kept
+            const int a = p->old_sec[itA->second].dim, a4 = (a + 3) / 4 * 4;
+            const int K = q.dim;
+            const int n = (int)ops.size();
+            struct Mem {
+                int k, kt, s;
+            };
+            std::vector<Mem> ms;
+            for (int s = 0; s < p->d; s++) {
+                auto itQ = st.new_idx.find(QN{q.n_up + p->site_qn[2 * s], q.n_dn + p->site_qn[2 * s + 1]});
+                if (itQ == st.new_idx.end()) continue;
+                const int k = itQ->second;
+                const rot_sector& Q = p->new_sec[k];
+                auto itT = st.new_idx.find(QN{Q.n_up + du, Q.n_dn + dd});
+                if (itT == st.new_idx.end()) continue;
+                bool any = false;
+                for (int b : ops) any = any || xbase[(size_t)b * p->n_new + k] >= 0;
+                if (any) ms.push_back({k, itT->second, s});
+            }
+            if (ms.empty()) continue;
+            const int64_t btab = (int64_t)S->boff.size();
+            for (int b : ops) {
+                S->boff.push_back(p->O_off[(int64_t)b * p->n_old + kq]);
+                S->coff.push_back(-1);
+            }
+            // member tables: C offsets of (operator, Q) + first padded row of s
+            auto member_tab = [&](const Mem& mm, int m0) {
+                const int64_t tab = (int64_t)S->coff.size();
+                for (int b : ops) {
+                    const int64_t x = xbase[(size_t)b * p->n_new + mm.k];
+                    S->boff.push_back(-1);
+                    S->coff.push_back(x < 0 ? -1 : x + (int64_t)m0 * ut.ld[mm.kt] + ut.pstart[mm.kt][mm.s]);
+                }
+                return tab;
+            };
+            if (K <= 16 * kStkResK) {
+                StkGroupR g{};
+                g.N = n * a4;
+                g.K = K;
+                g.nb = a4;
+                g.nvalid = a;
+                g.tab = btab;
+                g.mem0 = (int)S->mem.size();
+                int64_t work = 0;
+                for (const Mem& mm : ms) {
+                    const rot_sector& Q = p->new_sec[mm.k];
+                    for (int m0 = 0; m0 < Q.dim; m0 += 16 * kStkMB) {
+                        StkMember e{};
+                        e.M = std::min(16 * kStkMB, Q.dim - m0);
+                        e.lda = ut.ld[mm.k];
+                        e.ldcm = ut.ld[mm.kt];
+                        e.a_off = ut.off[mm.k] + (int64_t)m0 * ut.ld[mm.k] + ut.pstart[mm.k][mm.s];
+                        e.tab = member_tab(mm, m0);
+                        S->mem.push_back(e);
+                        work += (int64_t)((e.M + 15) / 16) * K;
+                    }
+                }
+                g.n_mem = (int)S->mem.size() - g.mem0;
+                const int gi = (int)S->gr.size();
+                S->gr.push_back(g);
+                for (int n0 = 0; n0 < g.N; n0 += 16 * kStkNB) S->tr.push_back(StkTile{gi, 0, n0, (int)work});
+            } else {
+                // wide source sectors: one streamed group per site state
+                for (const Mem& mm : ms) {
+                    const rot_sector& Q = p->new_sec[mm.k];
+                    StkGroup g1{};
+                    g1.M = Q.dim;
+                    g1.N = n * a4;
+                    g1.K = K;
+                    g1.nb = a4;
+                    g1.nvalid = a;
+                    g1.lda = ut.ld[mm.k];
+                    g1.ldb = K;
+                    g1.ldcm = ut.ld[mm.kt];
+                    g1.a_off = ut.off[mm.k] + ut.pstart[mm.k][mm.s];
+                    // B offsets: the operator blocks; C offsets: Xt blocks + first padded row of s
+                    g1.tab = (int64_t)S->boff.size();
+                    for (int b : ops) {
+                        const int64_t x = xbase[(size_t)b * p->n_new + mm.k];
+                        S->boff.push_back(p->O_off[(int64_t)b * p->n_old + kq]);
+                        S->coff.push_back(x < 0 ? -1 : x + ut.pstart[mm.kt][mm.s]);
+                    }
+                    const int gi1 = (int)S->g1.size();
+                    S->g1.push_back(g1);
+                    for (int m0 = 0; m0 < g1.M; m0 += 16 * kStkMB)
+                        for (int n0 = 0; n0 < g1.N; n0 += 16 * kStkNB) o1.push_back({K, StkTile{gi1, m0, n0, 0}});
+                }
+            }
+        }
+    }
+    std::stable_sort(o1.begin(), o1.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& o : o1) S->t1.push_back(o.second);
+    std::stable_sort(o2.begin(), o2.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& o : o2) S->t2.push_back(o.second);
+    // resident tiles: most work first (the work estimate rides in the pad field)
+    std::stable_sort(S->tr.begin(), S->tr.end(), [](const StkTile& x, const StkTile& y) { return x.pad > y.pad; });
 }
 
 struct Lists {
@@ -631,8 +1147,30 @@ struct Plan {
     int f_max_k = 0;
     int64_t ut_base = 0;   // transposed U area in the workspace (elements)
     int64_t ut_elems = 0;  // its size, slack included
-    int path = -1;  // 0 grouped two-stage, 1 fused, 2 fused wide, 3/4 row-block operands (narrow/wide); -1 not chosen yet
+    // stacked path: groups, tiles and per-operator tables of both stages
+    StkGroup* k_g1 = nullptr;
+    StkGroup* k_g2 = nullptr;
+    StkTile* k_t1 = nullptr;
+    StkTile* k_t2 = nullptr;
+    int64_t* k_boff = nullptr;
+    int64_t* k_coff = nullptr;
+    StkGroupR* k_gr = nullptr;
+    StkMember* k_mem = nullptr;
+    StkTile* k_tr = nullptr;
+    int k_n1 = 0, k_n2 = 0, k_nr = 0;
+    // 0 grouped two-stage, 1 fused, 2 fused wide, 3/4 row-block operands
+    // (narrow/wide), 5 stacked; -1 not chosen yet
+    int path = -1;
     ~Plan() {
+        (void)hipFree(k_g1);
+        (void)hipFree(k_g2);
+        (void)hipFree(k_t1);
+        (void)hipFree(k_t2);
+        (void)hipFree(k_boff);
+        (void)hipFree(k_coff);
+        (void)hipFree(k_gr);
+        (void)hipFree(k_mem);
+        (void)hipFree(k_tr);
         (void)hipFree(s1.probs);
         (void)hipFree(s1.tiles);
         (void)hipFree(s2.probs);
@@ -713,7 +1251,8 @@ size_t blocked_workspace_bytes(const rot_blocked_problem* p) {
     Structure st;
     std::string why;
     if (!build_structure(p, &st, &why)) return 0;
-    return (size_t)counter_offset(x_elements(p, st), ut_layout(p, st).elems) + 256;
+    const UtLayout ut = ut_layout(p, st);
+    return (size_t)counter_offset(x_elements(p, st, ut), ut.elems) + 256;
 }
 
 rot_status blocked_validate(const rot_blocked_problem* p, std::string* why) {
@@ -806,11 +1345,90 @@ hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, bool r
     });
 }
 
+// Stacked kernel variant: columns per wave (16 NB) and k steps in flight.
+// ROT_STK_CFG=NB,PF (e.g. "4,1") overrides the default 2,2.
+struct StkCfg {
+    int nb = 2, pf = 2;
+};
+StkCfg stacked_cfg() {
+    StkCfg c;
+    if (const char* e = getenv("ROT_STK_CFG")) {
+        int nb = 0, pf = 0;
+        const bool parsed = sscanf(e, "%d,%d", &nb, &pf) == 2;
+        const bool ok = (nb == 4 && (pf == 1 || pf == 2)) || (nb == 2 && pf >= 1 && pf <= 4) ||
+                        (nb == 1 && (pf == 2 || pf == 4));
+        if (parsed && ok) {
+            c.nb = nb;
+            c.pf = pf;
+        }
+    }
+    return c;
+}
+
+template <int NB, int PF, bool BVEC>
+void launch_stacked_v(int n, const StkTile* tiles, const StkGroup* groups, const Plan* plan, const float* A,
+                      const float* B, float* C, hipStream_t stream) {
+    const int waves = n * (kStkNB / NB);
+    hipLaunchKernelGGL((blocked_stacked_kernel<NB, PF, BVEC>), dim3((waves + 3) / 4), dim3(256), 0, stream, tiles, n,
+                       groups, plan->k_boff, plan->k_coff, A, B, C);
+}
+
+template <bool BVEC>
+hipError_t launch_stacked(StkCfg c, const StkTile* tiles, int n, const StkGroup* groups, const Plan* plan,
+                          const float* A, const float* B, float* C, hipStream_t stream) {
+    if (c.nb == 4) {
+        if (c.pf == 1) launch_stacked_v<4, 1, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+        else launch_stacked_v<4, 2, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+    } else if (c.nb == 2) {
+        if (c.pf == 1) launch_stacked_v<2, 1, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+        else if (c.pf == 2) launch_stacked_v<2, 2, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+        else if (c.pf == 3) launch_stacked_v<2, 3, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+        else launch_stacked_v<2, 4, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+    } else {
+        if (c.pf == 2) launch_stacked_v<1, 2, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+        else launch_stacked_v<1, 4, BVEC>(n, tiles, groups, plan, A, B, C, stream);
+    }
+    return hipGetLastError();
+}
+
+// Transposed U blocks into the workspace, then the two stacked launches
+// (stage 1 writes every element of Xt that stage 2 reads, padding included).
+hipError_t run_stacked(const rot_blocked_problem* p, Plan* plan, void* ws, hipStream_t stream) {
+    if (plan->k_n2 == 0) return hipSuccess;
+    float* ut = static_cast<float*>(ws) + plan->ut_base;
+    float* xt = static_cast<float*>(ws);
+    hipError_t e = prof_timed("blocked_transpose_u", stream, [&] {
+        hipError_t err = fill_zero(ut, plan->ut_elems * (int64_t)sizeof(float), stream);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(transpose_u_kernel, dim3(16, (unsigned)plan->f_n_segs), dim3(256), 0, stream,
+                           plan->f_segs, p->U_blk, ut);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    const StkCfg c = stacked_cfg();
+    e = prof_timed("blocked_stacked1_fp32", stream, [&] {
+        if (plan->k_nr > 0) {
+            constexpr int NB = 2;
+            const int waves = plan->k_nr * (kStkNB / NB);
+            hipLaunchKernelGGL(blocked_stacked_res_kernel<NB>, dim3((waves + 3) / 4), dim3(256), 0, stream,
+                               plan->k_tr, plan->k_nr, plan->k_gr, plan->k_mem, plan->k_boff, plan->k_coff, ut,
+                               p->O_blk, xt);
+        }
+        if (plan->k_n1 > 0)
+            return launch_stacked<false>(c, plan->k_t1, plan->k_n1, plan->k_g1, plan, ut, p->O_blk, xt, stream);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return prof_timed("blocked_stacked2_fp32", stream, [&] {
+        return launch_stacked<true>(c, plan->k_t2, plan->k_n2, plan->k_g2, plan, ut, xt, p->out_blk, stream);
+    });
+}
+
 // Paths: 0 two grouped launches, 1 fused (narrow passes), 2 fused (wide),
 // 3 / 4 the fused kernel with whole row blocks of operator rows (narrow /
-// wide).  ROT_BLOCKED_PATH = grouped | fused | fused_wide | rowblock |
-// rowblock_wide forces one; otherwise every applicable path is timed once
-// per block structure and the fastest is kept.
+// wide), 5 two stacked launches.  ROT_BLOCKED_PATH = grouped | fused |
+// fused_wide | rowblock | rowblock_wide | stacked forces one; otherwise every
+// applicable path is timed once per block structure and the fastest is kept.
 int forced_path() {
     const char* e = getenv("ROT_BLOCKED_PATH");
     if (!e) return -1;
@@ -819,12 +1437,14 @@ int forced_path() {
     if (!strcmp(e, "fused_wide")) return 2;
     if (!strcmp(e, "rowblock")) return 3;
     if (!strcmp(e, "rowblock_wide")) return 4;
+    if (!strcmp(e, "stacked")) return 5;
     return -1;
 }
 
 hipError_t run_path(const rot_blocked_problem* p, Plan* plan, void* ws, GroupedShape shape, int path,
                     hipStream_t stream) {
     if (path == 0) return run_grouped(p, plan, ws, shape, stream);
+    if (path == 5) return run_stacked(p, plan, ws, stream);
     return run_fused(p, plan, path == 2 || path == 4, path >= 3, ws, stream);
 }
 
@@ -858,8 +1478,10 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         const UtLayout ut = ut_layout(p, st);
         FusedLists F;
         build_fused(p, st, ut, &F);
+        StackedLists S;
+        build_stacked(p, st, ut, &S);
         auto np = std::make_unique<Plan>();
-        np->x_elems = L.x_elems;
+        np->x_elems = std::max(L.x_elems, S.x_elems);
         const int edge = grouped_tile_edge(shape);
         hipError_t e = upload(L.p1, make_tiles(L.p1, edge), &np->s1);
         if (e == hipSuccess) e = upload(L.p2, make_tiles(L.p2, edge), &np->s2);
@@ -867,9 +1489,9 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         np->f_max_mT = F.max_mT;
         np->f_max_k = F.max_k;
         np->f_n_segs = (int)ut.segs.size();
-        np->ut_base = (L.x_elems + 63) / 64 * 64;
+        np->ut_base = (np->x_elems + 63) / 64 * 64;
         np->ut_elems = ut.elems;
-        np->counter_off = counter_offset(L.x_elems, ut.elems);
+        np->counter_off = counter_offset(np->x_elems, ut.elems);
         if (e == hipSuccess && !ut.segs.empty()) e = hipMalloc(&np->f_segs, sizeof(UtSeg) * ut.segs.size());
         if (e == hipSuccess && !ut.segs.empty())
             e = hipMemcpy(np->f_segs, ut.segs.data(), sizeof(UtSeg) * ut.segs.size(), hipMemcpyHostToDevice);
@@ -879,28 +1501,58 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
             e = hipMemcpy(np->f_tasks, F.tasks.data(), sizeof(BlkTask) * F.tasks.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess && !F.terms.empty())
             e = hipMemcpy(np->f_terms, F.terms.data(), sizeof(BlkTerm) * F.terms.size(), hipMemcpyHostToDevice);
+        np->k_n1 = (int)S.t1.size();
+        np->k_n2 = (int)S.t2.size();
+        np->k_nr = (int)S.tr.size();
+        auto up = [&](auto** dst, const auto& v) {
+            if (e != hipSuccess || v.empty()) return;
+            e = hipMalloc(dst, sizeof(v[0]) * v.size());
+            if (e == hipSuccess) e = hipMemcpy(*dst, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice);
+        };
+        up(&np->k_g1, S.g1);
+        up(&np->k_g2, S.g2);
+        up(&np->k_t1, S.t1);
+        up(&np->k_t2, S.t2);
+        up(&np->k_boff, S.boff);
+        up(&np->k_coff, S.coff);
+        up(&np->k_gr, S.gr);
+        up(&np->k_mem, S.mem);
+        up(&np->k_tr, S.tr);
         if (e != hipSuccess) return e;
-        if (F.max_mT > 128) np->path = 0;  // the fused kernel keeps at most 8 x 16 output rows per lane set
         plan = g_plans.insert(std::move(sig), std::move(np));
     }
+    // paths that apply to this structure: the fused kernels keep at most
+    // 8 x 16 output rows per lane set
+    std::vector<int> paths{0};
+    if (plan->f_max_mT <= 128) {
+        paths.push_back(1);
+        paths.push_back(2);
+        if (rowblock_ok(plan)) {
+            paths.push_back(3);
+            paths.push_back(4);
+        }
+    }
+    paths.push_back(5);
     if (capturing) {
         g_plans.pin(plan);
-        // no timing under capture: the fused path unless the structure needs the grouped one
-        if (plan->path < 0 && forced < 0) plan->path = plan->f_max_mT > 128 ? 0 : 1;
+        // no timing under capture: the stacked path (it applies to every structure)
+        if (plan->path < 0 && forced < 0) plan->path = 5;
     }
     int path = forced >= 0 ? forced : plan->path;
-    if (path >= 3 && !rowblock_ok(plan)) path = path - 2;
-    if (path >= 1 && plan->f_max_mT > 128) path = 0;
+    if (path >= 0 && std::find(paths.begin(), paths.end(), path) == paths.end()) {
+        // a forced path that does not apply: the closest one that does
+        path = (path == 3 || path == 4) && plan->f_max_mT <= 128 ? path - 2 : 5;
+    }
     if (path < 0) {
         // time each applicable path (second run, after a warm-up run)
-        const int n_paths = plan->f_max_mT > 128 ? 1 : rowblock_ok(plan) ? 5 : 3;
-        hipEvent_t ev[6];
+        const int n_paths = (int)paths.size();
+        std::vector<hipEvent_t> ev(n_paths + 1, nullptr);
         hipError_t e = hipSuccess;
-        for (int i = 0; i < 6 && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
+        for (int i = 0; i <= n_paths && e == hipSuccess; i++) e = hipEventCreate(&ev[i]);
         for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
             for (int q = 0; q < n_paths && e == hipSuccess; q++) {
                 e = hipEventRecord(ev[q], stream);
-                if (e == hipSuccess) e = run_path(p, plan, ws, shape, q, stream);
+                if (e == hipSuccess) e = run_path(p, plan, ws, shape, paths[q], stream);
             }
             if (e == hipSuccess) e = hipEventRecord(ev[n_paths], stream);
         }
@@ -910,19 +1562,21 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         for (int q = 0; q < n_paths && e == hipSuccess; q++) {
             float ms = 0.f;
             e = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            log_msg(3, "blocked structure of %d operators: path %d %.3f ms", p->n_ops, paths[q], ms);
             if (ms < best) {
                 best = ms;
                 best_q = q;
             }
         }
-        for (int i = 0; i < 6; i++) (void)hipEventDestroy(ev[i]);
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
         if (e != hipSuccess) return e;
-        plan->path = best_q;
-        log_msg(2, "blocked structure of %d operators: execution path %d (%.3f ms when timed)", p->n_ops, best_q,
-                best);
+        plan->path = paths[best_q];
+        log_msg(2, "blocked structure of %d operators: execution path %d (%.3f ms when timed)", p->n_ops,
+                plan->path, best);
         // the chosen path writes the result, so this call matches every later
         // one bit for bit (the paths sum in different orders)
-        path = best_q;
+        path = plan->path;
     }
     return run_path(p, plan, ws, shape, path, stream);
 }

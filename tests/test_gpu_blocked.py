@@ -123,7 +123,7 @@ def test_blocked_repeat_uses_cached_plan_and_is_deterministic(rot):
     np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped", "rowblock", "rowblock_wide"])
+@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped", "rowblock", "rowblock_wide", "stacked"])
 def test_blocked_each_path_vs_oracle(rot, oracle_mod, monkeypatch, path):
     """Both execution paths (one fused wave per output block; two grouped
     launches through an intermediate) against the oracle, on sectors up to
@@ -138,7 +138,7 @@ def test_blocked_each_path_vs_oracle(rot, oracle_mod, monkeypatch, path):
     check(case, pk, flat, ref, range(len(case.shifts)))
 
 
-@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped", "rowblock", "rowblock_wide"])
+@pytest.mark.parametrize("path", ["fused", "fused_wide", "grouped", "rowblock", "rowblock_wide", "stacked"])
 def test_blocked_1024_each_path_sampled(rot, oracle_mod, monkeypatch, path):
     monkeypatch.setenv("ROT_BLOCKED_PATH", path)
     case = workloads.blocked_case()
@@ -287,3 +287,72 @@ def test_blocked_rowblock_paths_vs_oracle(rot, oracle_mod, monkeypatch, path, ma
     pk, flat = run_blocked(rot, case)
     ref, _ = oracle_mod.rotate_blocked(case)
     check(case, pk, flat, ref, range(len(case.shifts)))
+
+
+@pytest.mark.parametrize("max_dim", [76, 150])
+def test_blocked_stacked_path_vs_oracle(rot, oracle_mod, monkeypatch, max_dim):
+    """The stacked path (each shift's operators stacked along N, two
+    launches through Xt) against the oracle: ragged sectors up to 76 states
+    (one 80-row tile) and 150 (two, the second ragged), some operator blocks
+    absent (zero), and the operators of different shifts interleaved."""
+    monkeypatch.setenv("ROT_BLOCKED_PATH", "stacked")
+    total = 800 if max_dim == 76 else 1400
+    sizes = workloads.gaussian_sector_sizes(total, sigma=1.2, min_dim=3, max_dim=max_dim)
+    assert max(s for _, s in sizes) == max_dim
+    kept = [(qn, max(1, s - 5)) for qn, s in sizes]
+    case = workloads.blocked_case(sizes=sizes, kept_sizes=kept, n_conserving=4, n_up_shift=3, n_dn_shift=3,
+                                  cfg=70 + max_dim)
+    for b in (1, 5, 8):
+        keys = sorted(case.O_blocks[b])
+        del case.O_blocks[b][keys[len(keys) // 2]]
+    case = subset(case, [0, 4, 7, 1, 5, 8, 2, 6, 9, 3])
+    pk, flat = run_blocked(rot, case)
+    ref, _ = oracle_mod.rotate_blocked(case)
+    check(case, pk, flat, ref, range(len(case.shifts)))
+
+
+def test_blocked_stacked_path_skips_unrequested_blocks(rot, oracle_mod, monkeypatch):
+    """Output blocks not requested (out_off = -1) for some operators: the
+    stacked path computes the others exactly as the oracle and writes nothing
+    into the memory the dropped blocks would have used."""
+    monkeypatch.setenv("ROT_BLOCKED_PATH", "stacked")
+    sizes = workloads.gaussian_sector_sizes(600, sigma=1.2, min_dim=3, max_dim=70)
+    kept = [(qn, max(1, s - 4)) for qn, s in sizes]
+    case = workloads.blocked_case(sizes=sizes, kept_sizes=kept, n_conserving=3, n_up_shift=3, n_dn_shift=2,
+                                  cfg=91)
+    pk = workloads.pack_blocked(case)
+    n_new = len(case.new)
+    out_off = pk.out_off.copy()
+    dropped = []
+    for b in range(len(case.shifts)):
+        for k in range(n_new):
+            if out_off[b * n_new + k] >= 0 and (3 * b + k) % 5 == 0:
+                dropped.append((b, k, int(out_off[b * n_new + k])))
+                out_off[b * n_new + k] = -1
+    assert dropped
+    dev = torch.device("cuda")
+    U_blk = torch.from_numpy(pk.U_blk).float().to(dev)
+    O_blk = torch.from_numpy(pk.O_blk).float().to(dev)
+    out_blk = torch.full((pk.out_size,), float("nan"), device=dev)
+    rot.rotate_blocked(pk.site_qn, pk.old, pk.new, pk.shift, U_blk, pk.U_off, O_blk, pk.O_off, out_off, out_blk)
+    torch.cuda.synchronize()
+    flat = out_blk.double().cpu().numpy()
+    ref, _ = oracle_mod.rotate_blocked(case)
+    by_qn = {sec.qn: sec for sec in case.new}
+    worst = 0.0
+    for b in range(len(case.shifts)):
+        num = den = 0.0
+        for k, sec in enumerate(case.new):
+            off = out_off[b * n_new + k]
+            if off < 0:
+                continue
+            t = by_qn[(sec.qn[0] + case.shifts[b][0], sec.qn[1] + case.shifts[b][1])]
+            got = flat[off:off + t.dim * sec.dim].reshape(t.dim, sec.dim)
+            num += np.sum((got - ref[b][k]) ** 2)
+            den += np.sum(ref[b][k] ** 2)
+        if den > 0:
+            worst = max(worst, np.sqrt(num / den))
+    assert worst <= TOL32, worst
+    for b, k, off in dropped:
+        t = by_qn[(case.new[k].qn[0] + case.shifts[b][0], case.new[k].qn[1] + case.shifts[b][1])]
+        assert np.isnan(flat[off:off + t.dim * case.new[k].dim]).all(), (b, k)
