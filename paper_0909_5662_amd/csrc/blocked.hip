@@ -449,29 +449,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void b
 // Operators with the same shift Delta share every block of U, so each
 // stage's small products over all of them form one GEMM per sector
 // combination, with the operators stacked along N:
-//   stage 1, per (Q, s, Delta):
-//     Xt_b[beta][row of s in T] = sum_k U_Q[s rows][k][beta] O_b(q_s+Delta <- q_s)[i][k]
-//   stage 2, per (Q, Delta):
-//     out_b(T <- Q)[alpha][beta] = sum_r U_T[r][alpha] Xt_b[beta][r]
+//   stage 1, per (Delta, source sector q), for each site state s with
+//   Q = q + qn(s):
+//     Xt_b(Q)[beta][r_s + i] = sum_k U_Q[s rows][k][beta] O_b(q+Delta <- q)[i][k]
+//   stage 2, per (Delta, Q), T = Q + Delta:
+//     out_b(T <- Q)[alpha][beta] = sum_r U_T[r][alpha] Xt_b(Q)[beta][r]
 // Both are C[m][n] = sum_k A[m][k] B[n][k]: A is a row of the transposed-U
 // area shared by the group, B and C rows belong to operator j = n / nb.  The
 // 16-wide instruction tiles then pad only one extent per stage (M, a kept
-// sector dimension) instead of all three, and each wave runs a whole k loop
-// with 20 instructions per 16 k.  Xt_b (mQ rows of the padded row count of
-// U^T_T) lives in the workspace; its padding columns are written as zeros.
+// sector dimension) instead of all three.  Xt_b(Q) (m'_Q rows over the padded
+// rows r of U^T_T) lives in the workspace stored segment by segment: site
+// state s's columns [r_s, r_s + a4) form an m'_Q x a4 row-major block, so a
+// stage-1 tile writes whole cache lines; padding columns are written as zeros.
 struct StkGroup {
     int M, N, K;    // C is M x N, contraction length K
     int nb;         // columns per operator: n = j nb + i
     int nvalid;     // B rows with i >= nvalid are zero
     int lda, ldb;   // A row stride; B row stride inside an operator block
-    int ldcm;       // C stride per row m
+    int ldcm;       // C stride per row m (stage 2: m'_Q; streamed stage 1: the segment width)
     int64_t a_off;  // A row 0 in the transposed-U area
     int64_t tab;    // first entry of the group in the per-operator tables
+    // stage 2 reads Xt blocks stored segment by segment: k in [seg[s],
+    // seg[s + 1]) is column k - seg[s] of an nb x (seg[s + 1] - seg[s])
+    // row-major block at nb * seg[s]; unused entries hold kSegEnd
+    int seg[5];
+    int pad;
 };
 struct StkTile {
     int group, m0, n0, pad;
 };
 constexpr int kStkMB = 5;  // 16-row blocks per wave tile (80 rows)
+constexpr int kSegEnd = 1 << 30;
 constexpr int kStkNB = 4;  // 16-column blocks per wave tile (64 columns)
 
 // One wave per tile part (a 16 NB-column share of a 64-column tile), four
@@ -479,7 +487,7 @@ constexpr int kStkNB = 4;  // 16-column blocks per wave tile (64 columns)
 // absent, zero rows), coff[tab + j] its C block (-1: not written).  PF: 16-wide k steps whose
 // loads are in flight while a step multiplies.  BVEC: B rows are 16-byte
 // aligned (stage 2); otherwise only 4-byte aligned.
-template <int NB, int PF, bool BVEC>
+template <int NB, int PF, bool BVEC, bool SEG>
 __global__ __launch_bounds__(256) void blocked_stacked_kernel(const StkTile* __restrict__ tiles, int n_tiles,
                                                               const StkGroup* __restrict__ groups,
                                                               const int64_t* __restrict__ boff,
@@ -512,15 +520,17 @@ __global__ __launch_bounds__(256) void blocked_stacked_kernel(const StkTile* __r
     const float* brow[NB];
     float* crow[NB];
     bool bok[NB], cok[NB];
+    int brw[NB];  // SEG: this lane's row of the operator's Xt block
 #pragma unroll
     for (int nb = 0; nb < NB; nb++) {
         const int n = n0 + nb * 16 + li;
         cok[nb] = n < g.N;
         const int j = cok[nb] ? n / g.nb : 0;
         const int i = n - j * g.nb;
+        brw[nb] = i;
         const int64_t bo = cok[nb] ? boff[g.tab + j] : -1;
         bok[nb] = cok[nb] && i < g.nvalid && bo >= 0;
-        brow[nb] = B + (bok[nb] ? bo + (int64_t)i * g.ldb : 0);
+        brow[nb] = B + (bok[nb] ? bo + (SEG ? 0 : (int64_t)i * g.ldb) : 0);
         const int64_t co = cok[nb] ? coff[g.tab + j] : -1;
         cok[nb] = co >= 0;  // no output block: nothing to write
         crow[nb] = C + (cok[nb] ? co + i : 0);
@@ -539,10 +549,23 @@ __global__ __launch_bounds__(256) void blocked_stacked_kernel(const StkTile* __r
 #pragma unroll
         for (int mb = 0; mb < MB; mb++)
             if (mb < nbm) o.a[mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+        if (SEG) {
+            // the segment holding k = kk .. kk + 3 (segments are multiples of 4 wide)
+            const int sg = (kk >= g.seg[1]) + (kk >= g.seg[2]) + (kk >= g.seg[3]);
+            const int p0 = sg == 0 ? 0 : sg == 1 ? g.seg[1] : sg == 2 ? g.seg[2] : g.seg[3];
+            const int p1 = sg == 0 ? g.seg[1] : sg == 1 ? g.seg[2] : sg == 2 ? g.seg[3] : g.seg[4];
+            const int64_t off = (int64_t)g.nb * p0 - p0;
 #pragma unroll
-        for (int nb = 0; nb < NB; nb++)
-            if (nb < nbn) o.b[nb] = quad_or_zero<BVEC>(brow[nb], kk, bok[nb] && kk + 4 <= K, A);
-        if ((K & 3) != 0 && s == nks - 1 && kk < K && kk + 4 > K) {
+            for (int nb = 0; nb < NB; nb++)
+                if (nb < nbn)
+                    o.b[nb] = quad_or_zero<BVEC>(brow[nb] + off + (int64_t)brw[nb] * (p1 - p0), kk,
+                                                 bok[nb] && kk < K, A);
+        } else {
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++)
+                if (nb < nbn) o.b[nb] = quad_or_zero<BVEC>(brow[nb], kk, bok[nb] && kk + 4 <= K, A);
+        }
+        if (!SEG && (K & 3) != 0 && s == nks - 1 && kk < K && kk + 4 > K) {
 #pragma unroll
             for (int nb = 0; nb < NB; nb++)
                 if (nb < nbn && bok[nb]) {
@@ -595,117 +618,269 @@ __global__ __launch_bounds__(256) void blocked_stacked_kernel(const StkTile* __r
             }
 }
 
-// Stage 1 with the operator rows resident in registers (stage-1 K <= 80):
-// one group per (shift, source sector q) stacks the operators' blocks
-// O(q + Delta <- q) along N, and each wave keeps its 16 NB columns of them
-// for every k while it multiplies them by every member: the U^T_Q rows of
-// each site state s whose kept sector Q = q + qn(s) has output blocks (row
-// tiles of at most 80).  The operator rows are fetched once per wave instead
-// of once per site state, and the U^T values (L2-resident) one k step ahead.
+// Stage 1 for source sectors of at most 80 states: one group per (shift,
+// source sector q) stacks the operators' blocks O(q + Delta <- q) along N;
+// its members are the U^T_Q rows of each site state s whose kept sector
+// Q = q + qn(s) has output blocks (row tiles of at most 80).  One workgroup
+// takes 64 stacked columns and up to four members: the 64 operator rows
+// (every k) are staged once in LDS and shared by its eight waves, two per
+// member on 32 columns each, which multiply them by the member's U^T rows
+// (fetched one k step ahead) and store their tiles as their last memory
+// operation.  Each member tile writes one Xt segment (m'_Q x a4 row-major,
+// a4 the source block's row count rounded up to 4) as a dense block.
 struct StkMember {
     int M;          // rows of this member tile (<= 80)
-    int lda, ldcm;  // A row stride; C stride per row (padded row count of U^T_T)
+    int lda, ldcm;  // A row stride; C stride per row (the segment width a4)
     int pad;
     int64_t a_off;  // A row 0 in the transposed-U area
     int64_t tab;    // per-operator C offsets into Xt (-1: operator has no output block)
 };
 struct StkGroupR {
     int N, K, nb, nvalid;  // C columns, contraction length, columns per operator, non-zero rows of each
-    int mem0, n_mem;       // members
-    int64_t tab;           // per-operator B offsets into O_blk (-1: block absent)
+    int pad0, pad1;
+    int64_t tab;  // per-operator B offsets into O_blk (-1: block absent)
 };
-constexpr int kStkResK = 5;  // 16-wide k steps held per lane (K <= 80)
+constexpr int kStkResK = 5;  // 16-wide k steps staged (K <= 80)
 
-template <int NB>
-__global__ __launch_bounds__(256) void blocked_stacked_res_kernel(const StkTile* __restrict__ tiles, int n_tiles,
-                                                                  const StkGroupR* __restrict__ groups,
-                                                                  const StkMember* __restrict__ members,
+// tiles[blockIdx.x] = {group, first member, first stacked column, members};
+// eight waves: two per member, each on 32 of the columns.
+__global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile* __restrict__ tiles,
+                                                                        const StkGroupR* __restrict__ groups,
+                                                                        const StkMember* __restrict__ members,
+                                                                        const int64_t* __restrict__ boff,
+                                                                        const int64_t* __restrict__ coff,
+                                                                        const float* __restrict__ A,
+                                                                        const float* __restrict__ B,
+                                                                        float* __restrict__ C) {
+    constexpr int WPM = 2;  // waves per member
+    constexpr int MB = kStkMB, NB = kStkNB / WPM, KS = kStkResK, ROWS = 16 * kStkNB, NT = 256 * WPM;
+    __shared__ f32x4 bs[4 * KS][ROWS];  // operator rows: [k quad][stacked column], 20 KiB
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int li = lane & 15, lh = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = w / WPM;                 // member of this wave
+    const int c0 = (w % WPM) * 16 * NB;     // its first column in the tile
+    const StkTile tl = tiles[blockIdx.x];
+    const StkGroupR g = groups[tl.group];
+    const int K = g.K;
+    const int nks = (K + 15) >> 4;
+    const int n0 = tl.n0 + c0;
+    const int nbn = max(0, min(NB, (g.N - n0 + 15) >> 4));
+    // this wave's member: its U^T rows, output rows, first k step
+    const bool active = wm < tl.pad && nbn > 0;
+    StkMember mem{};
+    if (active) mem = members[tl.m0 + wm];
+    const int nbm = min(MB, (mem.M + 15) >> 4);
+    const float* arow[MB];
+    bool aok[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++) {
+        const int m = mb * 16 + li;
+        aok[mb] = active && m < mem.M;
+        arow[mb] = A + mem.a_off + (int64_t)(aok[mb] ? m : 0) * mem.lda;
+    }
+    f32x4 a[MB], an[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+        if (mb < nbm) a[mb] = quad_or_zero<true>(arow[mb], 4 * lh, aok[mb] && 4 * lh < K, A);
+    float* crow[NB];
+    bool wok[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+        const int n = n0 + nb * 16 + li;
+        const bool ok = active && n < g.N;
+        const int j = ok ? n / g.nb : 0;
+        const int64_t co = ok ? coff[mem.tab + j] : -1;
+        wok[nb] = co >= 0;
+        crow[nb] = C + (wok[nb] ? co + (n - j * g.nb) : 0);
+    }
+    // stage the operator rows: thread tid owns stacked column tid % 64 and
+    // k quads tid / 64 + (NT / 64) i (zero past K; a quad crossing K element
+    // by element)
+    {
+        const int r = tid & (ROWS - 1);
+        const int n = tl.n0 + r;
+        const bool ok = n < g.N;
+        const int j = ok ? n / g.nb : 0;
+        const int i = n - j * g.nb;
+        const int64_t bo = ok ? boff[g.tab + j] : -1;
+        const bool bok = ok && i < g.nvalid && bo >= 0;
+        const float* brow = B + (bok ? bo + (int64_t)i * K : 0);
+#pragma unroll
+        for (int x = 0; x < (4 * KS * ROWS + NT - 1) / NT; x++) {
+            const int kq = w + (NT / 64) * x;
+            if (kq < 4 * nks) {
+                const int kk = 4 * kq;
+                f32x4 v = quad_or_zero<false>(brow, kk, bok && kk + 4 <= K, A);
+                if ((K & 3) != 0 && bok && kk < K && kk + 4 > K) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) v[q] = kk + q < K ? brow[kk + q] : 0.f;
+                }
+                bs[kq][r] = v;
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+        if (s < nks) {
+            if (s + 1 < nks) {
+#pragma unroll
+                for (int mb = 0; mb < MB; mb++)
+                    if (mb < nbm) {
+                        const int kk = 16 * (s + 1) + 4 * lh;
+                        an[mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+                    }
+            }
+            // lane group lh takes k = 16 s + 4 lh + q at instruction q
+            f32x4 bf[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; nb++)
+                if (nb < nbn) bf[nb] = bs[4 * s + lh][c0 + nb * 16 + li];
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+                    for (int nb = 0; nb < NB; nb++)
+                        if (mb < nbm && nb < nbn)
+                            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][q], bf[nb][q], acc[mb][nb], 0, 0, 0);
+            if (s + 1 < nks) {
+#pragma unroll
+                for (int mb = 0; mb < MB; mb++) a[mb] = an[mb];
+            }
+        }
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++)
+            if (mb < nbm && nb < nbn && wok[nb]) {
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int m = mb * 16 + 4 * lh + v;
+                    if (m < mem.M) crow[nb][(int64_t)m * mem.ldcm] = acc[mb][nb][v];
+                }
+            }
+}
+
+// Stage 2 with U^T_T staged in LDS: one workgroup per (group, 80-row tile,
+// 128 stacked columns), four waves of 32 columns.  Each 16-wide k step of the
+// 80 A rows is fetched once for the four waves into one of two LDS buffers
+// while the other is multiplied; the waves' own B rows (Xt, read segment by
+// segment) stream through registers two k steps ahead.
+constexpr int kStk2Cols = 128;  // stacked columns per workgroup
+__global__ __launch_bounds__(256) void blocked_stacked2_wg_kernel(const StkTile* __restrict__ tiles,
+                                                                  const StkGroup* __restrict__ groups,
                                                                   const int64_t* __restrict__ boff,
                                                                   const int64_t* __restrict__ coff,
                                                                   const float* __restrict__ A,
                                                                   const float* __restrict__ B, float* __restrict__ C) {
-    constexpr int MB = kStkMB, KS = kStkResK;
-    constexpr int PARTS = kStkNB / NB;
-    const int lane = threadIdx.x & 63;
+    constexpr int MB = kStkMB, NB = 2, PF = 2, AR = 16 * kStkMB;
+    __shared__ f32x4 as[2][4][AR];  // [buffer][k quad][row], 10 KiB
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int li = lane & 15, lh = lane >> 4;
-    const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int t = w / PARTS;
-    if (t >= n_tiles) return;
-    const StkTile tl = tiles[t];
-    const StkGroupR g = groups[tl.group];
-    const int n0 = tl.n0 + (w % PARTS) * 16 * NB;
-    if (n0 >= g.N) return;
-    const int nbn = min(NB, (g.N - n0 + 15) >> 4);
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const StkTile tl = tiles[blockIdx.x];
+    const StkGroup g = groups[tl.group];
     const int K = g.K;
     const int nks = (K + 15) >> 4;
-    // this lane's operator row in each column block, every k step (quads as
-    // in blocked_stacked_kernel: the one crossing K element by element)
-    int jn[NB], in_[NB];
-    bool cok[NB];
-    f32x4 b[KS][NB];
+    const int nbm = min(MB, (g.M - tl.m0 + 15) >> 4);
+    const int n0 = tl.n0 + w * 16 * NB;
+    const int nbn = max(0, min(NB, (g.N - n0 + 15) >> 4));
+    // A staging: thread tid carries quads tid and tid + 256 of the 4 x 80 of a step
+    const float* ar[2];
+    bool aok[2], aq[2];
+    int akq[2], arw[2];
+#pragma unroll
+    for (int x = 0; x < 2; x++) {
+        const int q = tid + 256 * x;
+        aq[x] = q < 4 * AR;
+        arw[x] = q % AR;
+        akq[x] = q / AR;
+        const int m = tl.m0 + arw[x];
+        aok[x] = aq[x] && m < g.M;
+        ar[x] = A + g.a_off + (int64_t)(aok[x] ? m : 0) * g.lda;
+    }
+    auto stage_load = [&](int s, f32x4* v) __attribute__((always_inline)) {
+#pragma unroll
+        for (int x = 0; x < 2; x++) {
+            const int kk = 16 * s + 4 * akq[x];
+            v[x] = quad_or_zero<true>(ar[x], kk, aok[x] && kk < K, A);
+        }
+    };
+    auto stage_store = [&](int buf, const f32x4* v) __attribute__((always_inline)) {
+#pragma unroll
+        for (int x = 0; x < 2; x++)
+            if (aq[x]) as[buf][akq[x]][arw[x]] = v[x];
+    };
+    // this wave's B rows: row brw of operator j's Xt block
+    const float* brow[NB];
+    float* crow[NB];
+    bool bok[NB], cok[NB];
+    int brw[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; nb++) {
         const int n = n0 + nb * 16 + li;
-        cok[nb] = n < g.N;
-        jn[nb] = cok[nb] ? n / g.nb : 0;
-        in_[nb] = n - jn[nb] * g.nb;
-        const int64_t bo = cok[nb] ? boff[g.tab + jn[nb]] : -1;
-        const bool bok = cok[nb] && in_[nb] < g.nvalid && bo >= 0;
-        const float* brow = B + (bok ? bo + (int64_t)in_[nb] * K : 0);
-#pragma unroll
-        for (int s = 0; s < KS; s++) {
-            const int kk = 16 * s + 4 * lh;
-            if (s < nks && nb < nbn) b[s][nb] = quad_or_zero<false>(brow, kk, bok && kk + 4 <= K, A);
-        }
-        const int kt = 16 * (nks - 1) + 4 * lh;
-        if ((K & 3) != 0 && bok && nb < nbn && kt < K && kt + 4 > K) {
-#pragma unroll
-            for (int s = 0; s < KS; s++)
-                if (s == nks - 1) {
-#pragma unroll
-                    for (int q = 0; q < 4; q++) b[s][nb][q] = kt + q < K ? brow[kt + q] : 0.f;
-                }
-        }
+        const bool ok = n < g.N;
+        const int j = ok ? n / g.nb : 0;
+        brw[nb] = n - j * g.nb;
+        const int64_t bo = ok ? boff[g.tab + j] : -1;
+        bok[nb] = ok && brw[nb] < g.nvalid && bo >= 0;
+        brow[nb] = B + (bok[nb] ? bo : 0);
+        const int64_t co = ok ? coff[g.tab + j] : -1;
+        cok[nb] = co >= 0;
+        crow[nb] = C + (cok[nb] ? co + brw[nb] : 0);
     }
-    for (int mi = 0; mi < g.n_mem; mi++) {
-        const StkMember mem = members[g.mem0 + mi];
-        const int nbm = min(MB, (mem.M + 15) >> 4);
-        const float* arow[MB];
-        bool aok[MB];
+    struct Ops {
+        f32x4 b[NB];
+    };
+    auto fetch = [&](Ops& o, int s) __attribute__((always_inline)) {
+        const int kk = 16 * s + 4 * lh;
+        const int sg = (kk >= g.seg[1]) + (kk >= g.seg[2]) + (kk >= g.seg[3]);
+        const int p0 = sg == 0 ? 0 : sg == 1 ? g.seg[1] : sg == 2 ? g.seg[2] : g.seg[3];
+        const int p1 = sg == 0 ? g.seg[1] : sg == 1 ? g.seg[2] : sg == 2 ? g.seg[3] : g.seg[4];
+        const int64_t off = (int64_t)g.nb * p0 - p0;
 #pragma unroll
-        for (int mb = 0; mb < MB; mb++) {
-            const int m = mb * 16 + li;
-            aok[mb] = m < mem.M;
-            arow[mb] = A + mem.a_off + (int64_t)(aok[mb] ? m : 0) * mem.lda;
-        }
-        float* crow[NB];
-        bool wok[NB];
+        for (int nb = 0; nb < NB; nb++)
+            if (nb < nbn)
+                o.b[nb] = quad_or_zero<true>(brow[nb] + off + (int64_t)brw[nb] * (p1 - p0), kk, bok[nb] && kk < K, A);
+    };
+    f32x4 acc[MB][NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; nb++) {
-            const int64_t co = cok[nb] ? coff[mem.tab + jn[nb]] : -1;
-            wok[nb] = co >= 0;
-            crow[nb] = C + (wok[nb] ? co + in_[nb] : 0);
-        }
-        f32x4 acc[MB][NB];
+    for (int mb = 0; mb < MB; mb++)
 #pragma unroll
-        for (int mb = 0; mb < MB; mb++)
+        for (int nb = 0; nb < NB; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    Ops o[PF + 1];
+    if (nks > 0) {
+        f32x4 v[2];
+        stage_load(0, v);
+        stage_store(0, v);
+    }
 #pragma unroll
-            for (int nb = 0; nb < NB; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        f32x4 a[MB], an[MB];
+    for (int s = 0; s < PF; s++)
+        if (s < nks) fetch(o[s], s);
+    __syncthreads();
+    for (int s0 = 0; s0 < nks; s0 += PF + 1) {
 #pragma unroll
-        for (int mb = 0; mb < MB; mb++)
-            if (mb < nbm && nks > 0) a[mb] = quad_or_zero<true>(arow[mb], 4 * lh, aok[mb] && 4 * lh < K, A);
-#pragma unroll
-        for (int s = 0; s < KS; s++) {
+        for (int r = 0; r <= PF; r++) {
+            const int s = s0 + r;
             if (s < nks) {
-                if (s + 1 < nks) {
+                f32x4 vn[2];
+                if (s + 1 < nks) stage_load(s + 1, vn);
+                if (s + PF < nks) fetch(o[(r + PF) % (PF + 1)], s + PF);
+                f32x4 af[MB];
 #pragma unroll
-                    for (int mb = 0; mb < MB; mb++)
-                        if (mb < nbm) {
-                            const int kk = 16 * (s + 1) + 4 * lh;
-                            an[mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
-                        }
-                }
+                for (int mb = 0; mb < MB; mb++)
+                    if (mb < nbm) af[mb] = as[s & 1][lh][mb * 16 + li];
 #pragma unroll
                 for (int q = 0; q < 4; q++)
 #pragma unroll
@@ -713,26 +888,24 @@ __global__ __launch_bounds__(256) void blocked_stacked_res_kernel(const StkTile*
 #pragma unroll
                         for (int nb = 0; nb < NB; nb++)
                             if (mb < nbm && nb < nbn)
-                                acc[mb][nb] =
-                                    __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][q], b[s][nb][q], acc[mb][nb], 0, 0, 0);
-                if (s + 1 < nks) {
-#pragma unroll
-                    for (int mb = 0; mb < MB; mb++) a[mb] = an[mb];
-                }
+                                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][q], o[r].b[nb][q],
+                                                                                   acc[mb][nb], 0, 0, 0);
+                if (s + 1 < nks) stage_store((s + 1) & 1, vn);
+                __syncthreads();
             }
         }
-#pragma unroll
-        for (int mb = 0; mb < MB; mb++)
-#pragma unroll
-            for (int nb = 0; nb < NB; nb++)
-                if (mb < nbm && nb < nbn && wok[nb]) {
-#pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        const int m = mb * 16 + 4 * lh + v;
-                        if (m < mem.M) crow[nb][(int64_t)m * mem.ldcm] = acc[mb][nb][v];
-                    }
-                }
     }
+#pragma unroll
+    for (int mb = 0; mb < MB; mb++)
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++)
+            if (mb < nbm && nb < nbn && cok[nb]) {
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int m = tl.m0 + mb * 16 + 4 * lh + v;
+                    if (m < g.M) crow[nb][(int64_t)m * g.ldcm] = acc[mb][nb][v];
+                }
+            }
 }
 
 __global__ void reset_fused_counter(int* counter) {
@@ -867,12 +1040,13 @@ void build_fused(const rot_blocked_problem* p, const Structure& st, const UtLayo
 // Work-lists of the stacked path.  Xt offsets are relative to the workspace.
 struct StackedLists {
     std::vector<StkGroup> g1, g2;      // streamed stage-1 groups (K > 80, or K = 0: zero rows); stage 2
-    std::vector<StkTile> t1, t2;
+    std::vector<StkTile> t1, t2, t2w;  // t2w: stage-2 workgroup tiles (128 columns)
     std::vector<StkGroupR> gr;         // stage 1 with resident operator rows
     std::vector<StkMember> mem;
     std::vector<StkTile> tr;
     std::vector<int64_t> boff, coff;
     int64_t x_elems = 0;
+    bool ok = true;  // false: some kept sector has more than 4 site-state segments
 };
 
 void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLayout& ut, StackedLists* S) {
@@ -884,7 +1058,7 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
     // Xt block of (operator b, kept sector k): mQ rows of the padded row count
     // of U^T_T, allocated per (shift, kept sector) group, operators in order
     std::vector<int64_t> xbase((size_t)p->n_ops * p->n_new, -1);
-    std::vector<std::pair<int, StkTile>> o1, o2;  // (work, tile): longest first
+    std::vector<std::pair<int, StkTile>> o1, o2, o2w, o_r;  // (work, tile): longest first
     for (int si = 0; si < (int)shifts.size(); si++) {
         const int du = shifts[si].first, dd = shifts[si].second;
         std::vector<int> ops;  // every operator of this shift
@@ -913,6 +1087,19 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
             g2.ldcm = Q.dim;
             g2.a_off = ut.off[kt];
             g2.tab = (int64_t)S->boff.size();
+            {
+                int ns = 0;
+                for (int s = 0; s < p->d; s++)
+                    if (st.rowstart[kt][s] >= 0) {
+                        if (ns == 4) {
+                            S->ok = false;
+                            break;
+                        }
+                        g2.seg[ns++] = ut.pstart[kt][s];
+                    }
+                g2.seg[ns] = ldT;
+                for (int x = ns + 1; x < 5; x++) g2.seg[x] = kSegEnd;
+            }
             for (int j = 0; j < n; j++) {
                 const int64_t x = S->x_elems;
                 S->x_elems += ((int64_t)Q.dim * ldT + 63) / 64 * 64;  // keep 256-byte alignment
@@ -922,8 +1109,10 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
             }
             const int gi2 = (int)S->g2.size();
             S->g2.push_back(g2);
-            for (int m0 = 0; m0 < g2.M; m0 += 16 * kStkMB)
+            for (int m0 = 0; m0 < g2.M; m0 += 16 * kStkMB) {
                 for (int n0 = 0; n0 < g2.N; n0 += 16 * kStkNB) o2.push_back({g2.K, StkTile{gi2, m0, n0, 0}});
+                for (int n0 = 0; n0 < g2.N; n0 += kStk2Cols) o2w.push_back({g2.K, StkTile{gi2, m0, n0, 0}});
+            }
             // Xt columns of site states whose source sector q_s = Q - qn(s) is
             // absent while q_s + Delta exists: zero (streamed groups with K = 0)
             for (int s = 0; s < p->d; s++) {
@@ -937,11 +1126,11 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                 g1.nb = (a + 3) / 4 * 4;
                 g1.nvalid = a;
                 g1.lda = g1.ldb = 1;
-                g1.ldcm = ldT;
+                g1.ldcm = g1.nb;  // Xt segment s: mQ x a4, row-major
                 g1.tab = (int64_t)S->boff.size();
                 for (int j = 0; j < n; j++) {
                     S->boff.push_back(-1);
-                    S->coff.push_back(xbase[(size_t)J[j] * p->n_new + k] + ut.pstart[kt][s]);
+                    S->coff.push_back(xbase[(size_t)J[j] * p->n_new + k] + (int64_t)Q.dim * ut.pstart[kt][s]);
                 }
                 const int gi1 = (int)S->g1.size();
                 S->g1.push_back(g1);
@@ -985,7 +1174,9 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                 for (int b : ops) {
                     const int64_t x = xbase[(size_t)b * p->n_new + mm.k];
                     S->boff.push_back(-1);
-                    S->coff.push_back(x < 0 ? -1 : x + (int64_t)m0 * ut.ld[mm.kt] + ut.pstart[mm.kt][mm.s]);
+                    // Xt segment s of (b, Q): mQ x a4 row-major at mQ times the segment's first padded row
+                    const int64_t seg0 = (int64_t)p->new_sec[mm.k].dim * ut.pstart[mm.kt][mm.s];
+                    S->coff.push_back(x < 0 ? -1 : x + seg0 + (int64_t)m0 * a4);
                 }
                 return tab;
             };
@@ -996,25 +1187,31 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                 g.nb = a4;
                 g.nvalid = a;
                 g.tab = btab;
-                g.mem0 = (int)S->mem.size();
-                int64_t work = 0;
+                const int mem0 = (int)S->mem.size();
                 for (const Mem& mm : ms) {
                     const rot_sector& Q = p->new_sec[mm.k];
                     for (int m0 = 0; m0 < Q.dim; m0 += 16 * kStkMB) {
                         StkMember e{};
                         e.M = std::min(16 * kStkMB, Q.dim - m0);
                         e.lda = ut.ld[mm.k];
-                        e.ldcm = ut.ld[mm.kt];
+                        e.ldcm = a4;
                         e.a_off = ut.off[mm.k] + (int64_t)m0 * ut.ld[mm.k] + ut.pstart[mm.k][mm.s];
                         e.tab = member_tab(mm, m0);
                         S->mem.push_back(e);
-                        work += (int64_t)((e.M + 15) / 16) * K;
                     }
                 }
-                g.n_mem = (int)S->mem.size() - g.mem0;
+                const int n_mem = (int)S->mem.size() - mem0;
                 const int gi = (int)S->gr.size();
                 S->gr.push_back(g);
-                for (int n0 = 0; n0 < g.N; n0 += 16 * kStkNB) S->tr.push_back(StkTile{gi, 0, n0, (int)work});
+                // workgroups of up to four members over 64 stacked columns
+                for (int c0 = 0; c0 < n_mem; c0 += 4) {
+                    const int cnt = std::min(4, n_mem - c0);
+                    int work = 0;
+                    for (int x = 0; x < cnt; x++) work = std::max(work, (S->mem[mem0 + c0 + x].M + 15) / 16);
+                    work *= (K + 15) / 16;
+                    for (int n0 = 0; n0 < g.N; n0 += 16 * kStkNB)
+                        o_r.push_back({work, StkTile{gi, mem0 + c0, n0, cnt}});
+                }
             } else {
                 // wide source sectors: one streamed group per site state
                 for (const Mem& mm : ms) {
@@ -1027,14 +1224,14 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                     g1.nvalid = a;
                     g1.lda = ut.ld[mm.k];
                     g1.ldb = K;
-                    g1.ldcm = ut.ld[mm.kt];
+                    g1.ldcm = a4;
                     g1.a_off = ut.off[mm.k] + ut.pstart[mm.k][mm.s];
                     // B offsets: the operator blocks; C offsets: Xt blocks + first padded row of s
                     g1.tab = (int64_t)S->boff.size();
                     for (int b : ops) {
                         const int64_t x = xbase[(size_t)b * p->n_new + mm.k];
                         S->boff.push_back(p->O_off[(int64_t)b * p->n_old + kq]);
-                        S->coff.push_back(x < 0 ? -1 : x + ut.pstart[mm.kt][mm.s]);
+                        S->coff.push_back(x < 0 ? -1 : x + (int64_t)Q.dim * ut.pstart[mm.kt][mm.s]);
                     }
                     const int gi1 = (int)S->g1.size();
                     S->g1.push_back(g1);
@@ -1048,8 +1245,10 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
     for (const auto& o : o1) S->t1.push_back(o.second);
     std::stable_sort(o2.begin(), o2.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
     for (const auto& o : o2) S->t2.push_back(o.second);
-    // resident tiles: most work first (the work estimate rides in the pad field)
-    std::stable_sort(S->tr.begin(), S->tr.end(), [](const StkTile& x, const StkTile& y) { return x.pad > y.pad; });
+    std::stable_sort(o2w.begin(), o2w.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& o : o2w) S->t2w.push_back(o.second);
+    std::stable_sort(o_r.begin(), o_r.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& o : o_r) S->tr.push_back(o.second);
 }
 
 struct Lists {
@@ -1157,7 +1356,10 @@ struct Plan {
     StkGroupR* k_gr = nullptr;
     StkMember* k_mem = nullptr;
     StkTile* k_tr = nullptr;
+    StkTile* k_t2w = nullptr;
+    int k_n2w = 0;
     int k_n1 = 0, k_n2 = 0, k_nr = 0;
+    bool k_ok = false;  // the stacked path applies
     // 0 grouped two-stage, 1 fused, 2 fused wide, 3/4 row-block operands
     // (narrow/wide), 5 stacked; -1 not chosen yet
     int path = -1;
@@ -1171,6 +1373,7 @@ struct Plan {
         (void)hipFree(k_gr);
         (void)hipFree(k_mem);
         (void)hipFree(k_tr);
+        (void)hipFree(k_t2w);
         (void)hipFree(s1.probs);
         (void)hipFree(s1.tiles);
         (void)hipFree(s2.probs);
@@ -1345,50 +1548,23 @@ hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, bool r
     });
 }
 
-// Stacked kernel variant: columns per wave (16 NB) and k steps in flight.
-// ROT_STK_CFG=NB,PF (e.g. "4,1") overrides the default 2,2.
-struct StkCfg {
-    int nb = 2, pf = 2;
-};
-StkCfg stacked_cfg() {
-    StkCfg c;
-    if (const char* e = getenv("ROT_STK_CFG")) {
-        int nb = 0, pf = 0;
-        const bool parsed = sscanf(e, "%d,%d", &nb, &pf) == 2;
-        const bool ok = (nb == 4 && (pf == 1 || pf == 2)) || (nb == 2 && pf >= 1 && pf <= 4) ||
-                        (nb == 1 && (pf == 2 || pf == 4));
-        if (parsed && ok) {
-            c.nb = nb;
-            c.pf = pf;
-        }
-    }
-    return c;
-}
-
-template <int NB, int PF, bool BVEC>
-void launch_stacked_v(int n, const StkTile* tiles, const StkGroup* groups, const Plan* plan, const float* A,
-                      const float* B, float* C, hipStream_t stream) {
-    const int waves = n * (kStkNB / NB);
-    hipLaunchKernelGGL((blocked_stacked_kernel<NB, PF, BVEC>), dim3((waves + 3) / 4), dim3(256), 0, stream, tiles, n,
-                       groups, plan->k_boff, plan->k_coff, A, B, C);
-}
-
+// The streamed kernel's launch: 32 columns per wave, two k steps in flight.
 template <bool BVEC>
-hipError_t launch_stacked(StkCfg c, const StkTile* tiles, int n, const StkGroup* groups, const Plan* plan,
-                          const float* A, const float* B, float* C, hipStream_t stream) {
-    if (c.nb == 4) {
-        if (c.pf == 1) launch_stacked_v<4, 1, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-        else launch_stacked_v<4, 2, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-    } else if (c.nb == 2) {
-        if (c.pf == 1) launch_stacked_v<2, 1, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-        else if (c.pf == 2) launch_stacked_v<2, 2, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-        else if (c.pf == 3) launch_stacked_v<2, 3, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-        else launch_stacked_v<2, 4, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-    } else {
-        if (c.pf == 2) launch_stacked_v<1, 2, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-        else launch_stacked_v<1, 4, BVEC>(n, tiles, groups, plan, A, B, C, stream);
-    }
+hipError_t launch_stacked(const StkTile* tiles, int n, const StkGroup* groups, const Plan* plan, const float* A,
+                          const float* B, float* C, hipStream_t stream) {
+    constexpr int NB = 2, PF = 2;
+    // stage 2 (aligned B) reads the segment-ordered Xt blocks
+    const int waves = n * (kStkNB / NB);
+    hipLaunchKernelGGL((blocked_stacked_kernel<NB, PF, BVEC, BVEC>), dim3((waves + 3) / 4), dim3(256), 0, stream,
+                       tiles, n, groups, plan->k_boff, plan->k_coff, A, B, C);
     return hipGetLastError();
+}
+
+// ROT_STK2=wave: stage 2 on the streamed kernel (one wave per tile, U^T_T
+// from L2) instead of the workgroup kernel; a measurement switch.
+bool stage2_per_wave() {
+    const char* e = getenv("ROT_STK2");
+    return e && strcmp(e, "wave") == 0;
 }
 
 // Transposed U blocks into the workspace, then the two stacked launches
@@ -1405,22 +1581,21 @@ hipError_t run_stacked(const rot_blocked_problem* p, Plan* plan, void* ws, hipSt
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    const StkCfg c = stacked_cfg();
     e = prof_timed("blocked_stacked1_fp32", stream, [&] {
-        if (plan->k_nr > 0) {
-            constexpr int NB = 2;
-            const int waves = plan->k_nr * (kStkNB / NB);
-            hipLaunchKernelGGL(blocked_stacked_res_kernel<NB>, dim3((waves + 3) / 4), dim3(256), 0, stream,
-                               plan->k_tr, plan->k_nr, plan->k_gr, plan->k_mem, plan->k_boff, plan->k_coff, ut,
-                               p->O_blk, xt);
-        }
+        if (plan->k_nr > 0)
+            hipLaunchKernelGGL(blocked_stacked_lds_kernel, dim3(plan->k_nr), dim3(512), 0, stream, plan->k_tr,
+                               plan->k_gr, plan->k_mem, plan->k_boff, plan->k_coff, ut, p->O_blk, xt);
         if (plan->k_n1 > 0)
-            return launch_stacked<false>(c, plan->k_t1, plan->k_n1, plan->k_g1, plan, ut, p->O_blk, xt, stream);
+            return launch_stacked<false>(plan->k_t1, plan->k_n1, plan->k_g1, plan, ut, p->O_blk, xt, stream);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
     return prof_timed("blocked_stacked2_fp32", stream, [&] {
-        return launch_stacked<true>(c, plan->k_t2, plan->k_n2, plan->k_g2, plan, ut, xt, p->out_blk, stream);
+        if (stage2_per_wave())
+            return launch_stacked<true>(plan->k_t2, plan->k_n2, plan->k_g2, plan, ut, xt, p->out_blk, stream);
+        hipLaunchKernelGGL(blocked_stacked2_wg_kernel, dim3(plan->k_n2w), dim3(256), 0, stream, plan->k_t2w,
+                           plan->k_g2, plan->k_boff, plan->k_coff, ut, xt, p->out_blk);
+        return hipGetLastError();
     });
 }
 
@@ -1504,6 +1679,8 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         np->k_n1 = (int)S.t1.size();
         np->k_n2 = (int)S.t2.size();
         np->k_nr = (int)S.tr.size();
+        np->k_n2w = (int)S.t2w.size();
+        np->k_ok = S.ok;
         auto up = [&](auto** dst, const auto& v) {
             if (e != hipSuccess || v.empty()) return;
             e = hipMalloc(dst, sizeof(v[0]) * v.size());
@@ -1518,6 +1695,7 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         up(&np->k_gr, S.gr);
         up(&np->k_mem, S.mem);
         up(&np->k_tr, S.tr);
+        up(&np->k_t2w, S.t2w);
         if (e != hipSuccess) return e;
         plan = g_plans.insert(std::move(sig), std::move(np));
     }
@@ -1532,16 +1710,17 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
             paths.push_back(4);
         }
     }
-    paths.push_back(5);
+    if (plan->k_ok) paths.push_back(5);
     if (capturing) {
         g_plans.pin(plan);
-        // no timing under capture: the stacked path (it applies to every structure)
-        if (plan->path < 0 && forced < 0) plan->path = 5;
+        // no timing under capture: the stacked path, or the grouped one
+        if (plan->path < 0 && forced < 0) plan->path = plan->k_ok ? 5 : 0;
     }
     int path = forced >= 0 ? forced : plan->path;
     if (path >= 0 && std::find(paths.begin(), paths.end(), path) == paths.end()) {
         // a forced path that does not apply: the closest one that does
-        path = (path == 3 || path == 4) && plan->f_max_mT <= 128 ? path - 2 : 5;
+        if ((path == 3 || path == 4) && plan->f_max_mT <= 128) path -= 2;
+        else path = plan->k_ok ? 5 : 0;
     }
     if (path < 0) {
         // time each applicable path (second run, after a warm-up run)
