@@ -356,3 +356,22 @@ def test_blocked_stacked_path_skips_unrequested_blocks(rot, oracle_mod, monkeypa
     for b, k, off in dropped:
         t = by_qn[(case.new[k].qn[0] + case.shifts[b][0], case.new[k].qn[1] + case.shifts[b][1])]
         assert np.isnan(flat[off:off + t.dim * case.new[k].dim]).all(), (b, k)
+
+
+@pytest.mark.parametrize("path", ["auto", "stacked"])
+@pytest.mark.parametrize("site", ["d3", "d6"])
+def test_blocked_other_site_dimensions(rot, oracle_mod, monkeypatch, path, site):
+    """Sites of 3 states and of 6 states (repeated quantum numbers, so a
+    kept sector has up to 6 site-state segments): the stacked path handles
+    at most 4 segments per kept sector and is then left out (forcing it falls
+    back to another path); results against the oracle either way."""
+    if path == "stacked":
+        monkeypatch.setenv("ROT_BLOCKED_PATH", "stacked")
+    site_qn = ((0, 0), (1, 0), (0, 1)) if site == "d3" else ((0, 0), (1, 0), (0, 1), (1, 1), (0, 0), (1, 1))
+    sizes = workloads.gaussian_sector_sizes(300, sigma=1.2, min_dim=3, max_dim=40)
+    kept = [(qn, max(1, s - 2)) for qn, s in sizes]
+    case = workloads.blocked_case(sizes=sizes, kept_sizes=kept, n_conserving=2, n_up_shift=2, n_dn_shift=1,
+                                  cfg=95, d_site_qn=site_qn)
+    pk, flat = run_blocked(rot, case)
+    ref, _ = oracle_mod.rotate_blocked(case)
+    check(case, pk, flat, ref, range(len(case.shifts)))
