@@ -18,6 +18,7 @@
 // tiles, and tiles sharing an operand panel stay on one XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include "lds_slice.h"
 #include "rot_internal.h"
 
 namespace rot {
@@ -31,96 +32,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kTile = kGemmTile;   // BM = BN
 constexpr int kSlice = 16;   // K elements per LDS slice
-constexpr int kPadMN = 4;    // row padding (elements) of M/N-contiguous LDS tiles
-
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { typedef f32x4 type; };
-template <> struct Vec16<double> { typedef f64x2 type; };
-
-// XCD-aware workgroup order: hardware places workgroup id w on XCD w % 8.
-__device__ inline int xcd_linear_id() {
-    const int nwg = gridDim.x, wg = blockIdx.x;
-    const int per = nwg / 8, rem = nwg % 8;
-    const int xcd = wg % 8, idx = wg / 8;
-    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
-
-// One operand slice of R rows (M or N extent) by kSlice k-columns, staged
-// through registers (16-byte chunks) into LDS.
-template <typename T, bool KCONTIG, bool VEC>
-struct Slice {
-    typedef typename Vec16<T>::type V;
-    static constexpr int VW = 16 / sizeof(T);
-    static constexpr int CHUNKS = kTile * kSlice / VW / kThreads;
-    // K-contiguous rows are kSlice elements unpadded: NQ 16-byte chunks (4
-    // for FP32, 8 for FP64), RPB = 16 / NQ rows per 256 bytes, chunk q of row
-    // r stored in slot q ^ ((r / RPB) % NQ).  The stores of 16 lanes (RPB
-    // rows x NQ chunks) and the fragment reads of 16 lanes (16 rows, one
-    // chunk) then each cover all 64 LDS banks once.  M/N-contiguous slices
-    // are padded rows.
-    static constexpr int NQ = kSlice / VW;
-    static constexpr int RPB = 16 / NQ;
-    static constexpr int PITCH = KCONTIG ? kSlice : (kTile + kPadMN);
-    static constexpr int ELEMS = KCONTIG ? kTile * PITCH : kSlice * PITCH;
-    V r[CHUNKS];
-
-    // element offset of 16-byte chunk q (k = q*VW ..) of row `row` in a
-    // K-contiguous slice
-    __device__ static inline int kc_off(int row, int q) { return row * PITCH + (q ^ ((row / RPB) % NQ)) * VW; }
-
-    // base points at element (row 0, k 0) of the operand; rows/ks are the
-    // operand's full extents; r0/k0 the slice origin.  A slice wholly inside
-    // the operand (uniform over the workgroup) takes unconditional vector
-    // loads, so they are all in flight together; edge slices load element by
-    // element with bounds checks.
-    __device__ inline void load(const T* __restrict__ base, int64_t ld, int r0, int rows, int k0,
-                                int ks, int tid) {
-        const bool interior = VEC && r0 + kTile <= rows && k0 + kSlice <= ks;
-        if (interior) {
-#pragma unroll
-            for (int c = 0; c < CHUNKS; c++) {
-                const int f = tid + c * kThreads;
-                const int row = KCONTIG ? f / (kSlice / VW) : (f % (kTile / VW)) * VW;
-                const int k = KCONTIG ? (f % (kSlice / VW)) * VW : f / (kTile / VW);
-                const T* p = KCONTIG ? base + (int64_t)(r0 + row) * ld + k0 + k : base + (int64_t)(k0 + k) * ld + r0 + row;
-                r[c] = *reinterpret_cast<const V*>(p);
-            }
-            return;
-        }
-#pragma unroll
-        for (int c = 0; c < CHUNKS; c++) {
-            const int f = tid + c * kThreads;
-            int row, k;
-            if (KCONTIG) {
-                row = f / (kSlice / VW);
-                k = (f % (kSlice / VW)) * VW;
-            } else {
-                k = f / (kTile / VW);
-                row = (f % (kTile / VW)) * VW;
-            }
-            const int gr = r0 + row, gk = k0 + k;
-            const T* p = KCONTIG ? base + (int64_t)gr * ld + gk : base + (int64_t)gk * ld + gr;
-#pragma unroll
-            for (int e = 0; e < VW; e++) {
-                const bool ok = KCONTIG ? (gr < rows && gk + e < ks) : (gk < ks && gr + e < rows);
-                r[c][e] = ok ? p[e] : T(0);
-            }
-        }
-    }
-    __device__ inline void store(T* lds, int tid) const {
-#pragma unroll
-        for (int c = 0; c < CHUNKS; c++) {
-            const int f = tid + c * kThreads;
-            int off;
-            if (KCONTIG) {
-                off = kc_off(f / (kSlice / VW), f % (kSlice / VW));
-            } else {
-                off = (f / (kTile / VW)) * PITCH + (f % (kTile / VW)) * VW;
-            }
-            *reinterpret_cast<V*>(lds + off) = r[c];
-        }
-    }
-};
+static_assert(kSlice == LdsSlice<float, kTile, kThreads, true>::SK, "slice depth");
 
 struct TileCoord {
     int g, m0, n0;
@@ -154,8 +66,8 @@ __device__ inline TileCoord tile_coord(int lin, int tiles_m, int tiles_n, bool u
 // l%32); accumulator element v of lane l is C(8*(v/4) + 4*(l/32) + v%4, l%32).
 template <bool AK, bool BK, bool VEC, bool ACC>
 __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tiles_m, int tiles_n) {
-    typedef Slice<float, AK, VEC> SA;
-    typedef Slice<float, BK, VEC> SB;
+    typedef LdsSlice<float, kTile, kThreads, AK> SA;
+    typedef LdsSlice<float, kTile, kThreads, BK> SB;
     __shared__ __attribute__((aligned(16))) float As[2][SA::ELEMS];
     __shared__ __attribute__((aligned(16))) float Bs[2][SB::ELEMS];
 
@@ -196,8 +108,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 
     auto fetch = [&](int t) {
         const int kb = t / nk, k0 = (t % nk) * kSlice;
-        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, K, tid);
-        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, K, tid);
+        la.template load<VEC>(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, K, true, tid);
+        lb.template load<VEC>(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, K, true, tid);
     };
 
     fetch(0);
@@ -317,8 +229,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 // l%16); accumulator element v of lane l is C(4*v + l/16, l%16).
 template <bool AK, bool BK, bool VEC, bool ACC>
 __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tiles_m, int tiles_n) {
-    typedef Slice<double, AK, VEC> SA;
-    typedef Slice<double, BK, VEC> SB;
+    typedef LdsSlice<double, kTile, kThreads, AK> SA;
+    typedef LdsSlice<double, kTile, kThreads, BK> SB;
     __shared__ __attribute__((aligned(16))) double As[2][SA::ELEMS];
     __shared__ __attribute__((aligned(16))) double Bs[2][SB::ELEMS];
 
@@ -359,8 +271,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmDesc g, int tile
 
     auto fetch = [&](int t) {
         const int kb = t / nk, k0 = (t % nk) * kSlice;
-        la.load(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, K, tid);
-        lb.load(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, K, tid);
+        la.template load<VEC>(Ab + (int64_t)kb * g.a_ks, g.lda, tc.m0, g.M, k0, K, true, tid);
+        lb.template load<VEC>(Bb + (int64_t)kb * g.b_ks, g.ldb, tc.n0, g.N, k0, K, true, tid);
     };
 
     fetch(0);

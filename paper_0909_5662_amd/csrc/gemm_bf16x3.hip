@@ -34,6 +34,7 @@
 #include <string>
 #include <vector>
 
+#include "lds_slice.h"
 #include "rot_internal.h"
 
 namespace rot {
@@ -59,12 +60,6 @@ __device__ inline u32x2 split2(float a, float b) {
     return u32x2{__builtin_bit_cast(uint32_t, h), __builtin_bit_cast(uint32_t, l)};
 }
 
-__device__ inline int xcd_linear_id() {
-    const int nwg = gridDim.x, wg = blockIdx.x;
-    const int per = nwg / 8, rem = nwg % 8;
-    const int xcd = wg % 8, idx = wg / 8;
-    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
 
 constexpr int kSlabK = 16;  // k per slab
 constexpr int kDefaultOrder = 0;  // tile order of gemm_bf16x3_kernel (see launch_tile)

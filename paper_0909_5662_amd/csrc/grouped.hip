@@ -15,6 +15,7 @@
 
 #include <algorithm>
 
+#include "lds_slice.h"
 #include "rot_internal.h"
 
 namespace rot {
@@ -23,72 +24,7 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kSlice = 16;
-constexpr int kPad = 4;
-
-// Operand slice of R rows x kSlice k, NT threads, runtime choice of 16-byte
-// vector loads (per problem: alignment of base and leading dimension).
-template <int R, int NT, bool KCONTIG>
-struct GSlice {
-    static constexpr int CHUNKS = R * kSlice / 4 / NT;
-    // K-contiguous rows are 16 floats (four 16-byte chunks) unpadded, chunk q
-    // of row r in slot q ^ ((r >> 2) & 3), so that 16 lanes storing 4 rows x
-    // 4 chunks, or reading one chunk of 16 rows, each cover all 64 LDS banks
-    // once; M/N-contiguous slices are padded rows.
-    static constexpr int PITCH = KCONTIG ? kSlice : (R + kPad);
-    static constexpr int ELEMS = KCONTIG ? R * PITCH : kSlice * PITCH;
-    static_assert(CHUNKS >= 1 && CHUNKS * NT * 4 == R * kSlice, "slice must split evenly over threads");
-    f32x4 r[CHUNKS];
-
-    // offset of chunk q (k = 4q .. 4q + 3) of row `row` in a K-contiguous slice
-    __device__ static inline int kc_off(int row, int q) { return row * PITCH + (q ^ ((row >> 2) & 3)) * 4; }
-
-    // A slice wholly inside the operand (uniform over the workgroup) takes
-    // unconditional vector loads; edge slices load element by element.
-    __device__ inline void load(const float* __restrict__ base, int64_t ld, int r0, int rows, int k0, int ks,
-                                bool vec, int tid) {
-        if (vec && r0 + R <= rows && k0 + kSlice <= ks) {
-#pragma unroll
-            for (int c = 0; c < CHUNKS; c++) {
-                const int f = tid + c * NT;
-                const int row = KCONTIG ? f / (kSlice / 4) : (f % (R / 4)) * 4;
-                const int k = KCONTIG ? (f % (kSlice / 4)) * 4 : f / (R / 4);
-                const float* p = KCONTIG ? base + (int64_t)(r0 + row) * ld + k0 + k
-                                         : base + (int64_t)(k0 + k) * ld + r0 + row;
-                r[c] = *reinterpret_cast<const f32x4*>(p);
-            }
-            return;
-        }
-#pragma unroll
-        for (int c = 0; c < CHUNKS; c++) {
-            const int f = tid + c * NT;
-            int row, k;
-            if (KCONTIG) {
-                row = f / (kSlice / 4);
-                k = (f % (kSlice / 4)) * 4;
-            } else {
-                k = f / (R / 4);
-                row = (f % (R / 4)) * 4;
-            }
-            const int gr = r0 + row, gk = k0 + k;
-            const float* p = KCONTIG ? base + (int64_t)gr * ld + gk : base + (int64_t)gk * ld + gr;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const bool ok = KCONTIG ? (gr < rows && gk + e < ks) : (gk < ks && gr + e < rows);
-                r[c][e] = ok ? p[e] : 0.f;
-            }
-        }
-    }
-    __device__ inline void store(float* lds, int tid) const {
-#pragma unroll
-        for (int c = 0; c < CHUNKS; c++) {
-            const int f = tid + c * NT;
-            const int off = KCONTIG ? kc_off(f / (kSlice / 4), f % (kSlice / 4))
-                                    : (f / (R / 4)) * PITCH + (f % (R / 4)) * 4;
-            *reinterpret_cast<f32x4*>(lds + off) = r[c];
-        }
-    }
-};
+constexpr int kSlice = 16;  // K elements per LDS slice (LdsSlice::SK)
 
 // BM x BN tile, WM x WN waves, each wave (BM/WM) x (BN/WN) made of 32 x 32
 // blocks of v_mfma_f32_32x32x2f32 (lane layout as in gemm.hip).
@@ -96,8 +32,8 @@ template <int BM, int BN, int WM, int WN, bool AK, bool BK, bool DYN>
 __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch L) {
     constexpr int NT = WM * WN * 64;
     constexpr int BI = BM / WM / 32, BJ = BN / WN / 32;
-    typedef GSlice<BM, NT, AK> SA;
-    typedef GSlice<BN, NT, BK> SB;
+    typedef LdsSlice<float, BM, NT, AK> SA;
+    typedef LdsSlice<float, BN, NT, BK> SB;
     __shared__ __attribute__((aligned(16))) float As[2][SA::ELEMS];
     __shared__ __attribute__((aligned(16))) float Bs[2][SB::ELEMS];
     __shared__ int s_next;
@@ -140,8 +76,8 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
                 for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
 
         if (nk > 0) {
-            la.load(Ab, p.lda, tile.m0, p.M, 0, p.K, vec, tid);
-            lb.load(Bb, p.ldb, tile.n0, p.N, 0, p.K, vec, tid);
+            la.template load<true>(Ab, p.lda, tile.m0, p.M, 0, p.K, vec, tid);
+            lb.template load<true>(Bb, p.ldb, tile.n0, p.N, 0, p.K, vec, tid);
             la.store(As[0], tid);
             lb.store(Bs[0], tid);
         }
@@ -149,8 +85,8 @@ __global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch 
         for (int kt = 0; kt < nk; kt++) {
             const int cur = kt & 1;
             if (kt + 1 < nk) {
-                la.load(Ab, p.lda, tile.m0, p.M, (kt + 1) * kSlice, p.K, vec, tid);
-                lb.load(Bb, p.ldb, tile.n0, p.N, (kt + 1) * kSlice, p.K, vec, tid);
+                la.template load<true>(Ab, p.lda, tile.m0, p.M, (kt + 1) * kSlice, p.K, vec, tid);
+                lb.template load<true>(Bb, p.ldb, tile.n0, p.N, (kt + 1) * kSlice, p.K, vec, tid);
             }
             const float* a_s = As[cur];
             const float* b_s = Bs[cur];
