@@ -27,9 +27,12 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kSlice = 16;  // K elements per LDS slice (LdsSlice::SK)
 
 // BM x BN tile, WM x WN waves, each wave (BM/WM) x (BN/WN) made of 32 x 32
-// blocks of v_mfma_f32_32x32x2f32 (lane layout as in gemm.hip).
+// blocks of v_mfma_f32_32x32x2f32 (lane layout as in gemm.hip).  Registers
+// are capped for at least 3 waves per SIMD (the persistent loop's problem
+// and tile state would otherwise take the 128 x 128 tile to 2).
 template <int BM, int BN, int WM, int WN, bool AK, bool BK, bool DYN>
-__global__ __launch_bounds__(WM* WN * 64) void grouped_f32_kernel(GroupedLaunch L) {
+__global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(3))) void grouped_f32_kernel(
+    GroupedLaunch L) {
     constexpr int NT = WM * WN * 64;
     constexpr int BI = BM / WM / 32, BJ = BN / WN / 32;
     typedef LdsSlice<float, BM, NT, AK> SA;

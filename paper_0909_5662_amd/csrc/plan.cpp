@@ -208,9 +208,11 @@ hipError_t tune_class(rot_plan_s* P, int ci, int n_cu) {
         bool dynamic;
         int grid_per_cu;  // 0: one workgroup per tile
     };
+    // 128 x 128 tiles run at up to 3 workgroups (12 waves) per CU, 64 x 64 at 7
     const Cand cands[] = {
         {GroupedShape::k128, false, 0}, {GroupedShape::k128, true, 2}, {GroupedShape::k128, false, 2},
-        {GroupedShape::k64, false, 0},  {GroupedShape::k64, true, 6},
+        {GroupedShape::k128, true, 3},  {GroupedShape::k128, false, 3}, {GroupedShape::k64, false, 0},
+        {GroupedShape::k64, true, 6},
     };
     hipEvent_t a, b;
     hipError_t e = hipEventCreate(&a);
