@@ -388,6 +388,195 @@ __global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_kernel(Bf16Desc
                                   !EPI_T && g.upper && m0 != n0, !EPI_T && g.upper && m0 == n0);
 }
 
+// Variant with the B fragments loaded straight from global memory into
+// registers: in the slab layout a fragment (32 rows x one 16-byte k half) is
+// 1 KB of contiguous bytes, one buffer load per array.  Only A goes through
+// the LDS ring (S stages of A_hi, A_lo), so LDS carries half the copy writes
+// and two thirds of the fragment reads of gemm_bf16x3_kernel.  The prologue
+// issues A slabs 0 .. S-2 and B slabs 0, 1; every step t then issues A slab
+// t + S - 1 (direct to LDS) and B slab t + 2 (to one of three register
+// sets), past the last slab too (those loads read beyond the operand and
+// return zeros, into stages and sets no longer used), so each wait counts a
+// known number of later loads (smaller in the first steps).  The A
+// fragments of slab t + 1 are read from LDS row block by row block, each
+// right after the products of slab t that used the same registers.  Per
+// accumulator the products come in the same order as in gemm_bf16x3_kernel,
+// so the two kernels give the same bits.
+template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T, bool D4>
+__global__ __launch_bounds__(64 * WGM * WGN, 1) void gemm_bf16x3_db_kernel(Bf16Desc g, int tiles_m, int tiles_n,
+                                                                            int order) {
+    constexpr int NW = WGM * WGN;
+    constexpr int T = 32 * WGM * BI;
+    static_assert(32 * WGN * BJ == T, "square tile");
+    constexpr int NBLK = T / 32;     // 1 KB blocks per array in a stage
+    static_assert(NBLK % NW == 0, "whole blocks per wave");
+    constexpr int BPW = NBLK / NW;   // blocks per wave per array
+    constexpr int ARR = T * kSlabK;  // elements of one array in a stage
+    constexpr int STAGE = 2 * ARR;   // A_hi, A_lo
+    constexpr int LA = 2 * BPW;      // direct loads per wave per step
+    constexpr int LB = 2 * BJ;       // B fragment loads per wave per step
+    static_assert(S >= 3, "ring depth");
+    // loads issued after the one waited for: slab 0's A before the first
+    // step; slab t + 1's A at step t (t < S - 3 in the prologue's order,
+    // otherwise one step's B and S - 3 whole steps); slab t's B at step t
+    constexpr int WAIT_A0 = (S - 2) * LA + 2 * LB;
+    constexpr int WAIT_A = (S - 3) * LA + (S - 2) * LB;
+    constexpr int WAIT_B = 2 * (LA + LB), WAIT_B0 = LA + 2 * LB;
+    static_assert(S >= 4 && S <= 6 && WAIT_A0 <= 63 && WAIT_A <= 63 && WAIT_B <= 63, "vmcnt range");
+    __shared__ __attribute__((aligned(1024))) uint16_t lds[S * STAGE];
+
+    const int lin = xcd_linear_id();
+    int bidx, m0, n0;
+    if (order > 0) {
+        const int cols = tiles_n * (int)(gridDim.x / (tiles_m * tiles_n));
+        const int per_group = order * cols;
+        const int grp = lin / per_group, first = grp * order;
+        const int gsize = min(tiles_m - first, order);
+        const int r = lin % per_group;
+        m0 = (first + r % gsize) * T;
+        const int col = r / gsize;
+        bidx = col / tiles_n;
+        n0 = (col % tiles_n) * T;
+    } else {
+        const int per_batch = tiles_m * tiles_n;
+        bidx = lin / per_batch;
+        const int rr = lin % per_batch;
+        m0 = (order < 0 ? rr / tiles_n : rr % tiles_m) * T;
+        n0 = (order < 0 ? rr % tiles_n : rr / tiles_m) * T;
+    }
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int h = lane >> 5, c = lane & 31;
+
+    const __amdgpu_buffer_rsrc_t ra[2] = {operand_rsrc(g.a_hi + (int64_t)bidx * g.a_bs, g.M, g.K),
+                                          operand_rsrc(g.a_lo + (int64_t)bidx * g.a_bs, g.M, g.K)};
+    const __amdgpu_buffer_rsrc_t rb[2] = {operand_rsrc(g.b_hi + (int64_t)bidx * g.b_bs, g.N, g.K),
+                                          operand_rsrc(g.b_lo + (int64_t)bidx * g.b_bs, g.N, g.K)};
+    const uint32_t a_off = (uint32_t)((m0 + wave * 32) * kSlabK * 2 + lane * 16);
+    const uint32_t a_slab = (uint32_t)g.M * kSlabK * 2, b_slab = (uint32_t)g.N * kSlabK * 2;
+    const int nk = (int)n_slabs(g.K);
+    // fragment slot of this lane: rows c (+ multiples of 32) and k half h
+    const int fslot = (h ^ ((c >> 3) & 1)) * 8;
+    // byte offset of this lane's B fragment of block j in slab 0
+    const uint32_t b_off = (uint32_t)(((n0 + wn * 32 * BJ + c) * kSlabK + fslot) * 2);
+
+    auto issue_a = [&](int st) __attribute__((always_inline)) {
+        uint16_t* base = lds + (st % S) * STAGE + wave * 512;
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int x = 0; x < BPW; x++)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    ra[j], (__attribute__((address_space(3))) void*)(base + j * ARR + x * NW * 512), 16,
+                    a_off + (uint32_t)st * a_slab + (uint32_t)(x * NW * 1024), 0, 0, 0);
+    };
+    struct BSet {
+        bf16x8 bh[BJ], bl[BJ];
+    };
+    // slab st's B fragments (a negative or past-the-end slab reads zeros)
+    auto issue_b = [&](BSet& o, int st) __attribute__((always_inline)) {
+        const uint32_t off = b_off + (uint32_t)st * b_slab;
+#pragma unroll
+        for (int j = 0; j < BJ; j++) {
+            o.bh[j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb[0], off + j * 1024, 0, 0));
+            o.bl[j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb[1], off + j * 1024, 0, 0));
+        }
+    };
+
+    f32x16 acc[BI][BJ];
+#pragma unroll
+    for (int i = 0; i < BI; i++)
+#pragma unroll
+        for (int j = 0; j < BJ; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
+
+    bf16x8 ah[BI], al[BI];
+    auto read_a = [&](int i, int st) __attribute__((always_inline)) {
+        const uint16_t* sb = lds + (st % S) * STAGE;
+        const int ra_ = (wm * 32 * BI + i * 32 + c) * kSlabK + fslot;
+        ah[i] = *reinterpret_cast<const bf16x8*>(sb + ra_);
+        al[i] = *reinterpret_cast<const bf16x8*>(sb + ARR + ra_);
+    };
+    auto barrier = [&]() __attribute__((always_inline)) {
+        compiler_fence();
+        __builtin_amdgcn_s_barrier();
+        compiler_fence();
+    };
+
+    // the wait counts assume exactly this issue order: fences keep the
+    // compiler from reordering the loads
+    BSet bs[3];
+#pragma unroll
+    for (int st = 0; st <= S - 2; st++) {
+        issue_a(st);
+        compiler_fence();
+    }
+    issue_b(bs[0], 0);
+    compiler_fence();
+    issue_b(bs[1], 1);
+    compiler_fence();
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(WAIT_A0));
+    barrier();
+#pragma unroll
+    for (int i = 0; i < BI; i++) read_a(i, 0);
+
+    // Step t on B set CUR, filling set NB with slab t + 2; WA, WB: the
+    // immediate waits for slab t + 1's A and slab t's B.  A macro, so that the
+    // counts stay compile-time immediates and the steady loop has no branches
+    // (the compiler's own waits are then no stricter than these).
+#define BF16_DB_STEP(T_, CUR, NB, WA, WB)                                                                \
+    do {                                                                                                  \
+        const int t_ = (T_);                                                                              \
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(WA));                                                        \
+        barrier();                                                                                        \
+        issue_a(t_ + S - 1);                                                                              \
+        compiler_fence();                                                                                 \
+        issue_b(NB, t_ + 2);                                                                              \
+        compiler_fence();                                                                                 \
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(WB));                                                        \
+        compiler_fence();                                                                                 \
+        _Pragma("unroll") for (int i = 0; i < BI; i++) {                                                  \
+            _Pragma("unroll") for (int k = 0; k < BJ; k++) acc[i][k] =                                    \
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], (CUR).bh[k], acc[i][k], 0, 0, 0);          \
+            _Pragma("unroll") for (int k = 0; k < BJ; k++) acc[i][k] =                                    \
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], (CUR).bl[k], acc[i][k], 0, 0, 0);          \
+            _Pragma("unroll") for (int k = 0; k < BJ; k++) acc[i][k] =                                    \
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], (CUR).bh[k], acc[i][k], 0, 0, 0);          \
+            read_a(i, t_ + 1);                                                                            \
+        }                                                                                                 \
+        compiler_fence();                                                                                 \
+    } while (0)
+    // later loads when slab t + 1's A is waited for in the first steps (the
+    // prologue's order), then in every later step
+    constexpr int WA0 = (S - 3) * LA + 2 * LB;
+    constexpr int WA1 = S >= 5 ? (S - 3) * LA + 3 * LB : WAIT_A;
+    constexpr int WA2 = S >= 6 ? (S - 3) * LA + 4 * LB : WAIT_A;
+    // slab t uses set t % 3 and fills set (t + 2) % 3; the first three steps
+    // (nk >= 3 is required) run outside the loop so that the loop begins in
+    // the state its back edge leaves
+    BF16_DB_STEP(0, bs[0], bs[2], WA0, WAIT_B0);
+    BF16_DB_STEP(1, bs[1], bs[0], WA1, WAIT_B);
+    BF16_DB_STEP(2, bs[2], bs[1], WA2, WAIT_B);
+    int t = 3;
+    for (; t + 3 <= nk; t += 3) {
+        BF16_DB_STEP(t, bs[0], bs[2], WAIT_A, WAIT_B);
+        BF16_DB_STEP(t + 1, bs[1], bs[0], WAIT_A, WAIT_B);
+        BF16_DB_STEP(t + 2, bs[2], bs[1], WAIT_A, WAIT_B);
+    }
+    // the last one or two steps wait for every earlier load: their own B
+    // loads are never used, and the compiler may drop them, which would
+    // shorten the counts above
+    if (t < nk) BF16_DB_STEP(t, bs[0], bs[2], 0, 0);
+    if (t + 1 < nk) BF16_DB_STEP(t + 1, bs[1], bs[0], 0, 0);
+#undef BF16_DB_STEP
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    __builtin_amdgcn_s_waitcnt(kLgkmcnt0);
+    store_tile<BI, BJ, EPI_T, D4>(g, acc, bidx, m0 + wm * 32 * BI, n0 + wn * 32 * BJ, h, c, false, false);
+}
+
 // U (rows = m*d, cols = mp, row stride ldu), row r = j*d + s, both split
 // into hi/lo (slab layout):
 //   U1 (d*mp rows, K = m):   element (beta*d + s, j) = U[j*d+s][beta]
@@ -528,19 +717,43 @@ hipError_t launch_tile(const Bf16Desc& g, int nf, hipStream_t s) {
 // (Bf16Cfg and Bf16Choice are declared in rot_internal.h.)
 
 // The environment's measurement knobs override a configuration:
-// ROT_BF16_CFG=128 | ring5, ROT_BF16_ORDER=m | n | G.
+// ROT_BF16_CFG=128 | ring5 | direct5 | direct6, ROT_BF16_ORDER=m | n | G.
 Bf16Cfg with_env(Bf16Cfg c) {
     const char* env = getenv("ROT_BF16_CFG");
     if (env && !strcmp(env, "128")) c.tile = 128;
     if (env && !strcmp(env, "ring5")) c.ring = 5;
+    if (env && !strncmp(env, "direct", 6)) {
+        c.tile = 256;
+        c.direct = 1;
+        c.ring = env[6] == '6' ? 6 : 5;
+    }
     const char* ord = getenv("ROT_BF16_ORDER");
     if (ord) c.order = ord[0] == 'n' ? -1 : ord[0] == 'm' ? 0 : std::max(0, atoi(ord));
     return c;
 }
 
+template <int WGM, int WGN, int BI, int BJ, int S, bool EPI_T>
+hipError_t launch_tile_db(const Bf16Desc& g, int nf, hipStream_t s) {
+    constexpr int T = 32 * WGM * BI;
+    const int tm = (g.M + T - 1) / T, tn = (g.N + T - 1) / T;
+    const int64_t tiles = (int64_t)tm * tn * g.batch;
+    if (g.upper || tiles > 0x7fffffff) return hipErrorInvalidValue;
+    if (EPI_T && g.d == 4)
+        hipLaunchKernelGGL((gemm_bf16x3_db_kernel<WGM, WGN, BI, BJ, S, EPI_T, true>), dim3((unsigned)tiles),
+                           dim3(64 * WGM * WGN), 0, s, g, tm, tn, nf);
+    else
+        hipLaunchKernelGGL((gemm_bf16x3_db_kernel<WGM, WGN, BI, BJ, S, EPI_T, false>), dim3((unsigned)tiles),
+                           dim3(64 * WGM * WGN), 0, s, g, tm, tn, nf);
+    return hipGetLastError();
+}
+
 template <bool EPI_T>
 hipError_t launch_bf16(const Bf16Desc& g, const Bf16Cfg& cfg0, hipStream_t s) {
     const Bf16Cfg cfg = with_env(cfg0);
+    if (cfg.direct && cfg.tile == 256 && g.M >= 256 && g.N >= 256 && !g.upper && n_slabs(g.K) >= 3) {
+        if (cfg.ring == 6) return launch_tile_db<2, 4, 4, 2, 6, EPI_T>(g, cfg.order, s);
+        return launch_tile_db<2, 4, 4, 2, 5, EPI_T>(g, cfg.order, s);
+    }
     if (cfg.tile == 256 && g.M >= 256 && g.N >= 256) {
         if (cfg.ring == 5) return launch_tile<2, 4, 4, 2, 5, EPI_T>(g, cfg.order, s);
         return launch_tile<2, 4, 4, 2, 4, EPI_T>(g, cfg.order, s);
@@ -763,9 +976,12 @@ Bf16Desc stage2_desc(const rot_problem& p, const Bf16Layout& L, const Bf16Ws& w,
     return b;
 }
 
-const Bf16Cfg kCandidates[] = {{256, 4, kDefaultOrder}, {256, 5, kDefaultOrder}, {128, 4, kDefaultOrder}};
+const Bf16Cfg kCandidates[] = {{256, 4, kDefaultOrder, 0}, {256, 5, kDefaultOrder, 0}, {128, 4, kDefaultOrder, 0},
+                               {256, 5, kDefaultOrder, 1}, {256, 6, kDefaultOrder, 1}};
 
-std::string cfg_token(const Bf16Cfg& c) { return std::to_string(c.tile) + "r" + std::to_string(c.ring); }
+std::string cfg_token(const Bf16Cfg& c) {
+    return std::to_string(c.tile) + (c.direct ? "d" : "r") + std::to_string(c.ring);
+}
 
 bool parse_cfg(const std::string& t, Bf16Cfg* c) {
     for (const Bf16Cfg& k : kCandidates)

@@ -113,6 +113,7 @@ hipError_t gemm_f64(const GemmDesc& g, hipStream_t stream);
 // rotation stages for one shape.
 struct Bf16Cfg {
     int tile = 256, ring = 4, order = 0;
+    int direct = 0;  // 1: B fragments straight from global memory (256 x 256 tiles only)
 };
 struct Bf16Choice {
     Bf16Cfg s1, s2;

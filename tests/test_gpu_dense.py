@@ -465,13 +465,14 @@ def test_split_bf16_parity(rot, oracle_mod, shape, symmetric):
     assert err.max() <= TOL32, err
 
 
-@pytest.mark.parametrize("cfg", ["ring4", "ring5", "128"])
+@pytest.mark.parametrize("cfg", ["ring4", "ring5", "128", "direct5", "direct6"])
 @pytest.mark.parametrize("shape", [(300, 4, 270, 2), (290, 3, 300, 2)])
 def test_split_bf16_tile_configs_ragged(rot, oracle_mod, monkeypatch, cfg, shape):
     """Each tile configuration (256 x 256 with a ring of 4 or 5 stages;
-    128 x 128) on extents that leave ragged tiles in both stages and K not a
-    multiple of the 16-wide slab (zero padding); d = 3 takes the element-wise
-    split-transposed store."""
+    128 x 128; 256 x 256 with B fragments loaded straight into registers and
+    a 5- or 6-stage A ring) on extents that leave ragged tiles in both stages
+    and K not a multiple of the 16-wide slab (zero padding); d = 3 takes the
+    element-wise split-transposed store."""
     if cfg == "ring4":
         monkeypatch.delenv("ROT_BF16_CFG", raising=False)  # the default
     else:
@@ -565,4 +566,18 @@ torch.save({{"a": a.cpu(), "b": b.cpu()}}, sys.argv[1])
     assert torch.equal(outs["tuned"]["a"], outs["off"]["a"])
     lines = [l for l in cache.read_text().splitlines() if l.startswith("bf16|")]
     assert len(lines) == 1 and "|m300|d4|mp280|nb3" in lines[0]
-    assert all(t in ("256r4", "256r5", "128r4") for t in lines[0].split()[1:])
+    assert all(t in ("256r4", "256r5", "128r4", "256d5", "256d6") for t in lines[0].split()[1:])
+
+
+@pytest.mark.parametrize("cfg", ["ring5", "128", "direct5", "direct6"])
+def test_split_bf16_configs_give_the_same_bits(rot, monkeypatch, cfg):
+    """Every tile configuration sums each output element's products slab by
+    slab in the same order, so all give the default's bits (which the tuner
+    relies on: its choice never changes results)."""
+    case = workloads.dense_case(520, 4, 300, 3, cfg=733, dtype="f32", symmetric=True)
+    monkeypatch.delenv("ROT_BF16_CFG", raising=False)
+    monkeypatch.setenv("ROT_AUTOTUNE", "0")
+    base = run_rotate(rot, case, "split_bf16")
+    monkeypatch.setenv("ROT_BF16_CFG", cfg)
+    got = run_rotate(rot, case, "split_bf16")
+    np.testing.assert_array_equal(got, base)
