@@ -355,7 +355,9 @@ ROT_API rot_status rot_plan_destroy(rot_plan plan);
  * execution paths (one fused kernel in two register layouts, its variant
  * that loads whole row blocks of operator rows, two grouped launches, or two
  * launches that stack each shift's operators into one product per sector
- * combination) and keeps the fastest for later calls with the same
+ * combination; that one applies while no kept sector has more than four
+ * site-state segments and each shift's intermediates for one kept sector stay
+ * under 1 GiB) and keeps the fastest for later calls with the same
  * structure; every call's result comes from the kept path, so repeated calls
  * agree bit for bit.  ROT_BLOCKED_PATH=fused|fused_wide|rowblock|
  * rowblock_wide|grouped|stacked in the environment forces one.  Work-lists are cached for the 8 most recently used structures;

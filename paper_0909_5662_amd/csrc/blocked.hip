@@ -22,8 +22,10 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
+#include "buffer_rsrc.h"
 #include "pinned_lru.h"
 #include "rot_internal.h"
 
@@ -629,12 +631,20 @@ __global__ __launch_bounds__(256) void blocked_stacked_kernel(const StkTile* __r
 // operation.  Each member tile writes one Xt segment (m'_Q x a4 row-major,
 // a4 the source block's row count rounded up to 4) as a dense block.
 struct StkMember {
-    int M;          // rows of this member tile (<= 80)
-    int lda, ldcm;  // A row stride; C stride per row (the segment width a4)
-    int pad;
-    int64_t a_off;  // A row 0 in the transposed-U area
-    int64_t tab;    // per-operator C offsets into Xt (-1: operator has no output block)
+    int M;           // rows of this member tile (<= 80)
+    int lda, ldcm;   // A row stride; C stride per row (the segment width a4)
+    int span;        // bytes of the Xt group of the member's (shift, Q), at most kStkSpanMax
+    int64_t a_off;   // A row 0 in the transposed-U area
+    int64_t tab;     // per-operator C offsets into Xt (-1: operator has no output block)
+    int64_t c_base;  // first element of that Xt group: the stores address it through a buffer descriptor
 };
+// Stage-1 store offsets (bytes, 32-bit) into one Xt group of at most
+// kStkSpanMax bytes; the hardware drops a store at or past the group's end.
+// An operator without an output block starts its rows at kStkNoBlock (rows
+// add less than 2^16), a row past M stores at kStkDrop.
+constexpr int kStkSpanMax = 0x3fffffc0;
+constexpr int kStkNoBlock = 0x40000000;
+constexpr int kStkDrop = 0x7ffffff0;
 struct StkGroupR {
     int N, K, nb, nvalid;  // C columns, contraction length, columns per operator, non-zero rows of each
     int pad0, pad1;
@@ -644,6 +654,7 @@ constexpr int kStkResK = 5;  // 16-wide k steps staged (K <= 80)
 
 // tiles[blockIdx.x] = {group, first member, first stacked column, members};
 // eight waves: two per member, each on 32 of the columns.
+template <int PFA>
 __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile* __restrict__ tiles,
                                                                         const StkGroupR* __restrict__ groups,
                                                                         const StkMember* __restrict__ members,
@@ -680,20 +691,34 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
         aok[mb] = active && m < mem.M;
         arow[mb] = A + mem.a_off + (int64_t)(aok[mb] ? m : 0) * mem.lda;
     }
-    f32x4 a[MB], an[MB];
+    // U^T rows of k steps s .. s + PFA in flight: set s % (PFA + 1) holds step s
+    f32x4 a[PFA + 1][MB];
 #pragma unroll
-    for (int mb = 0; mb < MB; mb++)
-        if (mb < nbm) a[mb] = quad_or_zero<true>(arow[mb], 4 * lh, aok[mb] && 4 * lh < K, A);
-    float* crow[NB];
-    bool wok[NB];
+    for (int p = 0; p < PFA; p++)
+        if (p < nks) {
+#pragma unroll
+            for (int mb = 0; mb < MB; mb++)
+                if (mb < nbm) {
+                    const int kk = 16 * p + 4 * lh;
+                    a[p][mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+                }
+        }
+    // stores: 32-bit byte offsets into the member's Xt group; an operator
+    // without an output block, or a row past M, gets an offset past the group
+    // instead of a branch, and the hardware drops that store
+    const __amdgpu_buffer_rsrc_t cres =
+        __builtin_amdgcn_make_buffer_rsrc(C + mem.c_base, (short)0, mem.span, kBufferFlags);
+    // (lane part: column n and rows 4 lh .. 4 lh + 3 of each row block)
+    const int ldc4 = mem.ldcm * 4;
+    const int mrem = mem.M - 4 * lh;  // rows mb * 16 + v of this lane exist while below this
+    int cofs[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; nb++) {
         const int n = n0 + nb * 16 + li;
         const bool ok = active && n < g.N;
         const int j = ok ? n / g.nb : 0;
         const int64_t co = ok ? coff[mem.tab + j] : -1;
-        wok[nb] = co >= 0;
-        crow[nb] = C + (wok[nb] ? co + (n - j * g.nb) : 0);
+        cofs[nb] = (co >= 0 ? (int)((co - mem.c_base + (n - j * g.nb)) * 4) : kStkNoBlock) + 4 * lh * ldc4;
     }
     // stage the operator rows: thread tid owns stacked column tid % 64 and
     // k quads tid / 64 + (NT / 64) i (zero past K; a quad crossing K element
@@ -723,52 +748,61 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
     }
     __syncthreads();
     if (!active) return;
-    f32x4 acc[MB][NB];
+    // the member's row-block count as a compile-time constant, so the
+    // products and stores carry no per-instruction guards (a column past N
+    // multiplies the zeros staged for it and is not stored)
+    auto run = [&](auto nbm_c) __attribute__((always_inline)) {
+        constexpr int NBM = decltype(nbm_c)::value;
+        f32x4 acc[NBM][NB];
 #pragma unroll
-    for (int mb = 0; mb < MB; mb++)
+        for (int mb = 0; mb < NBM; mb++)
 #pragma unroll
-        for (int nb = 0; nb < NB; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nb = 0; nb < NB; nb++) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < KS; s++) {
-        if (s < nks) {
-            if (s + 1 < nks) {
+        for (int s = 0; s < KS; s++) {
+            if (s < nks) {
+                if (s + PFA < nks) {
 #pragma unroll
-                for (int mb = 0; mb < MB; mb++)
-                    if (mb < nbm) {
-                        const int kk = 16 * (s + 1) + 4 * lh;
-                        an[mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+                    for (int mb = 0; mb < NBM; mb++) {
+                        const int kk = 16 * (s + PFA) + 4 * lh;
+                        a[(s + PFA) % (PFA + 1)][mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
                     }
-            }
-            // lane group lh takes k = 16 s + 4 lh + q at instruction q
-            f32x4 bf[NB];
+                }
+                // lane group lh takes k = 16 s + 4 lh + q at instruction q
+                f32x4 bf[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; nb++)
-                if (nb < nbn) bf[nb] = bs[4 * s + lh][c0 + nb * 16 + li];
+                for (int nb = 0; nb < NB; nb++) bf[nb] = bs[4 * s + lh][c0 + nb * 16 + li];
 #pragma unroll
-            for (int q = 0; q < 4; q++)
+                for (int q = 0; q < 4; q++)
 #pragma unroll
-                for (int mb = 0; mb < MB; mb++)
+                    for (int mb = 0; mb < NBM; mb++)
 #pragma unroll
-                    for (int nb = 0; nb < NB; nb++)
-                        if (mb < nbm && nb < nbn)
-                            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mb][q], bf[nb][q], acc[mb][nb], 0, 0, 0);
-            if (s + 1 < nks) {
-#pragma unroll
-                for (int mb = 0; mb < MB; mb++) a[mb] = an[mb];
+                        for (int nb = 0; nb < NB; nb++)
+                            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s % (PFA + 1)][mb][q], bf[nb][q],
+                                                                               acc[mb][nb], 0, 0, 0);
             }
         }
-    }
 #pragma unroll
-    for (int mb = 0; mb < MB; mb++)
+        for (int mb = 0; mb < NBM; mb++)
 #pragma unroll
-        for (int nb = 0; nb < NB; nb++)
-            if (mb < nbm && nb < nbn && wok[nb]) {
+            for (int nb = 0; nb < NB; nb++)
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
-                    const int m = mb * 16 + 4 * lh + v;
-                    if (m < mem.M) crow[nb][(int64_t)m * mem.ldcm] = acc[mb][nb][v];
+                    const int r = mb * 16 + v;
+                    const int off = r < mrem ? cofs[nb] + r * ldc4 : kStkDrop;
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[mb][nb][v]), cres, off, 0,
+                                                          0);
                 }
-            }
+    };
+    static_assert(MB == 5, "one case per row-block count");
+    switch (nbm) {
+        case 1: run(std::integral_constant<int, 1>{}); break;
+        case 2: run(std::integral_constant<int, 2>{}); break;
+        case 3: run(std::integral_constant<int, 3>{}); break;
+        case 4: run(std::integral_constant<int, 4>{}); break;
+        case 5: run(std::integral_constant<int, 5>{}); break;
+        default: break;
+    }
 }
 
 // Stage 2 with U^T_T staged in LDS: one workgroup per (group, 80-row tile,
@@ -1061,6 +1095,8 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
     std::vector<std::pair<int, StkTile>> o1, o2, o2w, o_r;  // (work, tile): longest first
     for (int si = 0; si < (int)shifts.size(); si++) {
         const int du = shifts[si].first, dd = shifts[si].second;
+        // Xt elements [gx0[k], gx1[k]) hold the blocks of kept sector k for this shift
+        std::vector<int64_t> gx0(p->n_new, 0), gx1(p->n_new, 0);
         std::vector<int> ops;  // every operator of this shift
         for (int b = 0; b < p->n_ops; b++)
             if (p->shift[2 * b] == du && p->shift[2 * b + 1] == dd) ops.push_back(b);
@@ -1100,6 +1136,7 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                 g2.seg[ns] = ldT;
                 for (int x = ns + 1; x < 5; x++) g2.seg[x] = kSegEnd;
             }
+            gx0[k] = S->x_elems;
             for (int j = 0; j < n; j++) {
                 const int64_t x = S->x_elems;
                 S->x_elems += ((int64_t)Q.dim * ldT + 63) / 64 * 64;  // keep 256-byte alignment
@@ -1107,6 +1144,9 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                 S->boff.push_back(x);
                 S->coff.push_back(p->out_off[(int64_t)J[j] * p->n_new + k]);
             }
+            gx1[k] = S->x_elems;
+            // the stage-1 stores address one group with 32-bit byte offsets
+            if ((gx1[k] - gx0[k]) * (int64_t)sizeof(float) > kStkSpanMax) S->ok = false;
             const int gi2 = (int)S->g2.size();
             S->g2.push_back(g2);
             for (int m0 = 0; m0 < g2.M; m0 += 16 * kStkMB) {
@@ -1197,6 +1237,8 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                         e.ldcm = a4;
                         e.a_off = ut.off[mm.k] + (int64_t)m0 * ut.ld[mm.k] + ut.pstart[mm.k][mm.s];
                         e.tab = member_tab(mm, m0);
+                        e.c_base = gx0[mm.k];
+                        e.span = (int)((gx1[mm.k] - gx0[mm.k]) * (int64_t)sizeof(float));
                         S->mem.push_back(e);
                     }
                 }
@@ -1583,7 +1625,7 @@ hipError_t run_stacked(const rot_blocked_problem* p, Plan* plan, void* ws, hipSt
     if (e != hipSuccess) return e;
     e = prof_timed("blocked_stacked1_fp32", stream, [&] {
         if (plan->k_nr > 0)
-            hipLaunchKernelGGL(blocked_stacked_lds_kernel, dim3(plan->k_nr), dim3(512), 0, stream, plan->k_tr,
+            hipLaunchKernelGGL(blocked_stacked_lds_kernel<1>, dim3(plan->k_nr), dim3(512), 0, stream, plan->k_tr,
                                plan->k_gr, plan->k_mem, plan->k_boff, plan->k_coff, ut, p->O_blk, xt);
         if (plan->k_n1 > 0)
             return launch_stacked<false>(plan->k_t1, plan->k_n1, plan->k_g1, plan, ut, p->O_blk, xt, stream);

@@ -34,6 +34,7 @@
 #include <string>
 #include <vector>
 
+#include "buffer_rsrc.h"
 #include "lds_slice.h"
 #include "rot_internal.h"
 
@@ -96,7 +97,6 @@ struct Bf16Desc {
 
 // Buffer descriptor over one slab-layout operand (raw addressing; loads past
 // its last slab return zero).
-constexpr int kBufferFlags = 0x00020000;
 __device__ inline __amdgpu_buffer_rsrc_t operand_rsrc(const uint16_t* p, int rows, int K) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(p), (short)0,
                                              (int)(n_slabs(K) * rows * kSlabK * 2), kBufferFlags);
