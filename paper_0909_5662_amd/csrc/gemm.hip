@@ -18,6 +18,7 @@
 // tiles, and tiles sharing an operand panel stay on one XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include "buffer_rsrc.h"
 #include "lds_slice.h"
 #include "rot_internal.h"
 
@@ -224,6 +225,146 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
     }
 }
 
+// FP32 product of whole tiles with both slices filled by buffer loads with
+// LDS destination: no staging registers, no per-slice address arithmetic
+// (the slice advance is the scalar offset), and one wait and barrier per
+// slice.  Wave w copies 1 KB pieces w and w + 4 of each slice, lane l the
+// 16 bytes at piece offset 16 l.  LDS layouts (copied in this order):
+//  * K-contiguous operand: 128 rows of 16 floats, chunk q of row r in slot
+//    q ^ ((r / 4) % 4) (the layout of LdsSlice::kc_off); piece y holds rows
+//    16 y .. 16 y + 15, so lane l fetches row 16 y + l / 4, chunk
+//    (l % 4) ^ ((row / 4) % 4).
+//  * M/N-contiguous operand: k rows of 128 floats in pairs, pair p (rows 2p,
+//    2p + 1, one piece) at 264 p: rows k and k + 8, which the fragment reads
+//    of the two lane halves take together, then lie 32 banks apart.
+// Same fragment reads and products as gemm_f32_kernel, so the same bits.
+// Requires: M, N multiples of 128, K of 16, 16-byte aligned rows, no split,
+// accumulation or symmetric output, each operand under 4 GiB per batch entry.
+constexpr int kDlPair = 2 * kTile + 8;                  // floats per k-row pair (M/N-contiguous)
+constexpr int kDlElemsK = kTile * kSlice;               // K-contiguous slice
+constexpr int kDlElemsMN = (kSlice / 2) * kDlPair;      // M/N-contiguous slice
+__device__ inline int dl_mn_off(int kr, int col) { return (kr >> 1) * kDlPair + (kr & 1) * kTile + col; }
+
+template <bool AK, bool BK>
+__global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int tiles_m, int tiles_n) {
+    constexpr int EA = AK ? kDlElemsK : kDlElemsMN, EB = BK ? kDlElemsK : kDlElemsMN;
+    __shared__ __attribute__((aligned(1024))) float As[2][EA];
+    __shared__ __attribute__((aligned(1024))) float Bs[2][EB];
+
+    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, false);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int h = lane >> 5, c = lane & 31;
+
+    const float* Ab = static_cast<const float*>(g.A) + (int64_t)tc.g * g.a_bs;
+    const float* Bb = static_cast<const float*>(g.B) + (int64_t)tc.g * g.b_bs;
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Ab), (short)0, (int)0xffffffff, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bb), (short)0, (int)0xffffffff, kBufferFlags);
+    // this lane's byte offsets in pieces `wave` and `wave + 4` of slice 0, and
+    // the byte advance per slice
+    auto lane_off = [&](bool kc, int64_t ld, int r0, int y) -> uint32_t {
+        if (kc) {
+            const int row = 16 * y + (lane >> 2);
+            const int q = (lane & 3) ^ ((row >> 2) & 3);
+            return (uint32_t)(((int64_t)(r0 + row) * ld + 4 * q) * 4);
+        }
+        const int kr = 2 * y + (lane >> 5);
+        return (uint32_t)(((int64_t)kr * ld + r0 + 4 * (lane & 31)) * 4);
+    };
+    const uint32_t oa0 = lane_off(AK, g.lda, tc.m0, wave), oa1 = lane_off(AK, g.lda, tc.m0, wave + 4);
+    const uint32_t ob0 = lane_off(BK, g.ldb, tc.n0, wave), ob1 = lane_off(BK, g.ldb, tc.n0, wave + 4);
+    const uint32_t sa = (uint32_t)(AK ? kSlice * 4 : (int64_t)kSlice * g.lda * 4);
+    const uint32_t sb = (uint32_t)(BK ? kSlice * 4 : (int64_t)kSlice * g.ldb * 4);
+    auto piece = [](bool kc, int y) { return kc ? y * 256 : y * kDlPair; };
+    auto issue = [&](int t, int buf) __attribute__((always_inline)) {
+        typedef __attribute__((address_space(3))) void* lptr;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lptr)(As[buf] + piece(AK, wave)), 16, oa0, (int)(t * sa), 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lptr)(As[buf] + piece(AK, wave + 4)), 16, oa1, (int)(t * sa), 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lptr)(Bs[buf] + piece(BK, wave)), 16, ob0, (int)(t * sb), 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lptr)(Bs[buf] + piece(BK, wave + 4)), 16, ob1, (int)(t * sb), 0, 0);
+    };
+    auto sync = [&]() __attribute__((always_inline)) {
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's slice is in LDS
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    };
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
+
+    const int total = g.K / kSlice;
+    issue(0, 0);
+    sync();
+    for (int t = 0; t < total; t++) {
+        const int cur = t & 1;
+        if (t + 1 < total) issue(t + 1, cur ^ 1);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const float* a_s = As[cur];
+        const float* b_s = Bs[cur];
+        // 8 steps of k = 2: lane group h takes k = h*8 + j at step j
+        float av[2][8], bv[2][8];
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const int row = wm * 64 + i * 32 + c;
+            if (AK) {
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + row * kSlice + ((2 * h) ^ ((row >> 2) & 3)) * 4);
+                const f32x4 x1 =
+                    *reinterpret_cast<const f32x4*>(a_s + row * kSlice + ((2 * h + 1) ^ ((row >> 2) & 3)) * 4);
+#pragma unroll
+                for (int e = 0; e < 4; e++) { av[i][e] = x0[e]; av[i][4 + e] = x1[e]; }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; j++) av[i][j] = a_s[dl_mn_off(h * 8 + j, row)];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const int col = wn * 64 + i * 32 + c;
+            if (BK) {
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + col * kSlice + ((2 * h) ^ ((col >> 2) & 3)) * 4);
+                const f32x4 x1 =
+                    *reinterpret_cast<const f32x4*>(b_s + col * kSlice + ((2 * h + 1) ^ ((col >> 2) & 3)) * 4);
+#pragma unroll
+                for (int e = 0; e < 4; e++) { bv[i][e] = x0[e]; bv[i][4 + e] = x1[e]; }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; j++) bv[i][j] = b_s[dl_mn_off(h * 8 + j, col)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int k = 0; k < 2; k++)
+                    acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][j], bv[k][j], acc[i][k], 0, 0, 0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        sync();
+    }
+
+    float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs;
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int col = tc.n0 + wn * 64 + k * 32 + c;
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int row = tc.m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                Cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
+            }
+        }
+}
+
 // ---------------------------------------------------------------- FP64 ----
 // v_mfma_f64_16x16x4f64: lane l supplies A(row l%16, k l/16), B(k l/16, col
 // l%16); accumulator element v of lane l is C(4*v + l/16, l%16).
@@ -356,6 +497,18 @@ bool vector_ok(const GemmDesc& g) {
            g.b_bs % vw == 0 && g.a_ks % vw == 0 && g.b_ks % vw == 0 && (g.parts <= 1 || g.kp % vw == 0);
 }
 
+// The direct-to-LDS FP32 kernel's conditions (16-byte alignment is checked
+// by vector_ok): whole tiles and slices, no split, accumulation, symmetric
+// output or K batching, and every byte offset of an operand's batch entry
+// below 2^32.
+bool direct_lds_ok(const GemmDesc& g) {
+    if (g.upper || g.accumulate || g.parts > 1 || g.kbatch != 1) return false;
+    if (g.M % kTile != 0 || g.N % kTile != 0 || g.K % kSlice != 0 || g.K <= 0) return false;
+    const int64_t ea = g.a_kcontig ? (int64_t)(g.M - 1) * g.lda + g.K : (int64_t)(g.K - 1) * g.lda + g.M;
+    const int64_t eb = g.b_kcontig ? (int64_t)(g.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + g.N;
+    return ea * 4 < ((int64_t)1 << 32) && eb * 4 < ((int64_t)1 << 32);
+}
+
 #define ROT_DISPATCH(KERNEL)                                                                       \
     template <bool AK, bool BK, bool VEC>                                                          \
     hipError_t launch_##KERNEL##_acc(const GemmDesc& g, dim3 grid, int tm, int tn, hipStream_t s) { \
@@ -395,6 +548,15 @@ hipError_t gemm_any(const GemmDesc& g, hipStream_t stream) {
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles);
     const bool vec = vector_ok<T>(g);
+    if (sizeof(T) == 4 && vec && direct_lds_ok(g)) {
+        if (g.a_kcontig)
+            hipLaunchKernelGGL((g.b_kcontig ? gemm_f32_dl_kernel<true, true> : gemm_f32_dl_kernel<true, false>), grid,
+                               dim3(kThreads), 0, stream, g, tm, tn);
+        else
+            hipLaunchKernelGGL((g.b_kcontig ? gemm_f32_dl_kernel<false, true> : gemm_f32_dl_kernel<false, false>),
+                               grid, dim3(kThreads), 0, stream, g, tm, tn);
+        return hipGetLastError();
+    }
     if (sizeof(T) == 4) return launch_gemm_f32_kernel(g, vec, grid, tm, tn, stream);
     return launch_gemm_f64_kernel(g, vec, grid, tm, tn, stream);
 }
