@@ -225,31 +225,19 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
     }
 }
 
-// FP32 product of whole tiles with both slices filled by buffer loads with
-// LDS destination: no staging registers, no per-slice address arithmetic
-// (the slice advance is the scalar offset), and one wait and barrier per
-// slice.  Wave w copies 1 KB pieces w and w + 4 of each slice, lane l the
-// 16 bytes at piece offset 16 l.  LDS layouts (copied in this order):
-//  * K-contiguous operand: 128 rows of 16 floats, chunk q of row r in slot
-//    q ^ ((r / 4) % 4) (the layout of LdsSlice::kc_off); piece y holds rows
-//    16 y .. 16 y + 15, so lane l fetches row 16 y + l / 4, chunk
-//    (l % 4) ^ ((row / 4) % 4).
-//  * M/N-contiguous operand: k rows of 128 floats in pairs, pair p (rows 2p,
-//    2p + 1, one piece) at 264 p: rows k and k + 8, which the fragment reads
-//    of the two lane halves take together, then lie 32 banks apart.
-// Same fragment reads and products as gemm_f32_kernel, so the same bits.
-// Requires: M, N multiples of 128, K of 16, 16-byte aligned rows, no split,
-// accumulation or symmetric output, each operand under 4 GiB per batch entry.
-constexpr int kDlPair = 2 * kTile + 8;                  // floats per k-row pair (M/N-contiguous)
-constexpr int kDlElemsK = kTile * kSlice;               // K-contiguous slice
-constexpr int kDlElemsMN = (kSlice / 2) * kDlPair;      // M/N-contiguous slice
-__device__ inline int dl_mn_off(int kr, int col) { return (kr >> 1) * kDlPair + (kr & 1) * kTile + col; }
-
+// FP32 product of whole tiles with both K slices filled by buffer loads with
+// LDS destination (DmaSlice128): no staging registers, no per-slice address
+// arithmetic, one wait and barrier per slice.  Same fragment reads and
+// products as gemm_f32_kernel, so the same bits.  Requires M, N multiples of
+// 128, K of 16, 16-byte aligned rows, no split, accumulation or symmetric
+// output, and each operand's batch entry under 4 GiB (direct_lds_ok).
 template <bool AK, bool BK>
 __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int tiles_m, int tiles_n) {
-    constexpr int EA = AK ? kDlElemsK : kDlElemsMN, EB = BK ? kDlElemsK : kDlElemsMN;
-    __shared__ __attribute__((aligned(1024))) float As[2][EA];
-    __shared__ __attribute__((aligned(1024))) float Bs[2][EB];
+    typedef DmaSlice128<AK> DA;
+    typedef DmaSlice128<BK> DB;
+    static_assert(kTile == DA::R && kSlice == DA::SK, "slice shape");
+    __shared__ __attribute__((aligned(1024))) float As[2][DA::ELEMS];
+    __shared__ __attribute__((aligned(1024))) float Bs[2][DB::ELEMS];
 
     const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, false);
     const int tid = threadIdx.x;
@@ -263,35 +251,10 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Ab), (short)0, (int)0xffffffff, kBufferFlags);
     const __amdgpu_buffer_rsrc_t rb =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bb), (short)0, (int)0xffffffff, kBufferFlags);
-    // this lane's byte offsets in pieces `wave` and `wave + 4` of slice 0, and
-    // the byte advance per slice
-    auto lane_off = [&](bool kc, int64_t ld, int r0, int y) -> uint32_t {
-        if (kc) {
-            const int row = 16 * y + (lane >> 2);
-            const int q = (lane & 3) ^ ((row >> 2) & 3);
-            return (uint32_t)(((int64_t)(r0 + row) * ld + 4 * q) * 4);
-        }
-        const int kr = 2 * y + (lane >> 5);
-        return (uint32_t)(((int64_t)kr * ld + r0 + 4 * (lane & 31)) * 4);
-    };
-    const uint32_t oa0 = lane_off(AK, g.lda, tc.m0, wave), oa1 = lane_off(AK, g.lda, tc.m0, wave + 4);
-    const uint32_t ob0 = lane_off(BK, g.ldb, tc.n0, wave), ob1 = lane_off(BK, g.ldb, tc.n0, wave + 4);
-    const uint32_t sa = (uint32_t)(AK ? kSlice * 4 : (int64_t)kSlice * g.lda * 4);
-    const uint32_t sb = (uint32_t)(BK ? kSlice * 4 : (int64_t)kSlice * g.ldb * 4);
-    auto piece = [](bool kc, int y) { return kc ? y * 256 : y * kDlPair; };
-    auto issue = [&](int t, int buf) __attribute__((always_inline)) {
-        typedef __attribute__((address_space(3))) void* lptr;
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lptr)(As[buf] + piece(AK, wave)), 16, oa0, (int)(t * sa), 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lptr)(As[buf] + piece(AK, wave + 4)), 16, oa1, (int)(t * sa), 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lptr)(Bs[buf] + piece(BK, wave)), 16, ob0, (int)(t * sb), 0, 0);
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lptr)(Bs[buf] + piece(BK, wave + 4)), 16, ob1, (int)(t * sb), 0, 0);
-    };
-    auto sync = [&]() __attribute__((always_inline)) {
-        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's slice is in LDS
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_s_barrier();
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    };
+    DA da;
+    DB db;
+    da.init(g.lda, tc.m0, wave, lane);
+    db.init(g.ldb, tc.n0, wave, lane);
 
     f32x16 acc[2][2];
 #pragma unroll
@@ -302,11 +265,15 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
             for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
 
     const int total = g.K / kSlice;
-    issue(0, 0);
-    sync();
+    da.issue(ra, As[0], 0, wave);
+    db.issue(rb, Bs[0], 0, wave);
+    dma_slice_sync();
     for (int t = 0; t < total; t++) {
         const int cur = t & 1;
-        if (t + 1 < total) issue(t + 1, cur ^ 1);
+        if (t + 1 < total) {
+            da.issue(ra, As[cur ^ 1], t + 1, wave);
+            db.issue(rb, Bs[cur ^ 1], t + 1, wave);
+        }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         const float* a_s = As[cur];
         const float* b_s = Bs[cur];
@@ -316,28 +283,26 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
         for (int i = 0; i < 2; i++) {
             const int row = wm * 64 + i * 32 + c;
             if (AK) {
-                const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + row * kSlice + ((2 * h) ^ ((row >> 2) & 3)) * 4);
-                const f32x4 x1 =
-                    *reinterpret_cast<const f32x4*>(a_s + row * kSlice + ((2 * h + 1) ^ ((row >> 2) & 3)) * 4);
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(a_s + DA::kc_off(row, 2 * h));
+                const f32x4 x1 = *reinterpret_cast<const f32x4*>(a_s + DA::kc_off(row, 2 * h + 1));
 #pragma unroll
                 for (int e = 0; e < 4; e++) { av[i][e] = x0[e]; av[i][4 + e] = x1[e]; }
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; j++) av[i][j] = a_s[dl_mn_off(h * 8 + j, row)];
+                for (int j = 0; j < 8; j++) av[i][j] = a_s[DA::mn_off(h * 8 + j, row)];
             }
         }
 #pragma unroll
         for (int i = 0; i < 2; i++) {
             const int col = wn * 64 + i * 32 + c;
             if (BK) {
-                const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + col * kSlice + ((2 * h) ^ ((col >> 2) & 3)) * 4);
-                const f32x4 x1 =
-                    *reinterpret_cast<const f32x4*>(b_s + col * kSlice + ((2 * h + 1) ^ ((col >> 2) & 3)) * 4);
+                const f32x4 x0 = *reinterpret_cast<const f32x4*>(b_s + DB::kc_off(col, 2 * h));
+                const f32x4 x1 = *reinterpret_cast<const f32x4*>(b_s + DB::kc_off(col, 2 * h + 1));
 #pragma unroll
                 for (int e = 0; e < 4; e++) { bv[i][e] = x0[e]; bv[i][4 + e] = x1[e]; }
             } else {
 #pragma unroll
-                for (int j = 0; j < 8; j++) bv[i][j] = b_s[dl_mn_off(h * 8 + j, col)];
+                for (int j = 0; j < 8; j++) bv[i][j] = b_s[DB::mn_off(h * 8 + j, col)];
             }
         }
 #pragma unroll
@@ -348,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
                 for (int k = 0; k < 2; k++)
                     acc[i][k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i][j], bv[k][j], acc[i][k], 0, 0, 0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        sync();
+        dma_slice_sync();
     }
 
     float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs;

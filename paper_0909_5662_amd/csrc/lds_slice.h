@@ -1,6 +1,7 @@
 // Device helpers shared by the LDS-staged GEMM kernels (gemm.hip,
-// grouped.hip, gemm_bf16x3.hip): the XCD-aware workgroup order and the
-// operand slice staged through registers into LDS.
+// grouped.hip, gemm_bf16x3.hip): the XCD-aware workgroup order, the operand
+// slice staged through registers into LDS, and (gemm.hip) the FP32 slice
+// filled by buffer loads with LDS destination.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -106,6 +107,67 @@ struct LdsSlice {
         }
     }
 };
+
+// One FP32 K slice (16 k) of 128 rows (M/N extent) filled by buffer loads
+// with LDS destination, for a workgroup of 4 waves: no staging registers and
+// no per-slice address arithmetic (the slice advance is the scalar offset).
+// Wave w copies 1 KB pieces w and w + 4, lane l the 16 bytes at piece offset
+// 16 l.  LDS layouts:
+//  * K-contiguous operand: 128 rows of 16 floats, chunk q of row r in slot
+//    q ^ ((r / 4) % 4) (LdsSlice<float, 128, ., true>::kc_off); piece y holds
+//    rows 16 y .. 16 y + 15, so lane l fetches row 16 y + l / 4, chunk
+//    (l % 4) ^ ((row / 4) % 4).
+//  * M/N-contiguous operand: k rows of 128 floats in pairs, pair p (rows 2p,
+//    2p + 1, one piece) at 264 p floats: rows k and k + 8, which the fragment
+//    reads of the two lane halves take together, then lie 32 banks apart.
+// Both take as many floats as the LdsSlice layouts of the same slice.  The
+// operand's byte offsets (from the descriptor's base) must stay below 2^32.
+template <bool KCONTIG>
+struct DmaSlice128 {
+    static constexpr int R = 128, SK = 16, PAIR = 2 * R + 8;
+    static constexpr int ELEMS = KCONTIG ? R * SK : (SK / 2) * PAIR;
+    uint32_t off[2];  // this lane's byte offsets in its two pieces of slice 0
+    uint32_t step;    // bytes from one slice to the next
+
+    __device__ static inline int kc_off(int row, int q) { return row * SK + (q ^ ((row >> 2) & 3)) * 4; }
+    __device__ static inline int mn_off(int kr, int col) { return (kr >> 1) * PAIR + (kr & 1) * R + col; }
+    __device__ static inline int piece(int y) { return KCONTIG ? y * 256 : y * PAIR; }
+
+    // ld: the operand's row stride (elements); r0: the slice's first row (M/N)
+    __device__ inline void init(int64_t ld, int r0, int wave, int lane) {
+#pragma unroll
+        for (int x = 0; x < 2; x++) {
+            const int y = wave + 4 * x;
+            int64_t e;
+            if (KCONTIG) {
+                const int row = 16 * y + (lane >> 2);
+                e = (int64_t)(r0 + row) * ld + 4 * ((lane & 3) ^ ((row >> 2) & 3));
+            } else {
+                e = (int64_t)(2 * y + (lane >> 5)) * ld + r0 + 4 * (lane & 31);
+            }
+            off[x] = (uint32_t)(e * 4);
+        }
+        step = (uint32_t)(KCONTIG ? SK * 4 : (int64_t)SK * ld * 4);
+    }
+    // slice t of the operand behind `rs` into `buf` (ELEMS floats of LDS)
+    __device__ inline void issue(__amdgpu_buffer_rsrc_t rs, float* buf, int t, int wave) const {
+        typedef __attribute__((address_space(3))) void* lptr;
+#pragma unroll
+        for (int x = 0; x < 2; x++)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(buf + piece(wave + 4 * x)), 16, off[x],
+                                                     (int)((uint32_t)t * step), 0, 0);
+    }
+};
+
+// Wait until this wave's buffer loads with LDS destination are done, then
+// the workgroup barrier (the compiler neither moves memory accesses across
+// it nor counts those loads itself).
+__device__ inline void dma_slice_sync() {
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 }  // namespace
 }  // namespace rot
