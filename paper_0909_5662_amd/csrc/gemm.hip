@@ -18,6 +18,8 @@
 // tiles, and tiles sharing an operand panel stay on one XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "buffer_rsrc.h"
 #include "lds_slice.h"
 #include "rot_internal.h"
@@ -227,11 +229,12 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 
 // FP32 product of whole tiles with both K slices filled by buffer loads with
 // LDS destination (DmaSlice128): no staging registers, no per-slice address
-// arithmetic, one wait and barrier per slice.  Same fragment reads and
-// products as gemm_f32_kernel, so the same bits.  Requires M, N multiples of
-// 128, K of 16, 16-byte aligned rows, no split, accumulation or symmetric
-// output, and each operand's batch entry under 4 GiB (direct_lds_ok).
-template <bool AK, bool BK>
+// arithmetic, one wait and barrier per slice.  Same fragment reads,
+// products and stores as gemm_f32_kernel (UPPER: its symmetric output), so
+// the same bits.  Requires M, N multiples of 128, K of 16, 16-byte aligned
+// rows, no split or accumulation, and each operand's batch entry under 4 GiB
+// (direct_lds_ok).
+template <bool AK, bool BK, bool UPPER>
 __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int tiles_m, int tiles_n) {
     typedef DmaSlice128<AK> DA;
     typedef DmaSlice128<BK> DB;
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
     __shared__ __attribute__((aligned(1024))) float As[2][DA::ELEMS];
     __shared__ __attribute__((aligned(1024))) float Bs[2][DB::ELEMS];
 
-    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, false);
+    const TileCoord tc = tile_coord(xcd_linear_id(), tiles_m, tiles_n, UPPER);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -317,6 +320,10 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
     }
 
     float* Cb = static_cast<float*>(g.C) + (int64_t)tc.g * g.c_bs;
+    // symmetric output: a diagonal tile keeps row <= col and mirrors it; an
+    // off-diagonal tile is also stored transposed (a lane's rows 8q + 4h ..
+    // +3 become four consecutive entries of row `col`)
+    const bool diag = UPPER && tc.m0 == tc.n0;
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
@@ -325,9 +332,33 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int row = tc.m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-                Cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
+                if (!diag || row <= col) {
+                    Cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
+                    if (diag && row < col) Cb[(int64_t)col * g.ldc + row] = acc[i][k][v];
+                }
             }
         }
+    if (UPPER && !diag) {
+        const bool vec4 = (g.ldc & 3) == 0 && (reinterpret_cast<uintptr_t>(Cb) & 15) == 0;
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int col = tc.n0 + wn * 64 + k * 32 + c;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int row0 = tc.m0 + wm * 64 + i * 32 + 8 * q + 4 * h;
+                    float* p = Cb + (int64_t)col * g.ldc + row0;
+                    if (vec4) {
+                        *reinterpret_cast<f32x4*>(p) = f32x4{acc[i][k][4 * q], acc[i][k][4 * q + 1],
+                                                             acc[i][k][4 * q + 2], acc[i][k][4 * q + 3]};
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; e++) p[e] = acc[i][k][4 * q + e];
+                    }
+                }
+            }
+    }
 }
 
 // ---------------------------------------------------------------- FP64 ----
@@ -463,11 +494,10 @@ bool vector_ok(const GemmDesc& g) {
 }
 
 // The direct-to-LDS FP32 kernel's conditions (16-byte alignment is checked
-// by vector_ok): whole tiles and slices, no split, accumulation, symmetric
-// output or K batching, and every byte offset of an operand's batch entry
-// below 2^32.
+// by vector_ok): whole tiles and slices, no split, accumulation or K
+// batching, and every byte offset of an operand's batch entry below 2^32.
 bool direct_lds_ok(const GemmDesc& g) {
-    if (g.upper || g.accumulate || g.parts > 1 || g.kbatch != 1) return false;
+    if (g.accumulate || g.parts > 1 || g.kbatch != 1) return false;
     if (g.M % kTile != 0 || g.N % kTile != 0 || g.K % kSlice != 0 || g.K <= 0) return false;
     const int64_t ea = g.a_kcontig ? (int64_t)(g.M - 1) * g.lda + g.K : (int64_t)(g.K - 1) * g.lda + g.M;
     const int64_t eb = g.b_kcontig ? (int64_t)(g.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + g.N;
@@ -514,12 +544,14 @@ hipError_t gemm_any(const GemmDesc& g, hipStream_t stream) {
     const dim3 grid((unsigned)tiles);
     const bool vec = vector_ok<T>(g);
     if (sizeof(T) == 4 && vec && direct_lds_ok(g)) {
-        if (g.a_kcontig)
-            hipLaunchKernelGGL((g.b_kcontig ? gemm_f32_dl_kernel<true, true> : gemm_f32_dl_kernel<true, false>), grid,
-                               dim3(kThreads), 0, stream, g, tm, tn);
-        else
-            hipLaunchKernelGGL((g.b_kcontig ? gemm_f32_dl_kernel<false, true> : gemm_f32_dl_kernel<false, false>),
-                               grid, dim3(kThreads), 0, stream, g, tm, tn);
+        auto pick = [&](auto up) {
+            constexpr bool U = decltype(up)::value;
+            if (g.a_kcontig)
+                return g.b_kcontig ? gemm_f32_dl_kernel<true, true, U> : gemm_f32_dl_kernel<true, false, U>;
+            return g.b_kcontig ? gemm_f32_dl_kernel<false, true, U> : gemm_f32_dl_kernel<false, false, U>;
+        };
+        hipLaunchKernelGGL((g.upper ? pick(std::true_type{}) : pick(std::false_type{})), grid, dim3(kThreads), 0,
+                           stream, g, tm, tn);
         return hipGetLastError();
     }
     if (sizeof(T) == 4) return launch_gemm_f32_kernel(g, vec, grid, tm, tn, stream);
