@@ -230,12 +230,15 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 // FP32 product of whole tiles with both K slices filled by buffer loads with
 // LDS destination (DmaSlice128): no staging registers, no per-slice address
 // arithmetic, one wait and barrier per slice.  Same fragment reads,
-// products and stores as gemm_f32_kernel (UPPER: its symmetric output), so
-// the same bits.  Requires M, N multiples of 128, K of 16, 16-byte aligned
-// rows, no split or accumulation, and each operand's batch entry under 4 GiB
+// products and stores as gemm_f32_kernel, so the same bits.  MODE 0: one K
+// batch, plain stores; 1: symmetric output; 2: K batches (the slices of
+// batch kb after those of kb - 1) and, with g.accumulate, C += result.
+// Requires M, N multiples of 128, K of 16, 16-byte aligned rows, no split,
+// and each operand's batch entry (all its K batches) under 4 GiB
 // (direct_lds_ok).
-template <bool AK, bool BK, bool UPPER>
+template <bool AK, bool BK, int MODE>
 __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int tiles_m, int tiles_n) {
+    constexpr bool UPPER = MODE == 1;
     typedef DmaSlice128<AK> DA;
     typedef DmaSlice128<BK> DB;
     static_assert(kTile == DA::R && kSlice == DA::SK, "slice shape");
@@ -267,16 +270,24 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
 #pragma unroll
             for (int v = 0; v < 16; v++) acc[i][j][v] = 0.f;
 
-    const int total = g.K / kSlice;
-    da.issue(ra, As[0], 0, wave);
-    db.issue(rb, Bs[0], 0, wave);
+    const int nk = g.K / kSlice;
+    const int total = MODE == 2 ? nk * g.kbatch : nk;
+    // slice t: K batch t / nk, slice t % nk of it
+    auto issue = [&](int t, int buf) __attribute__((always_inline)) {
+        if (MODE == 2) {
+            const int kb = t / nk, kt = t - kb * nk;
+            da.issue_at(ra, As[buf], (uint32_t)kb * (uint32_t)(g.a_ks * 4) + (uint32_t)kt * da.step, wave);
+            db.issue_at(rb, Bs[buf], (uint32_t)kb * (uint32_t)(g.b_ks * 4) + (uint32_t)kt * db.step, wave);
+        } else {
+            da.issue(ra, As[buf], t, wave);
+            db.issue(rb, Bs[buf], t, wave);
+        }
+    };
+    issue(0, 0);
     dma_slice_sync();
     for (int t = 0; t < total; t++) {
         const int cur = t & 1;
-        if (t + 1 < total) {
-            da.issue(ra, As[cur ^ 1], t + 1, wave);
-            db.issue(rb, Bs[cur ^ 1], t + 1, wave);
-        }
+        if (t + 1 < total) issue(t + 1, cur ^ 1);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         const float* a_s = As[cur];
         const float* b_s = Bs[cur];
@@ -329,6 +340,20 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             const int col = tc.n0 + wn * 64 + k * 32 + c;
+            if (MODE == 2 && g.accumulate) {
+                // the previous values of each group of four rows are loaded
+                // before the group's stores, four loads in flight together
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int row0 = tc.m0 + wm * 64 + i * 32 + 8 * q + 4 * h;
+                    float old[4];
+#pragma unroll
+                    for (int e = 0; e < 4; e++) old[e] = Cb[(int64_t)(row0 + e) * g.ldc + col];
+#pragma unroll
+                    for (int e = 0; e < 4; e++) Cb[(int64_t)(row0 + e) * g.ldc + col] = old[e] + acc[i][k][4 * q + e];
+                }
+                continue;
+            }
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int row = tc.m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -494,13 +519,16 @@ bool vector_ok(const GemmDesc& g) {
 }
 
 // The direct-to-LDS FP32 kernel's conditions (16-byte alignment is checked
-// by vector_ok): whole tiles and slices, no split, accumulation or K
-// batching, and every byte offset of an operand's batch entry below 2^32.
+// by vector_ok): whole tiles and slices, no split, and every byte offset of
+// an operand's batch entry (over all K batches) below 2^32.
 bool direct_lds_ok(const GemmDesc& g) {
-    if (g.accumulate || g.parts > 1 || g.kbatch != 1) return false;
+    if (g.parts > 1 || g.kbatch < 1) return false;
     if (g.M % kTile != 0 || g.N % kTile != 0 || g.K % kSlice != 0 || g.K <= 0) return false;
-    const int64_t ea = g.a_kcontig ? (int64_t)(g.M - 1) * g.lda + g.K : (int64_t)(g.K - 1) * g.lda + g.M;
-    const int64_t eb = g.b_kcontig ? (int64_t)(g.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + g.N;
+    if (g.kbatch > 1 && (g.a_ks < 0 || g.b_ks < 0)) return false;
+    const int64_t ea = (g.a_kcontig ? (int64_t)(g.M - 1) * g.lda + g.K : (int64_t)(g.K - 1) * g.lda + g.M) +
+                       (int64_t)(g.kbatch - 1) * g.a_ks;
+    const int64_t eb = (g.b_kcontig ? (int64_t)(g.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + g.N) +
+                       (int64_t)(g.kbatch - 1) * g.b_ks;
     return ea * 4 < ((int64_t)1 << 32) && eb * 4 < ((int64_t)1 << 32);
 }
 
@@ -544,14 +572,17 @@ hipError_t gemm_any(const GemmDesc& g, hipStream_t stream) {
     const dim3 grid((unsigned)tiles);
     const bool vec = vector_ok<T>(g);
     if (sizeof(T) == 4 && vec && direct_lds_ok(g)) {
-        auto pick = [&](auto up) {
-            constexpr bool U = decltype(up)::value;
+        auto pick = [&](auto mode) {
+            constexpr int MD = decltype(mode)::value;
             if (g.a_kcontig)
-                return g.b_kcontig ? gemm_f32_dl_kernel<true, true, U> : gemm_f32_dl_kernel<true, false, U>;
-            return g.b_kcontig ? gemm_f32_dl_kernel<false, true, U> : gemm_f32_dl_kernel<false, false, U>;
+                return g.b_kcontig ? gemm_f32_dl_kernel<true, true, MD> : gemm_f32_dl_kernel<true, false, MD>;
+            return g.b_kcontig ? gemm_f32_dl_kernel<false, true, MD> : gemm_f32_dl_kernel<false, false, MD>;
         };
-        hipLaunchKernelGGL((g.upper ? pick(std::true_type{}) : pick(std::false_type{})), grid, dim3(kThreads), 0,
-                           stream, g, tm, tn);
+        const bool general = g.accumulate || g.kbatch > 1;
+        hipLaunchKernelGGL((g.upper     ? pick(std::integral_constant<int, 1>{})
+                            : general ? pick(std::integral_constant<int, 2>{})
+                                      : pick(std::integral_constant<int, 0>{})),
+                           grid, dim3(kThreads), 0, stream, g, tm, tn);
         return hipGetLastError();
     }
     if (sizeof(T) == 4) return launch_gemm_f32_kernel(g, vec, grid, tm, tn, stream);

@@ -149,13 +149,17 @@ struct DmaSlice128 {
         }
         step = (uint32_t)(KCONTIG ? SK * 4 : (int64_t)SK * ld * 4);
     }
-    // slice t of the operand behind `rs` into `buf` (ELEMS floats of LDS)
-    __device__ inline void issue(__amdgpu_buffer_rsrc_t rs, float* buf, int t, int wave) const {
+    // the slice `soff` bytes past slice 0 of the operand behind `rs` into
+    // `buf` (ELEMS floats of LDS)
+    __device__ inline void issue_at(__amdgpu_buffer_rsrc_t rs, float* buf, uint32_t soff, int wave) const {
         typedef __attribute__((address_space(3))) void* lptr;
 #pragma unroll
         for (int x = 0; x < 2; x++)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(buf + piece(wave + 4 * x)), 16, off[x],
-                                                     (int)((uint32_t)t * step), 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(buf + piece(wave + 4 * x)), 16, off[x], (int)soff, 0, 0);
+    }
+    // slice t
+    __device__ inline void issue(__amdgpu_buffer_rsrc_t rs, float* buf, int t, int wave) const {
+        issue_at(rs, buf, (uint32_t)t * step, wave);
     }
 };
 
