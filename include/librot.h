@@ -314,7 +314,11 @@ ROT_API rot_status rot_plan_execute(rot_plan plan, void* stream);
  * capture or tuning is repeated).  An execution in flight on another stream
  * must be ordered against the rebind by the caller.  The first rebind
  * allocates a pinned staging buffer; each rebind waits for the previous
- * rebind's copies to leave it.
+ * rebind's copies to leave it.  A size class tuned to the kernel that copies
+ * K slices straight into LDS (all its products in whole 128 x 128 tiles with
+ * 16-byte aligned U and O) keeps that kernel: new U or O buffers of such a
+ * class that are not 16-byte aligned are refused with ROT_ERR_INVALID_ARG
+ * before anything changes.
  */
 ROT_API rot_status rot_plan_rebind(rot_plan plan, const rot_problem* groups, int32_t n_groups, void* stream);
 ROT_API int32_t rot_plan_describe(rot_plan plan, char* buf, size_t len);

@@ -88,19 +88,25 @@ int ceil_log2(int64_t x) {
 }
 
 // ---------------------------------------------------------------- tuning --
-const char* shape_name(GroupedShape s) { return s == GroupedShape::k128 ? "128" : s == GroupedShape::k64 ? "64" : "32"; }
+const char* shape_name(GroupedShape s) {
+    return s == GroupedShape::k128d ? "128d" : s == GroupedShape::k128 ? "128" : s == GroupedShape::k64 ? "64" : "32";
+}
 
-// A plan class's cached choice: tokens "tile-edge schedule persistent-grid";
+// A plan class's cached choice: tokens "tile-edge schedule persistent-grid"
+// (tile edge 128d: 128 with K slices copied straight into LDS);
 // false when absent or not of that form.
 bool cached_choice(const std::string& key, GroupedShape* shape, bool* dynamic, int* grid) {
     std::vector<std::string> t;
     if (!tune_get(key, &t) || t.size() != 3) return false;
-    if (t[0] != "128" && t[0] != "64" && t[0] != "32") return false;
+    if (t[0] != "128" && t[0] != "128d" && t[0] != "64" && t[0] != "32") return false;
     if (t[1] != "static" && t[1] != "dynamic") return false;
     char* end = nullptr;
     const long g = strtol(t[2].c_str(), &end, 10);
     if (!end || *end || g < 0 || g > (1 << 24)) return false;
-    *shape = t[0] == "64" ? GroupedShape::k64 : t[0] == "32" ? GroupedShape::k32 : GroupedShape::k128;
+    *shape = t[0] == "64"     ? GroupedShape::k64
+             : t[0] == "32"   ? GroupedShape::k32
+             : t[0] == "128d" ? GroupedShape::k128d
+                              : GroupedShape::k128;
     *dynamic = t[1] == "dynamic";
     *grid = (int)g;
     return true;
@@ -141,7 +147,24 @@ GroupedProblem stage_problem(const rot_problem& p, int b, const float* T, int st
         g.ldc = p.ldout;
         g.flags = (al(U) && p.ldu % 4 == 0) ? kGroupedVec : 0;
     }
+    // whole tiles and slices for buffer loads with LDS destination (A is
+    // K-contiguous in stage 1, M-contiguous in stage 2; B is N-contiguous)
+    const int64_t ea = stage == 1 ? (int64_t)(g.M - 1) * g.lda + g.K : (int64_t)(g.K - 1) * g.lda + g.M;
+    const int64_t eb = (int64_t)(g.K - 1) * g.ldb + g.N;
+    if ((g.flags & kGroupedVec) && g.M % 128 == 0 && g.N % 128 == 0 && g.K % 16 == 0 && g.K > 0 &&
+        ea * 4 < ((int64_t)1 << 32) && eb * 4 < ((int64_t)1 << 32))
+        g.flags |= kGroupedWhole;
     return g;
+}
+
+// Every problem of class `ci`'s launches is whole (the k128d shape applies).
+bool class_whole(const rot_plan_s* P, int ci) {
+    for (size_t li = 0; li < P->launches.size(); li++) {
+        if (P->launches[li].cls != ci) continue;
+        for (const GroupedProblem& g : P->host_probs[li])
+            if (!(g.flags & kGroupedWhole)) return false;
+    }
+    return true;
 }
 
 std::vector<GroupedTile> tiles_for(const std::vector<GroupedProblem>& probs, int edge) {
@@ -208,12 +231,19 @@ hipError_t tune_class(rot_plan_s* P, int ci, int n_cu) {
         bool dynamic;
         int grid_per_cu;  // 0: one workgroup per tile
     };
-    // 128 x 128 tiles run at up to 3 workgroups (12 waves) per CU, 64 x 64 at 7
-    const Cand cands[] = {
-        {GroupedShape::k128, false, 0}, {GroupedShape::k128, true, 2}, {GroupedShape::k128, false, 2},
-        {GroupedShape::k128, true, 3},  {GroupedShape::k128, false, 3}, {GroupedShape::k64, false, 0},
-        {GroupedShape::k64, true, 6},
+    // 128 x 128 tiles run at up to 3 workgroups (12 waves) per CU, 64 x 64 at
+    // 7, 128 x 128 with slices by buffer loads with LDS destination (whole
+    // problems only) at 4
+    const bool whole = class_whole(P, ci);
+    const Cand all[] = {
+        {GroupedShape::k128, false, 0},  {GroupedShape::k128, true, 2},   {GroupedShape::k128, false, 2},
+        {GroupedShape::k128, true, 3},   {GroupedShape::k128, false, 3},  {GroupedShape::k64, false, 0},
+        {GroupedShape::k64, true, 6},    {GroupedShape::k128d, false, 0}, {GroupedShape::k128d, true, 4},
+        {GroupedShape::k128d, false, 4},
     };
+    std::vector<Cand> cands;
+    for (const Cand& cd : all)
+        if (cd.shape != GroupedShape::k128d || whole) cands.push_back(cd);
     hipEvent_t a, b;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
@@ -431,7 +461,8 @@ rot_status rot_plan_create(const rot_problem* groups, int32_t n_groups, rot_prec
             GroupedShape shape;
             bool dynamic;
             int grid;
-            if (!(flags & ROT_PLAN_RETUNE) && cached_choice(c.key, &shape, &dynamic, &grid)) {
+            if (!(flags & ROT_PLAN_RETUNE) && cached_choice(c.key, &shape, &dynamic, &grid) &&
+                (shape != GroupedShape::k128d || class_whole(P, ci))) {
                 c.shape = shape;
                 c.dynamic = dynamic;
                 c.grid = grid;
@@ -517,12 +548,27 @@ rot_status rot_plan_rebind(rot_plan plan, const rot_problem* groups, int32_t n_g
     e = hipEventSynchronize(plan->staged);
     if (e != hipSuccess) return perr(ROT_ERR_HIP, "rot_plan_rebind: %s", hipGetErrorString(e));
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // the new tables; a class tuned to the k128d shape needs every problem
+    // whole (16-byte aligned U and O), checked before anything changes
     size_t at = 0;
+    for (size_t li = 0; li < plan->launches.size(); li++) {
+        auto& L = plan->launches[li];
+        GroupedProblem* dst = plan->staging + at;
+        const bool need_whole = plan->classes[L.cls].shape == GroupedShape::k128d;
+        for (size_t k = 0; k < L.src.size(); k++) {
+            dst[k] = stage_problem(rg[L.src[k].first], L.src[k].second, L.t[k], L.stage);
+            if (need_whole && !(dst[k].flags & kGroupedWhole))
+                return perr(ROT_ERR_INVALID_ARG,
+                            "rot_plan_rebind: group %d's U or O is not 16-byte aligned, which the plan's kernels for "
+                            "its size class need (the plan was created with aligned buffers)",
+                            L.src[k].first);
+        }
+        at += L.src.size();
+    }
+    at = 0;
     for (size_t li = 0; li < plan->launches.size() && e == hipSuccess; li++) {
         auto& L = plan->launches[li];
         GroupedProblem* dst = plan->staging + at;
-        for (size_t k = 0; k < L.src.size(); k++)
-            dst[k] = stage_problem(rg[L.src[k].first], L.src[k].second, L.t[k], L.stage);
         plan->host_probs[li].assign(dst, dst + L.src.size());
         // in stream order: replays enqueued before this call read the old tables
         e = hipMemcpyAsync(L.probs, dst, sizeof(GroupedProblem) * L.src.size(), hipMemcpyHostToDevice, s);
@@ -551,7 +597,8 @@ int32_t rot_plan_describe(rot_plan plan, char* buf, size_t len) {
     for (size_t i = 0; i < plan->classes.size(); i++) {
         const auto& c = plan->classes[i];
         os << (i ? ", " : "") << "{\"key\": \"" << c.key << "\", \"ops\": " << c.n_ops << ", \"gflop\": "
-           << c.flops / 1e9 << ", \"tile\": " << shape_name(c.shape) << ", \"schedule\": \""
+           << c.flops / 1e9 << ", \"tile\": " << grouped_tile_edge(c.shape)
+           << ", \"lds_direct\": " << (c.shape == GroupedShape::k128d ? "true" : "false") << ", \"schedule\": \""
            << (c.dynamic ? "dynamic" : "static") << "\", \"grid\": " << c.grid << ", \"tuned_now\": "
            << (c.tuned ? "true" : "false") << "}";
     }

@@ -40,9 +40,15 @@ struct GemmDesc {
 };
 
 // ---- grouped GEMM over a work-list (grouped.hip) ----
-enum class GroupedShape : int { k128 = 0, k64 = 1, k32 = 2 };
+// k128d: 128 x 128 tiles whose K slices are filled by buffer loads with LDS
+// destination (every problem of the launch must carry kGroupedWhole).
+enum class GroupedShape : int { k128 = 0, k64 = 1, k32 = 2, k128d = 3 };
 constexpr int kGroupedVec = 1;         // 16-byte vector loads allowed for this problem
 constexpr int kGroupedAccumulate = 2;  // C += result
+// Whole 128 x 128 tiles and 16-wide K slices, 16-byte aligned rows, no
+// accumulation, and every byte offset of A and B (from the problem's
+// positions) below 2^32.
+constexpr int kGroupedWhole = 4;
 // One GEMM C (M x N) (+)= A (M x K) B (K x N); operand/result positions are
 // element offsets from the launch's base pointers (absolute byte addresses
 // when the base is null).  Layouts are per launch.

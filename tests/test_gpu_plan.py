@@ -224,4 +224,66 @@ def test_tune_cache_file_written_read_and_corrupt(rot, tmp_path):
     third = _plan_child(tmp_path, bad, False)
     assert third["err"] <= 1e-6
     for c in third["classes"]:
-        assert not c["tuned_now"] and (c["tile"], c["schedule"], c["grid"]) == (128, "static", 0)
+        assert not c["tuned_now"] and (c["tile"], c["schedule"], c["grid"], c["lds_direct"]) == (128, "static", 0, False)
+
+
+DIRECT_CHILD = r"""
+import json, sys, torch
+sys.path.insert(0, {root!r})
+import paper_0909_5662_amd as rot, workloads
+data = workloads.uneven_case_gpu([128, 256, 200], d=4, ops_per_rot=2, cfg=91)
+groups = [(U, O, torch.full((2, U.shape[1], U.shape[1]), float("nan"), device="cuda"), 4) for U, O in data]
+plan = rot.Plan(groups, tune=False)
+plan.execute()
+torch.cuda.synchronize()
+ref = [rot.rotate(U, O, d, "fp32") for U, O, _, d in groups]
+err = max(((out - r).norm() / r.norm()).item() for (_, _, out, _), r in zip(groups, ref))
+# a group of a direct-LDS class rebound to a U that is not 16-byte aligned is refused
+refused = None
+U0, O0, out0, d0 = groups[0]
+buf = torch.empty(U0.numel() + 1, device="cuda")
+U_bad = buf[1:].view(U0.shape)
+U_bad.copy_(U0)
+try:
+    plan.rebind([(U_bad, O0, out0, d0)] + groups[1:])
+    refused = False
+except rot.RotError as e:
+    refused = "16-byte" in str(e)
+for _, _, out, _ in groups:
+    out.fill_(float("nan"))
+plan.execute()
+torch.cuda.synchronize()
+err_after = max(((out - r).norm() / r.norm()).item() for (_, _, out, _), r in zip(groups, ref))
+print(json.dumps({{"classes": plan.describe()["classes"], "err": err, "err_after": err_after, "refused": refused}}))
+"""
+
+
+@pytest.mark.timeout(600)
+def test_plan_direct_lds_shape_from_cache_and_rebind_guard(rot, tmp_path):
+    """Classes whose products are all whole 128 x 128 tiles may run the kernel
+    that copies K slices straight into LDS (tile token 128d, forced here
+    through the tuning cache); a class with a ragged size keeps the
+    register-staged kernel although its cache line asks for 128d.  Results
+    equal the eager rotation; a rebind of a direct-LDS class to a U that is
+    not 16-byte aligned is refused and leaves the plan working on its old
+    buffers."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    first = _plan_child(tmp_path, tmp_path / "unused.txt", False)
+    cache = tmp_path / "direct.txt"
+    cache.write_text("".join(f"{c['key']} 128d dynamic 1024\n" for c in first["classes"]))
+    env = dict(os.environ, ROT_TUNE_CACHE=str(cache))
+    env.pop("ROT_SCHEDULE", None)
+    res = subprocess.run([sys.executable, "-c", DIRECT_CHILD.format(root=root)], capture_output=True, text=True,
+                         env=env, timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    out = json.loads(res.stdout.strip().splitlines()[-1])
+    assert out["err"] <= 1e-6 and out["err_after"] <= 1e-6
+    direct = [c for c in out["classes"] if c["lds_direct"]]
+    assert direct and all(c["tile"] == 128 and c["schedule"] == "dynamic" and c["grid"] == 1024 for c in direct)
+    # sizes 200 and 256 share a class (m*d and m' rounded up to powers of two); 200 is ragged
+    assert any(not c["lds_direct"] for c in out["classes"])
+    assert out["refused"] is True
