@@ -233,10 +233,13 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_kernel(GemmDesc g, int tile
 // products and stores as gemm_f32_kernel, so the same bits.  MODE 0: one K
 // batch, plain stores; 1: symmetric output; 2: K batches (the slices of
 // batch kb after those of kb - 1) and, with g.accumulate, C += result.
-// Requires M, N multiples of 128, K of 16, 16-byte aligned rows, no split,
-// and each operand's batch entry (all its K batches) under 4 GiB
-// (direct_lds_ok).
-template <bool AK, bool BK, int MODE>
+// Requires K a multiple of 16, 16-byte aligned rows, no split, and each
+// operand's batch entry (all its K batches) under 4 GiB (direct_lds_ok).
+// EDGE (M or N not a multiple of 128): slices of a last, partial tile read
+// whatever lies past the operand's rows or columns (zero past the batch
+// entry, whose extent bounds the descriptors); those values only reach rows
+// and columns of C that are not stored.
+template <bool AK, bool BK, int MODE, bool EDGE>
 __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int tiles_m, int tiles_n) {
     constexpr bool UPPER = MODE == 1;
     typedef DmaSlice128<AK> DA;
@@ -253,10 +256,13 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
 
     const float* Ab = static_cast<const float*>(g.A) + (int64_t)tc.g * g.a_bs;
     const float* Bb = static_cast<const float*>(g.B) + (int64_t)tc.g * g.b_bs;
-    const __amdgpu_buffer_rsrc_t ra =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Ab), (short)0, (int)0xffffffff, kBufferFlags);
-    const __amdgpu_buffer_rsrc_t rb =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Bb), (short)0, (int)0xffffffff, kBufferFlags);
+    const int kb1 = MODE == 2 ? g.kbatch - 1 : 0;
+    const int64_t ea = (AK ? (int64_t)(g.M - 1) * g.lda + g.K : (int64_t)(g.K - 1) * g.lda + g.M) + kb1 * g.a_ks;
+    const int64_t eb = (BK ? (int64_t)(g.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + g.N) + kb1 * g.b_ks;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(Ab), (short)0, EDGE ? (int)(uint32_t)(ea * 4) : (int)0xffffffff, kBufferFlags);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(Bb), (short)0, EDGE ? (int)(uint32_t)(eb * 4) : (int)0xffffffff, kBufferFlags);
     DA da;
     DB db;
     da.init(g.lda, tc.m0, wave, lane);
@@ -340,24 +346,29 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
 #pragma unroll
         for (int k = 0; k < 2; k++) {
             const int col = tc.n0 + wn * 64 + k * 32 + c;
+            if (EDGE && col >= g.N) continue;
             if (MODE == 2 && g.accumulate) {
                 // the previous values of each group of four rows are loaded
-                // before the group's stores, four loads in flight together
+                // before the group's stores (unconditionally, from element 0
+                // outside C), four loads in flight together
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int row0 = tc.m0 + wm * 64 + i * 32 + 8 * q + 4 * h;
                     float old[4];
 #pragma unroll
-                    for (int e = 0; e < 4; e++) old[e] = Cb[(int64_t)(row0 + e) * g.ldc + col];
+                    for (int e = 0; e < 4; e++)
+                        old[e] = Cb[!EDGE || row0 + e < g.M ? (int64_t)(row0 + e) * g.ldc + col : 0];
 #pragma unroll
-                    for (int e = 0; e < 4; e++) Cb[(int64_t)(row0 + e) * g.ldc + col] = old[e] + acc[i][k][4 * q + e];
+                    for (int e = 0; e < 4; e++)
+                        if (!EDGE || row0 + e < g.M)
+                            Cb[(int64_t)(row0 + e) * g.ldc + col] = old[e] + acc[i][k][4 * q + e];
                 }
                 continue;
             }
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int row = tc.m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-                if (!diag || row <= col) {
+                if ((!EDGE || row < g.M) && (!diag || row <= col)) {
                     Cb[(int64_t)row * g.ldc + col] = acc[i][k][v];
                     if (diag && row < col) Cb[(int64_t)col * g.ldc + row] = acc[i][k][v];
                 }
@@ -370,16 +381,18 @@ __global__ __launch_bounds__(kThreads) void gemm_f32_dl_kernel(GemmDesc g, int t
 #pragma unroll
             for (int k = 0; k < 2; k++) {
                 const int col = tc.n0 + wn * 64 + k * 32 + c;
+                if (EDGE && col >= g.N) continue;
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     const int row0 = tc.m0 + wm * 64 + i * 32 + 8 * q + 4 * h;
                     float* p = Cb + (int64_t)col * g.ldc + row0;
-                    if (vec4) {
+                    if (vec4 && (!EDGE || row0 + 4 <= g.M)) {
                         *reinterpret_cast<f32x4*>(p) = f32x4{acc[i][k][4 * q], acc[i][k][4 * q + 1],
                                                              acc[i][k][4 * q + 2], acc[i][k][4 * q + 3]};
                     } else {
 #pragma unroll
-                        for (int e = 0; e < 4; e++) p[e] = acc[i][k][4 * q + e];
+                        for (int e = 0; e < 4; e++)
+                            if (!EDGE || row0 + e < g.M) p[e] = acc[i][k][4 * q + e];
                     }
                 }
             }
@@ -519,17 +532,22 @@ bool vector_ok(const GemmDesc& g) {
 }
 
 // The direct-to-LDS FP32 kernel's conditions (16-byte alignment is checked
-// by vector_ok): whole tiles and slices, no split, and every byte offset of
-// an operand's batch entry (over all K batches) below 2^32.
+// by vector_ok): whole K slices, no split, and every byte offset of an
+// operand's batch entry (over all K batches, and the rows or columns a last
+// partial tile reads) below 2^32.
 bool direct_lds_ok(const GemmDesc& g) {
     if (g.parts > 1 || g.kbatch < 1) return false;
-    if (g.M % kTile != 0 || g.N % kTile != 0 || g.K % kSlice != 0 || g.K <= 0) return false;
+    if (g.K % kSlice != 0 || g.K <= 0) return false;
     if (g.kbatch > 1 && (g.a_ks < 0 || g.b_ks < 0)) return false;
     const int64_t ea = (g.a_kcontig ? (int64_t)(g.M - 1) * g.lda + g.K : (int64_t)(g.K - 1) * g.lda + g.M) +
                        (int64_t)(g.kbatch - 1) * g.a_ks;
     const int64_t eb = (g.b_kcontig ? (int64_t)(g.N - 1) * g.ldb + g.K : (int64_t)(g.K - 1) * g.ldb + g.N) +
                        (int64_t)(g.kbatch - 1) * g.b_ks;
-    return ea * 4 < ((int64_t)1 << 32) && eb * 4 < ((int64_t)1 << 32);
+    // a partial tile's slices reach up to 127 rows (K-contiguous) or columns
+    // past the operand
+    const int64_t ra = g.a_kcontig ? (int64_t)kTile * g.lda : kTile;
+    const int64_t rb = g.b_kcontig ? (int64_t)kTile * g.ldb : kTile;
+    return (ea + ra) * 4 < ((int64_t)1 << 32) && (eb + rb) * 4 < ((int64_t)1 << 32);
 }
 
 #define ROT_DISPATCH(KERNEL)                                                                       \
@@ -572,17 +590,21 @@ hipError_t gemm_any(const GemmDesc& g, hipStream_t stream) {
     const dim3 grid((unsigned)tiles);
     const bool vec = vector_ok<T>(g);
     if (sizeof(T) == 4 && vec && direct_lds_ok(g)) {
-        auto pick = [&](auto mode) {
+        const bool edge = g.M % kTile != 0 || g.N % kTile != 0;
+        auto pick = [&](auto mode, auto e) {
             constexpr int MD = decltype(mode)::value;
+            constexpr bool E = decltype(e)::value;
             if (g.a_kcontig)
-                return g.b_kcontig ? gemm_f32_dl_kernel<true, true, MD> : gemm_f32_dl_kernel<true, false, MD>;
-            return g.b_kcontig ? gemm_f32_dl_kernel<false, true, MD> : gemm_f32_dl_kernel<false, false, MD>;
+                return g.b_kcontig ? gemm_f32_dl_kernel<true, true, MD, E> : gemm_f32_dl_kernel<true, false, MD, E>;
+            return g.b_kcontig ? gemm_f32_dl_kernel<false, true, MD, E> : gemm_f32_dl_kernel<false, false, MD, E>;
         };
-        const bool general = g.accumulate || g.kbatch > 1;
-        hipLaunchKernelGGL((g.upper     ? pick(std::integral_constant<int, 1>{})
-                            : general ? pick(std::integral_constant<int, 2>{})
-                                      : pick(std::integral_constant<int, 0>{})),
-                           grid, dim3(kThreads), 0, stream, g, tm, tn);
+        auto pick_mode = [&](auto e) {
+            if (g.upper) return pick(std::integral_constant<int, 1>{}, e);
+            if (g.accumulate || g.kbatch > 1) return pick(std::integral_constant<int, 2>{}, e);
+            return pick(std::integral_constant<int, 0>{}, e);
+        };
+        hipLaunchKernelGGL((edge ? pick_mode(std::true_type{}) : pick_mode(std::false_type{})), grid,
+                           dim3(kThreads), 0, stream, g, tm, tn);
         return hipGetLastError();
     }
     if (sizeof(T) == 4) return launch_gemm_f32_kernel(g, vec, grid, tm, tn, stream);
