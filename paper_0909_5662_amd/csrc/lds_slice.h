@@ -163,6 +163,42 @@ struct DmaSlice128 {
     }
 };
 
+// The FP64 counterpart for a workgroup of 4 waves: 128 rows by 16 doubles,
+// 16 pieces of 1 KB, wave w copying pieces w, w + 4, w + 8, w + 12, in the
+// layouts of LdsSlice<double, 128, ., K>: a K-contiguous slice holds 8 rows
+// per piece (chunk q of row r in slot q ^ ((r / 2) % 8)), an M/N-contiguous
+// one a k row of 128 doubles per piece at a pitch of 132.
+template <bool KCONTIG>
+struct DmaSlice128D {
+    static constexpr int R = 128, SK = 16, PITCH = KCONTIG ? SK : R + 4;
+    static constexpr int ELEMS = KCONTIG ? R * SK : SK * PITCH;
+    uint32_t off[4];
+    uint32_t step;
+
+    __device__ static inline int piece(int y) { return KCONTIG ? y * 128 : y * PITCH; }
+    __device__ inline void init(int64_t ld, int r0, int wave, int lane) {
+#pragma unroll
+        for (int x = 0; x < 4; x++) {
+            const int y = wave + 4 * x;
+            int64_t e;
+            if (KCONTIG) {
+                const int row = 8 * y + (lane >> 3);
+                e = (int64_t)(r0 + row) * ld + 2 * ((lane & 7) ^ ((row >> 1) & 7));
+            } else {
+                e = (int64_t)y * ld + r0 + 2 * lane;
+            }
+            off[x] = (uint32_t)(e * 8);
+        }
+        step = (uint32_t)(KCONTIG ? SK * 8 : (int64_t)SK * ld * 8);
+    }
+    __device__ inline void issue_at(__amdgpu_buffer_rsrc_t rs, double* buf, uint32_t soff, int wave) const {
+        typedef __attribute__((address_space(3))) void* lptr;
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lptr)(buf + piece(wave + 4 * x)), 16, off[x], (int)soff, 0, 0);
+    }
+};
+
 // Wait until this wave's buffer loads with LDS destination are done, then
 // the workgroup barrier (the compiler neither moves memory accesses across
 // it nor counts those loads itself).
