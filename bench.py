@@ -121,7 +121,8 @@ def measure(rot, U, O, out, d, precision, steps, warmup, symmetric=False):
     peak = PEAK_TFLOPS[precision]
     exec_factor = 3.0 if precision == "split_bf16" else 1.0
     per_launch_flops = {"stage1": n * 2.0 * m * m * d * mp, "stage2": n * 2.0 * m * d * mp * mp,
-                        "stage2sym": n * 1.0 * m * d * mp * (mp + 1)}
+                        "stage2sym": n * 1.0 * m * d * mp * (mp + 1),
+                        "small": n * (2.0 * m * m * d * mp + 2.0 * m * d * mp * mp)}  # both stages, one launch
     stage_kernels = {k: v for k, v in kernels.items() if k.split("_")[0] in per_launch_flops}
     dom_name, (dom_count, dom_ms) = max(stage_kernels.items(), key=lambda kv: kv[1][1])
     dom_avg_ms = dom_ms / dom_count
@@ -659,9 +660,11 @@ def bench_dense(args, rot, torch, workloads, name):
         result["roofline"] = {"bound": "hbm", "achieved": result["algorithmic_gb_per_s_graph"],
                               "peak": 8000.0, "unit": "GB/s",
                               "frac": round(result["algorithmic_gb_per_s_graph"] / 8000.0, 5), "traffic": None,
-                              "kernel": "whole batch (2 launches)",
-                              "note": "134 MFLOP and 2.23 MB per batch: two dependent launches of 16 tiles "
-                                      "each; the time is launch latency, not bandwidth or matrix throughput"}
+                              "kernel": "whole batch (one launch, rotate_small_f64_kernel)",
+                              "note": "134 MFLOP and 2.23 MB per batch in one launch of 128 workgroups (both "
+                                      "stages, operator by operator, 16 output columns each); the time is "
+                                      "launch latency and the per-workgroup chain of 8 dependent products, "
+                                      "not bandwidth or matrix throughput"}
         del graph
 
     if precision == "fp32" and not args.no_split_bf16:

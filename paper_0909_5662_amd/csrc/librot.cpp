@@ -478,6 +478,12 @@ rot_status rot_batch_ex(const rot_problem* groups, int32_t n_groups, rot_precisi
             }
             continue;
         }
+        if (prec == ROT_FP64 && !sym && rotate_small_f64_applies(p)) {
+            // small blocks: both stages in one launch, no intermediate
+            hipError_t e = timed("small_fp64", s, [&] { return rotate_small_f64(p, s); });
+            if (e != hipSuccess) return hip_fail(e, "rot_batch small fp64");
+            continue;
+        }
         const size_t per_op = t_bytes(p, prec);
         // split-K stage 2 (general output only) when the workspace holds the
         // whole batch with its partial sums

@@ -125,6 +125,10 @@ struct Bf16Choice {
     Bf16Cfg s1, s2;
 };
 
+// FP64 rotation of small blocks (m, m' <= 64) in one launch (small.hip).
+bool rotate_small_f64_applies(const rot_problem& p);
+hipError_t rotate_small_f64(const rot_problem& p, hipStream_t stream);
+
 // Zero `bytes` bytes with a fill kernel (safe under stream capture).
 hipError_t fill_zero(void* p, int64_t bytes, hipStream_t stream);
 

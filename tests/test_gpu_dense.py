@@ -72,6 +72,19 @@ def test_fp64_parity(rot, oracle_mod, shape):
     assert rel_fro(got, ref).max() <= TOL64
 
 
+@pytest.mark.parametrize("shape", [(37, 3, 29, 5), (64, 4, 64, 3), (1, 4, 3, 3), (16, 1, 16, 2), (50, 2, 64, 4),
+                                   (64, 4, 17, 2), (64, 4, 65, 2)])
+def test_fp64_small_blocks(rot, oracle_mod, shape):
+    """FP64 blocks with m, m' <= 64 run both stages in one launch (zero-padded
+    64 x 64 tiles in LDS, partial output columns and rows); (64, 4, 65) takes
+    the two-stage path next to it."""
+    m, d, mp, n = shape
+    case = workloads.dense_case(m, d, mp, n, cfg=240 + m + mp, dtype="f64", symmetric=False)
+    got = run_rotate(rot, case, "fp64")
+    ref = oracle_mod.rotate(case.U, case.O, d)
+    assert rel_fro(got, ref).max() <= TOL64
+
+
 def test_fp64_config_m64_full(rot, oracle_mod):
     """The 64-state FP64 workload in full: 32 symmetric 64 x 64 operators."""
     case = workloads.named_dense("dense_m64_f64")
