@@ -108,7 +108,8 @@ typedef struct {
  * are deterministic for a given workspace size but may differ in the last
  * bits from a call whose workspace is too small to split.  An FP64 group
  * with m <= 64 and mp <= 64 (not ROT_OUT_SYMMETRIC) is rotated in a single
- * launch that keeps both stages in LDS and uses no workspace.  Groups may have
+ * launch that keeps both stages in LDS and leaves the workspace untouched
+ * (its size is still checked as for any group).  Groups may have
  * different m, d, mp.  ROT_SPLIT_BF16 picks each stage's tile configuration per shape (m, d,
  * mp, chunk): from the tuning cache (in memory, and in the file named by
  * ROT_TUNE_CACHE), else on the shape's first call by timing the candidates
