@@ -139,6 +139,8 @@ def padded(a, dtype, pad_rows=0, pad_cols=0, fill=float("nan")):
     ((96, 4, 80, 3), (4, 5, 3)),     # ld not a multiple of 4: element loads
     ((130, 4, 120, 2), (8, 4, 8)),   # ld multiples of 4: vector loads
     ((257, 3, 300, 2), (1, 7, 12)),
+    ((37, 3, 29, 3), (3, 5, 2)),     # FP64: the one-launch small-block path
+    ((64, 4, 64, 2), (1, 2, 3)),
 ])
 def test_padded_leading_dimensions(rot, oracle_mod, precision, shape, pads):
     """U, O and out with row strides ldu > mp, ldo > m, ldout > mp (and taller
