@@ -38,26 +38,47 @@ __global__ __launch_bounds__(256) void rotate_small_f64_kernel(const double* __r
     const double* Ob = O + (int64_t)b * stride_o;
     constexpr int PER = kSmall * kSmall / 256;  // elements of a 64 x 64 tile per thread
 
+    // Tile staging: thread tid owns column a = tid % 64 and rows j0 + 4 x
+    // (j0 = tid / 64, x < PER).  Every load is unconditional, from a clamped
+    // in-range row and column, so the loads stay in flight; entries outside
+    // the block are replaced by zeros when the tile is stored to LDS.
+    const int a = tid & (kSmall - 1), j0 = tid >> 6;
+    const int ac = min(a, mp - 1), jb = min(j0, m - 1);
+    const int xl = j0 < m ? (m - 1 - j0) >> 2 : 0;  // last x whose row exists
+    auto keep = [&](int x, int cols) __attribute__((always_inline)) { return a < cols && j0 + 4 * x < m; };
     // U_s through registers: site state s + 1 is loaded while s is multiplied
     double ur[PER];
+    const int64_t ustep = (int64_t)4 * d * ldu;  // four rows j further
     auto load_u = [&](int s) __attribute__((always_inline)) {
+        const double* u0 = U + ((int64_t)jb * d + s) * ldu + ac;
+        if (m == kSmall) {  // every row exists: addresses step by a uniform stride
 #pragma unroll
-        for (int x = 0; x < PER; x++) {
-            const int e = tid + 256 * x, j = e / kSmall, a = e % kSmall;
-            ur[x] = j < m && a < mp ? U[((int64_t)j * d + s) * ldu + a] : 0.0;
+            for (int x = 0; x < PER; x++) ur[x] = u0[x * ustep];
+        } else {
+            const double* ul = u0 + (int64_t)xl * ustep;
+#pragma unroll
+            for (int x = 0; x < PER; x++) ur[x] = *(x <= xl ? u0 + x * ustep : ul);
         }
     };
     auto store_u = [&](double* dst) __attribute__((always_inline)) {
 #pragma unroll
-        for (int x = 0; x < PER; x++) {
-            const int e = tid + 256 * x;
-            dst[(e / kSmall) * kSmallPitch + e % kSmall] = ur[x];
-        }
+        for (int x = 0; x < PER; x++) dst[(j0 + 4 * x) * kSmallPitch + a] = keep(x, mp) ? ur[x] : 0.0;
     };
     load_u(0);
-    for (int e = tid; e < kSmall * kSmall; e += 256) {
-        const int j = e / kSmall, k = e % kSmall;
-        Os[j * kSmallPitch + k] = j < m && k < m ? Ob[(int64_t)j * ldo + k] : 0.0;
+    {
+        double orr[PER];
+        const double* o0 = Ob + (int64_t)jb * ldo + min(a, m - 1);
+        const int64_t ostep = 4 * ldo;
+        if (m == kSmall) {
+#pragma unroll
+            for (int x = 0; x < PER; x++) orr[x] = o0[x * ostep];
+        } else {
+            const double* ol = o0 + (int64_t)xl * ostep;
+#pragma unroll
+            for (int x = 0; x < PER; x++) orr[x] = *(x <= xl ? o0 + x * ostep : ol);
+        }
+#pragma unroll
+        for (int x = 0; x < PER; x++) Os[(j0 + 4 * x) * kSmallPitch + a] = keep(x, m) ? orr[x] : 0.0;
     }
     store_u(Us[0]);
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -67,7 +88,7 @@ __global__ __launch_bounds__(256) void rotate_small_f64_kernel(const double* __r
         __syncthreads();  // U_s stored; the previous T_s consumed
         // T_s rows 16 w .. 16 w + 15 over the 16 columns of this chunk
         f64x4 t = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+#pragma unroll
         for (int q = 0; q < kSmall / 4; q++) {
             const int k = 4 * q + h;
             t = __builtin_amdgcn_mfma_f64_16x16x4f64(Os[(16 * w + c) * kSmallPitch + k],
@@ -77,7 +98,7 @@ __global__ __launch_bounds__(256) void rotate_small_f64_kernel(const double* __r
         for (int v = 0; v < 4; v++) Ts[(16 * w + 4 * v + h) * kSmallCols + c] = t[v];
         __syncthreads();
         // O'_b rows alpha = 16 w .. 16 w + 15 += U_s^T T_s
-#pragma unroll 4
+#pragma unroll
         for (int q = 0; q < kSmall / 4; q++) {
             const int j = 4 * q + h;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(us[j * kSmallPitch + 16 * w + c], Ts[j * kSmallCols + c], acc,
