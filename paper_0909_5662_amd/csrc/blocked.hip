@@ -153,6 +153,7 @@ struct UtSeg {
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 // Slack after the transposed-U area: stage 1 reads up to CG - 1 column
@@ -666,6 +667,11 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
     constexpr int WPM = 2;  // waves per member
     constexpr int MB = kStkMB, NB = kStkNB / WPM, KS = kStkResK, ROWS = 16 * kStkNB, NT = 256 * WPM;
     __shared__ f32x4 bs[4 * KS][ROWS];  // operator rows: [k quad][stacked column], 20 KiB
+    // per wave: one 16-row block of its 16 x 32 output tile, transposed so
+    // that each lane stores four consecutive columns (row pitch 36: the four
+    // lane groups of a write fall in different banks), 18 KiB
+    constexpr int TP = 36;
+    __shared__ __attribute__((aligned(16))) float tt[NT / 64][16 * TP];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int li = lane & 15, lh = lane >> 4;
@@ -710,16 +716,19 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
         __builtin_amdgcn_make_buffer_rsrc(C + mem.c_base, (short)0, mem.span, kBufferFlags);
     // (lane part: column n and rows 4 lh .. 4 lh + 3 of each row block)
     const int ldc4 = mem.ldcm * 4;
-    const int mrem = mem.M - 4 * lh;  // rows mb * 16 + v of this lane exist while below this
-    int cofs[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; nb++) {
-        const int n = n0 + nb * 16 + li;
+    // this lane's stores: columns 4 (lane % 8) .. + 3 of the wave's 32 (one
+    // operator's: segments are multiples of 4 wide), rows lane / 8 and
+    // lane / 8 + 8 of each 16-row block
+    const int sq = lane & 7, sr = lane >> 3;
+    int qofs;
+    {
+        const int n = n0 + 4 * sq;
         const bool ok = active && n < g.N;
         const int j = ok ? n / g.nb : 0;
         const int64_t co = ok ? coff[mem.tab + j] : -1;
-        cofs[nb] = (co >= 0 ? (int)((co - mem.c_base + (n - j * g.nb)) * 4) : kStkNoBlock) + 4 * lh * ldc4;
+        qofs = (co >= 0 ? (int)((co - mem.c_base + (n - j * g.nb)) * 4) : kStkNoBlock) + sr * ldc4;
     }
+    const int mrem8 = mem.M - sr;  // rows mb * 16 + 8 h of this lane exist while below this
     // stage the operator rows: thread tid owns stacked column tid % 64 and
     // k quads tid / 64 + (NT / 64) i (zero past K; a quad crossing K element
     // by element)
@@ -782,17 +791,26 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
                                                                                acc[mb][nb], 0, 0, 0);
             }
         }
+        float* tw = tt[w];
 #pragma unroll
-        for (int mb = 0; mb < NBM; mb++)
+        for (int mb = 0; mb < NBM; mb++) {
+            // accumulator element v of lane l: row 4 (l / 16) + v, column nb * 16 + l % 16
 #pragma unroll
             for (int nb = 0; nb < NB; nb++)
 #pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int r = mb * 16 + v;
-                    const int off = r < mrem ? cofs[nb] + r * ldc4 : kStkDrop;
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[mb][nb][v]), cres, off, 0,
-                                                          0);
-                }
+                for (int v = 0; v < 4; v++) tw[(4 * lh + v) * TP + nb * 16 + li] = acc[mb][nb][v];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int r = mb * 16 + 8 * h;
+                const f32x4 q = *reinterpret_cast<const f32x4*>(tw + (sr + 8 * h) * TP + 4 * sq);
+                const int off = r < mrem8 ? qofs + r * ldc4 : kStkDrop;
+                __builtin_amdgcn_raw_buffer_store_b128(
+                    u32x4{__float_as_uint(q[0]), __float_as_uint(q[1]), __float_as_uint(q[2]), __float_as_uint(q[3])},
+                    cres, off, 0, 0);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
     };
     static_assert(MB == 5, "one case per row-block count");
     switch (nbm) {
