@@ -145,7 +145,8 @@ struct BlkTerm {
     int rt, rq;      // first padded row of site state s in U^T_T and in U^T_Q (multiples of 4)
     int64_t o_off;   // operator block (a x k, leading dimension k) in O_blk
 };
-// One site state's rows of one kept sector in the transposed-U area.
+// One site state's rows of one kept sector in the transposed-U area; with
+// rows = 0, mp = ld = 1, a run of rows4 zeros (alignment gaps, the slack).
 struct UtSeg {
     int64_t u_off;   // first row of the segment in U_blk (leading dimension mp)
     int64_t ut_off;  // U^T area offset of column 0 of this segment (leading dimension ld)
@@ -159,8 +160,8 @@ typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 // Slack after the transposed-U area: stage 1 reads up to CG - 1 column
 // blocks (and a partial one) past a sector, i.e. fewer than 96 rows of the
 // widest block, and padded k runs past a row by fewer than 16 values.  The
-// whole area, slack and alignment gaps included, is zero before the
-// transpose fills it, so such reads only ever meet finite values.
+// transpose writes the whole area (zeros in the padding rows, the alignment
+// gaps between sectors and the slack), so such reads only meet finite values.
 inline int64_t ut_slack(int max_ld) { return 96 * (int64_t)max_ld + 64; }
 
 __global__ __launch_bounds__(256) void transpose_u_kernel(const UtSeg* __restrict__ segs, const float* __restrict__ U,
@@ -1008,9 +1009,12 @@ UtLayout ut_layout(const rot_blocked_problem* p, const Structure& st) {
             L.segs.push_back(g);
         }
         off += (int64_t)Q.dim * ld;
-        off = (off + 3) / 4 * 4;
+        const int64_t next = (off + 3) / 4 * 4;
+        if (next > off) L.segs.push_back(UtSeg{0, off, 0, (int)(next - off), 1, 1});
+        off = next;
     }
     L.elems = off + ut_slack(L.max_ld);
+    L.segs.push_back(UtSeg{0, off, 0, (int)ut_slack(L.max_ld), 1, 1});
     return L;
 }
 
@@ -1581,8 +1585,6 @@ hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, bool r
     if (plan->f_n_tasks == 0) return hipSuccess;
     float* ut = static_cast<float*>(ws) + plan->ut_base;
     hipError_t e = prof_timed("blocked_transpose_u", stream, [&] {
-        hipError_t err = fill_zero(ut, plan->ut_elems * (int64_t)sizeof(float), stream);
-        if (err != hipSuccess) return err;
         hipLaunchKernelGGL(transpose_u_kernel, dim3(16, (unsigned)plan->f_n_segs), dim3(256), 0, stream,
                            plan->f_segs, p->U_blk, ut);
         return hipGetLastError();
@@ -1634,8 +1636,6 @@ hipError_t run_stacked(const rot_blocked_problem* p, Plan* plan, void* ws, hipSt
     float* ut = static_cast<float*>(ws) + plan->ut_base;
     float* xt = static_cast<float*>(ws);
     hipError_t e = prof_timed("blocked_transpose_u", stream, [&] {
-        hipError_t err = fill_zero(ut, plan->ut_elems * (int64_t)sizeof(float), stream);
-        if (err != hipSuccess) return err;
         hipLaunchKernelGGL(transpose_u_kernel, dim3(16, (unsigned)plan->f_n_segs), dim3(256), 0, stream,
                            plan->f_segs, p->U_blk, ut);
         return hipGetLastError();
