@@ -145,11 +145,13 @@ struct BlkTerm {
     int rt, rq;      // first padded row of site state s in U^T_T and in U^T_Q (multiples of 4)
     int64_t o_off;   // operator block (a x k, leading dimension k) in O_blk
 };
-// One site state's rows of one kept sector in the transposed-U area; with
-// rows = 0, mp = ld = 1, a run of rows4 zeros (alignment gaps, the slack).
+// One site state's rows of one kept sector in the transposed-U area.  With
+// rows = 0 it writes zeros instead: mp runs of rows4 zeros, ld apart (the
+// alignment gaps and the slack of the area; the Xt segments of site states
+// whose source sector is absent, one run per operator).
 struct UtSeg {
     int64_t u_off;   // first row of the segment in U_blk (leading dimension mp)
-    int64_t ut_off;  // U^T area offset of column 0 of this segment (leading dimension ld)
+    int64_t ut_off;  // workspace offset (floats) of column 0 of this segment (leading dimension ld)
     int rows, rows4, mp, ld;
 };
 
@@ -168,6 +170,11 @@ __global__ __launch_bounds__(256) void transpose_u_kernel(const UtSeg* __restric
                                                           float* __restrict__ Ut) {
     const UtSeg g = segs[blockIdx.y];
     const int64_t n = (int64_t)g.rows4 * g.mp;
+    if (g.rows == 0) {  // zero runs, each written contiguously
+        for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+            Ut[g.ut_off + (e / g.rows4) * g.ld + e % g.rows4] = 0.f;
+        return;
+    }
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e / g.mp), beta = (int)(e % g.mp);
         Ut[g.ut_off + (int64_t)beta * g.ld + i] = i < g.rows ? U[g.u_off + (int64_t)i * g.mp + beta] : 0.f;
@@ -1101,6 +1108,7 @@ struct StackedLists {
     std::vector<StkMember> mem;
     std::vector<StkTile> tr;
     std::vector<int64_t> boff, coff;
+    std::vector<UtSeg> xzero;  // zero Xt segments (site states whose source sector is absent)
     int64_t x_elems = 0;
     bool ok = true;  // false: some kept sector has more than 4 site-state segments
 };
@@ -1176,28 +1184,15 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
                 for (int n0 = 0; n0 < g2.N; n0 += kStk2Cols) o2w.push_back({g2.K, StkTile{gi2, m0, n0, 0}});
             }
             // Xt columns of site states whose source sector q_s = Q - qn(s) is
-            // absent while q_s + Delta exists: zero (streamed groups with K = 0)
+            // absent while q_s + Delta exists: zero, one run of m'_Q x a4 per
+            // operator (the operators' Xt blocks are equally spaced)
             for (int s = 0; s < p->d; s++) {
                 if (st.rowstart[kt][s] < 0 || st.rowstart[k][s] >= 0) continue;
                 const QN qt{T.n_up - p->site_qn[2 * s], T.n_dn - p->site_qn[2 * s + 1]};
                 const int a = p->old_sec[st.old_idx.at(qt)].dim;
-                StkGroup g1{};
-                g1.M = Q.dim;
-                g1.N = n * ((a + 3) / 4 * 4);
-                g1.K = 0;
-                g1.nb = (a + 3) / 4 * 4;
-                g1.nvalid = a;
-                g1.lda = g1.ldb = 1;
-                g1.ldcm = g1.nb;  // Xt segment s: mQ x a4, row-major
-                g1.tab = (int64_t)S->boff.size();
-                for (int j = 0; j < n; j++) {
-                    S->boff.push_back(-1);
-                    S->coff.push_back(xbase[(size_t)J[j] * p->n_new + k] + (int64_t)Q.dim * ut.pstart[kt][s]);
-                }
-                const int gi1 = (int)S->g1.size();
-                S->g1.push_back(g1);
-                for (int m0 = 0; m0 < g1.M; m0 += 16 * kStkMB)
-                    for (int n0 = 0; n0 < g1.N; n0 += 16 * kStkNB) o1.push_back({0, StkTile{gi1, m0, n0, 0}});
+                const int64_t spacing = ((int64_t)Q.dim * ldT + 63) / 64 * 64;
+                S->xzero.push_back(UtSeg{0, xbase[(size_t)J[0] * p->n_new + k] + (int64_t)Q.dim * ut.pstart[kt][s], 0,
+                                         Q.dim * ((a + 3) / 4 * 4), n, (int)spacing});
             }
         }
         // stage 1 per source sector q: every operator's block O(q + Delta <- q)
@@ -1405,7 +1400,8 @@ struct Plan {
     BlkTerm* f_terms = nullptr;
     UtSeg* f_segs = nullptr;
     int f_n_tasks = 0;
-    int f_n_segs = 0;
+    int f_n_segs = 0;   // transpose segments (f_segs); the stacked path's zero Xt segments follow
+    int k_n_xzero = 0;
     int f_max_mT = 0;
     int f_max_k = 0;
     int64_t ut_base = 0;   // transposed U area in the workspace (elements)
@@ -1583,13 +1579,13 @@ bool rowblock_ok(const Plan* plan) {
 hipError_t run_fused(const rot_blocked_problem* p, Plan* plan, bool wide, bool rowblock, void* ws,
                      hipStream_t stream) {
     if (plan->f_n_tasks == 0) return hipSuccess;
-    float* ut = static_cast<float*>(ws) + plan->ut_base;
     hipError_t e = prof_timed("blocked_transpose_u", stream, [&] {
         hipLaunchKernelGGL(transpose_u_kernel, dim3(16, (unsigned)plan->f_n_segs), dim3(256), 0, stream,
-                           plan->f_segs, p->U_blk, ut);
+                           plan->f_segs, p->U_blk, static_cast<float*>(ws));
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
+    float* ut = static_cast<float*>(ws) + plan->ut_base;
     int* counter = reinterpret_cast<int*>(static_cast<char*>(ws) + plan->counter_off);
     return prof_timed("blocked_fused_fp32", stream, [&] {
         hipLaunchKernelGGL(reset_fused_counter, dim3(1), dim3(64), 0, stream, counter);
@@ -1629,15 +1625,16 @@ bool stage2_per_wave() {
     return e && strcmp(e, "wave") == 0;
 }
 
-// Transposed U blocks into the workspace, then the two stacked launches
-// (stage 1 writes every element of Xt that stage 2 reads, padding included).
+// Transposed U blocks into the workspace together with the zero Xt segments,
+// then the two stacked launches (stage 1 writes every other element of Xt
+// that stage 2 reads, padding included).
 hipError_t run_stacked(const rot_blocked_problem* p, Plan* plan, void* ws, hipStream_t stream) {
     if (plan->k_n2 == 0) return hipSuccess;
     float* ut = static_cast<float*>(ws) + plan->ut_base;
     float* xt = static_cast<float*>(ws);
     hipError_t e = prof_timed("blocked_transpose_u", stream, [&] {
-        hipLaunchKernelGGL(transpose_u_kernel, dim3(16, (unsigned)plan->f_n_segs), dim3(256), 0, stream,
-                           plan->f_segs, p->U_blk, ut);
+        hipLaunchKernelGGL(transpose_u_kernel, dim3(16, (unsigned)(plan->f_n_segs + plan->k_n_xzero)), dim3(256),
+                           0, stream, plan->f_segs, p->U_blk, xt);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
@@ -1727,9 +1724,15 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         np->ut_base = (np->x_elems + 63) / 64 * 64;
         np->ut_elems = ut.elems;
         np->counter_off = counter_offset(np->x_elems, ut.elems);
-        if (e == hipSuccess && !ut.segs.empty()) e = hipMalloc(&np->f_segs, sizeof(UtSeg) * ut.segs.size());
-        if (e == hipSuccess && !ut.segs.empty())
-            e = hipMemcpy(np->f_segs, ut.segs.data(), sizeof(UtSeg) * ut.segs.size(), hipMemcpyHostToDevice);
+        // the transpose segments (offsets from the workspace base), then the
+        // stacked path's zero Xt segments
+        std::vector<UtSeg> segs = ut.segs;
+        for (UtSeg& g : segs) g.ut_off += np->ut_base;
+        if (S.ok) segs.insert(segs.end(), S.xzero.begin(), S.xzero.end());
+        np->k_n_xzero = S.ok ? (int)S.xzero.size() : 0;
+        if (e == hipSuccess && !segs.empty()) e = hipMalloc(&np->f_segs, sizeof(UtSeg) * segs.size());
+        if (e == hipSuccess && !segs.empty())
+            e = hipMemcpy(np->f_segs, segs.data(), sizeof(UtSeg) * segs.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess && !F.tasks.empty()) e = hipMalloc(&np->f_tasks, sizeof(BlkTask) * F.tasks.size());
         if (e == hipSuccess && !F.terms.empty()) e = hipMalloc(&np->f_terms, sizeof(BlkTerm) * F.terms.size());
         if (e == hipSuccess && !F.tasks.empty())
