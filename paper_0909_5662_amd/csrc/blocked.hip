@@ -1447,42 +1447,57 @@ struct Plan {
 std::mutex g_mu;
 PinnedLru<std::vector<unsigned char>, Plan> g_plans(kPlanCacheSize);
 
-template <class T>
-void put(std::vector<unsigned char>& v, const T* p, size_t n) {
-    const unsigned char* c = reinterpret_cast<const unsigned char*>(p);
-    v.insert(v.end(), c, c + sizeof(T) * n);
-}
-
 // Everything the work-lists depend on: the tables' contents, the shape, and
 // the 16-byte alignment of the buffers (which decides vector loads).  The
-// chosen path (fused or two grouped launches) is cached with the lists.
-std::vector<unsigned char> signature(const rot_blocked_problem* p, const void* ws, GroupedShape shape) {
-    std::vector<unsigned char> v;
+// chosen path (fused or two grouped launches) is cached with the lists.  The
+// pieces are handed to `f(bytes, size)` in a fixed order.
+template <class F>
+void walk_signature(const rot_blocked_problem* p, const void* ws, GroupedShape shape, F&& f) {
+    auto put = [&](const auto* x, size_t n) { f(reinterpret_cast<const unsigned char*>(x), sizeof(*x) * n); };
     const int32_t head[4] = {p->d, p->n_old, p->n_new, p->n_ops};
-    put(v, head, 4);
+    put(head, 4);
     const unsigned char align[4] = {
         (unsigned char)(reinterpret_cast<uintptr_t>(p->U_blk) & 15),
         (unsigned char)(reinterpret_cast<uintptr_t>(p->O_blk) & 15),
         (unsigned char)(reinterpret_cast<uintptr_t>(p->out_blk) & 15),
         (unsigned char)(reinterpret_cast<uintptr_t>(ws) & 15)};
-    put(v, align, 4);
-    put(v, &shape, 1);
-    put(v, p->site_qn, 2 * p->d);
+    put(align, 4);
+    put(&shape, 1);
+    put(p->site_qn, 2 * (size_t)p->d);
     for (int k = 0; k < p->n_old; k++) {
-        const int64_t f[4] = {p->old_sec[k].n_up, p->old_sec[k].n_dn, p->old_sec[k].dim, p->old_sec[k].offset};
-        put(v, f, 4);
+        const int64_t v[4] = {p->old_sec[k].n_up, p->old_sec[k].n_dn, p->old_sec[k].dim, p->old_sec[k].offset};
+        put(v, 4);
     }
     for (int k = 0; k < p->n_new; k++) {
-        const int64_t f[4] = {p->new_sec[k].n_up, p->new_sec[k].n_dn, p->new_sec[k].dim, p->new_sec[k].offset};
-        put(v, f, 4);
+        const int64_t v[4] = {p->new_sec[k].n_up, p->new_sec[k].n_dn, p->new_sec[k].dim, p->new_sec[k].offset};
+        put(v, 4);
     }
-    put(v, p->U_off, p->n_new);
+    put(p->U_off, (size_t)p->n_new);
     if (p->n_ops > 0) {
-        put(v, p->shift, 2 * (size_t)p->n_ops);
-        put(v, p->O_off, (size_t)p->n_ops * p->n_old);
-        put(v, p->out_off, (size_t)p->n_ops * p->n_new);
+        put(p->shift, 2 * (size_t)p->n_ops);
+        put(p->O_off, (size_t)p->n_ops * p->n_old);
+        put(p->out_off, (size_t)p->n_ops * p->n_new);
     }
+}
+
+std::vector<unsigned char> signature(const rot_blocked_problem* p, const void* ws, GroupedShape shape) {
+    std::vector<unsigned char> v;
+    walk_signature(p, ws, shape, [&](const unsigned char* b, size_t n) { v.insert(v.end(), b, b + n); });
     return v;
+}
+
+// Whether `key` is the signature of (p, ws, shape), compared piece by piece
+// without building it.
+bool signature_matches(const rot_blocked_problem* p, const void* ws, GroupedShape shape,
+                       const std::vector<unsigned char>& key) {
+    size_t at = 0;
+    bool same = true;
+    walk_signature(p, ws, shape, [&](const unsigned char* b, size_t n) {
+        if (!same) return;
+        same = at + n <= key.size() && (n == 0 || memcmp(key.data() + at, b, n) == 0);
+        at += n;
+    });
+    return same && at == key.size();
 }
 
 hipError_t upload(const std::vector<GroupedProblem>& probs, const std::vector<GroupedTile>& tiles, DeviceLists* d) {
@@ -1687,14 +1702,14 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
     if (p->n_ops == 0) return hipSuccess;
     const GroupedShape shape = blocked_shape();
     const int forced = forced_path();
-    std::vector<unsigned char> sig = signature(p, ws, shape);
     // Under stream capture the graph keeps the plan's device work-lists: the
     // plan is pinned (never evicted), and a structure not seen before cannot
     // be planned (its lists are copied to the device synchronously).
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool capturing = hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
     std::lock_guard<std::mutex> lk(g_mu);
-    Plan* plan = g_plans.find(sig);
+    Plan* plan = g_plans.find_if(
+        [&](const std::vector<unsigned char>& key) { return signature_matches(p, ws, shape, key); });
     if (!plan && capturing) {
         set_error(ROT_ERR_UNSUPPORTED,
                   "rot_batch_blocked: the first call for a block structure must run outside stream capture "
@@ -1760,7 +1775,7 @@ hipError_t rotate_blocked(const rot_blocked_problem* p, void* ws, size_t ws_byte
         up(&np->k_tr, S.tr);
         up(&np->k_t2w, S.t2w);
         if (e != hipSuccess) return e;
-        plan = g_plans.insert(std::move(sig), std::move(np));
+        plan = g_plans.insert(signature(p, ws, shape), std::move(np));
     }
     // paths that apply to this structure: the fused kernels keep at most
     // 8 x 16 output rows per lane set

@@ -31,6 +31,18 @@ class PinnedLru {
         return nullptr;
     }
 
+    // The first entry (most recent first) whose key satisfies `pred`, made
+    // the most recent; nullptr when none does.
+    template <class Pred>
+    Value* find_if(Pred pred) {
+        for (auto it = entries_.begin(); it != entries_.end(); ++it)
+            if (pred(it->key)) {
+                entries_.splice(entries_.begin(), entries_, it);
+                return entries_.front().value.get();
+            }
+        return nullptr;
+    }
+
     // Insert as the most recent entry, then evict least recently used
     // unpinned entries until at most `capacity` unpinned ones remain.
     // Returns the stored value.

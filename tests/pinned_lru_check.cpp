@@ -34,6 +34,12 @@ int main() {
         CHECK(c.size() == 2);
         CHECK(c.find("b") == nullptr);  // least recent unpinned entry evicted
         CHECK(c.find("a") == a && Val::alive == 2);
+        // find_if: the first match, most recent first, made the most recent
+        Val* cc = c.find_if([](const std::string& k) { return k == "c"; });
+        CHECK(cc != nullptr && cc->id == 3);
+        CHECK(c.find_if([](const std::string& k) { return k == "b"; }) == nullptr);
+        c.insert("d", std::make_unique<Val>(4));  // evicts a (c was used last)
+        CHECK(c.find("a") == nullptr && c.find("c") == cc && c.size() == 2);
         (void)b;
     }
     CHECK(Val::alive == 0);  // the cache owns and frees its values
