@@ -722,8 +722,7 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
     // instead of a branch, and the hardware drops that store
     const __amdgpu_buffer_rsrc_t cres =
         __builtin_amdgcn_make_buffer_rsrc(C + mem.c_base, (short)0, mem.span, kBufferFlags);
-    // (lane part: column n and rows 4 lh .. 4 lh + 3 of each row block)
-    const int ldc4 = mem.ldcm * 4;
+    const int ldc4 = mem.ldcm * 4;  // bytes from one Xt row to the next
     // this lane's stores: columns 4 (lane % 8) .. + 3 of the wave's 32 (one
     // operator's: segments are multiples of 4 wide), rows lane / 8 and
     // lane / 8 + 8 of each 16-row block
