@@ -671,7 +671,7 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
                                                                         const int64_t* __restrict__ coff,
                                                                         const float* __restrict__ A,
                                                                         const float* __restrict__ B,
-                                                                        float* __restrict__ C) {
+                                                                        float* __restrict__ C, int abytes) {
     constexpr int WPM = 2;  // waves per member
     constexpr int MB = kStkMB, NB = kStkNB / WPM, KS = kStkResK, ROWS = 16 * kStkNB, NT = 256 * WPM;
     __shared__ f32x4 bs[4 * KS][ROWS];  // operator rows: [k quad][stacked column], 20 KiB
@@ -697,14 +697,21 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
     StkMember mem{};
     if (active) mem = members[tl.m0 + wm];
     const int nbm = min(MB, (mem.M + 15) >> 4);
-    const float* arow[MB];
-    bool aok[MB];
+    // U^T rows through a descriptor over the transposed-U area (abytes <
+    // 2^30) at 32-bit byte offsets; a row past M, or a quad at or past K,
+    // reads at kStkDrop, past the end, and gets zeros
+    const __amdgpu_buffer_rsrc_t ares =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(A), (short)0, abytes, kBufferFlags);
+    int aofs[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; mb++) {
         const int m = mb * 16 + li;
-        aok[mb] = active && m < mem.M;
-        arow[mb] = A + mem.a_off + (int64_t)(aok[mb] ? m : 0) * mem.lda;
+        aofs[mb] = active && m < mem.M ? (int)((mem.a_off + (int64_t)m * mem.lda) * 4) : kStkDrop;
     }
+    auto aquad = [&](int mb, int kk) __attribute__((always_inline)) {
+        const int off = kk < K && aofs[mb] != kStkDrop ? aofs[mb] + 4 * kk : kStkDrop;
+        return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ares, off, 0, 0));
+    };
     // U^T rows of k steps s .. s + PFA in flight: set s % (PFA + 1) holds step s
     f32x4 a[PFA + 1][MB];
 #pragma unroll
@@ -713,8 +720,7 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
 #pragma unroll
             for (int mb = 0; mb < MB; mb++)
                 if (mb < nbm) {
-                    const int kk = 16 * p + 4 * lh;
-                    a[p][mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+                    a[p][mb] = aquad(mb, 16 * p + 4 * lh);
                 }
         }
     // stores: 32-bit byte offsets into the member's Xt group; an operator
@@ -780,8 +786,7 @@ __global__ __launch_bounds__(512) void blocked_stacked_lds_kernel(const StkTile*
                 if (s + PFA < nks) {
 #pragma unroll
                     for (int mb = 0; mb < NBM; mb++) {
-                        const int kk = 16 * (s + PFA) + 4 * lh;
-                        a[(s + PFA) % (PFA + 1)][mb] = quad_or_zero<true>(arow[mb], kk, aok[mb] && kk < K, A);
+                        a[(s + PFA) % (PFA + 1)][mb] = aquad(mb, 16 * (s + PFA) + 4 * lh);
                     }
                 }
                 // lane group lh takes k = 16 s + 4 lh + q at instruction q
@@ -1307,6 +1312,8 @@ void build_stacked(const rot_blocked_problem* p, const Structure& st, const UtLa
     for (const auto& o : o2w) S->t2w.push_back(o.second);
     std::stable_sort(o_r.begin(), o_r.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
     for (const auto& o : o_r) S->tr.push_back(o.second);
+    // stage 1 reads the transposed-U area through one descriptor with 32-bit byte offsets
+    if (ut.elems * (int64_t)sizeof(float) > kStkSpanMax) S->ok = false;
 }
 
 struct Lists {
@@ -1655,7 +1662,8 @@ hipError_t run_stacked(const rot_blocked_problem* p, Plan* plan, void* ws, hipSt
     e = prof_timed("blocked_stacked1_fp32", stream, [&] {
         if (plan->k_nr > 0)
             hipLaunchKernelGGL(blocked_stacked_lds_kernel<1>, dim3(plan->k_nr), dim3(512), 0, stream, plan->k_tr,
-                               plan->k_gr, plan->k_mem, plan->k_boff, plan->k_coff, ut, p->O_blk, xt);
+                               plan->k_gr, plan->k_mem, plan->k_boff, plan->k_coff, ut, p->O_blk, xt,
+                               (int)(plan->ut_elems * (int64_t)sizeof(float)));
         if (plan->k_n1 > 0)
             return launch_stacked<false>(plan->k_t1, plan->k_n1, plan->k_g1, plan, ut, p->O_blk, xt, stream);
         return hipGetLastError();
