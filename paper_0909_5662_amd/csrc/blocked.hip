@@ -846,7 +846,8 @@ __global__ __launch_bounds__(256) void blocked_stacked2_wg_kernel(const StkTile*
                                                                   const int64_t* __restrict__ boff,
                                                                   const int64_t* __restrict__ coff,
                                                                   const float* __restrict__ A,
-                                                                  const float* __restrict__ B, float* __restrict__ C) {
+                                                                  const float* __restrict__ B, float* __restrict__ C,
+                                                                  int abytes) {
     constexpr int MB = kStkMB, NB = 2, PF = 2, AR = 16 * kStkMB;
     __shared__ f32x4 as[2][4][AR];  // [buffer][k quad][row], 10 KiB
     const int tid = threadIdx.x;
@@ -860,9 +861,14 @@ __global__ __launch_bounds__(256) void blocked_stacked2_wg_kernel(const StkTile*
     const int nbm = min(MB, (g.M - tl.m0 + 15) >> 4);
     const int n0 = tl.n0 + w * 16 * NB;
     const int nbn = max(0, min(NB, (g.N - n0 + 15) >> 4));
-    // A staging: thread tid carries quads tid and tid + 256 of the 4 x 80 of a step
-    const float* ar[2];
-    bool aok[2], aq[2];
+    // A staging: thread tid carries quads tid and tid + 256 of the 4 x 80 of
+    // a step, read through a descriptor over the transposed-U area (abytes <
+    // 2^30) at 32-bit byte offsets; a row past M or a quad at or past K reads
+    // at kStkDrop, past the end, and gets zeros
+    const __amdgpu_buffer_rsrc_t ares =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(A), (short)0, abytes, kBufferFlags);
+    int aofs[2];
+    bool aq[2];
     int akq[2], arw[2];
 #pragma unroll
     for (int x = 0; x < 2; x++) {
@@ -871,14 +877,14 @@ __global__ __launch_bounds__(256) void blocked_stacked2_wg_kernel(const StkTile*
         arw[x] = q % AR;
         akq[x] = q / AR;
         const int m = tl.m0 + arw[x];
-        aok[x] = aq[x] && m < g.M;
-        ar[x] = A + g.a_off + (int64_t)(aok[x] ? m : 0) * g.lda;
+        aofs[x] = aq[x] && m < g.M ? (int)((g.a_off + (int64_t)m * g.lda) * 4) : kStkDrop;
     }
     auto stage_load = [&](int s, f32x4* v) __attribute__((always_inline)) {
 #pragma unroll
         for (int x = 0; x < 2; x++) {
             const int kk = 16 * s + 4 * akq[x];
-            v[x] = quad_or_zero<true>(ar[x], kk, aok[x] && kk < K, A);
+            const int off = kk < K && aofs[x] != kStkDrop ? aofs[x] + 4 * kk : kStkDrop;
+            v[x] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ares, off, 0, 0));
         }
     };
     auto stage_store = [&](int buf, const f32x4* v) __attribute__((always_inline)) {
@@ -1673,7 +1679,8 @@ hipError_t run_stacked(const rot_blocked_problem* p, Plan* plan, void* ws, hipSt
         if (stage2_per_wave())
             return launch_stacked<true>(plan->k_t2, plan->k_n2, plan->k_g2, plan, ut, xt, p->out_blk, stream);
         hipLaunchKernelGGL(blocked_stacked2_wg_kernel, dim3(plan->k_n2w), dim3(256), 0, stream, plan->k_t2w,
-                           plan->k_g2, plan->k_boff, plan->k_coff, ut, xt, p->out_blk);
+                           plan->k_g2, plan->k_boff, plan->k_coff, ut, xt, p->out_blk,
+                           (int)(plan->ut_elems * (int64_t)sizeof(float)));
         return hipGetLastError();
     });
 }
